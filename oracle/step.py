@@ -1,0 +1,328 @@
+"""One time step of the N-component free-energy LBM, vectorised over the
+lattice with NumPy in FP64.  Test infrastructure only.
+
+State (post-streaming, time t):
+  f[Q, nz, ny, nx]      hydrodynamic populations (Sec. III A)
+  g[N, Q, nz, ny, nx]   one population set per component (Sec. III B)
+
+Order of one step (the paper gives no pseudo-code; this is the order in which
+each quantity is defined in terms of the previous ones):
+  1. C_i = sum_k g_{i,k}                                   (zeroth moment of g)
+  2. E_B(C) pointwise                                      (Eq. FreeEnergy)
+  3. grad C_i, lap C_i, grad E_B with the isotropic stencils (Eq. gradstencil
+     and the Laplacian after it); a neighbour inside a wall is replaced by the
+     centre value (last paragraph before the open-boundary conditions).
+  4. mu~_i (factored form by default; see potential.py)
+  5. F = grad E_B + sum_{i != j} kappa_ij lap C_j grad C_i + F_b   (Eq. Fsnew)
+     or, as a negative control, F = sum_i mu_i grad C_i + F_b     (Eq. ststand)
+  6. v = sum_k e_k f_k + F/2                               (Eq. nmom, rho = 1)
+     P = c_s^2/(1-w_0) [sum_{k != 0} f_k + s_0(v)]          (Eq. pres, grad rho = 0)
+  7. tau = tau_i of the component with the largest C (lowest index on ties);
+     omega+ = 1/tau; omega- = omega+ (BGK) or from the magic parameter
+     Lambda^TRT = (1/omega+ - 1/2)(1/omega- - 1/2).
+  8. TRT collision of f towards f^eq (Eq. feq) with the forcing of Eqs. FTRT and
+     hydroforce (grad rho = 0).
+  9. BGK collision of g (Eq. glbe) towards g^eq.
+ 10. Streaming psi_k(x + e_k) <- psi*_k(x), periodic, or halfway bounce-back
+     psi_kbar(x) <- psi*_k(x) when x + e_k is inside a wall.
+
+Readings (where the printed text is garbled or silent):
+  * N - 1 concentration LBEs are evolved and one component (``implicit``,
+    default the last as in Sec. II) follows from sum_i C_i = 1 (text after
+    Eq. CHFlux).  The slot of the implicit component in g stays zero.  Any
+    component can be chosen; an absent component must not be the implicit one,
+    because 1 - sum of the others is zero only to rounding.
+  * f^eq_0 carries (P/c_s^2)(w_0 - 1) so that sum_k f^eq_k = 0.  f_0 is read by
+    no other quantity (P sums k != 0, e_0 = 0, TRT pairs 0 with itself), so the
+    choice affects only f_0 itself.
+  * g^eq ("rest" form): g^eq_{i,0} = C_i (1 + s_0) + (1 - w_0) m mu~_i,
+    g^eq_{i,k} = C_i s_k - w_k m mu~_i for k != 0.  Zeroth moment C_i, first
+    moment C_i v, second moment C_i v v - c_s^2 m mu~_i I: the Cahn-Hilliard
+    flux J_i = M grad mu~_i with M = c_s^2 m (tau_g - 1/2).  The "printed" option
+    adds w_k C_i to every direction, which adds a Fickian c_s^2 C_i I to the
+    second moment.
+  * rho = 1 exactly (rho_i = 1 for every component), so grad rho terms vanish.
+"""
+import numpy as np
+
+from . import potential
+from .lattice import CS2
+
+
+class Params:
+    """Problem statement of one simulation (Sec. II-III)."""
+
+    def __init__(self, lattice, shape, sigma, tau, *, D=4.0, omega_stab=0.0,
+                 trt_magic=0.0, tau_g=None, m=0.02, body_force=(0.0, 0.0, 0.0),
+                 walls=(False, False, False), mu_form="factored",
+                 force_form="conservative", geq_form="rest", hydro=True,
+                 implicit=None):
+        from .coeffs import Coefficients
+        self.lat = lattice
+        nx, ny, nz = shape
+        if lattice.dim == 2 and nz != 1:
+            raise ValueError("D2Q9 needs nz == 1")
+        self.shape = (nx, ny, nz)
+        self.co = Coefficients(sigma, D)
+        self.N = self.co.N
+        self.tau = np.asarray(tau, dtype=np.float64).reshape(self.N)
+        self.tau_g = (np.ones(self.N) if tau_g is None
+                      else np.asarray(tau_g, dtype=np.float64).reshape(self.N))
+        self.omega_stab = float(omega_stab)
+        self.trt_magic = float(trt_magic)
+        self.m = float(m)
+        self.body_force = np.asarray(body_force, dtype=np.float64).reshape(3)
+        self.walls = tuple(bool(w) for w in walls)
+        self.mu_form = mu_form
+        self.force_form = force_form
+        self.geq_form = geq_form
+        self.hydro = hydro
+        self.implicit = self.N - 1 if implicit is None else int(implicit)
+        if not 0 <= self.implicit < self.N:
+            raise ValueError("implicit component out of range")
+        self.evolved = [i for i in range(self.N) if i != self.implicit]
+
+    @property
+    def grid(self):
+        nx, ny, nz = self.shape
+        return (nz, ny, nx)
+
+
+def _axis(a):
+    """Array axis of lattice axis a (0 = x, 1 = y, 2 = z) for [..., nz, ny, nx]."""
+    return -1 - a
+
+
+def wall_mask(par, e):
+    """True at nodes whose neighbour x + e lies inside a wall."""
+    nz, ny, nx = par.grid
+    mask = np.zeros((nz, ny, nx), dtype=bool)
+    n = (nx, ny, nz)
+    for a in range(3):
+        if not par.walls[a] or e[a] == 0:
+            continue
+        idx = [slice(None)] * 3
+        idx[_axis(a) + 3] = n[a] - 1 if e[a] > 0 else 0
+        mask[tuple(idx)] = True
+    return mask
+
+
+def neighbour(psi, e, par):
+    """psi(x + e) with periodic wrap, or psi(x) where x + e is inside a wall."""
+    out = np.roll(psi, shift=(-int(e[2]), -int(e[1]), -int(e[0])), axis=(-3, -2, -1))
+    mask = wall_mask(par, e)
+    if mask.any():
+        out = np.where(mask, psi, out)
+    return out
+
+
+def gradient(psi, par):
+    """(1/c_s^2) sum_{k>=1} w_k e_k [psi(x+e_k) - psi(x)]  -> [3, ...]."""
+    lat = par.lat
+    out = np.zeros((3,) + psi.shape)
+    for k in range(1, lat.Q):
+        d = neighbour(psi, lat.e[k], par) - psi
+        for a in range(3):
+            if lat.e[k, a] != 0:
+                out[a] = out[a] + lat.w[k] * lat.e[k, a] * d
+    return out / CS2
+
+
+def laplacian(psi, par):
+    """(2/c_s^2) sum_{k>=1} w_k [psi(x+e_k) - psi(x)]."""
+    lat = par.lat
+    out = np.zeros(psi.shape)
+    for k in range(1, lat.Q):
+        out = out + lat.w[k] * (neighbour(psi, lat.e[k], par) - psi)
+    return 2.0 * out / CS2
+
+
+def s_k(lat, v):
+    """s_k(v) = w_k [v.e_k/c_s^2 + (v.e_k)^2/(2c_s^4) - v.v/(2c_s^2)] -> [Q, ...]."""
+    vv = (v * v).sum(axis=0)
+    out = np.empty((lat.Q,) + v.shape[1:])
+    for k in range(lat.Q):
+        ev = sum(lat.e[k, a] * v[a] for a in range(3))
+        out[k] = lat.w[k] * (ev / CS2 + ev * ev / (2 * CS2 * CS2) - vv / (2 * CS2))
+    return out
+
+
+def concentrations(g, par):
+    """C_i = sum_k g_{i,k} for the evolved components; the implicit component
+    is 1 minus the others, summed in increasing component order."""
+    C = g.sum(axis=1)
+    rest = np.zeros(C.shape[1:])
+    for i in par.evolved:
+        rest = rest + C[i]
+    C[par.implicit] = 1.0 - rest
+    return C
+
+
+def macroscopic(f, g, par):
+    """Steps 1-7: every node quantity the collision needs, as a dict."""
+    lat, co, N = par.lat, par.co, par.N
+    C = concentrations(g, par)
+    EB = potential.bulk_energy(C, co)
+    gradC = np.stack([gradient(C[i], par) for i in range(N)])      # [N, 3, ...]
+    lapC = np.stack([laplacian(C[i], par) for i in range(N)])      # [N, ...]
+    gradEB = gradient(EB, par)
+    if par.mu_form == "factored":
+        mut = potential.mu_tilde_factored(C, lapC, co, par.omega_stab)
+    elif par.mu_form == "literal":
+        mut = potential.mu_tilde_literal(C, lapC, co, par.omega_stab)
+    elif par.mu_form == "no_phi":
+        mut = potential.mu_tilde_literal(C, lapC, co, par.omega_stab, with_phi=False)
+    else:
+        raise ValueError(par.mu_form)
+    if par.force_form == "conservative":
+        F = gradEB.copy()
+        for i in range(N):
+            for j in range(N):
+                if i != j:
+                    F = F + co.kappa[i, j] * lapC[j] * gradC[i]
+    elif par.force_form == "potential":
+        mu = potential.mu_full(C, lapC, co)
+        F = np.zeros_like(gradEB)
+        for i in range(N):
+            F = F + mu[i] * gradC[i]
+    else:
+        raise ValueError(par.force_form)
+    F = F + par.body_force.reshape(3, 1, 1, 1)
+    if par.hydro:
+        mom = np.zeros((3,) + f.shape[1:])
+        for k in range(lat.Q):
+            for a in range(3):
+                if lat.e[k, a] != 0:
+                    mom[a] = mom[a] + lat.e[k, a] * f[k]
+        v = mom + 0.5 * F
+    else:
+        v = np.zeros((3,) + f.shape[1:])
+    s = s_k(lat, v)
+    P = CS2 / (1.0 - lat.w[0]) * (f[1:].sum(axis=0) + s[0])
+    istar = np.argmax(C, axis=0)                 # first index on ties
+    tau = par.tau[istar]
+    wp = 1.0 / tau
+    if par.trt_magic > 0.0:
+        wm = 1.0 / (0.5 + par.trt_magic / (tau - 0.5))
+    else:
+        wm = wp.copy()
+    return dict(C=C, EB=EB, gradC=gradC, lapC=lapC, gradEB=gradEB, mu_tilde=mut,
+                F=F, v=v, P=P, s=s, tau=tau, omega_plus=wp, omega_minus=wm)
+
+
+def f_equilibrium(lat, P, s):
+    """Eq. feq with rho = 1; the rest direction takes (P/c_s^2)(w_0 - 1)."""
+    feq = np.empty_like(s)
+    feq[0] = P / CS2 * (lat.w[0] - 1.0) + s[0]
+    for k in range(1, lat.Q):
+        feq[k] = P / CS2 * lat.w[k] + s[k]
+    return feq
+
+
+def force_populations(lat, v, F):
+    """Eq. hydroforce with grad rho = 0:
+    F_k = w_k [e_k.F/c_s^2 + ((v.e_k)(F.e_k) - c_s^2 v.F)/c_s^4]."""
+    vF = (v * F).sum(axis=0)
+    out = np.empty((lat.Q,) + v.shape[1:])
+    for k in range(lat.Q):
+        eF = sum(lat.e[k, a] * F[a] for a in range(3))
+        ev = sum(lat.e[k, a] * v[a] for a in range(3))
+        out[k] = lat.w[k] * (eF / CS2 + (ev * eF - CS2 * vF) / (CS2 * CS2))
+    return out
+
+
+def g_equilibrium(lat, C, s, mut, m, form="rest"):
+    """g^eq[N, Q, ...]; see the module docstring for the two forms."""
+    N = C.shape[0]
+    geq = np.empty((N, lat.Q) + C.shape[1:])
+    for i in range(N):
+        geq[i, 0] = C[i] * (1.0 + s[0]) + (1.0 - lat.w[0]) * m * mut[i]
+        for k in range(1, lat.Q):
+            geq[i, k] = C[i] * s[k] - lat.w[k] * m * mut[i]
+        if form == "printed":
+            geq[i, 0] = geq[i, 0] - C[i] + lat.w[0] * C[i]
+            for k in range(1, lat.Q):
+                geq[i, k] = geq[i, k] + lat.w[k] * C[i]
+        elif form != "rest":
+            raise ValueError(form)
+    return geq
+
+
+def collide(f, g, par, mac=None):
+    """Steps 8-9: post-collision f*, g* (before streaming)."""
+    lat = par.lat
+    if mac is None:
+        mac = macroscopic(f, g, par)
+    s, wp, wm = mac["s"], mac["omega_plus"], mac["omega_minus"]
+    if par.hydro:
+        feq = f_equilibrium(lat, mac["P"], s)
+        Fk = force_populations(lat, mac["v"], mac["F"])
+        fs = np.empty_like(f)
+        for k in range(lat.Q):
+            kb = lat.opp[k]
+            fp, fm = 0.5 * (f[k] + f[kb]), 0.5 * (f[k] - f[kb])
+            ep, em = 0.5 * (feq[k] + feq[kb]), 0.5 * (feq[k] - feq[kb])
+            fs[k] = (f[k] - wp * (fp - ep) - wm * (fm - em)
+                     + 0.5 * (1.0 - 0.5 * wp) * (Fk[k] + Fk[kb])
+                     + 0.5 * (1.0 - 0.5 * wm) * (Fk[k] - Fk[kb]))
+    else:
+        fs = f.copy()
+    geq = g_equilibrium(lat, mac["C"], s, mac["mu_tilde"], par.m, par.geq_form)
+    gs = g - (g - geq) / par.tau_g.reshape(-1, 1, 1, 1, 1)
+    gs[par.implicit] = 0.0
+    return fs, gs, mac
+
+
+def stream(post, par):
+    """Step 10 for one population array [..., Q, nz, ny, nx]."""
+    lat = par.lat
+    out = np.empty_like(post)
+    for k in range(lat.Q):
+        e = lat.e[k]
+        out[..., k, :, :, :] = np.roll(post[..., k, :, :, :],
+                                       shift=(int(e[2]), int(e[1]), int(e[0])),
+                                       axis=(-3, -2, -1))
+    # halfway bounce-back: a population leaving x towards a wall returns to x
+    # reversed, which overwrites the value the periodic roll brought in.
+    for k in range(1, lat.Q):
+        e = lat.e[k]
+        mask = wall_mask(par, e)                 # x + e_k inside a wall
+        if mask.any():
+            kb = lat.opp[k]
+            out[..., kb, :, :, :] = np.where(mask, post[..., k, :, :, :],
+                                             out[..., kb, :, :, :])
+    return out
+
+
+def step(f, g, par):
+    """One full time step; returns (f, g, mac) with mac the macroscopic fields
+    of the input state."""
+    fs, gs, mac = collide(f, g, par)
+    return stream(fs, par), stream(gs, par), mac
+
+
+def run(f, g, par, steps):
+    for _ in range(steps):
+        f, g, _ = step(f, g, par)
+    return f, g
+
+
+def initial_state(par, C0, v0=None, P0=None):
+    """f = f^eq(P0, v0) and g_{i,0} = C_i, g_{i,k>=1} = 0 (initialisation is not
+    specified in the paper; these values are exactly representable and are
+    forgotten after one step when tau_g = 1)."""
+    lat = par.lat
+    C0 = np.asarray(C0, dtype=np.float64).reshape((par.N,) + par.grid)
+    if v0 is None:
+        v0 = np.zeros((3,) + par.grid)
+    else:
+        v0 = np.asarray(v0, dtype=np.float64).reshape((3,) + par.grid)
+    if P0 is None:
+        P0 = np.zeros(par.grid)
+    else:
+        P0 = np.asarray(P0, dtype=np.float64).reshape(par.grid)
+    f = f_equilibrium(lat, P0, s_k(lat, v0))
+    g = np.zeros((par.N, lat.Q) + par.grid)
+    g[:, 0] = C0
+    g[par.implicit] = 0.0
+    return f, g
