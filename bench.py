@@ -1,0 +1,173 @@
+"""Throughput of the N-component free-energy LBM update on one MI355X.
+
+Workload: D3Q19 quaternary phase separation with a fifth component that is
+exactly zero (the reduction-consistency check), 256^3 periodic nodes,
+C_i = 0.25 + U(-0.02, 0.02) renormalised (seed 0), sigma = 0.01 for every
+pair, tau = tau_g = 1, m = 0.1.  One "step" is one full time step of the
+method over the whole lattice (concentration reconstruction + the fused
+stencil / force / collide / stream launch).
+
+Prints ONE JSON line.  value = MLUPS (million lattice-node updates per second)
+of the FP32-storage form; the FP16S and FP64 forms are timed the same way and
+reported under "forms".  roofline: the update kernel's algorithmic HBM bytes
+per launch divided by its mean launch time (HIP events on the stream the
+kernel runs on), against the 8 TB/s HBM3E peak.  cpu_baseline: the FP64 NumPy
+oracle on a 64^3 sample of the same recipe.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS at N components (FP32/FP16-store vs FP64) and % of HBM roofline"
+HBM_PEAK_GBS = 8000.0
+Q = 19
+
+
+def update_bytes_per_node(N, fs, g0s, ts):
+    """Algorithmic HBM bytes of one update launch per node: read the Q-1
+    moving f populations and the N-1 reconstructed concentrations, write the
+    Q-1 f populations and all Q populations of the N-1 evolved components."""
+    NE = N - 1
+    return (Q - 1) * fs + NE * ts + (Q - 1) * fs + NE * ((Q - 1) * fs + g0s)
+
+
+def conc_bytes_per_node(N, fs, g0s, ts):
+    NE = N - 1
+    return NE * ((Q - 1) * fs + g0s) + NE * ts
+
+
+SIZES = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "fp16s": (2, 4, 4)}
+
+
+def run_form(nf, w, form, steps, warmup, timing_steps):
+    import torch
+    prec = nf.PRECISIONS[form]
+    sim = nf.Simulation.from_workload(w, precision=prec, implicit=0)
+    sim.set_fields(w["C0"])
+    d0 = sim.diagnostics(vcm_component=0)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_events = sim.step_timed(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # separate pass: events around every update launch (same stream)
+    _, ms_upd = sim.step_timed(timing_steps, per_update=True)
+    d1 = sim.diagnostics(vcm_component=0)
+    C = None
+    n = w["C0"][0].size
+    mlups = n * steps / wall / 1e6
+    fs, g0s, ts = SIZES[form]
+    N = w["sigma"].shape[0]
+    ub = update_bytes_per_node(N, fs, g0s, ts)
+    cb = conc_bytes_per_node(N, fs, g0s, ts)
+    upd_ms = ms_upd / timing_steps
+    out = {
+        "mlups": mlups,
+        "ms_per_step": wall / steps * 1e3,
+        "ms_per_step_events": ms_events / steps,
+        "update_ms": upd_ms,
+        "update_bytes_per_node": ub,
+        "step_bytes_per_node": ub + cb,
+        "update_gbs": n * ub / (upd_ms * 1e-3) / 1e9,
+        "step_gbs": n * (ub + cb) / (wall / steps) / 1e9,
+        "absent_max_abs": d1["max_abs_c"][4],
+        "mass_rel_drift": max(abs(a - b) / abs(b) for a, b in zip(d1["mass"][:4], d0["mass"][:4])),
+        "momentum_drift": [a - b for a, b in zip(d1["momentum"], d0["momentum"])],
+        "nan": d1["nan"],
+    }
+    out["step_frac_of_peak"] = out["step_gbs"] / HBM_PEAK_GBS
+    sim.close()
+    del C
+    return out
+
+
+def cpu_baseline(sample_n=64, steps=10):
+    """The FP64 oracle (not tuned) on a sample_n^3 lattice of the same recipe."""
+    import workloads as W
+    from oracle import step as S
+    from oracle.lattice import D3Q19
+    w = W.quaternary_3d(sample_n)
+    par = S.Params(D3Q19, w["shape"], w["sigma"], w["tau"], m=w["m"], implicit=0)
+    f, g = S.initial_state(par, w["C0"])
+    f, g, _ = S.step(f, g, par)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f, g, _ = S.step(f, g, par)
+    dt = time.perf_counter() - t0
+    return {"value": sample_n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{sample_n}^3 D3Q19 N=5 (same recipe), {steps} steps, NumPy FP64 on one "
+                      f"core ({len(os.sched_getaffinity(0))} visible), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="lattice side")
+    ap.add_argument("--forms", default="fp32,fp16s,fp64")
+    ap.add_argument("--timing-steps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this workload runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU domain decomposition is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2605_22214_amd as nf
+    import workloads as W
+    nf.lib()
+    w = W.quaternary_3d(args.n)
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    for form in forms:
+        print(f"bench: timing {form} ({args.n}^3, {args.steps} steps)", file=sys.stderr, flush=True)
+        results[form] = run_form(nf, w, form, args.steps, args.warmup, args.timing_steps)
+        print(f"bench: {form} {results[form]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+    main_form = forms[0]
+    r = results[main_form]
+    roof = {"bound": "hbm", "achieved": r["update_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r["update_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_update", "bytes_per_node": r["update_bytes_per_node"],
+            "mean_launch_ms": r["update_ms"]}
+    cpu = None
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    line = {
+        "metric": METRIC,
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16s": "f16-store/f32", "fp64": "f64"}[main_form],
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 quaternary phase separation + absent 5th component, "
+                               f"{args.n}^3 periodic, {main_form} storage",
+                   "lattice": "D3Q19", "shape": [args.n] * 3, "ncomp": 5, "precision": main_form},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

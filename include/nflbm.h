@@ -1,0 +1,224 @@
+/*
+ * nflbm — per-time-step update of the N-component free-energy lattice
+ * Boltzmann method with reduction consistency and global momentum
+ * conservation (Rennick, Zhang, Bingert, Krause, Kusumaatmaja,
+ * arXiv 2605.22214), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Every function returns an int
+ * status (NFLBM_OK = 0, negative on error) unless stated otherwise; none
+ * aborts or exits.  After an error, nflbm_last_error(sim) (or
+ * nflbm_last_error(NULL) for errors before a simulation exists) returns a
+ * message.  All host arrays passed in are copied during the call; the
+ * caller keeps ownership.  Device state is owned by the library.
+ *
+ * Field layout on the host is C order [component][z][y][x] (x fastest),
+ * FP64 whatever the storage precision.  Node index = x + nx (y + ny z).
+ */
+#ifndef NFLBM_H
+#define NFLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NFLBM_MAX_COMP 8
+#define NFLBM_ABI_VERSION 1
+
+/* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
+ * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
+enum { NFLBM_D2Q9 = 0, NFLBM_D3Q19 = 1 };
+
+/* Storage precision of the populations.
+ *   FP64   populations and arithmetic in double.
+ *   FP32   populations and arithmetic in float.
+ *   FP16S  moving populations (f_k, g_{i,k}, k >= 1) stored as binary16
+ *          scaled by 2^12, rest populations g_{i,0} as float; arithmetic in
+ *          float.  The rest population of each component absorbs the
+ *          rounding of the moving ones, so node mass is kept to float
+ *          rounding.
+ * Global reductions (mass, momentum) are always accumulated in double. */
+enum { NFLBM_FP64 = 0, NFLBM_FP32 = 1, NFLBM_FP16S = 2 };
+
+enum {
+  NFLBM_OK = 0,
+  NFLBM_EINVAL = -1,    /* bad argument or configuration                    */
+  NFLBM_ESINGULAR = -2, /* a coefficient system (alpha, Lambda, Theta) is singular */
+  NFLBM_EUNSTABLE = -3, /* mobility above the linear stability bound        */
+  NFLBM_ENOMEM = -4,    /* device or host allocation failed                 */
+  NFLBM_EDEVICE = -5,   /* a HIP runtime call failed                        */
+  NFLBM_ENUMERIC = -6,  /* a NaN or Inf was found in the state              */
+  NFLBM_ENOTSUP = -7    /* combination not supported by this build          */
+};
+
+/* Readback fields for nflbm_get_field (sizes in doubles, n = nx ny nz):
+ *   C      N n   concentrations C_i (zeroth moment of g, Sec. III B)
+ *   V      3 n   velocity v (Eq. nmom, rho = 1)
+ *   P      n     hydrodynamic pressure (Eq. pres)
+ *   F      3 n   total force: surface tension (Eq. Fsnew) + body force
+ *   MU     N n   flux potential mu~_i = sum_j alpha_ij (mu_j+phi_j+xi_j) (Eq. MU);
+ *                zero for the implicit component
+ *   F_RAW  (Q-1) n   populations f_1..f_{Q-1} (f_0 is not stored: no
+ *                quantity of the scheme reads it)
+ *   G_RAW  N Q n populations g_{i,k}; the implicit component's are zero
+ * C, V, P, F and MU are the moments of the current (post-streaming) state,
+ * i.e. the values the next collision uses. */
+enum {
+  NFLBM_FIELD_C = 0,
+  NFLBM_FIELD_V = 1,
+  NFLBM_FIELD_P = 2,
+  NFLBM_FIELD_F = 3,
+  NFLBM_FIELD_MU = 4,
+  NFLBM_FIELD_F_RAW = 5,
+  NFLBM_FIELD_G_RAW = 6
+};
+
+/* Option flags. */
+enum {
+  NFLBM_FLAG_POTENTIAL_FORCE = 1, /* F_s = sum_i mu_i grad C_i (Eq. ststand)
+                                     instead of the conservative Eq. Fsnew;
+                                     a negative control that drifts          */
+  NFLBM_FLAG_ALLOW_UNSTABLE = 2   /* skip the mobility stability check      */
+};
+
+/*
+ * Problem statement (Sec. II-III).
+ *   lattice      NFLBM_D2Q9 (nz must be 1) or NFLBM_D3Q19.
+ *   nx, ny, nz   lattice nodes, each >= 1.
+ *   wall[a]      0: periodic along axis a (x, y, z); 1: halfway bounce-back
+ *                walls half a spacing beyond both faces (Sec. III C).  Stencil
+ *                neighbours inside a wall take the centre value.
+ *   ncomp        N, 2..NFLBM_MAX_COMP.
+ *   implicit_comp  the component not evolved by its own LBE; it follows from
+ *                sum_i C_i = 1 (Sec. II, after Eq. CHFlux).  -1 selects the
+ *                last component, as in the paper.  An absent component must
+ *                not be the implicit one if it is to stay exactly zero.
+ *   sigma        N*N row-major pairwise surface tensions: symmetric, zero
+ *                diagonal, positive off-diagonal.
+ *   width_D      interface width D (the paper uses 4).  beta = 6 sigma/D,
+ *                kappa = 3 sigma D/4.
+ *   omega_stab   Omega of the stabilising term xi_j (Eq. P); 0 disables.
+ *   tau          N hydrodynamic relaxation times, > 1/2; a node takes the
+ *                tau of its majority component (Sec. III B), the lowest
+ *                index on ties.  omega+ = 1/tau.
+ *   trt_magic    Lambda^TRT > 0 selects TRT with omega- from
+ *                Lambda = (1/omega+ - 1/2)(1/omega- - 1/2); <= 0 selects BGK.
+ *   tau_g        N Cahn-Hilliard relaxation times (> 1/2; the paper uses 1),
+ *                or NULL for all 1.
+ *   m            mobility parameter of g^eq; M = c_s^2 m (tau_g - 1/2).
+ *   body_force   uniform body force density added at every node.
+ *   precision    NFLBM_FP64 / NFLBM_FP32 / NFLBM_FP16S.
+ *   flags        NFLBM_FLAG_* bits.
+ */
+typedef struct nflbm_config {
+  int lattice;
+  int nx, ny, nz;
+  int wall[3];
+  int ncomp;
+  int implicit_comp;
+  const double *sigma;
+  double width_D;
+  double omega_stab;
+  const double *tau;
+  double trt_magic;
+  const double *tau_g;
+  double m;
+  double body_force[3];
+  int precision;
+  int flags;
+} nflbm_config;
+
+typedef struct nflbm_sim nflbm_sim; /* opaque */
+
+/* Global diagnostics of the current state, FP64 (entries >= N unused):
+ *   mass[i]       sum_x C_i
+ *   momentum[a]   sum_x (sum_k e_k f_k + F/2)_a
+ *   max_abs_c[i]  max_x |C_i|     min_c[i]  min_x C_i
+ *   max_sum_dev   max_x |sum_i C_i - 1|
+ *   vcm[a]        sum_x C_c v_a / sum_x C_c for c = vcm_component
+ *   nan           1 if any population is NaN or Inf */
+typedef struct nflbm_diag {
+  double mass[NFLBM_MAX_COMP];
+  double momentum[3];
+  double max_abs_c[NFLBM_MAX_COMP];
+  double min_c[NFLBM_MAX_COMP];
+  double max_sum_dev;
+  double vcm[3];
+  int vcm_component;
+  int nan;
+} nflbm_diag;
+
+/* Validate cfg, compute the coefficient tables (alpha, gamma: Eqs. alpha1,
+ * alpha2; Lambda: Eq. ngamma; Theta: the system after Eq. P) on the host in
+ * FP64, allocate the device state on the current HIP device and set the
+ * state to rest with C_1 = 1.  *out receives the handle. */
+int nflbm_create(const nflbm_config *cfg, nflbm_sim **out);
+
+/* Release all device and host memory of sim (NULL is ignored). */
+void nflbm_destroy(nflbm_sim *sim);
+
+/* Run all subsequent device work of sim on this hipStream_t (NULL = the
+ * default stream), e.g. torch.cuda.current_stream().cuda_stream. */
+int nflbm_set_stream(nflbm_sim *sim, void *hip_stream);
+
+/* Initialise the state from host fields: C (N n, required), v (3 n or NULL
+ * for rest), P (n or NULL for 0).  f = f^eq(P, v) for k >= 1; g_{i,0} = C_i,
+ * g_{i,k>=1} = 0 for the evolved components.  Synchronises. */
+int nflbm_set_fields(nflbm_sim *sim, const double *C, const double *v, const double *P);
+
+/* Advance nsteps time steps (Sec. III: collide, stream, boundaries), each one
+ * a reconstruction of C and one fused update launch on the sim's stream.
+ * Asynchronous: returns after queueing the work. */
+int nflbm_step(nflbm_sim *sim, long long nsteps);
+
+/* Advance nsteps and return, through *ms, the elapsed device time measured
+ * with HIP events recorded on the sim's stream around the launches; if
+ * ms_update is not NULL also time each update launch separately (events
+ * around every update kernel) and return their summed duration.
+ * Synchronises. */
+int nflbm_step_timed(nflbm_sim *sim, long long nsteps, double *ms, double *ms_update);
+
+/* Copy one field (NFLBM_FIELD_*) of the current state to host_out (sizes in
+ * the field list above).  Synchronises. */
+int nflbm_get_field(nflbm_sim *sim, int field, double *host_out);
+
+/* Raw state checkpoint: nflbm_state_bytes gives the size, get_state copies
+ * the device state (both population sets, storage precision) to host_raw,
+ * set_state restores it bit for bit.  Synchronise. */
+int nflbm_state_bytes(nflbm_sim *sim, size_t *bytes);
+int nflbm_get_state(nflbm_sim *sim, void *host_raw);
+int nflbm_set_state(nflbm_sim *sim, const void *host_raw);
+
+/* FP64 global diagnostics (see nflbm_diag); vcm_component selects C_c for the
+ * centre-of-mass velocity (Sec. V A).  ENUMERIC if a NaN/Inf was found.
+ * Synchronises. */
+int nflbm_diagnostics(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
+
+/* Host-only (no device needed): the coefficient tables for N tensions sigma
+ * (N*N row-major) and width D.  Any output pointer may be NULL.
+ *   alpha  N*N, gamma N                   (Eqs. alpha1, alpha2)
+ *   psi    N*N*N  Psi[i][l][m], l < m, l,m != i   (factored bulk + phi)
+ *   xtab   N*N*N  X[i][k][l],  k < l, i not in {k,l}  (factored xi)
+ *   ztab   N*N*N  Z[i][l][m],  l != i, m not in {i,l} (factored xi)
+ * Entries outside the stated index sets are 0. */
+int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, double *gamma,
+                       double *psi, double *xtab, double *ztab);
+
+/* Bytes moved per lattice-node update by the reconstruction and update
+ * kernels together, counting every stored population once read and once
+ * written plus the reconstructed concentrations (written once, read once). */
+int nflbm_bytes_per_node(nflbm_sim *sim, double *bytes);
+
+/* Message of the last error on sim (or of the calling thread if sim is NULL).
+ * The pointer stays valid until the next call on the same sim / thread. */
+const char *nflbm_last_error(const nflbm_sim *sim);
+
+/* NFLBM_ABI_VERSION of the built library. */
+int nflbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFLBM_H */

@@ -1,0 +1,279 @@
+"""Python binding of libnflbm (the HIP library of the N-component free-energy
+lattice Boltzmann update, arXiv 2605.22214) for MI355X / gfx950.
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  The library must have been built (``python -m
+paper_2605_22214_amd.build``); importing works without it, but any call that
+needs it raises ``RuntimeError`` -- there is no fallback implementation.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_PKG)
+LIB_PATH = os.path.join(_PKG, "libnflbm.so")
+HEADER = os.path.join(_ROOT, "include", "nflbm.h")
+MAX_COMP = 8
+
+D2Q9, D3Q19 = 0, 1
+FP64, FP32, FP16S = 0, 1, 2
+FLAG_POTENTIAL_FORCE = 1
+FLAG_ALLOW_UNSTABLE = 2
+FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESINGULAR", -3: "EUNSTABLE", -4: "ENOMEM",
+          -5: "EDEVICE", -6: "ENUMERIC", -7: "ENOTSUP"}
+
+
+class NflbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("wall", ctypes.c_int * 3),
+        ("ncomp", ctypes.c_int),
+        ("implicit_comp", ctypes.c_int),
+        ("sigma", ctypes.POINTER(ctypes.c_double)),
+        ("width_D", ctypes.c_double),
+        ("omega_stab", ctypes.c_double),
+        ("tau", ctypes.POINTER(ctypes.c_double)),
+        ("trt_magic", ctypes.c_double),
+        ("tau_g", ctypes.POINTER(ctypes.c_double)),
+        ("m", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+        ("precision", ctypes.c_int),
+        ("flags", ctypes.c_int),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double * MAX_COMP),
+        ("momentum", ctypes.c_double * 3),
+        ("max_abs_c", ctypes.c_double * MAX_COMP),
+        ("min_c", ctypes.c_double * MAX_COMP),
+        ("max_sum_dev", ctypes.c_double),
+        ("vcm", ctypes.c_double * 3),
+        ("vcm_component", ctypes.c_int),
+        ("nan", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libnflbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2605_22214_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+        DP = ctypes.POINTER(ctypes.c_double)
+        sigs = {
+            "nflbm_create": (I, [ctypes.POINTER(Config), ctypes.POINTER(P)]),
+            "nflbm_destroy": (None, [P]),
+            "nflbm_set_stream": (I, [P, P]),
+            "nflbm_set_fields": (I, [P, DP, DP, DP]),
+            "nflbm_step": (I, [P, LL]),
+            "nflbm_step_timed": (I, [P, LL, DP, DP]),
+            "nflbm_get_field": (I, [P, I, DP]),
+            "nflbm_state_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+            "nflbm_get_state": (I, [P, P]),
+            "nflbm_set_state": (I, [P, P]),
+            "nflbm_diagnostics": (I, [P, I, ctypes.POINTER(Diag)]),
+            "nflbm_coefficients": (I, [I, DP, D, DP, DP, DP, DP, DP]),
+            "nflbm_bytes_per_node": (I, [P, DP]),
+            "nflbm_last_error": (ctypes.c_char_p, [P]),
+            "nflbm_abi_version": (I, []),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/nflbm.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nflbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(code, handle=None):
+    if code != 0:
+        msg = lib().nflbm_last_error(handle)
+        raise NflbmError(code, msg.decode() if msg else "")
+
+
+def coefficients(sigma, D=4.0):
+    """Host-side coefficient tables computed by the library (no GPU needed)."""
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    N = sigma.shape[0]
+    alpha = np.zeros((N, N))
+    gamma = np.zeros(N)
+    psi = np.zeros((N, N, N))
+    xt = np.zeros((N, N, N))
+    zt = np.zeros((N, N, N))
+    _check(lib().nflbm_coefficients(N, _dptr(sigma), float(D), _dptr(alpha), _dptr(gamma),
+                                    _dptr(psi), _dptr(xt), _dptr(zt)))
+    return dict(alpha=alpha, gamma=gamma, psi=psi, X=xt, Z=zt)
+
+
+class Simulation:
+    """One lattice on the current HIP device (see include/nflbm.h)."""
+
+    def __init__(self, lattice, shape, sigma, tau, *, walls=(False, False, False),
+                 implicit=-1, D=4.0, omega_stab=0.0, trt_magic=0.0, tau_g=None, m=0.02,
+                 body_force=(0.0, 0.0, 0.0), precision=FP64, flags=0):
+        L = lib()
+        self.lattice = {"D2Q9": D2Q9, "D3Q19": D3Q19}.get(lattice, lattice)
+        self.Q = 9 if self.lattice == D2Q9 else 19
+        self.shape = tuple(int(s) for s in shape)
+        nx, ny, nz = self.shape
+        self.n = nx * ny * nz
+        self._sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        self.N = self._sigma.shape[0]
+        self._tau = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, float), (self.N,)))
+        self._tau_g = None if tau_g is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(tau_g, float), (self.N,)))
+        self.precision = PRECISIONS.get(precision, precision)
+        cfg = Config()
+        cfg.lattice = self.lattice
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        for a in range(3):
+            cfg.wall[a] = int(bool(walls[a]))
+        cfg.ncomp = self.N
+        cfg.implicit_comp = -1 if implicit is None else int(implicit)
+        cfg.sigma = _dptr(self._sigma)
+        cfg.width_D = float(D)
+        cfg.omega_stab = float(omega_stab)
+        cfg.tau = _dptr(self._tau)
+        cfg.trt_magic = float(trt_magic)
+        cfg.tau_g = _dptr(self._tau_g) if self._tau_g is not None else None
+        cfg.m = float(m)
+        for a in range(3):
+            cfg.body_force[a] = float(body_force[a])
+        cfg.precision = int(self.precision)
+        cfg.flags = int(flags)
+        h = ctypes.c_void_p()
+        _check(L.nflbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, precision=FP64, implicit=-1, flags=0):
+        return cls(w["lattice"], w["shape"], w["sigma"], w["tau"], walls=w["walls"],
+                   implicit=implicit, D=w["D"], omega_stab=w["omega_stab"],
+                   trt_magic=w["trt_magic"], tau_g=w["tau_g"], m=w["m"],
+                   body_force=w["body_force"], precision=precision, flags=flags)
+
+    @property
+    def grid(self):
+        nx, ny, nz = self.shape
+        return (nz, ny, nx)
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("simulation already closed")
+        return self._h
+
+    def set_stream(self, stream_ptr):
+        _check(lib().nflbm_set_stream(self._handle(), ctypes.c_void_p(stream_ptr)), self._h)
+
+    def set_fields(self, C, v=None, P=None):
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(self.N, self.n))
+        vv = None if v is None else np.ascontiguousarray(np.asarray(v, float).reshape(3, self.n))
+        PP = None if P is None else np.ascontiguousarray(np.asarray(P, float).reshape(self.n))
+        _check(lib().nflbm_set_fields(self._handle(), _dptr(C),
+                                      _dptr(vv) if vv is not None else None,
+                                      _dptr(PP) if PP is not None else None), self._h)
+
+    def step(self, nsteps=1):
+        _check(lib().nflbm_step(self._handle(), int(nsteps)), self._h)
+
+    def step_timed(self, nsteps, per_update=False):
+        """Device milliseconds for nsteps (HIP events on the sim's stream);
+        with per_update also the summed duration of the update launches."""
+        ms = ctypes.c_double()
+        mu = ctypes.c_double()
+        _check(lib().nflbm_step_timed(self._handle(), int(nsteps), ctypes.byref(ms),
+                                      ctypes.byref(mu) if per_update else None), self._h)
+        return (ms.value, mu.value) if per_update else ms.value
+
+    def get_field(self, name):
+        fid = FIELDS[name]
+        rows = {"C": self.N, "V": 3, "P": 1, "F": 3, "MU": self.N,
+                "F_RAW": self.Q - 1, "G_RAW": self.N * self.Q}[name]
+        out = np.empty(rows * self.n, dtype=np.float64)
+        _check(lib().nflbm_get_field(self._handle(), fid, _dptr(out)), self._h)
+        if name == "G_RAW":
+            return out.reshape((self.N, self.Q) + self.grid)
+        if name == "P":
+            return out.reshape(self.grid)
+        return out.reshape((rows,) + self.grid)
+
+    def state_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib().nflbm_state_bytes(self._handle(), ctypes.byref(b)), self._h)
+        return b.value
+
+    def get_state(self):
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        _check(lib().nflbm_get_state(self._handle(), buf.ctypes.data_as(ctypes.c_void_p)), self._h)
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        if buf.size != self.state_bytes():
+            raise ValueError("state size mismatch")
+        _check(lib().nflbm_set_state(self._handle(), buf.ctypes.data_as(ctypes.c_void_p)), self._h)
+
+    def diagnostics(self, vcm_component=0, check=True):
+        d = Diag()
+        code = lib().nflbm_diagnostics(self._handle(), int(vcm_component), ctypes.byref(d))
+        if check:
+            _check(code, self._h)
+        N = self.N
+        return {"mass": list(d.mass[:N]), "momentum": list(d.momentum),
+                "max_abs_c": list(d.max_abs_c[:N]), "min_c": list(d.min_c[:N]),
+                "max_sum_dev": d.max_sum_dev, "vcm": list(d.vcm), "nan": d.nan,
+                "status": code}
+
+    def bytes_per_node(self):
+        b = ctypes.c_double()
+        _check(lib().nflbm_bytes_per_node(self._handle(), ctypes.byref(b)), self._h)
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().nflbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

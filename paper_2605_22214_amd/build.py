@@ -1,0 +1,86 @@
+"""Build the HIP library libnflbm.so in-tree for gfx950 with hipcc.
+
+Usage: python -m paper_2605_22214_amd.build  (or build() from Python).
+Objects go to _build/ at the repository root; the shared library is written
+next to this file so that it ships with the package tree.
+"""
+import concurrent.futures
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libnflbm.so")
+ARCH = os.environ.get("NFLBM_OFFLOAD_ARCH", "gfx950")
+
+# Device-code flags: gfx950 only; packed FP32 instructions are kept out of the
+# generated code (the compiler would otherwise form them from float code).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
+          "-Wall", "-Wno-unused-function"]
+
+# Translation units: (source, object, is_device_code, extra defines)
+UNITS = [
+    ("coeffs.cpp", "coeffs.o", False, []),
+    ("api.cpp", "api.o", False, []),
+    ("kernels.hip", "kernels_f64.o", True, ["-DNFLBM_UNIT_STORE=0"]),
+    ("kernels.hip", "kernels_f32.o", True, ["-DNFLBM_UNIT_STORE=1"]),
+    ("kernels.hip", "kernels_f16s.o", True, ["-DNFLBM_UNIT_STORE=2"]),
+    ("kernels.hip", "kernels_common.o", True, ["-DNFLBM_UNIT_STORE=-1"]),
+]
+
+
+def hipcc():
+    path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(path):
+        raise RuntimeError("hipcc not found; the HIP library cannot be built")
+    return path
+
+
+def _compile(unit):
+    src, obj, device, defs = unit
+    cmd = [hipcc()] + COMMON + defs
+    if device:
+        cmd += ["-x", "hip", f"--offload-arch={ARCH}"] + DEVICE_FLAGS
+    else:
+        # host-only C++ that calls the HIP runtime API
+        cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+    cmd += ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    t = time.time()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return obj, time.time() - t, res.stderr
+
+
+def build(verbose=True, jobs=None):
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 4)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for obj, dt, warn in ex.map(_compile, UNITS):
+            if verbose:
+                print(f"  compiled {obj} in {dt:.1f}s", flush=True)
+                w = "\n".join(l for l in warn.splitlines() if "packed-fp32-ops" not in l
+                              and "not a recognized feature" not in l)
+                if w.strip():
+                    print(w, flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
+          [os.path.join(BUILD, u[1]) for u in UNITS]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"  linked {LIB}", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

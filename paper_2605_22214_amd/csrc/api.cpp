@@ -1,0 +1,611 @@
+// C ABI of the N-component free-energy LBM library (see include/nflbm.h).
+#include "nflbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "coeffs.h"
+#include "internal.h"
+
+using namespace nflbm;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+}  // namespace
+
+struct nflbm_sim {
+  // problem
+  int lat = 0, N = 0, NE = 0, Q = 0, store = 0, flags = 0;
+  int nx = 0, ny = 0, nz = 0, wall[3] = {0, 0, 0};
+  int implicit = 0;
+  int uidx[kMaxComp] = {};  // internal -> user component
+  size_t n = 0;
+  Coeffs co;
+  // storage sizes (bytes per value)
+  size_t fs = 0, g0s = 0, ts = 0;
+  // device state: two population sets (A/B), reconstructed C, parameters
+  void* f[2] = {nullptr, nullptr};
+  void* g0[2] = {nullptr, nullptr};
+  void* gk[2] = {nullptr, nullptr};
+  void* conc = nullptr;
+  void* params = nullptr;
+  double* fields = nullptr;
+  double* red = nullptr;
+  int red_blocks = 0;
+  int cur = 0;
+  hipStream_t stream = nullptr;
+  // launch shape
+  int tx_log2 = 6, zchunk = 1, tiles_x = 1, tiles_y = 1, chunks_z = 1;
+  int step_flags = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(nflbm_sim* s, int code, const std::string& msg) {
+  if (s) s->err = msg;
+  else g_thread_error = msg;
+  return code;
+}
+
+int hip_fail(nflbm_sim* s, hipError_t e, const char* what) {
+  return fail(s, NFLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(sim, call)                              \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(sim, e_, #call); \
+  } while (0)
+
+template <class T>
+void fill_params(const nflbm_sim& s, const double* tau, const double* tau_g, double trt,
+                 double m, double omega, const double* fb, DevParams<T>* p) {
+  std::memset(p, 0, sizeof(*p));
+  const int N = s.N;
+  const Coeffs& c = s.co;
+  for (int i = 0; i < N; ++i) {
+    const int ui = s.uidx[i];
+    p->uidx[i] = ui;
+    for (int j = 0; j < N; ++j) {
+      const int uj = s.uidx[j];
+      p->beta[i][j] = static_cast<T>(c.beta[ui][uj]);
+      p->kappa[i][j] = static_cast<T>(c.kappa[ui][uj]);
+      for (int k = 0; k < N; ++k) {
+        const int uk = s.uidx[k];
+        const int lo = uj < uk ? uj : uk, hi = uj < uk ? uk : uj;
+        if (j != k && j != i && k != i) {
+          p->psi[i][j][k] = static_cast<T>(c.psi[ui][lo][hi]);
+          p->xt[i][j][k] = static_cast<T>(c.xt[ui][lo][hi]);
+        }
+        if (j != i && k != i && k != j) p->zt[i][j][k] = static_cast<T>(c.zt[ui][uj][uk]);
+      }
+    }
+    const double t = tau[ui];
+    const double wp = 1.0 / t;
+    const double wm = trt > 0.0 ? 1.0 / (0.5 + trt / (t - 0.5)) : wp;
+    p->omega_p[i] = static_cast<T>(wp);
+    p->omega_m[i] = static_cast<T>(wm);
+    p->inv_tau_g[i] = static_cast<T>(1.0 / (tau_g ? tau_g[ui] : 1.0));
+  }
+  p->m = static_cast<T>(m);
+  p->k34D = static_cast<T>(0.75 * c.D);
+  p->k12D = static_cast<T>(12.0 / c.D);
+  p->omega_stab = static_cast<T>(omega);
+  for (int d = 0; d < 3; ++d) p->fb[d] = static_cast<T>(fb[d]);
+}
+
+void free_device(nflbm_sim* s) {
+  for (int b = 0; b < 2; ++b) {
+    if (s->f[b]) (void)hipFree(s->f[b]);
+    if (s->g0[b]) (void)hipFree(s->g0[b]);
+    if (s->gk[b]) (void)hipFree(s->gk[b]);
+    s->f[b] = s->g0[b] = s->gk[b] = nullptr;
+  }
+  if (s->conc) (void)hipFree(s->conc);
+  if (s->params) (void)hipFree(s->params);
+  if (s->fields) (void)hipFree(s->fields);
+  if (s->red) (void)hipFree(s->red);
+  s->conc = s->params = nullptr;
+  s->fields = s->red = nullptr;
+}
+
+int next_pow2_log(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Tile width: the smallest power of two covering nx, between 16 and 64, then
+// narrowed until the LDS window fits the device's per-workgroup limit.
+int choose_launch(nflbm_sim* s) {
+  int l = next_pow2_log(s->nx);
+  if (l < 4) l = 4;
+  if (l > 6) l = 6;
+  int dev = 0;
+  size_t lds_max = 65536;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      prop.sharedMemPerBlock > 0)
+    lds_max = prop.sharedMemPerBlock;
+  while (l > 4 && update_lds_bytes(s->lat, s->N, s->store, l) > lds_max) --l;
+  if (update_lds_bytes(s->lat, s->N, s->store, l) > lds_max) return -1;
+  s->tx_log2 = l;
+  const int TX = 1 << l, TY = 256 >> l;
+  s->tiles_x = (s->nx + TX - 1) / TX;
+  s->tiles_y = (s->ny + TY - 1) / TY;
+  if (s->lat == NFLBM_D3Q19) {
+    const long long xy = static_cast<long long>(s->tiles_x) * s->tiles_y;
+    long long chunks = 4096 / (xy > 0 ? xy : 1);
+    if (chunks < 1) chunks = 1;
+    if (chunks > s->nz) chunks = s->nz;
+    int zc = static_cast<int>((s->nz + chunks - 1) / chunks);
+    if (zc < 4) zc = s->nz < 4 ? s->nz : 4;
+    s->zchunk = zc;
+    s->chunks_z = (s->nz + zc - 1) / zc;
+  } else {
+    s->zchunk = 1;
+    s->chunks_z = 1;
+  }
+  return 0;
+}
+
+StepArgs make_args(const nflbm_sim* s, int src) {
+  StepArgs a{};
+  a.f_src = s->f[src];
+  a.f_dst = s->f[1 - src];
+  a.g0_src = s->g0[src];
+  a.g0_dst = s->g0[1 - src];
+  a.gk_src = s->gk[src];
+  a.gk_dst = s->gk[1 - src];
+  a.conc = s->conc;
+  a.fields = s->fields;
+  a.params = s->params;
+  a.n = static_cast<long long>(s->n);
+  a.nx = s->nx;
+  a.ny = s->ny;
+  a.nz = s->nz;
+  a.wall_x = s->wall[0];
+  a.wall_y = s->wall[1];
+  a.wall_z = s->wall[2];
+  a.tx_log2 = s->tx_log2;
+  a.zchunk = s->zchunk;
+  a.tiles_x = s->tiles_x;
+  a.tiles_y = s->tiles_y;
+  a.chunks_z = s->chunks_z;
+  a.flags = s->step_flags;
+  return a;
+}
+
+int ensure_fields(nflbm_sim* s) {
+  if (!s->fields) {
+    const size_t bytes = size_t(2 * s->N + 7) * s->n * sizeof(double);
+    if (hipMalloc(reinterpret_cast<void**>(&s->fields), bytes) != hipSuccess) {
+      s->fields = nullptr;
+      return fail(s, NFLBM_ENOMEM, "cannot allocate the readback field buffer");
+    }
+  }
+  return NFLBM_OK;
+}
+
+// Reconstruct C and evaluate the node fields of the current state.
+int compute_fields(nflbm_sim* s) {
+  int rc = ensure_fields(s);
+  if (rc) return rc;
+  StepArgs a = make_args(s, s->cur);
+  HIPCHK(s, launch_conc(s->lat, s->N, s->store, a, s->stream));
+  HIPCHK(s, launch_update(s->lat, s->N, s->store, a, true, s->stream));
+  return NFLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nflbm_abi_version(void) { return NFLBM_ABI_VERSION; }
+
+const char* nflbm_last_error(const nflbm_sim* sim) {
+  return sim ? sim->err.c_str() : g_thread_error.c_str();
+}
+
+int nflbm_coefficients(int N, const double* sigma, double D, double* alpha, double* gamma,
+                       double* psi, double* xtab, double* ztab) {
+  if (!sigma) return fail(nullptr, NFLBM_EINVAL, "sigma is NULL");
+  Coeffs c;
+  char msg[256] = {0};
+  const int rc = compute_coeffs(N, sigma, D, &c, msg);
+  if (rc == -1) return fail(nullptr, NFLBM_EINVAL, msg);
+  if (rc == -2) return fail(nullptr, NFLBM_ESINGULAR, msg);
+  for (int i = 0; i < N; ++i) {
+    if (gamma) gamma[i] = c.gamma[i];
+    for (int j = 0; j < N; ++j) {
+      if (alpha) alpha[i * N + j] = c.alpha[i][j];
+      for (int k = 0; k < N; ++k) {
+        const size_t o = (size_t(i) * N + j) * N + k;
+        if (psi) psi[o] = c.psi[i][j][k];
+        if (xtab) xtab[o] = c.xt[i][j][k];
+        if (ztab) ztab[o] = c.zt[i][j][k];
+      }
+    }
+  }
+  return NFLBM_OK;
+}
+
+int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
+  if (!cfg || !out) return fail(nullptr, NFLBM_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->lattice != NFLBM_D2Q9 && cfg->lattice != NFLBM_D3Q19)
+    return fail(nullptr, NFLBM_EINVAL, "unknown lattice");
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+    return fail(nullptr, NFLBM_EINVAL, "lattice dimensions must be >= 1");
+  if (cfg->lattice == NFLBM_D2Q9 && cfg->nz != 1)
+    return fail(nullptr, NFLBM_EINVAL, "D2Q9 needs nz == 1");
+  const long long nn = 1LL * cfg->nx * cfg->ny * cfg->nz;
+  if (nn >= (1LL << 31)) return fail(nullptr, NFLBM_EINVAL, "more than 2^31-1 nodes");
+  const int N = cfg->ncomp;
+  if (N < 2 || N > NFLBM_MAX_COMP) return fail(nullptr, NFLBM_EINVAL, "ncomp outside 2..8");
+  if (!cfg->sigma || !cfg->tau) return fail(nullptr, NFLBM_EINVAL, "sigma and tau are required");
+  if (cfg->precision < NFLBM_FP64 || cfg->precision > NFLBM_FP16S)
+    return fail(nullptr, NFLBM_EINVAL, "unknown precision");
+  const int imp = cfg->implicit_comp < 0 ? N - 1 : cfg->implicit_comp;
+  if (imp >= N) return fail(nullptr, NFLBM_EINVAL, "implicit_comp out of range");
+  for (int i = 0; i < N; ++i) {
+    if (!(cfg->tau[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau must exceed 1/2");
+    if (cfg->tau_g && !(cfg->tau_g[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau_g must exceed 1/2");
+  }
+  if (!(cfg->m > 0.0)) return fail(nullptr, NFLBM_EINVAL, "m must be positive");
+  if (!(cfg->omega_stab >= 0.0)) return fail(nullptr, NFLBM_EINVAL, "omega_stab must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (cfg->wall[a] != 0 && cfg->wall[a] != 1) return fail(nullptr, NFLBM_EINVAL, "wall flags are 0 or 1");
+  if (cfg->lattice == NFLBM_D2Q9 && cfg->wall[2])
+    return fail(nullptr, NFLBM_EINVAL, "D2Q9 has no z walls");
+
+  nflbm_sim* s = new nflbm_sim();
+  s->lat = cfg->lattice;
+  s->N = N;
+  s->NE = N - 1;
+  s->Q = s->lat == NFLBM_D2Q9 ? 9 : 19;
+  s->store = cfg->precision;
+  s->flags = cfg->flags;
+  s->nx = cfg->nx;
+  s->ny = cfg->ny;
+  s->nz = cfg->nz;
+  for (int a = 0; a < 3; ++a) s->wall[a] = cfg->wall[a];
+  s->implicit = imp;
+  s->n = static_cast<size_t>(nn);
+  {
+    int q = 0;
+    for (int u = 0; u < N; ++u)
+      if (u != imp) s->uidx[q++] = u;
+    s->uidx[N - 1] = imp;
+  }
+  char msg[256] = {0};
+  const int rc = compute_coeffs(N, cfg->sigma, cfg->width_D, &s->co, msg);
+  if (rc) {
+    delete s;
+    return fail(nullptr, rc == -1 ? NFLBM_EINVAL : NFLBM_ESINGULAR, msg);
+  }
+  // Linear stability of the explicit Cahn-Hilliard update in a pure phase:
+  // a mode of -lap eigenvalue lam grows by 1 + M lam (a - (3D/4) lam) per step
+  // with a = -12/D; |growth| <= 1 up to lam_max = 16/3 needs the bound below.
+  if (!(cfg->flags & NFLBM_FLAG_ALLOW_UNSTABLE)) {
+    const double lam = 16.0 / 3.0;
+    for (int i = 0; i < N; ++i) {
+      const double tg = cfg->tau_g ? cfg->tau_g[i] : 1.0;
+      const double M = cfg->m * (tg - 0.5) / 3.0;
+      if (M * lam * (0.75 * cfg->width_D * lam + 12.0 / cfg->width_D) >= 2.0) {
+        delete s;
+        return fail(nullptr, NFLBM_EUNSTABLE,
+                    "mobility M = c_s^2 m (tau_g - 1/2) exceeds the linear stability bound");
+      }
+    }
+  }
+  switch (s->store) {
+    case NFLBM_FP64: s->fs = 8; s->g0s = 8; s->ts = 8; break;
+    case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; break;
+    default: s->fs = 2; s->g0s = 4; s->ts = 4; break;
+  }
+  s->step_flags = 0;
+  for (int i = 0; i < N; ++i)
+    if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
+  if (cfg->flags & NFLBM_FLAG_POTENTIAL_FORCE) s->step_flags |= kFlagPotential;
+  if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
+  if (choose_launch(s) != 0) {
+    delete s;
+    return fail(nullptr, NFLBM_ENOTSUP, "LDS window does not fit the device for this N and precision");
+  }
+
+  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  bool ok = true;
+  for (int b = 0; b < 2 && ok; ++b) {
+    ok &= hipMalloc(&s->f[b], Qm * n * s->fs) == hipSuccess;
+    ok &= hipMalloc(&s->g0[b], NE * n * s->g0s) == hipSuccess;
+    ok &= hipMalloc(&s->gk[b], NE * Qm * n * s->fs) == hipSuccess;
+  }
+  ok = ok && hipMalloc(&s->conc, NE * n * s->ts) == hipSuccess;
+  const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
+  ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
+  if (!ok) {
+    free_device(s);
+    delete s;
+    return fail(nullptr, NFLBM_ENOMEM, "device allocation failed");
+  }
+  if (s->ts == 8) {
+    DevParams<double> p;
+    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, cfg->m, cfg->omega_stab, cfg->body_force, &p);
+    if (hipMemcpy(s->params, &p, sizeof(p), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+  } else {
+    DevParams<float> p;
+    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, cfg->m, cfg->omega_stab, cfg->body_force, &p);
+    if (hipMemcpy(s->params, &p, sizeof(p), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+  }
+  // rest state with C_1 = 1 everywhere until set_fields is called
+  if (ok) {
+    std::vector<double> C(size_t(N) * n, 0.0);
+    for (size_t q = 0; q < n; ++q) C[q] = 1.0;
+    *out = s;
+    const int r2 = nflbm_set_fields(s, C.data(), nullptr, nullptr);
+    if (r2 != NFLBM_OK) {
+      std::string m2 = s->err;
+      free_device(s);
+      delete s;
+      *out = nullptr;
+      return fail(nullptr, r2, m2);
+    }
+    return NFLBM_OK;
+  }
+  free_device(s);
+  delete s;
+  return fail(nullptr, NFLBM_EDEVICE, "cannot upload parameters");
+}
+
+void nflbm_destroy(nflbm_sim* sim) {
+  if (!sim) return;
+  if (sim->stream) (void)hipStreamSynchronize(sim->stream);
+  else (void)hipDeviceSynchronize();
+  free_device(sim);
+  delete sim;
+}
+
+int nflbm_set_stream(nflbm_sim* sim, void* stream) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  sim->stream = static_cast<hipStream_t>(stream);
+  return NFLBM_OK;
+}
+
+int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const double* P) {
+  if (!sim || !C) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const size_t n = sim->n;
+  const size_t cnt = size_t(sim->N) * n + (v ? 3 * n : 0) + (P ? n : 0);
+  double* tmp = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&tmp), cnt * sizeof(double)) != hipSuccess)
+    return fail(sim, NFLBM_ENOMEM, "cannot allocate the initialisation buffer");
+  double* dC = tmp;
+  double* dv = v ? tmp + size_t(sim->N) * n : nullptr;
+  double* dP = P ? tmp + size_t(sim->N) * n + (v ? 3 * n : 0) : nullptr;
+  hipError_t e = hipMemcpyAsync(dC, C, size_t(sim->N) * n * sizeof(double), hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess && v) e = hipMemcpyAsync(dv, v, 3 * n * sizeof(double), hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess && P) e = hipMemcpyAsync(dP, P, n * sizeof(double), hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess) {
+    InitArgs a{};
+    a.f = sim->f[sim->cur];
+    a.g0 = sim->g0[sim->cur];
+    a.gk = sim->gk[sim->cur];
+    a.C = dC;
+    a.v = dv;
+    a.P = dP;
+    a.params = sim->params;
+    a.n = static_cast<long long>(n);
+    e = launch_init(sim->lat, sim->N, sim->store, a, sim->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(sim, e, "set_fields");
+  return NFLBM_OK;
+}
+
+int nflbm_step(nflbm_sim* sim, long long nsteps) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (nsteps < 0) return fail(sim, NFLBM_EINVAL, "nsteps < 0");
+  for (long long t = 0; t < nsteps; ++t) {
+    StepArgs a = make_args(sim, sim->cur);
+    HIPCHK(sim, launch_conc(sim->lat, sim->N, sim->store, a, sim->stream));
+    HIPCHK(sim, launch_update(sim->lat, sim->N, sim->store, a, false, sim->stream));
+    sim->cur ^= 1;
+  }
+  return NFLBM_OK;
+}
+
+int nflbm_step_timed(nflbm_sim* sim, long long nsteps, double* ms, double* ms_update) {
+  if (!sim || !ms) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  hipEvent_t e0, e1;
+  HIPCHK(sim, hipEventCreate(&e0));
+  HIPCHK(sim, hipEventCreate(&e1));
+  std::vector<hipEvent_t> ev;
+  if (ms_update) {
+    ev.resize(2 * size_t(nsteps));
+    for (auto& x : ev) HIPCHK(sim, hipEventCreate(&x));
+  }
+  HIPCHK(sim, hipEventRecord(e0, sim->stream));
+  for (long long t = 0; t < nsteps; ++t) {
+    StepArgs a = make_args(sim, sim->cur);
+    HIPCHK(sim, launch_conc(sim->lat, sim->N, sim->store, a, sim->stream));
+    if (ms_update) HIPCHK(sim, hipEventRecord(ev[2 * t], sim->stream));
+    HIPCHK(sim, launch_update(sim->lat, sim->N, sim->store, a, false, sim->stream));
+    if (ms_update) HIPCHK(sim, hipEventRecord(ev[2 * t + 1], sim->stream));
+    sim->cur ^= 1;
+  }
+  HIPCHK(sim, hipEventRecord(e1, sim->stream));
+  HIPCHK(sim, hipEventSynchronize(e1));
+  float t_ms = 0.f;
+  HIPCHK(sim, hipEventElapsedTime(&t_ms, e0, e1));
+  *ms = t_ms;
+  if (ms_update) {
+    double tot = 0.0;
+    for (long long t = 0; t < nsteps; ++t) {
+      float u = 0.f;
+      HIPCHK(sim, hipEventElapsedTime(&u, ev[2 * t], ev[2 * t + 1]));
+      tot += u;
+    }
+    *ms_update = tot;
+    for (auto& x : ev) (void)hipEventDestroy(x);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return NFLBM_OK;
+}
+
+int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
+  if (!sim || !host_out) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const size_t n = sim->n;
+  const int N = sim->N;
+  if (field >= NFLBM_FIELD_C && field <= NFLBM_FIELD_MU) {
+    int rc = compute_fields(sim);
+    if (rc) return rc;
+    size_t off = 0, cnt = 0;
+    switch (field) {
+      case NFLBM_FIELD_C: off = 0; cnt = N; break;
+      case NFLBM_FIELD_V: off = N; cnt = 3; break;
+      case NFLBM_FIELD_P: off = N + 3; cnt = 1; break;
+      case NFLBM_FIELD_F: off = N + 4; cnt = 3; break;
+      default: off = N + 7; cnt = N; break;
+    }
+    HIPCHK(sim, hipMemcpyAsync(host_out, sim->fields + off * n, cnt * n * sizeof(double),
+                               hipMemcpyDeviceToHost, sim->stream));
+    HIPCHK(sim, hipStreamSynchronize(sim->stream));
+    return NFLBM_OK;
+  }
+  if (field == NFLBM_FIELD_F_RAW || field == NFLBM_FIELD_G_RAW) {
+    const int Qm = sim->Q - 1;
+    std::vector<unsigned char> fbuf, g0buf, gkbuf;
+    if (field == NFLBM_FIELD_F_RAW) fbuf.resize(Qm * n * sim->fs);
+    else {
+      g0buf.resize(sim->NE * n * sim->g0s);
+      gkbuf.resize(size_t(sim->NE) * Qm * n * sim->fs);
+    }
+    if (field == NFLBM_FIELD_F_RAW)
+      HIPCHK(sim, hipMemcpyAsync(fbuf.data(), sim->f[sim->cur], fbuf.size(), hipMemcpyDeviceToHost, sim->stream));
+    else {
+      HIPCHK(sim, hipMemcpyAsync(g0buf.data(), sim->g0[sim->cur], g0buf.size(), hipMemcpyDeviceToHost, sim->stream));
+      HIPCHK(sim, hipMemcpyAsync(gkbuf.data(), sim->gk[sim->cur], gkbuf.size(), hipMemcpyDeviceToHost, sim->stream));
+    }
+    HIPCHK(sim, hipStreamSynchronize(sim->stream));
+    auto val = [&](const unsigned char* base, size_t idx, size_t bytes, bool moving) -> double {
+      if (bytes == 8) return reinterpret_cast<const double*>(base)[idx];
+      if (bytes == 4) return reinterpret_cast<const float*>(base)[idx];
+      const _Float16 h = reinterpret_cast<const _Float16*>(base)[idx];
+      return moving ? static_cast<double>(static_cast<float>(h) * (1.0f / kHalfScale)) : 0.0;
+    };
+    if (field == NFLBM_FIELD_F_RAW) {
+      for (size_t q = 0; q < Qm * n; ++q) host_out[q] = val(fbuf.data(), q, sim->fs, true);
+      return NFLBM_OK;
+    }
+    std::memset(host_out, 0, size_t(N) * sim->Q * n * sizeof(double));
+    for (int i = 0; i < sim->NE; ++i) {
+      const int u = sim->uidx[i];
+      double* o = host_out + size_t(u) * sim->Q * n;
+      for (size_t q = 0; q < n; ++q) o[q] = val(g0buf.data(), size_t(i) * n + q, sim->g0s, false);
+      for (int k = 0; k < Qm; ++k)
+        for (size_t q = 0; q < n; ++q)
+          o[size_t(k + 1) * n + q] = val(gkbuf.data(), (size_t(i) * Qm + k) * n + q, sim->fs, true);
+    }
+    return NFLBM_OK;
+  }
+  return fail(sim, NFLBM_EINVAL, "unknown field");
+}
+
+int nflbm_state_bytes(nflbm_sim* sim, size_t* bytes) {
+  if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
+  *bytes = Qm * n * sim->fs + NE * n * sim->g0s + NE * Qm * n * sim->fs;
+  return NFLBM_OK;
+}
+
+int nflbm_get_state(nflbm_sim* sim, void* host_raw) {
+  if (!sim || !host_raw) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
+  unsigned char* p = static_cast<unsigned char*>(host_raw);
+  HIPCHK(sim, hipMemcpyAsync(p, sim->f[sim->cur], Qm * n * sim->fs, hipMemcpyDeviceToHost, sim->stream));
+  p += Qm * n * sim->fs;
+  HIPCHK(sim, hipMemcpyAsync(p, sim->g0[sim->cur], NE * n * sim->g0s, hipMemcpyDeviceToHost, sim->stream));
+  p += NE * n * sim->g0s;
+  HIPCHK(sim, hipMemcpyAsync(p, sim->gk[sim->cur], NE * Qm * n * sim->fs, hipMemcpyDeviceToHost, sim->stream));
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  return NFLBM_OK;
+}
+
+int nflbm_set_state(nflbm_sim* sim, const void* host_raw) {
+  if (!sim || !host_raw) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
+  const unsigned char* p = static_cast<const unsigned char*>(host_raw);
+  HIPCHK(sim, hipMemcpyAsync(sim->f[sim->cur], p, Qm * n * sim->fs, hipMemcpyHostToDevice, sim->stream));
+  p += Qm * n * sim->fs;
+  HIPCHK(sim, hipMemcpyAsync(sim->g0[sim->cur], p, NE * n * sim->g0s, hipMemcpyHostToDevice, sim->stream));
+  p += NE * n * sim->g0s;
+  HIPCHK(sim, hipMemcpyAsync(sim->gk[sim->cur], p, NE * Qm * n * sim->fs, hipMemcpyHostToDevice, sim->stream));
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  return NFLBM_OK;
+}
+
+int nflbm_diagnostics(nflbm_sim* sim, int vcm_component, nflbm_diag* out) {
+  if (!sim || !out) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  if (vcm_component < 0 || vcm_component >= sim->N) return fail(sim, NFLBM_EINVAL, "vcm_component out of range");
+  int rc = compute_fields(sim);
+  if (rc) return rc;
+  const int N = sim->N;
+  const int rec = reduce_record_len(N);
+  if (!sim->red) {
+    long long blocks = static_cast<long long>((sim->n + 4095) / 4096);
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    sim->red_blocks = static_cast<int>(blocks);
+    if (hipMalloc(reinterpret_cast<void**>(&sim->red), size_t(blocks + 1) * rec * sizeof(double)) != hipSuccess) {
+      sim->red = nullptr;
+      return fail(sim, NFLBM_ENOMEM, "cannot allocate the reduction buffer");
+    }
+  }
+  ReduceArgs a{};
+  a.fields = sim->fields;
+  a.partial = sim->red;
+  a.out = sim->red + size_t(sim->red_blocks) * rec;
+  a.n = static_cast<long long>(sim->n);
+  a.N = N;
+  a.vcm_comp = vcm_component;
+  a.blocks = sim->red_blocks;
+  HIPCHK(sim, launch_reduce(a, sim->stream));
+  std::vector<double> r(rec);
+  HIPCHK(sim, hipMemcpyAsync(r.data(), a.out, rec * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < N; ++i) {
+    out->mass[i] = r[i];
+    out->max_abs_c[i] = r[N + 3 + i];
+    out->min_c[i] = r[2 * N + 3 + i];
+  }
+  for (int d = 0; d < 3; ++d) out->momentum[d] = r[N + d];
+  out->max_sum_dev = r[3 * N + 3];
+  const double cm = r[3 * N + 7];
+  for (int d = 0; d < 3; ++d) out->vcm[d] = cm != 0.0 ? r[3 * N + 4 + d] / cm : 0.0;
+  out->vcm_component = vcm_component;
+  out->nan = r[3 * N + 8] != 0.0 ? 1 : 0;
+  if (out->nan) return fail(sim, NFLBM_ENUMERIC, "NaN or Inf in the state");
+  return NFLBM_OK;
+}
+
+int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
+  if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  const double Qm = sim->Q - 1, NE = sim->NE;
+  double b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * NE * sim->ts;
+  if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;
+  *bytes = b;
+  return NFLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Declarations shared by the C ABI (api.cpp) and the device code (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "coeffs.h"
+
+namespace nflbm {
+
+enum StoreKind { kStoreF64 = 0, kStoreF32 = 1, kStoreF16S = 2 };
+
+// Scale applied to binary16 moving populations so that typical magnitudes
+// (1e-5 .. 1e-1) stay in the normal range; a power of two, so scaling is exact.
+constexpr float kHalfScale = 4096.0f;
+
+// Per-simulation constants read by every kernel, in the compute precision T.
+// Components are in internal order: the evolved ones first (user order kept),
+// the implicit one last.
+template <class T>
+struct DevParams {
+  T beta[kMaxComp][kMaxComp];
+  T kappa[kMaxComp][kMaxComp];
+  T psi[kMaxComp][kMaxComp][kMaxComp];
+  T xt[kMaxComp][kMaxComp][kMaxComp];
+  T zt[kMaxComp][kMaxComp][kMaxComp];
+  T omega_p[kMaxComp];    // 1/tau_i
+  T omega_m[kMaxComp];    // TRT odd rate (== omega_p for BGK)
+  T inv_tau_g[kMaxComp];
+  T m;                    // mobility parameter of g^eq
+  T k34D;                 // 3D/4
+  T k12D;                 // 12/D
+  T omega_stab;           // Omega of xi
+  T fb[3];                // body force
+  int uidx[kMaxComp];     // user index of internal component i
+};
+
+enum StepFlags {
+  kFlagNeedG = 1,         // some tau_g != 1: the update reads g
+  kFlagPotential = 2,     // potential-form surface tension
+  kFlagOmega = 4          // Omega != 0
+};
+
+struct StepArgs {
+  const void* f_src; void* f_dst;     // [Q-1][n] moving hydrodynamic populations
+  const void* g0_src; void* g0_dst;   // [NE][n] rest populations of evolved components
+  const void* gk_src; void* gk_dst;   // [NE][Q-1][n] moving populations
+  void* conc;                         // [NE][n] reconstructed C (compute precision)
+  double* fields;                     // fields-mode output [2N+7][n]
+  const void* params;                 // DevParams<T>
+  long long n;
+  int nx, ny, nz;
+  int wall_x, wall_y, wall_z;
+  int tx_log2;                        // tile width TX = 1 << tx_log2, TY = 256 / TX
+  int zchunk;                         // planes per workgroup (D3Q19)
+  int tiles_x, tiles_y, chunks_z;
+  int flags;
+};
+
+struct InitArgs {
+  void* f; void* g0; void* gk;
+  const double* C;                    // [N][n] user order
+  const double* v;                    // [3][n] or null
+  const double* P;                    // [n] or null
+  const void* params;
+  long long n;
+};
+
+struct ReduceArgs {
+  const double* fields;               // as written by the fields mode
+  double* partial;                    // [blocks][rec]
+  double* out;                        // [rec]
+  long long n;
+  int N;
+  int vcm_comp;                       // user index
+  int blocks;
+};
+
+// Launchers: lat 0 = D2Q9, 1 = D3Q19; nc = N; store = StoreKind.
+hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
+hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s);
+hipError_t launch_init(int lat, int nc, int store, const InitArgs& a, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+__host__ __device__ int reduce_record_len(int N);
+size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
+
+}  // namespace nflbm

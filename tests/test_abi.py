@@ -1,0 +1,107 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/nflbm.h declares, computes the coefficient tables on the host in
+agreement with the oracle's independent computation, and rejects invalid
+configurations before touching a device."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+from oracle.coeffs import Coefficients, equal_sigma
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(nf.LIB_PATH):
+        from paper_2605_22214_amd import build
+        build.build(verbose=False)
+    return nf.lib()
+
+
+def test_exports_every_header_function(L):
+    names = nf.header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.nflbm_abi_version() == 1
+
+
+def random_sigma(N, rng, lo=0.003, hi=0.009):
+    s = rng.uniform(lo, hi, size=(N, N))
+    s = 0.5 * (s + s.T)
+    np.fill_diagonal(s, 0.0)
+    return s
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
+def test_host_coefficients_match_oracle(L, N):
+    rng = np.random.default_rng(500 + N)
+    sig = random_sigma(N, rng)
+    lib_c = nf.coefficients(sig, 4.0)
+    orc = Coefficients(sig, 4.0)
+    sa = np.abs(orc.alpha).max()
+    np.testing.assert_allclose(lib_c["alpha"], orc.alpha, atol=1e-12 * sa)
+    np.testing.assert_allclose(lib_c["gamma"], orc.gamma, atol=1e-13)
+    for key in ("Psi", "X", "Z"):
+        ref = getattr(orc, key)
+        got = lib_c[key.lower() if key == "Psi" else key]
+        valid = ~np.isnan(ref)
+        scale = max(1.0, np.abs(ref[valid]).max()) if valid.any() else 1.0
+        assert np.abs(got[valid] - ref[valid]).max(initial=0.0) < 1e-10 * scale
+        assert np.all(got[~valid] == 0.0)
+
+
+def test_equal_sigma_host_tables(L):
+    s = 0.004
+    c = nf.coefficients(equal_sigma(5, s))
+    N = 5
+    np.testing.assert_allclose(c["alpha"], -(np.eye(N) - np.ones((N, N)) / N) / s, atol=1e-9)
+
+
+def _cfg(**kw):
+    N = kw.pop("N", 3)
+    sig = kw.pop("sigma", equal_sigma(N, 0.005))
+    tau = kw.pop("tau", np.ones(N))
+    cfg = nf.Config()
+    cfg.lattice = kw.pop("lattice", nf.D2Q9)
+    cfg.nx, cfg.ny, cfg.nz = kw.pop("shape", (8, 8, 1))
+    cfg.ncomp = N
+    cfg.implicit_comp = kw.pop("implicit", -1)
+    keep = (np.ascontiguousarray(sig, float), np.ascontiguousarray(tau, float))
+    cfg.sigma = keep[0].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.tau = keep[1].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.width_D = kw.pop("D", 4.0)
+    cfg.m = kw.pop("m", 0.05)
+    cfg.precision = kw.pop("precision", nf.FP64)
+    for a, w in enumerate(kw.pop("walls", (0, 0, 0))):
+        cfg.wall[a] = w
+    assert not kw
+    return cfg, keep
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lattice=5), dict(shape=(8, 8, 2)), dict(shape=(0, 8, 1)), dict(N=9, sigma=equal_sigma(9, 0.005)),
+    dict(sigma=np.array([[0, 0.01, 0.01], [0.02, 0, 0.01], [0.01, 0.01, 0]])),
+    dict(tau=np.array([1.0, 0.5, 1.0])), dict(m=0.0), dict(implicit=3), dict(precision=7),
+    dict(walls=(0, 0, 1)),
+])
+def test_invalid_configs_rejected_on_host(L, bad):
+    cfg, keep = _cfg(**bad)
+    h = ctypes.c_void_p()
+    rc = L.nflbm_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == -1, nf.lib().nflbm_last_error(None)
+    assert not h.value
+    assert L.nflbm_last_error(None)
+
+
+def test_unstable_mobility_rejected(L):
+    cfg, keep = _cfg(m=0.2)       # M = m/6 above 0.0197
+    h = ctypes.c_void_p()
+    assert L.nflbm_create(ctypes.byref(cfg), ctypes.byref(h)) == -3
+
+
+def test_coefficients_invalid_sigma(L):
+    with pytest.raises(nf.NflbmError):
+        nf.coefficients(np.array([[0.0, -1.0], [-1.0, 0.0]]))
