@@ -32,15 +32,17 @@ Q = 19
 
 def update_bytes_per_node(N, fs, g0s, ts):
     """Algorithmic HBM bytes of one update launch per node: read the Q-1
-    moving f populations and the N-1 reconstructed concentrations, write the
-    Q-1 f populations and all Q populations of the N-1 evolved components."""
+    moving f populations, the N-1 reconstructed concentrations and E_B, write
+    the Q-1 f populations and all Q populations of the N-1 evolved
+    components (halo re-reads of C and E_B are not counted)."""
     NE = N - 1
-    return (Q - 1) * fs + NE * ts + (Q - 1) * fs + NE * ((Q - 1) * fs + g0s)
+    return (Q - 1) * fs + (NE + 1) * ts + (Q - 1) * fs + NE * ((Q - 1) * fs + g0s)
 
 
 def conc_bytes_per_node(N, fs, g0s, ts):
+    """Read all Q populations of the N-1 evolved components, write C and E_B."""
     NE = N - 1
-    return NE * ((Q - 1) * fs + g0s) + NE * ts
+    return NE * ((Q - 1) * fs + g0s) + (NE + 1) * ts
 
 
 SIZES = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "fp16s": (2, 4, 4)}

@@ -205,6 +205,16 @@ int nflbm_diagnostics(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
 int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, double *gamma,
                        double *psi, double *xtab, double *ztab);
 
+/* Launch shape of the update kernel: 256-thread workgroups covering a tile
+ * 2^tx_log2 wide (tx_log2 4 or 6: 16 x 16 or 64 x 4 tiles); in D3Q19 each
+ * workgroup marches through zchunk planes (1 = a single plane) keeping three
+ * planes of concentrations in LDS.  A value <= 0 keeps the current setting.
+ * EINVAL if the shape is invalid or its LDS window exceeds the device limit.
+ * Results do not depend on the shape.  nflbm_get_launch also reports the
+ * device's LDS bytes per workgroup (any output pointer may be NULL). */
+int nflbm_set_launch(nflbm_sim *sim, int tx_log2, int zchunk);
+int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
+
 /* Bytes moved per lattice-node update by the reconstruction and update
  * kernels together, counting every stored population once read and once
  * written plus the reconstructed concentrations (written once, read once). */

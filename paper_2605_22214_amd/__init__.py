@@ -94,6 +94,8 @@ def lib():
             "nflbm_diagnostics": (I, [P, I, ctypes.POINTER(Diag)]),
             "nflbm_coefficients": (I, [I, DP, D, DP, DP, DP, DP, DP]),
             "nflbm_bytes_per_node": (I, [P, DP]),
+            "nflbm_set_launch": (I, [P, I, I]),
+            "nflbm_get_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_last_error": (ctypes.c_char_p, [P]),
             "nflbm_abi_version": (I, []),
         }
@@ -255,6 +257,15 @@ class Simulation:
                 "max_abs_c": list(d.max_abs_c[:N]), "min_c": list(d.min_c[:N]),
                 "max_sum_dev": d.max_sum_dev, "vcm": list(d.vcm), "nan": d.nan,
                 "status": code}
+
+    def set_launch(self, tx_log2=0, zchunk=0):
+        _check(lib().nflbm_set_launch(self._handle(), int(tx_log2), int(zchunk)), self._h)
+
+    def get_launch(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().nflbm_get_launch(self._handle(), ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(c)), self._h)
+        return a.value, b.value, c.value
 
     def bytes_per_node(self):
         b = ctypes.c_double()

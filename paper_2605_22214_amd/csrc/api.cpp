@@ -18,6 +18,15 @@ namespace {
 
 thread_local std::string g_thread_error;
 
+// Velocity sets (the same ordering as the device code: opposite directions
+// adjacent, k + 1 for odd k).
+constexpr int kD2Q9[19][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                              {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+constexpr int kD3Q19[19][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
 }  // namespace
 
 struct nflbm_sim {
@@ -35,6 +44,7 @@ struct nflbm_sim {
   void* g0[2] = {nullptr, nullptr};
   void* gk[2] = {nullptr, nullptr};
   void* conc = nullptr;
+  void* eb = nullptr;
   void* params = nullptr;
   double* fields = nullptr;
   double* red = nullptr;
@@ -43,6 +53,7 @@ struct nflbm_sim {
   hipStream_t stream = nullptr;
   // launch shape
   int tx_log2 = 6, zchunk = 1, tiles_x = 1, tiles_y = 1, chunks_z = 1;
+  size_t lds_max = 65536;
   int step_flags = 0;
   std::string err;
 };
@@ -110,10 +121,11 @@ void free_device(nflbm_sim* s) {
     s->f[b] = s->g0[b] = s->gk[b] = nullptr;
   }
   if (s->conc) (void)hipFree(s->conc);
+  if (s->eb) (void)hipFree(s->eb);
   if (s->params) (void)hipFree(s->params);
   if (s->fields) (void)hipFree(s->fields);
   if (s->red) (void)hipFree(s->red);
-  s->conc = s->params = nullptr;
+  s->conc = s->params = s->eb = nullptr;
   s->fields = s->red = nullptr;
 }
 
@@ -123,38 +135,51 @@ int next_pow2_log(int v) {
   return l;
 }
 
-// Tile width: the smallest power of two covering nx, between 16 and 64, then
-// narrowed until the LDS window fits the device's per-workgroup limit.
-int choose_launch(nflbm_sim* s) {
-  int l = next_pow2_log(s->nx);
-  if (l < 4) l = 4;
-  if (l > 6) l = 6;
+size_t device_lds_max() {
   int dev = 0;
-  size_t lds_max = 65536;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
       prop.sharedMemPerBlock > 0)
-    lds_max = prop.sharedMemPerBlock;
-  while (l > 4 && update_lds_bytes(s->lat, s->N, s->store, l) > lds_max) --l;
-  if (update_lds_bytes(s->lat, s->N, s->store, l) > lds_max) return -1;
-  s->tx_log2 = l;
+    return prop.sharedMemPerBlock;
+  return 65536;
+}
+
+// Apply a launch shape; returns false if it is invalid or its LDS does not fit.
+bool apply_launch(nflbm_sim* s, int l, int zc) {
+  if (l != 4 && l != 6) return false;
+  if (s->lat != NFLBM_D3Q19) zc = 1;
+  if (zc < 1) return false;
+  if (zc > s->nz) zc = s->nz;
+  if (update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
   const int TX = 1 << l, TY = 256 >> l;
+  s->tx_log2 = l;
+  s->zchunk = zc;
   s->tiles_x = (s->nx + TX - 1) / TX;
   s->tiles_y = (s->ny + TY - 1) / TY;
+  s->chunks_z = s->lat == NFLBM_D3Q19 ? (s->nz + zc - 1) / zc : 1;
+  return true;
+}
+
+// Default shape: tiles 64 x 4 (16 x 16 when nx <= 16 or when the wider LDS
+// window does not fit); in 3-D a z run per workgroup that leaves about 4096
+// workgroups (1024 in FP64, where longer runs measured faster).
+int choose_launch(nflbm_sim* s) {
+  s->lds_max = device_lds_max();
+  int l = s->nx <= 16 ? 4 : 6;
+  if (l == 6 && update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) l = 4;
+  if (update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return -1;
+  int zc = 1;
   if (s->lat == NFLBM_D3Q19) {
-    const long long xy = static_cast<long long>(s->tiles_x) * s->tiles_y;
-    long long chunks = 4096 / (xy > 0 ? xy : 1);
+    const int TX = 1 << l, TY = 256 >> l;
+    const long long xy = static_cast<long long>((s->nx + TX - 1) / TX) * ((s->ny + TY - 1) / TY);
+    const long long target = s->store == NFLBM_FP64 ? 1024 : 4096;
+    long long chunks = target / (xy > 0 ? xy : 1);
     if (chunks < 1) chunks = 1;
     if (chunks > s->nz) chunks = s->nz;
-    int zc = static_cast<int>((s->nz + chunks - 1) / chunks);
+    zc = static_cast<int>((s->nz + chunks - 1) / chunks);
     if (zc < 4) zc = s->nz < 4 ? s->nz : 4;
-    s->zchunk = zc;
-    s->chunks_z = (s->nz + zc - 1) / zc;
-  } else {
-    s->zchunk = 1;
-    s->chunks_z = 1;
   }
-  return 0;
+  return apply_launch(s, l, zc) ? 0 : -1;
 }
 
 StepArgs make_args(const nflbm_sim* s, int src) {
@@ -166,6 +191,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.gk_src = s->gk[src];
   a.gk_dst = s->gk[1 - src];
   a.conc = s->conc;
+  a.eb = s->eb;
   a.fields = s->fields;
   a.params = s->params;
   a.n = static_cast<long long>(s->n);
@@ -323,6 +349,11 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   }
 
   const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  if (double(n) * double(NE) * double(s->fs > s->ts ? s->fs : s->ts) >= 4294967296.0 ||
+      double(n) * double(NE) * double(s->g0s) >= 4294967296.0) {
+    delete s;
+    return fail(nullptr, NFLBM_ENOTSUP, "lattice too large: in-plane byte offsets must fit 32 bits");
+  }
   bool ok = true;
   for (int b = 0; b < 2 && ok; ++b) {
     ok &= hipMalloc(&s->f[b], Qm * n * s->fs) == hipSuccess;
@@ -330,6 +361,7 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
     ok &= hipMalloc(&s->gk[b], NE * Qm * n * s->fs) == hipSuccess;
   }
   ok = ok && hipMalloc(&s->conc, NE * n * s->ts) == hipSuccess;
+  ok = ok && hipMalloc(&s->eb, n * s->ts) == hipSuccess;
   const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
   ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
   if (!ok) {
@@ -403,6 +435,7 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
     a.P = dP;
     a.params = sim->params;
     a.n = static_cast<long long>(n);
+    a.sa = make_args(sim, sim->cur);
     e = launch_init(sim->lat, sim->N, sim->store, a, sim->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
@@ -483,16 +516,17 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     return NFLBM_OK;
   }
   if (field == NFLBM_FIELD_F_RAW || field == NFLBM_FIELD_G_RAW) {
+    // The device holds post-collision populations (pull streaming); the
+    // post-streaming values are gathered here on the host.
     const int Qm = sim->Q - 1;
+    const int NE = sim->NE;
     std::vector<unsigned char> fbuf, g0buf, gkbuf;
-    if (field == NFLBM_FIELD_F_RAW) fbuf.resize(Qm * n * sim->fs);
-    else {
-      g0buf.resize(sim->NE * n * sim->g0s);
-      gkbuf.resize(size_t(sim->NE) * Qm * n * sim->fs);
-    }
-    if (field == NFLBM_FIELD_F_RAW)
+    if (field == NFLBM_FIELD_F_RAW) {
+      fbuf.resize(Qm * n * sim->fs);
       HIPCHK(sim, hipMemcpyAsync(fbuf.data(), sim->f[sim->cur], fbuf.size(), hipMemcpyDeviceToHost, sim->stream));
-    else {
+    } else {
+      g0buf.resize(size_t(NE) * n * sim->g0s);
+      gkbuf.resize(size_t(NE) * Qm * n * sim->fs);
       HIPCHK(sim, hipMemcpyAsync(g0buf.data(), sim->g0[sim->cur], g0buf.size(), hipMemcpyDeviceToHost, sim->stream));
       HIPCHK(sim, hipMemcpyAsync(gkbuf.data(), sim->gk[sim->cur], gkbuf.size(), hipMemcpyDeviceToHost, sim->stream));
     }
@@ -503,19 +537,43 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
       const _Float16 h = reinterpret_cast<const _Float16*>(base)[idx];
       return moving ? static_cast<double>(static_cast<float>(h) * (1.0f / kHalfScale)) : 0.0;
     };
-    if (field == NFLBM_FIELD_F_RAW) {
-      for (size_t q = 0; q < Qm * n; ++q) host_out[q] = val(fbuf.data(), q, sim->fs, true);
-      return NFLBM_OK;
-    }
-    std::memset(host_out, 0, size_t(N) * sim->Q * n * sizeof(double));
-    for (int i = 0; i < sim->NE; ++i) {
-      const int u = sim->uidx[i];
-      double* o = host_out + size_t(u) * sim->Q * n;
-      for (size_t q = 0; q < n; ++q) o[q] = val(g0buf.data(), size_t(i) * n + q, sim->g0s, false);
-      for (int k = 0; k < Qm; ++k)
-        for (size_t q = 0; q < n; ++q)
-          o[size_t(k + 1) * n + q] = val(gkbuf.data(), (size_t(i) * Qm + k) * n + q, sim->fs, true);
-    }
+    const int (*E)[3] = sim->lat == NFLBM_D2Q9 ? kD2Q9 : kD3Q19;
+    const int dims[3] = {sim->nx, sim->ny, sim->nz};
+    // (direction, node) the population f_k of node q is read from
+    auto source = [&](int k, int x, int y, int z, int& dir) -> size_t {
+      int c[3] = {x - E[k][0], y - E[k][1], z - E[k][2]};
+      for (int d = 0; d < 3; ++d) {
+        if (c[d] < 0 || c[d] >= dims[d]) {
+          if (sim->wall[d]) {
+            dir = (k & 1) ? k + 1 : k - 1;
+            return size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
+          }
+          c[d] = (c[d] + dims[d]) % dims[d];
+        }
+      }
+      dir = k;
+      return size_t(c[0]) + size_t(sim->nx) * (size_t(c[1]) + size_t(sim->ny) * c[2]);
+    };
+    if (field == NFLBM_FIELD_G_RAW) std::memset(host_out, 0, size_t(N) * sim->Q * n * sizeof(double));
+    for (int z = 0; z < sim->nz; ++z)
+      for (int y = 0; y < sim->ny; ++y)
+        for (int x = 0; x < sim->nx; ++x) {
+          const size_t q = size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
+          if (field == NFLBM_FIELD_G_RAW)
+            for (int i = 0; i < NE; ++i)
+              host_out[size_t(sim->uidx[i]) * sim->Q * n + q] = val(g0buf.data(), q * NE + i, sim->g0s, false);
+          for (int k = 1; k <= Qm; ++k) {
+            int dir = k;
+            const size_t src = source(k, x, y, z, dir);
+            if (field == NFLBM_FIELD_F_RAW) {
+              host_out[size_t(k - 1) * n + q] = val(fbuf.data(), size_t(dir - 1) * n + src, sim->fs, true);
+            } else {
+              for (int i = 0; i < NE; ++i)
+                host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] =
+                    val(gkbuf.data(), (size_t(dir - 1) * n + src) * NE + i, sim->fs, true);
+            }
+          }
+        }
     return NFLBM_OK;
   }
   return fail(sim, NFLBM_EINVAL, "unknown field");
@@ -599,10 +657,26 @@ int nflbm_diagnostics(nflbm_sim* sim, int vcm_component, nflbm_diag* out) {
   return NFLBM_OK;
 }
 
+int nflbm_set_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  const int l = tx_log2 > 0 ? tx_log2 : sim->tx_log2;
+  const int zc = zchunk > 0 ? zchunk : sim->zchunk;
+  if (!apply_launch(sim, l, zc)) return fail(sim, NFLBM_EINVAL, "invalid launch shape or LDS too large");
+  return NFLBM_OK;
+}
+
+int nflbm_get_launch(nflbm_sim* sim, int* tx_log2, int* zchunk, int* lds_limit) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (tx_log2) *tx_log2 = sim->tx_log2;
+  if (zchunk) *zchunk = sim->zchunk;
+  if (lds_limit) *lds_limit = static_cast<int>(sim->lds_max);
+  return NFLBM_OK;
+}
+
 int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const double Qm = sim->Q - 1, NE = sim->NE;
-  double b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * NE * sim->ts;
+  double b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;
   if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;
   *bytes = b;
   return NFLBM_OK;

@@ -42,11 +42,15 @@ enum StepFlags {
   kFlagOmega = 4          // Omega != 0
 };
 
+// Population arrays hold post-collision values (pull streaming):
+//   f [k-1][node], gk [k-1][node][i], g0 [node][i], conc [node][i], eb [node].
+// In-plane byte offsets are 32-bit: n * NE * sizeof(value) must stay below 2^32.
 struct StepArgs {
-  const void* f_src; void* f_dst;     // [Q-1][n] moving hydrodynamic populations
-  const void* g0_src; void* g0_dst;   // [NE][n] rest populations of evolved components
-  const void* gk_src; void* gk_dst;   // [NE][Q-1][n] moving populations
-  void* conc;                         // [NE][n] reconstructed C (compute precision)
+  const void* f_src; void* f_dst;     // moving hydrodynamic populations
+  const void* g0_src; void* g0_dst;   // rest populations of evolved components
+  const void* gk_src; void* gk_dst;   // moving populations of evolved components
+  void* conc;                         // reconstructed C (compute precision)
+  void* eb;                           // E_B per node (compute precision)
   double* fields;                     // fields-mode output [2N+7][n]
   const void* params;                 // DevParams<T>
   long long n;
@@ -59,12 +63,13 @@ struct StepArgs {
 };
 
 struct InitArgs {
-  void* f; void* g0; void* gk;
+  void* f; void* g0; void* gk;        // post-collision arrays of the target set
   const double* C;                    // [N][n] user order
   const double* v;                    // [3][n] or null
   const double* P;                    // [n] or null
   const void* params;
   long long n;
+  StepArgs sa;                        // lattice size and walls
 };
 
 struct ReduceArgs {

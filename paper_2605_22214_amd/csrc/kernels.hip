@@ -1,17 +1,30 @@
 // Device code of the N-component free-energy LBM time step for gfx950.
 //
+// Storage (pull streaming): each population set holds the POST-COLLISION
+// populations of the previous step; a node gathers its post-streaming values
+// f_k(x) = f*_k(x - e_k), or f*_kbar(x) when x - e_k lies inside a wall
+// (halfway bounce-back).  Every store of the update is then aligned with the
+// node that computes it, and only loads are shifted.
+//
+// Layout, node = x + nx (y + ny z):
+//   f [k-1][node]            moving hydrodynamic populations, k = 1..Q-1
+//   gk[k-1][node][i]         moving populations of the evolved components,
+//                            component innermost: one vector access moves
+//                            all components of a direction
+//   g0[node][i]              rest populations of the evolved components
+//   conc[node][i]            reconstructed concentrations (compute precision)
+//   eb[node]                 bulk free energy E_B of the reconstructed C
+//
 // One time step = two launches:
-//   k_conc    C_i = sum_k g_{i,k} for the evolved components (zeroth moment
-//             of g, Sec. III B).  Reads every g population once, writes NE
-//             values per node.
-//   k_update  per node: C of all components from an LDS halo tile (the
-//             implicit one as 1 - sum of the others), E_B, the isotropic
+//   k_conc    C_i = sum_k g_{i,k} of the evolved components (zeroth moment of
+//             g, Sec. III B), gathering the streamed populations, and E_B(C).
+//   k_update  per node: C of all components and E_B from an LDS halo tile
+//             (the implicit C as 1 - sum of the others), the isotropic
 //             gradient/Laplacian stencils (Eq. gradstencil) with the wall
 //             rule, the flux potential mu~ in factored form, the conservative
 //             surface-tension force (Eq. Fsnew), v and P (Eqs. nmom, pres),
 //             node viscosity, TRT collision with forcing (Eqs. TRT, FTRT,
-//             hydroforce), BGK collision of g (Eq. glbe), push streaming with
-//             halfway bounce-back.  Reads f once, writes f and g once.
+//             hydroforce) and BGK collision of g (Eq. glbe).
 // The concentration equilibrium is the rest-population form
 //   g^eq_{i,0} = C_i (1 + s_0) + (1 - w_0) m mu~_i,  g^eq_{i,k} = C_i s_k - w_k m mu~_i;
 // the rest population is written as C_i minus the stored moving populations,
@@ -19,8 +32,8 @@
 // rounding of one value in every storage precision.
 //
 // Workgroups are 256 threads covering a TX x TY tile of the x-y plane.  The
-// D2Q9 kernel loads one LDS plane; the D3Q19 kernel marches along z through
-// zchunk planes with a rolling window of three LDS planes.
+// D2Q9 update loads one LDS plane; the D3Q19 update marches along z through
+// zchunk planes with a rolling window of LDS planes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -50,6 +63,7 @@ struct D3Q19 {
                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
 // In both sets the opposite of direction k (k >= 1) is k + 1 for odd k.
+__host__ __device__ constexpr int opposite(int k) { return (k & 1) ? k + 1 : k - 1; }
 
 // ----------------------------------------------------------- storage types
 template <int ST> struct StoreT;
@@ -73,6 +87,59 @@ template <> struct StoreT<kStoreF16S> {
   static __device__ __forceinline__ FS pack(T v) { return static_cast<_Float16>(v * kHalfScale); }
   static __device__ __forceinline__ T unpack(FS v) { return static_cast<float>(v) * (1.0f / kHalfScale); }
 };
+
+// ------------------------------------------------- per-node vector access
+// The NE values a node holds for one direction are contiguous; groups of 4,
+// 8, 16 or 32 bytes move with single vector instructions.  Node offsets are
+// multiples of the group size, so these accesses are aligned.
+template <class E, int NE>
+__device__ __forceinline__ void vld(const E* p, E (&o)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+    __builtin_memcpy(o, &t, 4);
+  } else if constexpr (B == 8) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);
+    __builtin_memcpy(o, &t, 8);
+  } else if constexpr (B == 16) {
+    const uint4 t = *reinterpret_cast<const uint4*>(p);
+    __builtin_memcpy(o, &t, 16);
+  } else if constexpr (B == 32) {
+    uint4 t[2];
+    t[0] = reinterpret_cast<const uint4*>(p)[0];
+    t[1] = reinterpret_cast<const uint4*>(p)[1];
+    __builtin_memcpy(o, t, 32);
+  } else {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) o[e] = p[e];
+  }
+}
+
+template <class E, int NE>
+__device__ __forceinline__ void vst(E* p, const E (&v)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    uint32_t t;
+    __builtin_memcpy(&t, v, 4);
+    *reinterpret_cast<uint32_t*>(p) = t;
+  } else if constexpr (B == 8) {
+    uint2 t;
+    __builtin_memcpy(&t, v, 8);
+    *reinterpret_cast<uint2*>(p) = t;
+  } else if constexpr (B == 16) {
+    uint4 t;
+    __builtin_memcpy(&t, v, 16);
+    *reinterpret_cast<uint4*>(p) = t;
+  } else if constexpr (B == 32) {
+    uint4 t[2];
+    __builtin_memcpy(t, v, 32);
+    reinterpret_cast<uint4*>(p)[0] = t[0];
+    reinterpret_cast<uint4*>(p)[1] = t[1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) p[e] = v[e];
+  }
+}
 
 template <class T>
 __device__ __forceinline__ T fpoly(T c) {
@@ -103,51 +170,173 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
+// ------------------------------------------------------- streaming sources
+// Offsets of the neighbour rows of a node: x-1, x, x+1 with periodic wrap
+// (y and z pre-multiplied by the row and plane strides), and which faces of
+// the node are walls.
+struct Nbr {
+  uint32_t xo[3], yo[3], zo[3];
+  bool wlo[3], whi[3];
+};
+
+template <bool WALLS, bool D3>
+__device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a) {
+  Nbr b;
+  const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
+  b.xo[0] = x - 1; b.xo[1] = x; b.xo[2] = x + 1;
+  b.yo[0] = y - 1; b.yo[1] = y; b.yo[2] = y + 1;
+  b.zo[0] = z - 1; b.zo[1] = z; b.zo[2] = z + 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) b.wlo[d] = b.whi[d] = false;
+  if (x == 0) { if (WALLS && a.wall_x) b.wlo[0] = true; else b.xo[0] = a.nx - 1; }
+  if (x == a.nx - 1) { if (WALLS && a.wall_x) b.whi[0] = true; else b.xo[2] = 0; }
+  if (y == 0) { if (WALLS && a.wall_y) b.wlo[1] = true; else b.yo[0] = a.ny - 1; }
+  if (y == a.ny - 1) { if (WALLS && a.wall_y) b.whi[1] = true; else b.yo[2] = 0; }
+  if (D3) {
+    if (z == 0) { if (WALLS && a.wall_z) b.wlo[2] = true; else b.zo[0] = a.nz - 1; }
+    if (z == a.nz - 1) { if (WALLS && a.wall_z) b.whi[2] = true; else b.zo[2] = 0; }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b.yo[d] *= nx;
+    b.zo[d] *= nxy;
+  }
+  return b;
+}
+
+// The population streaming into this node along e_k comes from x - e_k; if
+// that node lies inside a wall it is this node's own post-collision
+// population of the opposite direction (halfway bounce-back, Sec. III C).
+template <class L, bool WALLS>
+__device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
+  if (!WALLS) return false;
+  bool w = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (L::e[k][d] > 0) w = w || b.wlo[d];
+    if (L::e[k][d] < 0) w = w || b.whi[d];
+  }
+  return w;
+}
+template <class L>
+__device__ __forceinline__ uint32_t upstream(const Nbr& b, int k) {
+  return b.xo[1 - L::e[k][0]] + b.yo[1 - L::e[k][1]] + b.zo[1 - L::e[k][2]];
+}
+
+// Workgroup -> tile.  Consecutive workgroup ids are dealt round-robin to the
+// 8 XCDs, each with its own L2; the remap hands every XCD a contiguous run of
+// tiles, so the halo rows and planes a workgroup re-reads were mostly fetched
+// into the same L2 by its neighbours.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Element idx of an array addressed with a 32-bit byte offset from a uniform
+// base: the load/store can then take the base in scalar registers.
+template <class E>
+__device__ __forceinline__ const E* at(const E* base, uint32_t idx) {
+  return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(E)));
+}
+template <class E>
+__device__ __forceinline__ E* at(E* base, uint32_t idx) {
+  return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(E)));
+}
+
 // ------------------------------------------------------------------ k_conc
-template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_conc(StepArgs a, int ne) {
+// One node per thread over TX x TY tiles of one z plane: C of the evolved
+// components from the gathered g, and the bulk free energy E_B(C), which the
+// update reads for its gradient.
+template <class L, int NE, int ST, bool WALLS>
+__global__ void __launch_bounds__(256)
+k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   using S = StoreT<ST>;
   using T = typename S::T;
-  const typename S::G0S* g0 = static_cast<const typename S::G0S*>(a.g0_src);
-  const typename S::FS* gk = static_cast<const typename S::FS*>(a.gk_src);
-  T* C = static_cast<T*>(a.conc);
+  using FS = typename S::FS;
+  using G0S = typename S::G0S;
+  constexpr int Q = L::Q;
+  constexpr int NC = NE + 1;
+  const DevParams<T>& P = *Pp;
+  const int TX = 1 << a.tx_log2;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> a.tx_log2;
+  int b = static_cast<int>(blockIdx.x);
+  const int tile_x = b % a.tiles_x;
+  b /= a.tiles_x;
+  const int tile_y = b % a.tiles_y;
+  const int z = b / a.tiles_y;
+  const int x = tile_x * TX + tx, y = tile_y * (256 >> a.tx_log2) + ty;
+  if (x >= a.nx || y >= a.ny) return;
   const size_t n = static_cast<size_t>(a.n);
-  for (size_t node = blockIdx.x * size_t(256) + threadIdx.x; node < n;
-       node += size_t(gridDim.x) * 256) {
-    for (int e = 0; e < ne; ++e) {
-      T s = static_cast<T>(g0[e * n + node]);
-      const typename S::FS* base = gk + size_t(e) * (Q - 1) * n + node;
+  const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
+  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
+  const G0S* g0 = static_cast<const G0S*>(a.g0_src);
+  const FS* gk = static_cast<const FS*>(a.gk_src);
+  T s[NE];
+  {
+    G0S r[NE];
+    vld<G0S, NE>(at(g0, node * NE), r);
 #pragma unroll
-      for (int k = 0; k < Q - 1; ++k) s += S::ld(base, size_t(k) * n);
-      C[e * n + node] = s;
-    }
+    for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]);
   }
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    FS v[NE];
+    if (pulled_from_wall<L, WALLS>(nb, k))
+      vld<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
+    else
+      vld<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+  }
+  vst<T, NE>(at(static_cast<T*>(a.conc), node * NE), s);
+  T c[NC];
+  T rest = T(0);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    c[e] = s[e];
+    rest += s[e];
+  }
+  c[NE] = T(1) - rest;
+  *at(static_cast<T*>(a.eb), node) = bulk_energy<NC, T>(c, P);
 }
 
 // ---------------------------------------------------------------- k_update
-template <class L, int NC, int ST, bool FIELDS>
-__global__ void __launch_bounds__(256) k_update(StepArgs a) {
+// Occupancy target of the update kernel: three waves per SIMD (at most 168
+// VGPRs) where that needs no spilling (float compute, D3Q19 with N <= 5, all
+// D2Q9); otherwise the compiler's own choice.
+template <class L, int NC, int ST>
+constexpr int update_waves() {
+  return (ST != kStoreF64 && (L::DIM == 2 || NC <= 5)) ? 3 : 1;
+}
+
+template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL>
+__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
+k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
   using G0S = typename S::G0S;
   constexpr int Q = L::Q;
   constexpr int NE = NC - 1;
-  constexpr int NPL = (L::DIM == 3) ? 3 : 1;
+  constexpr bool D3 = (L::DIM == 3);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const DevParams<T>& P = *static_cast<const DevParams<T>*>(a.params);
+  const DevParams<T>& P = *Pp;
 
+  // tile width as a compile-time constant: every LDS access of the stencil
+  // is then an immediate offset from one base address
+  constexpr int TX = 1 << TXL;
+  constexpr int TY = 256 >> TXL;
+  constexpr int PX = TX + 2;
+  constexpr int PXY = PX * (TY + 2);
+  constexpr int plane_stride = NC * PXY;   // NE concentrations + E_B per LDS slot
   const int tid = threadIdx.x;
-  const int TX = 1 << a.tx_log2;
-  const int TY = 256 >> a.tx_log2;
   const int tx = tid & (TX - 1);
-  const int ty = tid >> a.tx_log2;
-  const int PX = TX + 2;
-  const int PXY = PX * (TY + 2);
-  const int plane_stride = (NE + 1) * PXY;
+  const int ty = tid >> TXL;
 
-  int b = blockIdx.x;
+  const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
+  int b = xcd_remap(static_cast<int>(blockIdx.x), nblocks);
   const int tile_x = b % a.tiles_x;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
@@ -158,43 +347,71 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
   const int x = x0 + tx, y = y0 + ty;
   const bool active = (x < a.nx) && (y < a.ny);
   const size_t n = static_cast<size_t>(a.n);
+  const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
   const T* conc = static_cast<const T*>(a.conc);
+  const T* eb = static_cast<const T*>(a.eb);
+  const FS* fsrc = static_cast<const FS*>(a.f_src);
 
-  // Fill LDS slot with C (evolved components) and E_B for plane gz, tile plus
-  // a one-node ring.  Positions inside a wall are not filled: the stencil
-  // never reads them.
-  auto load_plane = [&](int slot, int gz) {
-    T* base = sm + slot * plane_stride;
-    bool zok = true;
-    if (gz < 0 || gz >= a.nz) {
-      if (a.wall_z) zok = false;
-      else gz = wrap(gz, a.nz);
-    }
-    for (int idx = tid; idx < PXY; idx += 256) {
+  // Each thread fills at most two positions of the (TX+2) x (TY+2) LDS window
+  // of every plane; their in-plane node offsets are fixed for the workgroup.
+  uint32_t fill_off[2];
+  bool fill_ok[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int idx = tid + 256 * r;
+    fill_ok[r] = idx < PXY;
+    fill_off[r] = 0;
+    if (fill_ok[r]) {
       const int ly = idx / PX;
       const int lx = idx - ly * PX;
       int gx = x0 + lx - 1, gy = y0 + ly - 1;
-      bool ok = zok;
       if (gx < 0 || gx >= a.nx) {
-        if (a.wall_x) ok = false;
+        if (WALLS && a.wall_x) fill_ok[r] = false;
         else gx = wrap(gx, a.nx);
       }
       if (gy < 0 || gy >= a.ny) {
-        if (a.wall_y) ok = false;
+        if (WALLS && a.wall_y) fill_ok[r] = false;
         else gy = wrap(gy, a.ny);
       }
-      if (!ok) continue;
-      const size_t node = size_t(gx) + size_t(a.nx) * (size_t(gy) + size_t(a.ny) * size_t(gz));
-      T c[NC];
-      T rest = T(0);
+      fill_off[r] = uint32_t(gx) + nx * uint32_t(gy);
+    }
+  }
+
+  // Fill an LDS slot with C (evolved components) and E_B of plane gz.
+  // Positions inside a wall are left unfilled: the stencil never reads them.
+  auto load_plane = [&](int slot, int gz) {
+    T* base = sm + slot * plane_stride;
+    if (gz < 0 || gz >= a.nz) {
+      if (WALLS && a.wall_z) return;
+      gz = (gz < 0) ? gz + a.nz : gz - a.nz;
+    }
+    const uint32_t zoff = uint32_t(gz) * nxy;
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        c[e] = conc[e * n + node];
-        rest += c[e];
-        base[e * PXY + idx] = c[e];
+    for (int r = 0; r < 2; ++r) {
+      if (!fill_ok[r]) continue;
+      const int idx = tid + 256 * r;
+      const uint32_t node = fill_off[r] + zoff;
+      T ce[NE];
+      vld<T, NE>(at(conc, node * NE), ce);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) base[e * PXY + idx] = ce[e];
+      base[NE * PXY + idx] = *at(eb, node);
+    }
+  };
+
+  // post-streaming f of this node, gathered from the upstream neighbours
+  T f[Q];
+  auto load_f = [&](int z) {
+    {
+      const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
+      const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        if (pulled_from_wall<L, WALLS>(nb, k))
+          f[k] = S::ld(at(fsrc + size_t(opposite(k) - 1) * n, node), 0);
+        else
+          f[k] = S::ld(at(fsrc + size_t(k - 1) * n, upstream<L>(nb, k)), 0);
       }
-      c[NE] = T(1) - rest;
-      base[NE * PXY + idx] = bulk_energy<NC, T>(c, P);
     }
   };
 
@@ -226,33 +443,35 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
       const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
       const T wk = static_cast<T>(L::w[k]);
       bool wall = false;
-      if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
-      if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
-      if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+      if (WALLS) {
+        if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
+        if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
+        if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+      }
       if (!wall) {
         const int slot = (ez == 0) ? s_c : (ez > 0 ? s_up : s_dn);
         const T* Cn = sm + slot * plane_stride + li + ey * PX + ex;
-        T rest = T(0);
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-          T cn;
-          if (i < NE) {
-            cn = Cn[i * PXY];
-            rest += cn;
-          } else {
-            cn = T(1) - rest;
-          }
-          const T d = cn - c[i];
-          lap[i] += wk * d;
-          if (ex != 0) gC[i][0] += (ex > 0) ? wk * d : -(wk * d);
-          if (ey != 0) gC[i][1] += (ey > 0) ? wk * d : -(wk * d);
-          if (ez != 0) gC[i][2] += (ez > 0) ? wk * d : -(wk * d);
+        for (int i = 0; i < NE; ++i) {
+          const T d = Cn[i * PXY] - c[i];
+          lap[i] = fma(wk, d, lap[i]);
+          if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, d, gC[i][0]);
+          if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, d, gC[i][1]);
+          if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, d, gC[i][2]);
         }
         const T dE = Cn[NE * PXY] - E0;
-        if (ex != 0) gE[0] += (ex > 0) ? wk * dE : -(wk * dE);
-        if (ey != 0) gE[1] += (ey > 0) ? wk * dE : -(wk * dE);
-        if (ez != 0) gE[2] += (ez > 0) ? wk * dE : -(wk * dE);
+        if (ex != 0) gE[0] = fma((ex > 0) ? wk : -wk, dE, gE[0]);
+        if (ey != 0) gE[1] = fma((ey > 0) ? wk : -wk, dE, gE[1]);
+        if (ez != 0) gE[2] = fma((ez > 0) ? wk : -wk, dE, gE[2]);
       }
+    }
+    // the implicit component is 1 - sum of the others, so each of its stencil
+    // differences is minus the sum of theirs
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      lap[NE] -= lap[i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gC[NE][d] -= gC[i][d];
     }
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
@@ -263,16 +482,20 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) gE[d] *= T(3);
 
-    // ---- flux potential mu~ (factored; exact zero for an absent component)
-    T mu[NC];
+    // ---- flux potential mu~ of the evolved components (factored form)
+    T mu[NE];
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
+    for (int i = 0; i < NE; ++i) {
       T br = -(T(1) - T(3) * c[i] + T(2) * c[i] * c[i]);
 #pragma unroll
-      for (int l = 0; l < NC; ++l)
+      for (int l = 0; l < NC; ++l) {
+        if (l == i) continue;
+        T row = T(0);
 #pragma unroll
         for (int m = l + 1; m < NC; ++m)
-          if (l != i && m != i) br += P.psi[i][l][m] * c[l] * c[m];
+          if (m != i) row = fma(P.psi[i][l][m], c[m], row);
+        br = fma(row, c[l], br);
+      }
       T val = P.k34D * lap[i] + P.k12D * c[i] * br;
       if (a.flags & kFlagOmega) {
         T sx = T(0);
@@ -296,7 +519,7 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
       mu[i] = val;
     }
 
-    // ---- surface tension force + body force
+    // ---- surface tension force (Eq. Fsnew, or Eq. ststand) + body force
     T F[3];
     if (a.flags & kFlagPotential) {
       F[0] = F[1] = F[2] = T(0);
@@ -319,21 +542,19 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
         T kl = T(0);
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-          if (j != i) kl += P.kappa[i][j] * lap[j];
+          if (j != i) kl = fma(P.kappa[i][j], lap[j], kl);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) F[d] += kl * gC[i][d];
+        for (int d = 0; d < 3; ++d) F[d] = fma(kl, gC[i][d], F[d]);
       }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) F[d] += P.fb[d];
 
-    // ---- hydrodynamic moments
-    const size_t node = size_t(x) + size_t(a.nx) * (size_t(y) + size_t(a.ny) * size_t(z));
-    const FS* fsrc = static_cast<const FS*>(a.f_src);
-    T f[Q];
-    f[0] = T(0);
-#pragma unroll
-    for (int k = 1; k < Q; ++k) f[k] = S::ld(fsrc, size_t(k - 1) * n + node);
+    // ---- hydrodynamic moments (Eqs. nmom, pres with rho = 1).  f is gathered
+    // only now: loading it before the stencil would keep Q-1 more registers
+    // live through it and cost occupancy.
+    const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
+    load_f(z);
     T v[3] = {T(0), T(0), T(0)};
     T fsum = T(0);
 #pragma unroll
@@ -344,18 +565,10 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
         if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? f[k] : -f[k];
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) v[d] += T(0.5) * F[d];
+    for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
     const T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    T sk[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      T ev = T(0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (L::e[k][d] != 0) ev += (L::e[k][d] > 0) ? v[d] : -v[d];
-      sk[k] = static_cast<T>(L::w[k]) * (T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv);
-    }
-    const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + sk[0]);
+    const T s0 = static_cast<T>(L::w[0]) * (-T(1.5) * vv);
+    const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + s0);
 
     if constexpr (FIELDS) {
       double* out = a.fields;
@@ -388,48 +601,23 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
       }
     }
 
-    // ---- streaming destinations (push), halfway bounce-back at walls
-    int dst[Q];
-    int dir[Q];
-#pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
-      int X = x + ex, Y = y + ey, Z = z + ez;
-      bool wall = false;
-      if (ex != 0) {
-        if (X < 0 || X >= a.nx) {
-          if (a.wall_x) wall = true;
-          else X = (X < 0) ? X + a.nx : X - a.nx;
-        }
-      }
-      if (ey != 0) {
-        if (Y < 0 || Y >= a.ny) {
-          if (a.wall_y) wall = true;
-          else Y = (Y < 0) ? Y + a.ny : Y - a.ny;
-        }
-      }
-      if (ez != 0) {
-        if (Z < 0 || Z >= a.nz) {
-          if (a.wall_z) wall = true;
-          else Z = (Z < 0) ? Z + a.nz : Z - a.nz;
-        }
-      }
-      const int kb = (k & 1) ? k + 1 : k - 1;
-      if (wall) {
-        dst[k] = static_cast<int>(node);
-        dir[k] = kb;
-      } else {
-        dst[k] = X + a.nx * (Y + a.ny * Z);
-        dir[k] = k;
-      }
-    }
-
-    // ---- TRT collision of f with forcing
     FS* fdst = static_cast<FS*>(a.f_dst);
+    FS* gkdst = static_cast<FS*>(a.gk_dst);
+    G0S* g0dst = static_cast<G0S*>(a.g0_dst);
+    const FS* gksrc = static_cast<const FS*>(a.gk_src);
     const T vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
     const T cP = T(3) * Pn;
     const T hp = T(0.5) * (T(1) - T(0.5) * wp);
     const T hm = T(0.5) * (T(1) - T(0.5) * wm);
+    const T base_s = -T(1.5) * vv;
+    T moved[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) moved[i] = T(0);
+    Nbr nb;
+    if (a.flags & kFlagNeedG) nb = neighbours<WALLS, D3>(x, y, z, a);
+
+    // ---- per direction pair: TRT collision of f with forcing and BGK
+    // collision of every evolved g; stores go to this node (pull layout)
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
       const int kb = k + 1;
@@ -441,52 +629,66 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
           ev += (L::e[k][d] > 0) ? v[d] : -v[d];
           eF += (L::e[k][d] > 0) ? F[d] : -F[d];
         }
-      const T feq_k = wk * cP + sk[k];
-      const T feq_b = wk * cP + sk[kb];
-      const T Fk = wk * (T(3) * eF + T(9) * ev * eF - T(3) * vF);
-      const T Fb = wk * (-T(3) * eF + T(9) * ev * eF - T(3) * vF);
+      const T quad = fma(T(4.5) * ev, ev, base_s);
+      const T sk_k = wk * fma(T(3), ev, quad);
+      const T sk_b = wk * fma(-T(3), ev, quad);
+      const T feq_k = fma(wk, cP, sk_k);
+      const T feq_b = fma(wk, cP, sk_b);
+      const T fodd = wk * fma(T(9) * ev, eF, -T(3) * vF);
+      const T Fk = fma(wk * T(3), eF, fodd);
+      const T Fb = fma(-wk * T(3), eF, fodd);
       const T fp = T(0.5) * (f[k] + f[kb]), fm = T(0.5) * (f[k] - f[kb]);
       const T ep = T(0.5) * (feq_k + feq_b), em = T(0.5) * (feq_k - feq_b);
-      const T sym = -wp * (fp - ep) + hp * (Fk + Fb);
-      const T asym = -wm * (fm - em) + hm * (Fk - Fb);
-      const T post_k = f[k] + sym + asym;
-      const T post_b = f[kb] + sym - asym;
-      fdst[size_t(dir[k] - 1) * n + size_t(dst[k])] = S::pack(post_k);
-      fdst[size_t(dir[kb] - 1) * n + size_t(dst[kb])] = S::pack(post_b);
-    }
-
-    // ---- BGK collision of g towards the rest-form equilibrium
-    FS* gkdst = static_cast<FS*>(a.gk_dst);
-    G0S* g0dst = static_cast<G0S*>(a.g0_dst);
-    const FS* gksrc = static_cast<const FS*>(a.gk_src);
-    const G0S* g0src = static_cast<const G0S*>(a.g0_src);
-    (void)g0src;
-#pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const T ci = c[i];
-      const T mm = P.m * mu[i];
-      T moved = T(0);
-#pragma unroll
-      for (int k = 1; k < Q; ++k) {
-        T post = ci * sk[k] - static_cast<T>(L::w[k]) * mm;
-        if (a.flags & kFlagNeedG) {
-          const T gv = S::ld(gksrc, (size_t(i) * (Q - 1) + (k - 1)) * n + node);
-          post = gv - (gv - post) * P.inv_tau_g[i];
-        }
-        const FS q = S::pack(post);
-        moved += S::unpack(q);
-        gkdst[(size_t(i) * (Q - 1) + size_t(dir[k] - 1)) * n + size_t(dst[k])] = q;
+      const T sym = fma(-wp, fp - ep, hp * (Fk + Fb));
+      const T asym = fma(-wm, fm - em, hm * (Fk - Fb));
+      *at(fdst + size_t(k - 1) * n, node) = S::pack(f[k] + sym + asym);
+      *at(fdst + size_t(kb - 1) * n, node) = S::pack(f[kb] + sym - asym);
+      const T mw = wk * P.m;
+      FS qk[NE], qb[NE];
+      FS ok[NE], ob[NE];
+      if (a.flags & kFlagNeedG) {
+        if (pulled_from_wall<L, WALLS>(nb, k))
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * n * NE, node * NE), ok);
+        else
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), ok);
+        if (pulled_from_wall<L, WALLS>(nb, kb))
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * n * NE, node * NE), ob);
+        else
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * n * NE, upstream<L>(nb, kb) * NE), ob);
       }
-      g0dst[size_t(i) * n + node] = static_cast<G0S>(ci - moved);
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const T mmu = mw * mu[i];
+        T gk = fma(c[i], sk_k, -mmu);
+        T gb = fma(c[i], sk_b, -mmu);
+        if (a.flags & kFlagNeedG) {
+          const T o1 = S::unpack(ok[i]), o2 = S::unpack(ob[i]);
+          gk = o1 - (o1 - gk) * P.inv_tau_g[i];
+          gb = o2 - (o2 - gb) * P.inv_tau_g[i];
+        }
+        qk[i] = S::pack(gk);
+        qb[i] = S::pack(gb);
+        moved[i] += S::unpack(qk[i]) + S::unpack(qb[i]);
+      }
+      vst<FS, NE>(at(gkdst + size_t(k - 1) * n * NE, node * NE), qk);
+      vst<FS, NE>(at(gkdst + size_t(kb - 1) * n * NE, node * NE), qb);
     }
+    G0S r0[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) r0[i] = static_cast<G0S>(c[i] - moved[i]);
+    vst<G0S, NE>(at(g0dst, node * NE), r0);
   };
 
-  if constexpr (NPL == 3) {
+  if constexpr (D3) {
+    // rolling window of three LDS planes: z-1, z, z+1
     load_plane(0, z0 - 1);
     load_plane(1, z0);
     for (int z = z0; z < z1; ++z) {
       const int r = z - z0;
       const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
+      // keep the per-plane coefficient loads inside the loop (scalar cache
+      // hits) instead of holding every coefficient live across all planes
+      asm volatile("" ::: "memory");
       load_plane(s_up, z + 1);
       __syncthreads();
       if (active) process(z, s_dn, s_c, s_up);
@@ -500,7 +702,11 @@ __global__ void __launch_bounds__(256) k_update(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ k_init
-template <class L, int NC, int ST>
+// Writes the post-collision arrays so that the first gather yields
+// f_k = f^eq_k(P0, v0) (k >= 1), g_{i,0} = C_i, g_{i,k>=1} = 0: the value a
+// node must receive along e_k is stored where that node will pull it from.
+// Every slot is written exactly once.
+template <class L, int NC, int ST, bool WALLS>
 __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   using S = StoreT<ST>;
   using T = typename S::T;
@@ -513,26 +719,41 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   FS* f = static_cast<FS*>(a.f);
   FS* gk = static_cast<FS*>(a.gk);
   G0S* g0 = static_cast<G0S*>(a.g0);
-  for (size_t node = blockIdx.x * size_t(256) + threadIdx.x; node < n;
-       node += size_t(gridDim.x) * 256) {
-    double v[3] = {0.0, 0.0, 0.0};
-    double Pn = 0.0;
-    if (a.v)
-      for (int d = 0; d < 3; ++d) v[d] = a.v[size_t(d) * n + node];
-    if (a.P) Pn = a.P[node];
-    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z = blockIdx.z;
+  if (x >= a.sa.nx || y >= a.sa.ny) return;
+  const uint32_t node = uint32_t(x) + uint32_t(a.sa.nx) * (uint32_t(y) + uint32_t(a.sa.ny) * uint32_t(z));
+  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a.sa);
+  double v[3] = {0.0, 0.0, 0.0};
+  double Pn = 0.0;
+  if (a.v)
+    for (int d = 0; d < 3; ++d) v[d] = a.v[size_t(d) * n + node];
+  if (a.P) Pn = a.P[node];
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  FS zero[NE];
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      double ev = 0.0;
-      for (int d = 0; d < 3; ++d) ev += L::e[k][d] * v[d];
-      const double s = L::w[k] * (3.0 * ev + 4.5 * ev * ev - 1.5 * vv);
-      f[size_t(k - 1) * n + node] = S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s));
-    }
-    for (int i = 0; i < NE; ++i) {
-      g0[size_t(i) * n + node] = static_cast<G0S>(a.C[size_t(P.uidx[i]) * n + node]);
-      for (int k = 1; k < Q; ++k) gk[(size_t(i) * (Q - 1) + (k - 1)) * n + node] = S::pack(T(0));
+  for (int e = 0; e < NE; ++e) zero[e] = S::pack(T(0));
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    double ev = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ev += L::e[k][d] * v[d];
+    const double s = L::w[k] * (3.0 * ev + 4.5 * ev * ev - 1.5 * vv);
+    const FS val = S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s));
+    if (pulled_from_wall<L, WALLS>(nb, k)) {
+      f[size_t(opposite(k) - 1) * n + node] = val;
+      vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, zero);
+    } else {
+      const uint32_t src = upstream<L>(nb, k);
+      f[size_t(k - 1) * n + src] = val;
+      vst<FS, NE>(gk + (size_t(k - 1) * n + src) * NE, zero);
     }
   }
+  G0S c0[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) c0[i] = static_cast<G0S>(a.C[size_t(P.uidx[i]) * n + node]);
+  vst<G0S, NE>(g0 + size_t(node) * NE, c0);
 }
 
 // ---------------------------------------------------------------- k_reduce
@@ -661,33 +882,6 @@ hipError_t conc_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
 
 #if defined(NFLBM_UNIT_STORE) && NFLBM_UNIT_STORE >= 0
 
-template <class L, int NC, int ST>
-hipError_t launch_update_t(const StepArgs& a, bool fields, hipStream_t s) {
-  const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
-  const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
-  if (fields)
-    hipLaunchKernelGGL((k_update<L, NC, ST, true>), dim3(blocks), dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_update<L, NC, ST, false>), dim3(blocks), dim3(256), lds, s, a);
-  return hipGetLastError();
-}
-
-template <class L, int NC, int ST>
-hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
-  long long blocks = (a.n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL((k_init<L, NC, ST>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int Q, int ST>
-hipError_t launch_conc_t(const StepArgs& a, int ne, hipStream_t s) {
-  long long blocks = (a.n + 255) / 256;
-  if (blocks > (1 << 20)) blocks = 1 << 20;
-  hipLaunchKernelGGL((k_conc<Q, ST>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a, ne);
-  return hipGetLastError();
-}
-
 #define NFLBM_NC_SWITCH(NCV, CALL)        \
   switch (NCV) {                          \
     case 2: return CALL(2);               \
@@ -699,6 +893,62 @@ hipError_t launch_conc_t(const StepArgs& a, int ne, hipStream_t s) {
     case 8: return CALL(8);               \
     default: return hipErrorInvalidValue; \
   }
+
+inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z; }
+
+template <class L, int NC, int ST>
+hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
+  const auto* P = static_cast<const DevParams<TT<ST>>*>(a0.params);
+  if (fields) {
+    // diagnostics only: one variant (16-wide tiles, walls handled at run time)
+    StepArgs a = a0;
+    a.tx_log2 = 4;
+    a.tiles_x = (a.nx + 15) / 16;
+    a.tiles_y = (a.ny + 15) / 16;
+    const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
+    const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, 4);
+    hipLaunchKernelGGL((k_update<L, NC, ST, true, true, 4>), dim3(blocks), dim3(256), lds, s, a, P);
+    return hipGetLastError();
+  }
+  const StepArgs& a = a0;
+  const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
+  const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
+  const bool w = any_wall(a);
+  if (a.tx_log2 == 6) {
+    if (w) hipLaunchKernelGGL((k_update<L, NC, ST, false, true, 6>), dim3(blocks), dim3(256), lds, s, a, P);
+    else hipLaunchKernelGGL((k_update<L, NC, ST, false, false, 6>), dim3(blocks), dim3(256), lds, s, a, P);
+  } else if (a.tx_log2 == 4) {
+    if (w) hipLaunchKernelGGL((k_update<L, NC, ST, false, true, 4>), dim3(blocks), dim3(256), lds, s, a, P);
+    else hipLaunchKernelGGL((k_update<L, NC, ST, false, false, 4>), dim3(blocks), dim3(256), lds, s, a, P);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class L, int NC, int ST>
+hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
+  const dim3 grid((a.sa.nx + 63) / 64, (a.sa.ny + 3) / 4, a.sa.nz);
+  if (any_wall(a.sa)) hipLaunchKernelGGL((k_init<L, NC, ST, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_init<L, NC, ST, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class L, int NC, int ST>
+hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
+  const int blocks = a.tiles_x * a.tiles_y * a.nz;
+  const auto* P = static_cast<const DevParams<TT<ST>>*>(a.params);
+  if (any_wall(a)) hipLaunchKernelGGL((k_conc<L, NC - 1, ST, true>), dim3(blocks), dim3(256), 0, s, a, P);
+  else hipLaunchKernelGGL((k_conc<L, NC - 1, ST, false>), dim3(blocks), dim3(256), 0, s, a, P);
+  return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t conc_nc(int nc, const StepArgs& a, hipStream_t s) {
+#define CALL_C(K) launch_conc_t<L, K, ST>(a, s)
+  NFLBM_NC_SWITCH(nc, CALL_C)
+#undef CALL_C
+}
 
 template <class L, int ST>
 hipError_t update_nc(int nc, const StepArgs& a, bool fields, hipStream_t s) {
@@ -725,7 +975,7 @@ hipError_t NFLBM_CAT(init_st, NFLBM_ST)(int lat, int nc, const InitArgs& a, hipS
   return lat == 0 ? init_nc<D2Q9, NFLBM_ST>(nc, a, s) : init_nc<D3Q19, NFLBM_ST>(nc, a, s);
 }
 hipError_t NFLBM_CAT(conc_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
-  return lat == 0 ? launch_conc_t<9, NFLBM_ST>(a, nc - 1, s) : launch_conc_t<19, NFLBM_ST>(a, nc - 1, s);
+  return lat == 0 ? conc_nc<D2Q9, NFLBM_ST>(nc, a, s) : conc_nc<D3Q19, NFLBM_ST>(nc, a, s);
 }
 
 #else  // common unit
