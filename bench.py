@@ -15,6 +15,7 @@ kernel runs on), against the 8 TB/s HBM3E peak.  cpu_baseline: the FP64 NumPy
 oracle on a 64^3 sample of the same recipe.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -47,6 +48,25 @@ def conc_bytes_per_node(N, fs, g0s, ts):
 
 SIZES = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "fp16s": (2, 4, 4)}
 
+# HBM bytes per node of one update launch at 256^3, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE (each scaled by what the counter reads for a 1 GiB device copy:
+# x2.0 and x1.0), keyed by the SHA-256 of the kernel sources they were taken on.
+# The committed summary under profiles/ gives the commands and the raw figures.
+TRAFFIC = {
+    "sources_sha256": "2d5dbdf1c73613d9f4b2c4958aaf8585c500cdbbc49b6974853ca4ce653e2cb2",
+    "n": 256,
+    "update_bytes_per_node": {"fp32": 490.7, "fp16s": 257.8, "fp64": 942.7},
+}
+KERNEL_SOURCES = ("paper_2605_22214_amd/csrc/kernels.hip", "paper_2605_22214_amd/csrc/internal.h")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def run_form(nf, w, form, steps, warmup, timing_steps):
     import torch
@@ -63,7 +83,6 @@ def run_form(nf, w, form, steps, warmup, timing_steps):
     # separate pass: events around every update launch (same stream)
     _, ms_upd = sim.step_timed(timing_steps, per_update=True)
     d1 = sim.diagnostics(vcm_component=0)
-    C = None
     n = w["C0"][0].size
     mlups = n * steps / wall / 1e6
     fs, g0s, ts = SIZES[form]
@@ -87,11 +106,10 @@ def run_form(nf, w, form, steps, warmup, timing_steps):
     }
     out["step_frac_of_peak"] = out["step_gbs"] / HBM_PEAK_GBS
     sim.close()
-    del C
     return out
 
 
-def cpu_baseline(sample_n=64, steps=10):
+def cpu_baseline(sample_n=64, steps=60):
     """The FP64 oracle (not tuned) on a sample_n^3 lattice of the same recipe."""
     import workloads as W
     from oracle import step as S
@@ -119,7 +137,19 @@ def main():
     ap.add_argument("--forms", default="fp32,fp16s,fp64")
     ap.add_argument("--timing-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB, 3 times (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * (1 << 28)}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this workload runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU domain decomposition is not part of this build)", file=sys.stderr)
@@ -140,8 +170,13 @@ def main():
         print(f"bench: {form} {results[form]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
     main_form = forms[0]
     r = results[main_form]
+    traffic = None
+    if (kernel_sources_sha256() == TRAFFIC["sources_sha256"] and args.n == TRAFFIC["n"]
+            and main_form in TRAFFIC["update_bytes_per_node"]):
+        traffic = TRAFFIC["update_bytes_per_node"][main_form] * args.n ** 3
     roof = {"bound": "hbm", "achieved": r["update_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r["update_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "frac": r["update_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
             "kernel": "k_update", "bytes_per_node": r["update_bytes_per_node"],
             "mean_launch_ms": r["update_ms"]}
     cpu = None

@@ -272,13 +272,14 @@ k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
   const G0S* g0 = static_cast<const G0S*>(a.g0_src);
   const FS* gk = static_cast<const FS*>(a.gk_src);
+  // The small moving populations are summed first and the O(1) rest
+  // population added last: one rounding at the scale of C per node.  Adding
+  // them one by one onto the rest population would round every addition at
+  // that scale, with errors that are alike at neighbouring nodes of a smooth
+  // field and accumulate into a drift of the total mass in float storage.
   T s[NE];
-  {
-    G0S r[NE];
-    vld<G0S, NE>(at(g0, node * NE), r);
 #pragma unroll
-    for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]);
-  }
+  for (int e = 0; e < NE; ++e) s[e] = T(0);
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
     FS v[NE];
@@ -288,6 +289,12 @@ k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
       vld<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
 #pragma unroll
     for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+  }
+  {
+    G0S r[NE];
+    vld<G0S, NE>(at(g0, node * NE), r);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]) + s[e];
   }
   vst<T, NE>(at(static_cast<T*>(a.conc), node * NE), s);
   T c[NC];

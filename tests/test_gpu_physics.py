@@ -1,0 +1,163 @@
+"""Results of the HIP path in each storage precision against the paper's
+closed forms and against FP64.
+
+* Liquid lens (64 x 64, N = 3, equal tensions, 5000 steps): FP64 matches the
+  oracle after 5000 steps; the lens angle is 120 degrees in theory
+  (Eq. neucosine); FP32 and FP16S are stated against FP64.
+* Laplace pressure of a 2-D drop (Delta P = sigma / R) at R = 12 and R = 24,
+  40000 steps: the drop rings for several thousand steps before it settles.
+  The diffuse-interface excess over sigma / R falls as R grows.
+* Layered Poiseuille (16 x 16 x 192, six layers, TRT Lambda = 3/16, halfway
+  bounce-back, 50000 steps from the analytic profile): L2 of the x-y averaged
+  u_x(z) against Eq. velocityprof (physical sign).  In float storage the
+  momentum a step adds at a node (F = 1e-7) is about 1e-4 of the populations
+  it is added to (|f_k| ~ 6e-4), so the rounding of every stored population
+  acts as a spurious force of ~1e-3 F: float storage moves the profile by
+  ~6e-4 relative to FP64, ten times the FP64 discretisation error.
+* Conservation in float storage: per-component mass and global momentum.
+
+Measured values are written to gpurun_out/physics.json.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+import workloads as W
+from oracle import analysis as A
+from oracle import step as S
+from oracle.lattice import D2Q9
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RESULTS = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def record():
+    yield
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "physics.json"), "w") as fh:
+        json.dump(RESULTS, fh, indent=1, sort_keys=True)
+
+
+FORMS = (("fp64", nf.FP64), ("fp32", nf.FP32), ("fp16s", nf.FP16S))
+
+
+def test_lens_angle_all_precisions():
+    w = W.lens_2d()
+    steps = 5000
+    par = S.Params(D2Q9, w["shape"], w["sigma"], w["tau"], m=w["m"])
+    f, g = S.initial_state(par, w["C0"])
+    for _ in range(steps):
+        f, g, _ = S.step(f, g, par)
+    Co = S.concentrations(g, par)[:, 0]
+    ang = {"oracle": A.lens_angles(Co[2], w["y_interface"])}
+    C64 = None
+    for name, prec in FORMS:
+        sim = nf.Simulation.from_workload(w, precision=prec)
+        sim.set_fields(w["C0"])
+        sim.step(steps)
+        C = sim.get_field("C")[:, 0]
+        if prec == nf.FP64:
+            C64 = C
+            assert np.abs(C - Co).max() < 1e-12 * np.abs(Co).max()
+        ang[name] = A.lens_angles(C[2], w["y_interface"])
+        ang[name]["max_abs_dC_vs_fp64"] = float(np.abs(C - C64).max())
+        sim.close()
+    RESULTS["lens"] = {k: {q: (v[q] if not isinstance(v[q], tuple) else list(v[q]))
+                           for q in v} for k, v in ang.items()}
+    assert abs(ang["fp64"]["lens"] - 120.0) < 3.0
+    assert abs(ang["fp64"]["lens"] - ang["oracle"]["lens"]) < 1e-6
+    assert abs(ang["fp32"]["lens"] - ang["fp64"]["lens"]) < 0.05
+    assert abs(ang["fp16s"]["lens"] - ang["fp64"]["lens"]) < 1.5
+
+
+def test_laplace_pressure_all_precisions():
+    sig = 0.005
+    steps = 40000
+    out = {}
+    for side, radius in ((48, 12.0), (96, 24.0)):
+        w = W.droplet_2d(side, side, radius=radius, sigma12=sig, m=0.05)
+        res = {}
+        for name, prec in FORMS:
+            sim = nf.Simulation.from_workload(w, precision=prec)
+            sim.set_fields(w["C0"])
+            sim.step(steps)
+            P = sim.get_field("P")[0]
+            C = sim.get_field("C")[:, 0]
+            R = math.sqrt(C[1].sum() / math.pi)
+            c = side // 2
+            dP = P[c, c] - P[2, 2]
+            res[name] = {"dP": dP, "R": R, "sigma_over_R": sig / R,
+                         "rel_err_vs_laplace": dP / (sig / R) - 1.0}
+            sim.close()
+        for name in ("fp32", "fp16s"):
+            res[name]["rel_diff_vs_fp64"] = res[name]["dP"] / res["fp64"]["dP"] - 1.0
+        out[f"R{int(radius)}"] = res
+    RESULTS["laplace"] = out
+    e12 = out["R12"]["fp64"]["rel_err_vs_laplace"]
+    e24 = out["R24"]["fp64"]["rel_err_vs_laplace"]
+    assert abs(e24) < 0.05
+    assert abs(e24) < abs(e12)
+    for r in ("R12", "R24"):
+        assert abs(out[r]["fp32"]["rel_diff_vs_fp64"]) < 1e-3
+        assert abs(out[r]["fp16s"]["rel_diff_vs_fp64"]) < 5e-2
+
+
+def test_layered_poiseuille_all_precisions():
+    nz, F = 192, 1e-7
+    eta = (np.linspace(0.6, 1.5, 6) - 0.5) / 3.0
+    z = np.arange(nz) + 0.5
+    prof = A.layered_profile(z, [32.0 * q for q in range(7)], eta, F)
+    w = W.layered_3d(16, 16, nz, v0_profile=prof)
+    steps = 50000
+    out = {}
+    u64 = None
+    for name, prec in FORMS:
+        sim = nf.Simulation.from_workload(w, precision=prec)
+        sim.set_fields(w["C0"], w["v0"])
+        sim.step(steps)
+        V = sim.get_field("V")
+        u = V[0].mean(axis=(1, 2))
+        if prec == nf.FP64:
+            u64 = u
+        out[name] = {"L2_vs_analytic": float(np.linalg.norm(u - prof) / np.linalg.norm(prof)),
+                     "L2_vs_fp64": float(np.linalg.norm(u - u64) / np.linalg.norm(u64)),
+                     "u_max": float(u.max()), "u_max_analytic": float(prof.max()),
+                     "max_abs_uz": float(np.abs(V[2]).max())}
+        sim.close()
+    RESULTS["poiseuille"] = out
+    assert out["fp64"]["L2_vs_analytic"] < 1e-2
+    assert out["fp32"]["L2_vs_fp64"] < 2e-3
+    assert out["fp16s"]["L2_vs_fp64"] < 2e-3
+
+
+@pytest.mark.parametrize("name,prec", FORMS)
+def test_mass_and_momentum_conservation(name, prec):
+    """Quaternary phase separation with an absent fifth component, 48^3 periodic,
+    2000 steps: per-component mass and total momentum."""
+    w = W.quaternary_3d(48)
+    sim = nf.Simulation.from_workload(w, precision=prec, implicit=0)
+    sim.set_fields(w["C0"])
+    d0 = sim.diagnostics()
+    sim.step(2000)
+    d1 = sim.diagnostics()
+    rel = [abs(b - a) / a for a, b in zip(d0["mass"][1:4], d1["mass"][1:4])]
+    mom = max(abs(v) for v in d1["momentum"])
+    RESULTS.setdefault("conservation", {})[name] = {
+        "max_rel_mass_drift_2000_steps": max(rel), "max_abs_momentum": mom,
+        "absent_max_abs": d1["max_abs_c"][4], "max_sum_dev": d1["max_sum_dev"]}
+    sim.close()
+    assert d1["max_abs_c"][4] == 0.0
+    if prec == nf.FP64:
+        assert max(rel) < 1e-13
+        assert mom < 1e-12
+    else:
+        assert max(rel) < 1e-6
+        assert mom < 1e-4
