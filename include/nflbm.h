@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 1
+#define NFLBM_ABI_VERSION 2
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -219,6 +219,74 @@ int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
  * kernels together, counting every stored population once read and once
  * written plus the reconstructed concentrations (written once, read once). */
 int nflbm_bytes_per_node(nflbm_sim *sim, double *bytes);
+
+/* Launch-shape autotuner: times every shape nflbm_set_launch accepts (tile
+ * width 16 or 64; in D3Q19 z runs of 1, 2, 4, ... planes and the whole
+ * height) for a few steps each and keeps the fastest.  The halo is one node
+ * wide in every shape: the stencils (Eq. gradstencil) reach nearest
+ * neighbours only.  The state is copied on the device before the trials and
+ * restored afterwards, so results are unchanged.  cache_path (may be NULL)
+ * names a text file of earlier choices, one "<key>|<values>" line each, keyed
+ * by lattice, N, precision, shape, walls, options and device; a cached
+ * choice is applied without timing, a new one is appended.  Synchronises. */
+int nflbm_autotune(nflbm_sim *sim, const char *cache_path);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent simulations (each a full problem statement of
+ * Secs. II-III with its own size, walls, tensions, relaxation times and
+ * mobility) that share lattice, ncomp and precision, advanced together.
+ * Every time step of the whole batch is two kernel launches whose workgroups
+ * cover the tiles of all members; NFLBM_BATCH_GRAPH replays runs of
+ * graph_steps such steps from a captured HIP graph.  Each member is an
+ * nflbm_sim owned by the batch: nflbm_batch_member returns it for set_fields,
+ * get_field, diagnostics, state I/O or stepping on its own (never
+ * nflbm_destroy it).  All members run on the batch's stream.
+ * ---------------------------------------------------------------------- */
+typedef struct nflbm_batch nflbm_batch; /* opaque */
+
+/* Stepping modes. */
+enum {
+  NFLBM_BATCH_LAUNCH = 0,  /* two launches per step for the whole batch          */
+  NFLBM_BATCH_GRAPH = 1,   /* the same launches replayed from a HIP graph         */
+  NFLBM_BATCH_PER_SIM = 2  /* each member's own launch sequence, one after another
+                              (the reference point the batch is measured against) */
+};
+
+/* Create count members from cfgs[0..count) (copied).  EINVAL if count < 1 or
+ * the members differ in lattice, ncomp or precision; any error of
+ * nflbm_create, prefixed with the member index.  Members start at rest with
+ * C_1 = 1, as from nflbm_create.  *out receives the handle. */
+int nflbm_batch_create(const nflbm_config *cfgs, int count, nflbm_batch **out);
+/* Release the batch and all its members (NULL is ignored). */
+void nflbm_batch_destroy(nflbm_batch *b);
+/* Number of members (0 for NULL). */
+int nflbm_batch_count(const nflbm_batch *b);
+/* Borrowed handle of member idx, or NULL (with an error on b) if out of range. */
+nflbm_sim *nflbm_batch_member(nflbm_batch *b, int idx);
+/* Run the batch and its members on this hipStream_t; NULL returns to the
+ * batch's own stream (the legacy default stream cannot be captured). */
+int nflbm_batch_set_stream(nflbm_batch *b, void *hip_stream);
+/* nflbm_set_fields / nflbm_get_field of member idx. */
+int nflbm_batch_set_fields(nflbm_batch *b, int idx, const double *C, const double *v, const double *P);
+int nflbm_batch_get_field(nflbm_batch *b, int idx, int field, double *host_out);
+/* Advance every member nsteps time steps in mode NFLBM_BATCH_*.  The result
+ * is bit-for-bit that of stepping each member alone.  Asynchronous. */
+int nflbm_batch_step(nflbm_batch *b, long long nsteps, int mode);
+/* As nflbm_batch_step, returning in *ms the device time between HIP events
+ * recorded on the batch stream before and after.  Synchronises. */
+int nflbm_batch_step_timed(nflbm_batch *b, long long nsteps, int mode, double *ms);
+/* Tile width 2^tx_log2 (4 or 6) used for every member in the batch launches,
+ * and steps per captured graph (even, >= 2); values <= 0 keep the current
+ * setting.  Discards captured graphs when the shape changes.  Synchronises. */
+int nflbm_batch_set_launch(nflbm_batch *b, int tx_log2, int graph_steps);
+int nflbm_batch_get_launch(nflbm_batch *b, int *tx_log2, int *graph_steps, int *blocks_update);
+/* Total lattice nodes over all members. */
+int nflbm_batch_nodes(const nflbm_batch *b, long long *nodes);
+/* Autotuner of the batch tile width (graph mode), as nflbm_autotune; the cache
+ * key adds the member count, node total and a hash of the member shapes. */
+int nflbm_batch_autotune(nflbm_batch *b, const char *cache_path);
+/* Message of the last error on b (of the calling thread if b is NULL). */
+const char *nflbm_batch_last_error(const nflbm_batch *b);
 
 /* Message of the last error on sim (or of the calling thread if sim is NULL).
  * The pointer stays valid until the next call on the same sim / thread. */

@@ -24,6 +24,7 @@ FLAG_POTENTIAL_FORCE = 1
 FLAG_ALLOW_UNSTABLE = 2
 FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+BATCH_MODES = {"launch": 0, "graph": 1, "per_sim": 2}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESINGULAR", -3: "EUNSTABLE", -4: "ENOMEM",
           -5: "EDEVICE", -6: "ENUMERIC", -7: "ENOTSUP"}
 
@@ -98,6 +99,21 @@ def lib():
             "nflbm_get_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_last_error": (ctypes.c_char_p, [P]),
             "nflbm_abi_version": (I, []),
+            "nflbm_autotune": (I, [P, ctypes.c_char_p]),
+            "nflbm_batch_create": (I, [ctypes.POINTER(Config), I, ctypes.POINTER(P)]),
+            "nflbm_batch_destroy": (None, [P]),
+            "nflbm_batch_count": (I, [P]),
+            "nflbm_batch_member": (P, [P, I]),
+            "nflbm_batch_set_stream": (I, [P, P]),
+            "nflbm_batch_set_fields": (I, [P, I, DP, DP, DP]),
+            "nflbm_batch_get_field": (I, [P, I, I, DP]),
+            "nflbm_batch_step": (I, [P, LL, I]),
+            "nflbm_batch_step_timed": (I, [P, LL, I, DP]),
+            "nflbm_batch_set_launch": (I, [P, I, I]),
+            "nflbm_batch_get_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+            "nflbm_batch_nodes": (I, [P, ctypes.POINTER(LL)]),
+            "nflbm_batch_autotune": (I, [P, ctypes.c_char_p]),
+            "nflbm_batch_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -125,6 +141,57 @@ def _check(code, handle=None):
         raise NflbmError(code, msg.decode() if msg else "")
 
 
+def _bcheck(code, handle=None):
+    if code != 0:
+        msg = lib().nflbm_batch_last_error(handle)
+        raise NflbmError(code, msg.decode() if msg else "")
+
+
+class _Problem:
+    """An nflbm_config together with the arrays it points into."""
+
+    def __init__(self, lattice, shape, sigma, tau, *, walls=(False, False, False),
+                 implicit=-1, D=4.0, omega_stab=0.0, trt_magic=0.0, tau_g=None, m=0.02,
+                 body_force=(0.0, 0.0, 0.0), precision=FP64, flags=0):
+        self.lattice = {"D2Q9": D2Q9, "D3Q19": D3Q19}.get(lattice, lattice)
+        self.Q = 9 if self.lattice == D2Q9 else 19
+        self.shape = tuple(int(s) for s in shape)
+        nx, ny, nz = self.shape
+        self.n = nx * ny * nz
+        self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        self.N = self.sigma.shape[0]
+        self.tau = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, float), (self.N,)))
+        self.tau_g = None if tau_g is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(tau_g, float), (self.N,)))
+        self.precision = PRECISIONS.get(precision, precision)
+        cfg = Config()
+        cfg.lattice = self.lattice
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        for a in range(3):
+            cfg.wall[a] = int(bool(walls[a]))
+        cfg.ncomp = self.N
+        cfg.implicit_comp = -1 if implicit is None else int(implicit)
+        cfg.sigma = _dptr(self.sigma)
+        cfg.width_D = float(D)
+        cfg.omega_stab = float(omega_stab)
+        cfg.tau = _dptr(self.tau)
+        cfg.trt_magic = float(trt_magic)
+        cfg.tau_g = _dptr(self.tau_g) if self.tau_g is not None else None
+        cfg.m = float(m)
+        for a in range(3):
+            cfg.body_force[a] = float(body_force[a])
+        cfg.precision = int(self.precision)
+        cfg.flags = int(flags)
+        self.cfg = cfg
+
+    @classmethod
+    def from_workload(cls, w, precision=FP64, implicit=-1, flags=0):
+        return cls(w["lattice"], w["shape"], w["sigma"], w["tau"], walls=w["walls"],
+                   implicit=implicit, D=w["D"], omega_stab=w["omega_stab"],
+                   trt_magic=w["trt_magic"], tau_g=w["tau_g"], m=w["m"],
+                   body_force=w["body_force"], precision=precision, flags=flags)
+
+
 def coefficients(sigma, D=4.0):
     """Host-side coefficient tables computed by the library (no GPU needed)."""
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -142,42 +209,26 @@ def coefficients(sigma, D=4.0):
 class Simulation:
     """One lattice on the current HIP device (see include/nflbm.h)."""
 
-    def __init__(self, lattice, shape, sigma, tau, *, walls=(False, False, False),
-                 implicit=-1, D=4.0, omega_stab=0.0, trt_magic=0.0, tau_g=None, m=0.02,
-                 body_force=(0.0, 0.0, 0.0), precision=FP64, flags=0):
-        L = lib()
-        self.lattice = {"D2Q9": D2Q9, "D3Q19": D3Q19}.get(lattice, lattice)
-        self.Q = 9 if self.lattice == D2Q9 else 19
-        self.shape = tuple(int(s) for s in shape)
-        nx, ny, nz = self.shape
-        self.n = nx * ny * nz
-        self._sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-        self.N = self._sigma.shape[0]
-        self._tau = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, float), (self.N,)))
-        self._tau_g = None if tau_g is None else np.ascontiguousarray(
-            np.broadcast_to(np.asarray(tau_g, float), (self.N,)))
-        self.precision = PRECISIONS.get(precision, precision)
-        cfg = Config()
-        cfg.lattice = self.lattice
-        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
-        for a in range(3):
-            cfg.wall[a] = int(bool(walls[a]))
-        cfg.ncomp = self.N
-        cfg.implicit_comp = -1 if implicit is None else int(implicit)
-        cfg.sigma = _dptr(self._sigma)
-        cfg.width_D = float(D)
-        cfg.omega_stab = float(omega_stab)
-        cfg.tau = _dptr(self._tau)
-        cfg.trt_magic = float(trt_magic)
-        cfg.tau_g = _dptr(self._tau_g) if self._tau_g is not None else None
-        cfg.m = float(m)
-        for a in range(3):
-            cfg.body_force[a] = float(body_force[a])
-        cfg.precision = int(self.precision)
-        cfg.flags = int(flags)
+    def __init__(self, lattice, shape, sigma, tau, **kw):
+        self._adopt(_Problem(lattice, shape, sigma, tau, **kw))
         h = ctypes.c_void_p()
-        _check(L.nflbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        _check(lib().nflbm_create(ctypes.byref(self._prob.cfg), ctypes.byref(h)))
         self._h = h
+        self._owned = True
+
+    def _adopt(self, prob):
+        self._prob = prob
+        self.lattice, self.Q, self.shape, self.n = prob.lattice, prob.Q, prob.shape, prob.n
+        self.N, self.precision = prob.N, prob.precision
+
+    @classmethod
+    def _borrowed(cls, handle, prob):
+        """A member of a Batch: the batch owns (and frees) the handle."""
+        self = cls.__new__(cls)
+        self._adopt(prob)
+        self._h = ctypes.c_void_p(handle)
+        self._owned = False
+        return self
 
     @classmethod
     def from_workload(cls, w, precision=FP64, implicit=-1, flags=0):
@@ -272,9 +323,98 @@ class Simulation:
         _check(lib().nflbm_bytes_per_node(self._handle(), ctypes.byref(b)), self._h)
         return b.value
 
+    def autotune(self, cache_path=None):
+        """Time the launch shapes and keep the fastest (state unchanged)."""
+        _check(lib().nflbm_autotune(self._handle(), None if cache_path is None
+                                    else os.fsencode(cache_path)), self._h)
+        return self.get_launch()
+
     def close(self):
         if getattr(self, "_h", None) is not None:
-            lib().nflbm_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().nflbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Independent simulations of one lattice, N and precision advanced
+    together (see include/nflbm.h).  members: _Problem-style keyword dicts
+    (``lattice, shape, sigma, tau`` plus the Simulation keywords) or workload
+    dicts with ``from_workloads``."""
+
+    def __init__(self, problems):
+        probs = [p if isinstance(p, _Problem) else _Problem(**p) for p in problems]
+        if not probs:
+            raise ValueError("a batch needs at least one member")
+        arr = (Config * len(probs))(*[p.cfg for p in probs])
+        h = ctypes.c_void_p()
+        _bcheck(lib().nflbm_batch_create(arr, len(probs), ctypes.byref(h)))
+        self._h = h
+        self._probs = probs
+        self.members = [Simulation._borrowed(lib().nflbm_batch_member(h, i), p)
+                        for i, p in enumerate(probs)]
+
+    @classmethod
+    def from_workloads(cls, ws, precision=FP64, implicit=-1, flags=0):
+        return cls([_Problem.from_workload(w, precision=precision, implicit=implicit, flags=flags)
+                    for w in ws])
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("batch already closed")
+        return self._h
+
+    def __len__(self):
+        return len(self.members)
+
+    def nodes(self):
+        n = ctypes.c_longlong()
+        _bcheck(lib().nflbm_batch_nodes(self._handle(), ctypes.byref(n)), self._h)
+        return n.value
+
+    def set_stream(self, stream_ptr):
+        _bcheck(lib().nflbm_batch_set_stream(self._handle(), ctypes.c_void_p(stream_ptr)), self._h)
+
+    def step(self, nsteps=1, mode="graph"):
+        _bcheck(lib().nflbm_batch_step(self._handle(), int(nsteps), BATCH_MODES[mode]), self._h)
+
+    def step_timed(self, nsteps, mode="graph"):
+        ms = ctypes.c_double()
+        _bcheck(lib().nflbm_batch_step_timed(self._handle(), int(nsteps), BATCH_MODES[mode],
+                                             ctypes.byref(ms)), self._h)
+        return ms.value
+
+    def set_launch(self, tx_log2=0, graph_steps=0):
+        _bcheck(lib().nflbm_batch_set_launch(self._handle(), int(tx_log2), int(graph_steps)), self._h)
+
+    def get_launch(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _bcheck(lib().nflbm_batch_get_launch(self._handle(), ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.byref(c)), self._h)
+        return a.value, b.value, c.value
+
+    def autotune(self, cache_path=None):
+        _bcheck(lib().nflbm_batch_autotune(self._handle(), None if cache_path is None
+                                           else os.fsencode(cache_path)), self._h)
+        return self.get_launch()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            for m in self.members:
+                m._h = None
+            lib().nflbm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

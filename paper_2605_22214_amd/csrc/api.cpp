@@ -3,9 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -55,6 +59,29 @@ struct nflbm_sim {
   int tx_log2 = 6, zchunk = 1, tiles_x = 1, tiles_y = 1, chunks_z = 1;
   size_t lds_max = 65536;
   int step_flags = 0;
+  std::string err;
+};
+
+struct nflbm_batch {
+  std::vector<nflbm_sim*> members;
+  int lat = 0, N = 0, store = 0;
+  int walls = 0;
+  long long nodes = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  // launch shape shared by all members
+  int tx_log2 = 6;
+  int graph_steps = 32;
+  // device: step arguments for the two parities [2][count], coefficient
+  // tables [count], work lists
+  StepArgs* args = nullptr;
+  void* params = nullptr;
+  int2* work_conc = nullptr;
+  int2* work_update = nullptr;
+  int blocks_conc = 0, blocks_update = 0;
+  std::vector<int> key;     // member parities that args[0..count) was built for
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::string err;
 };
 
@@ -229,6 +256,276 @@ int compute_fields(nflbm_sim* s) {
   HIPCHK(s, launch_conc(s->lat, s->N, s->store, a, s->stream));
   HIPCHK(s, launch_update(s->lat, s->N, s->store, a, true, s->stream));
   return NFLBM_OK;
+}
+
+
+// ------------------------------------------------------------ batches
+int bfail(nflbm_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  else g_thread_error = msg;
+  return code;
+}
+
+#define BHIPCHK(b, call)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return bfail(b, NFLBM_EDEVICE, std::string(#call) + ": " + \
+                                       hipGetErrorString(e_));                        \
+  } while (0)
+
+// Step arguments of member m under the batch launch shape, reading from
+// population set src.
+StepArgs batch_args(const nflbm_batch* b, const nflbm_sim* m, int src) {
+  StepArgs a = make_args(m, src);
+  const int TX = 1 << b->tx_log2, TY = 256 >> b->tx_log2;
+  a.tx_log2 = b->tx_log2;
+  a.tiles_x = (m->nx + TX - 1) / TX;
+  a.tiles_y = (m->ny + TY - 1) / TY;
+  return a;
+}
+
+void destroy_graphs(nflbm_batch* b) {
+  for (int h = 0; h < 2; ++h) {
+    if (b->exec[h]) (void)hipGraphExecDestroy(b->exec[h]);
+    if (b->graph[h]) (void)hipGraphDestroy(b->graph[h]);
+    b->exec[h] = nullptr;
+    b->graph[h] = nullptr;
+  }
+}
+
+void free_batch_tables(nflbm_batch* b) {
+  if (b->args) (void)hipFree(b->args);
+  if (b->work_conc) (void)hipFree(b->work_conc);
+  if (b->work_update) (void)hipFree(b->work_update);
+  b->args = nullptr;
+  b->work_conc = b->work_update = nullptr;
+}
+
+// (Re)build the work lists and the step arguments of both parities for the
+// members' current population sets.  Graph nodes keep pointing at the same
+// buffers, so a captured graph stays valid as long as the lists keep their
+// sizes; a new launch shape discards the graphs.
+int build_batch_tables(nflbm_batch* b, bool new_shape) {
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  const int count = static_cast<int>(b->members.size());
+  std::vector<int2> wc, wu;
+  std::vector<StepArgs> args(2 * size_t(count));
+  b->key.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    const nflbm_sim* m = b->members[i];
+    b->key[i] = m->cur;
+    args[i] = batch_args(b, m, m->cur);
+    args[count + i] = batch_args(b, m, m->cur ^ 1);
+    const StepArgs& a = args[i];
+    const long long nc = 1LL * a.tiles_x * a.tiles_y * m->nz;
+    const long long nu = 1LL * a.tiles_x * a.tiles_y * a.chunks_z;
+    if (static_cast<long long>(wc.size()) + nc > 0x7fffffffLL || static_cast<long long>(wu.size()) + nu > 0x7fffffffLL)
+      return bfail(b, NFLBM_ENOTSUP, "batch too large: more than 2^31-1 workgroups per launch");
+    for (long long t = 0; t < nc; ++t) wc.push_back(make_int2(i, static_cast<int>(t)));
+    for (long long t = 0; t < nu; ++t) wu.push_back(make_int2(i, static_cast<int>(t)));
+  }
+  if (new_shape || !b->args || static_cast<int>(wc.size()) != b->blocks_conc ||
+      static_cast<int>(wu.size()) != b->blocks_update) {
+    destroy_graphs(b);
+    free_batch_tables(b);
+    bool ok = hipMalloc(reinterpret_cast<void**>(&b->args), args.size() * sizeof(StepArgs)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b->work_conc), wc.size() * sizeof(int2)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b->work_update), wu.size() * sizeof(int2)) == hipSuccess;
+    if (!ok) {
+      free_batch_tables(b);
+      return bfail(b, NFLBM_ENOMEM, "cannot allocate the batch work lists");
+    }
+    b->blocks_conc = static_cast<int>(wc.size());
+    b->blocks_update = static_cast<int>(wu.size());
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->args, args.data(), args.size() * sizeof(StepArgs), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->work_conc, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->work_update, wu.data(), wu.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return NFLBM_OK;
+}
+
+// Which half of the argument table matches the members' current population
+// sets (0 or 1); rebuilds the tables if some member was stepped on its own.
+int batch_half(nflbm_batch* b, int* half) {
+  const int count = static_cast<int>(b->members.size());
+  bool same = true, flipped = true;
+  for (int i = 0; i < count; ++i) {
+    same = same && b->members[i]->cur == b->key[i];
+    flipped = flipped && b->members[i]->cur != b->key[i];
+  }
+  if (same) { *half = 0; return NFLBM_OK; }
+  if (flipped) { *half = 1; return NFLBM_OK; }
+  *half = 0;
+  return build_batch_tables(b, false);
+}
+
+hipError_t launch_half(nflbm_batch* b, int half) {
+  BatchLaunch bl{};
+  bl.args = b->args + size_t(half) * b->members.size();
+  bl.params = b->params;
+  bl.work_conc = b->work_conc;
+  bl.work_update = b->work_update;
+  bl.blocks_conc = b->blocks_conc;
+  bl.blocks_update = b->blocks_update;
+  bl.tx_log2 = b->tx_log2;
+  bl.walls = b->walls;
+  return launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+}
+
+// Capture graph_steps time steps of the whole batch, starting from argument
+// half `half`, into an executable graph.
+int capture_graph(nflbm_batch* b, int half) {
+  hipGraph_t g = nullptr;
+  BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < b->graph_steps && e == hipSuccess; ++t) e = launch_half(b, (half + t) & 1);
+  const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bfail(b, NFLBM_EDEVICE, std::string("graph capture failed: ") +
+                                       hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return bfail(b, NFLBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  b->graph[half] = g;
+  b->exec[half] = x;
+  return NFLBM_OK;
+}
+
+int batch_run(nflbm_batch* b, long long nsteps, int mode) {
+  if (mode == NFLBM_BATCH_PER_SIM) {
+    for (nflbm_sim* m : b->members) {
+      const int rc = nflbm_step(m, nsteps);
+      if (rc != NFLBM_OK) return bfail(b, rc, m->err);
+    }
+    return NFLBM_OK;
+  }
+  int half = 0;
+  int rc = batch_half(b, &half);
+  if (rc != NFLBM_OK) return rc;
+  long long t = 0;
+  if (mode == NFLBM_BATCH_GRAPH) {
+    const long long reps = nsteps / b->graph_steps;
+    if (reps > 0 && !b->exec[half]) {
+      rc = capture_graph(b, half);
+      if (rc != NFLBM_OK) return rc;
+    }
+    for (long long r = 0; r < reps; ++r) BHIPCHK(b, hipGraphLaunch(b->exec[half], b->stream));
+    t = reps * b->graph_steps;  // an even count: the parity is unchanged
+  }
+  for (; t < nsteps; ++t) {
+    BHIPCHK(b, launch_half(b, half));
+    half ^= 1;
+  }
+  if (nsteps & 1)
+    for (nflbm_sim* m : b->members) m->cur ^= 1;
+  return NFLBM_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::ostringstream o;
+  o << prop.gcnArchName << "/cu" << prop.multiProcessorCount;
+  std::string t = o.str();
+  for (char& c : t)
+    if (c == ' ' || c == '|') c = '_';
+  return t;
+}
+
+// Cache file: one entry per line, "<key>|<values separated by spaces>"; the
+// last line with a matching key wins.
+bool cache_lookup(const char* path, const std::string& key, std::vector<int>* vals) {
+  if (!path || !*path) return false;
+  std::ifstream in(path);
+  if (!in) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    const size_t bar = line.find('|');
+    if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+    std::istringstream vs(line.substr(bar + 1));
+    std::vector<int> v;
+    int x;
+    while (vs >> x) v.push_back(x);
+    if (v.size() == vals->size()) {
+      *vals = v;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const std::vector<int>& vals) {
+  if (!path || !*path) return;
+  std::ofstream out(path, std::ios::app);
+  if (!out) return;
+  out << key << '|';
+  for (size_t i = 0; i < vals.size(); ++i) out << (i ? " " : "") << vals[i];
+  out << '\n';
+}
+
+std::string sim_key(const nflbm_sim* s) {
+  std::ostringstream o;
+  o << "sim lat=" << s->lat << " N=" << s->N << " store=" << s->store << " shape=" << s->nx << 'x' << s->ny
+    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " flags=" << s->step_flags
+    << " dev=" << device_tag();
+  return o.str();
+}
+
+// Device copy of the current population set of s (restored after timing).
+struct SavedState {
+  void* f = nullptr;
+  void* g0 = nullptr;
+  void* gk = nullptr;
+  int cur = 0;
+};
+
+int save_state(nflbm_sim* s, SavedState* st) {
+  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  st->cur = s->cur;
+  bool ok = hipMalloc(&st->f, Qm * n * s->fs) == hipSuccess;
+  ok = ok && hipMalloc(&st->g0, NE * n * s->g0s) == hipSuccess;
+  ok = ok && hipMalloc(&st->gk, NE * Qm * n * s->fs) == hipSuccess;
+  if (!ok) return fail(s, NFLBM_ENOMEM, "cannot allocate the autotuner's state copy");
+  HIPCHK(s, hipMemcpyAsync(st->f, s->f[s->cur], Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(st->g0, s->g0[s->cur], NE * n * s->g0s, hipMemcpyDeviceToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(st->gk, s->gk[s->cur], NE * Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream));
+  return NFLBM_OK;
+}
+
+int restore_state(nflbm_sim* s, SavedState* st) {
+  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  s->cur = st->cur;
+  hipError_t e = hipSuccess;
+  if (st->f) e = hipMemcpyAsync(s->f[s->cur], st->f, Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && st->g0)
+    e = hipMemcpyAsync(s->g0[s->cur], st->g0, NE * n * s->g0s, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && st->gk)
+    e = hipMemcpyAsync(s->gk[s->cur], st->gk, NE * Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (st->f) (void)hipFree(st->f);
+  if (st->g0) (void)hipFree(st->g0);
+  if (st->gk) (void)hipFree(st->gk);
+  st->f = st->g0 = st->gk = nullptr;
+  if (e != hipSuccess) return hip_fail(s, e, "autotune: restoring the state");
+  return NFLBM_OK;
+}
+
+// Even number of timed steps giving roughly 5 ms of work per candidate.
+long long tune_steps(double nodes, double bytes_per_node) {
+  const double est = nodes * bytes_per_node / 4.0e12;  // seconds per step at 4 TB/s
+  long long k = static_cast<long long>(5.0e-3 / (est > 0 ? est : 1e-6));
+  if (k < 2) k = 2;
+  if (k > 40) k = 40;
+  return k & ~1LL;
 }
 
 }  // namespace
@@ -681,5 +978,270 @@ int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   *bytes = b;
   return NFLBM_OK;
 }
+
+
+int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  const std::string key = sim_key(sim);
+  std::vector<int> best = {sim->tx_log2, sim->zchunk};
+  if (cache_lookup(cache_path, key, &best)) {
+    if (apply_launch(sim, best[0], best[1])) return NFLBM_OK;
+  }
+  std::vector<std::pair<int, int>> cands;
+  for (int l : {4, 6}) {
+    if (update_lds_bytes(sim->lat, sim->N, sim->store, l) > sim->lds_max) continue;
+    if (sim->lat == NFLBM_D3Q19) {
+      for (int zc = 1; zc <= sim->nz; zc *= 2) cands.emplace_back(l, zc);
+      if ((sim->nz & (sim->nz - 1)) != 0) cands.emplace_back(l, sim->nz);
+    } else {
+      cands.emplace_back(l, 1);
+    }
+  }
+  if (cands.empty()) return fail(sim, NFLBM_ENOTSUP, "no launch shape fits the device");
+  SavedState st;
+  int rc = save_state(sim, &st);
+  if (rc != NFLBM_OK) {
+    (void)restore_state(sim, &st);
+    return rc;
+  }
+  double bpn = 0.0;
+  (void)nflbm_bytes_per_node(sim, &bpn);
+  const long long K = tune_steps(double(sim->n), bpn);
+  double best_ms = 1e300;
+  const int keep_l = sim->tx_log2, keep_zc = sim->zchunk;
+  best = {keep_l, keep_zc};
+  for (const auto& c : cands) {
+    if (!apply_launch(sim, c.first, c.second)) continue;
+    rc = nflbm_step(sim, 2);
+    double ms = 0.0;
+    if (rc == NFLBM_OK) rc = nflbm_step_timed(sim, K, &ms, nullptr);
+    if (rc != NFLBM_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = {c.first, c.second};
+    }
+  }
+  const int rc2 = restore_state(sim, &st);
+  if (!apply_launch(sim, best[0], best[1])) (void)apply_launch(sim, keep_l, keep_zc);
+  if (rc != NFLBM_OK) return rc;
+  if (rc2 != NFLBM_OK) return rc2;
+  cache_store(cache_path, key, best);
+  return NFLBM_OK;
+}
+
+int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
+  if (!cfgs || !out || count < 1) return bfail(nullptr, NFLBM_EINVAL, "batch needs count >= 1 configurations");
+  *out = nullptr;
+  for (int i = 1; i < count; ++i)
+    if (cfgs[i].lattice != cfgs[0].lattice || cfgs[i].ncomp != cfgs[0].ncomp ||
+        cfgs[i].precision != cfgs[0].precision)
+      return bfail(nullptr, NFLBM_EINVAL, "batch members must share lattice, ncomp and precision");
+  nflbm_batch* b = new nflbm_batch();
+  b->lat = cfgs[0].lattice;
+  b->N = cfgs[0].ncomp;
+  b->store = cfgs[0].precision;
+  auto cleanup = [&](int code, const std::string& msg) {
+    for (nflbm_sim* m : b->members) nflbm_destroy(m);
+    if (b->params) (void)hipFree(b->params);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    delete b;
+    return bfail(nullptr, code, msg);
+  };
+  for (int i = 0; i < count; ++i) {
+    nflbm_sim* m = nullptr;
+    const int rc = nflbm_create(&cfgs[i], &m);
+    if (rc != NFLBM_OK) return cleanup(rc, "member " + std::to_string(i) + ": " + nflbm_last_error(nullptr));
+    b->members.push_back(m);
+    b->nodes += static_cast<long long>(m->n);
+    if (m->wall[0] || m->wall[1] || m->wall[2]) b->walls = 1;
+  }
+  if (hipStreamCreate(&b->own_stream) != hipSuccess) {
+    b->own_stream = nullptr;
+    return cleanup(NFLBM_EDEVICE, "cannot create the batch stream");
+  }
+  b->stream = b->own_stream;
+  for (nflbm_sim* m : b->members) m->stream = b->stream;
+  // coefficient tables of all members in one array
+  const size_t psize = b->members[0]->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
+  if (hipMalloc(&b->params, psize * count) != hipSuccess) {
+    b->params = nullptr;
+    return cleanup(NFLBM_ENOMEM, "cannot allocate the batch coefficient tables");
+  }
+  for (int i = 0; i < count; ++i)
+    if (hipMemcpy(static_cast<char*>(b->params) + psize * i, b->members[i]->params, psize,
+                  hipMemcpyDeviceToDevice) != hipSuccess)
+      return cleanup(NFLBM_EDEVICE, "cannot copy the coefficient tables");
+  // default tile: 64 x 4 unless some member is at most 16 wide or the window
+  // does not fit
+  int l = 6;
+  for (nflbm_sim* m : b->members)
+    if (m->nx <= 16) l = 4;
+  if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max) l = 4;
+  b->tx_log2 = l;
+  const int rc = build_batch_tables(b, true);
+  if (rc != NFLBM_OK) {
+    const std::string msg = b->err;
+    free_batch_tables(b);
+    return cleanup(rc, msg);
+  }
+  *out = b;
+  return NFLBM_OK;
+}
+
+void nflbm_batch_destroy(nflbm_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  destroy_graphs(b);
+  free_batch_tables(b);
+  if (b->params) (void)hipFree(b->params);
+  for (nflbm_sim* m : b->members) {
+    m->stream = nullptr;
+    nflbm_destroy(m);
+  }
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  delete b;
+}
+
+int nflbm_batch_count(const nflbm_batch* b) { return b ? static_cast<int>(b->members.size()) : 0; }
+
+nflbm_sim* nflbm_batch_member(nflbm_batch* b, int idx) {
+  if (!b || idx < 0 || idx >= static_cast<int>(b->members.size())) {
+    bfail(b, NFLBM_EINVAL, "member index out of range");
+    return nullptr;
+  }
+  return b->members[idx];
+}
+
+int nflbm_batch_set_stream(nflbm_batch* b, void* stream) {
+  if (!b) return bfail(nullptr, NFLBM_EINVAL, "NULL batch");
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  b->stream = stream ? static_cast<hipStream_t>(stream) : b->own_stream;
+  for (nflbm_sim* m : b->members) m->stream = b->stream;
+  return NFLBM_OK;
+}
+
+int nflbm_batch_set_fields(nflbm_batch* b, int idx, const double* C, const double* v, const double* P) {
+  nflbm_sim* m = nflbm_batch_member(b, idx);
+  if (!m) return NFLBM_EINVAL;
+  const int rc = nflbm_set_fields(m, C, v, P);
+  return rc == NFLBM_OK ? rc : bfail(b, rc, m->err);
+}
+
+int nflbm_batch_get_field(nflbm_batch* b, int idx, int field, double* host_out) {
+  nflbm_sim* m = nflbm_batch_member(b, idx);
+  if (!m) return NFLBM_EINVAL;
+  const int rc = nflbm_get_field(m, field, host_out);
+  return rc == NFLBM_OK ? rc : bfail(b, rc, m->err);
+}
+
+int nflbm_batch_step(nflbm_batch* b, long long nsteps, int mode) {
+  if (!b) return bfail(nullptr, NFLBM_EINVAL, "NULL batch");
+  if (nsteps < 0) return bfail(b, NFLBM_EINVAL, "nsteps < 0");
+  if (mode != NFLBM_BATCH_LAUNCH && mode != NFLBM_BATCH_GRAPH && mode != NFLBM_BATCH_PER_SIM)
+    return bfail(b, NFLBM_EINVAL, "unknown batch mode");
+  return batch_run(b, nsteps, mode);
+}
+
+int nflbm_batch_step_timed(nflbm_batch* b, long long nsteps, int mode, double* ms) {
+  if (!b || !ms) return bfail(b, NFLBM_EINVAL, "NULL argument");
+  if (nsteps < 0) return bfail(b, NFLBM_EINVAL, "nsteps < 0");
+  if (mode != NFLBM_BATCH_LAUNCH && mode != NFLBM_BATCH_GRAPH && mode != NFLBM_BATCH_PER_SIM)
+    return bfail(b, NFLBM_EINVAL, "unknown batch mode");
+  hipEvent_t e0, e1;
+  BHIPCHK(b, hipEventCreate(&e0));
+  BHIPCHK(b, hipEventCreate(&e1));
+  BHIPCHK(b, hipEventRecord(e0, b->stream));
+  int rc = batch_run(b, nsteps, mode);
+  if (rc == NFLBM_OK) {
+    BHIPCHK(b, hipEventRecord(e1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(e1));
+    float t = 0.f;
+    BHIPCHK(b, hipEventElapsedTime(&t, e0, e1));
+    *ms = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int nflbm_batch_set_launch(nflbm_batch* b, int tx_log2, int graph_steps) {
+  if (!b) return bfail(nullptr, NFLBM_EINVAL, "NULL batch");
+  const int l = tx_log2 > 0 ? tx_log2 : b->tx_log2;
+  const int g = graph_steps > 0 ? graph_steps : b->graph_steps;
+  if (l != 4 && l != 6) return bfail(b, NFLBM_EINVAL, "tx_log2 must be 4 or 6");
+  if (g < 2 || (g & 1)) return bfail(b, NFLBM_EINVAL, "graph_steps must be even and >= 2");
+  if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max)
+    return bfail(b, NFLBM_EINVAL, "LDS window too large for this tile");
+  const bool shape = l != b->tx_log2 || g != b->graph_steps;
+  b->tx_log2 = l;
+  b->graph_steps = g;
+  return shape ? build_batch_tables(b, true) : NFLBM_OK;
+}
+
+int nflbm_batch_get_launch(nflbm_batch* b, int* tx_log2, int* graph_steps, int* blocks_update) {
+  if (!b) return bfail(nullptr, NFLBM_EINVAL, "NULL batch");
+  if (tx_log2) *tx_log2 = b->tx_log2;
+  if (graph_steps) *graph_steps = b->graph_steps;
+  if (blocks_update) *blocks_update = b->blocks_update;
+  return NFLBM_OK;
+}
+
+int nflbm_batch_nodes(const nflbm_batch* b, long long* nodes) {
+  if (!b || !nodes) return bfail(nullptr, NFLBM_EINVAL, "NULL argument");
+  *nodes = b->nodes;
+  return NFLBM_OK;
+}
+
+int nflbm_batch_autotune(nflbm_batch* b, const char* cache_path) {
+  if (!b) return bfail(nullptr, NFLBM_EINVAL, "NULL batch");
+  std::ostringstream ko;
+  unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the member shapes
+  for (nflbm_sim* m : b->members)
+    for (int v : {m->nx, m->ny, m->nz, m->wall[0], m->wall[1], m->wall[2], m->step_flags}) {
+      h ^= static_cast<unsigned long long>(static_cast<unsigned>(v));
+      h *= 1099511628211ULL;
+    }
+  ko << "batch lat=" << b->lat << " N=" << b->N << " store=" << b->store << " count=" << b->members.size()
+     << " nodes=" << b->nodes << " shapes=" << std::hex << h << std::dec << " dev=" << device_tag();
+  const std::string key = ko.str();
+  std::vector<int> best = {b->tx_log2};
+  if (cache_lookup(cache_path, key, &best)) return nflbm_batch_set_launch(b, best[0], 0);
+  std::vector<SavedState> saved(b->members.size());
+  int rc = NFLBM_OK;
+  for (size_t i = 0; i < b->members.size() && rc == NFLBM_OK; ++i) {
+    rc = save_state(b->members[i], &saved[i]);
+    if (rc != NFLBM_OK) rc = bfail(b, rc, b->members[i]->err);
+  }
+  double bpn = 0.0;
+  (void)nflbm_bytes_per_node(b->members[0], &bpn);
+  const long long K = std::max<long long>(tune_steps(double(b->nodes), bpn), b->graph_steps);
+  double best_ms = 1e300;
+  best = {b->tx_log2};
+  for (int l : {4, 6}) {
+    if (rc != NFLBM_OK) break;
+    if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max) continue;
+    rc = nflbm_batch_set_launch(b, l, 0);
+    double ms = 0.0;
+    if (rc == NFLBM_OK) rc = batch_run(b, b->graph_steps, NFLBM_BATCH_GRAPH);  // warm-up and capture
+    if (rc == NFLBM_OK) rc = nflbm_batch_step_timed(b, K, NFLBM_BATCH_GRAPH, &ms);
+    if (rc == NFLBM_OK && ms < best_ms) {
+      best_ms = ms;
+      best = {l};
+    }
+  }
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const int r2 = restore_state(b->members[i], &saved[i]);
+    if (r2 != NFLBM_OK && rc == NFLBM_OK) rc = bfail(b, r2, b->members[i]->err);
+  }
+  if (rc != NFLBM_OK) return rc;
+  rc = nflbm_batch_set_launch(b, best[0], 0);
+  if (rc != NFLBM_OK) return rc;
+  rc = build_batch_tables(b, false);
+  if (rc != NFLBM_OK) return rc;
+  cache_store(cache_path, key, best);
+  return NFLBM_OK;
+}
+
+const char* nflbm_batch_last_error(const nflbm_batch* b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
 
 }  // extern "C"

@@ -42,17 +42,30 @@ enum StepFlags {
   kFlagOmega = 4          // Omega != 0
 };
 
+// Device code sees the pointers in the argument structs as pointers to global
+// memory, so that it emits global (not flat) accesses and scalar loads for
+// uniform reads also where a StepArgs was itself read from memory (batches);
+// the host sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NFLBM_GLOBAL __attribute__((address_space(1)))
+#else
+#define NFLBM_GLOBAL
+#endif
+
 // Population arrays hold post-collision values (pull streaming):
 //   f [k-1][node], gk [k-1][node][i], g0 [node][i], conc [node][i], eb [node].
 // In-plane byte offsets are 32-bit: n * NE * sizeof(value) must stay below 2^32.
 struct StepArgs {
-  const void* f_src; void* f_dst;     // moving hydrodynamic populations
-  const void* g0_src; void* g0_dst;   // rest populations of evolved components
-  const void* gk_src; void* gk_dst;   // moving populations of evolved components
-  void* conc;                         // reconstructed C (compute precision)
-  void* eb;                           // E_B per node (compute precision)
-  double* fields;                     // fields-mode output [2N+7][n]
-  const void* params;                 // DevParams<T>
+  const NFLBM_GLOBAL void* f_src;     // moving hydrodynamic populations
+  NFLBM_GLOBAL void* f_dst;
+  const NFLBM_GLOBAL void* g0_src;    // rest populations of evolved components
+  NFLBM_GLOBAL void* g0_dst;
+  const NFLBM_GLOBAL void* gk_src;    // moving populations of evolved components
+  NFLBM_GLOBAL void* gk_dst;
+  NFLBM_GLOBAL void* conc;            // reconstructed C (compute precision)
+  NFLBM_GLOBAL void* eb;              // E_B per node (compute precision)
+  NFLBM_GLOBAL double* fields;        // fields-mode output [2N+7][n]
+  const NFLBM_GLOBAL void* params;    // DevParams<T>
   long long n;
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
@@ -72,6 +85,23 @@ struct InitArgs {
   StepArgs sa;                        // lattice size and walls
 };
 
+// One step of a batch of simulations that share lattice, N and storage
+// precision.  args[m] are the step arguments of member m for this step's
+// parity and params[m] its coefficient tables (a DevParams<T> array, T the
+// compute precision); a work entry (m, b) is tile b of member m.  The reconstruction's
+// tiles are those of one z plane (tiles_x tiles_y nz per member), the update's
+// those of its z runs (tiles_x tiles_y chunks_z), all with tile width
+// 1 << tx_log2.
+struct BatchLaunch {
+  const StepArgs* args;               // device [count]
+  const void* params;                 // device DevParams<T>[count]
+  const int2* work_conc;              // device [blocks_conc]
+  const int2* work_update;            // device [blocks_update]
+  int blocks_conc, blocks_update;
+  int tx_log2;
+  int walls;                          // some member has a wall
+};
+
 struct ReduceArgs {
   const double* fields;               // as written by the fields mode
   double* partial;                    // [blocks][rec]
@@ -86,6 +116,7 @@ struct ReduceArgs {
 hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s);
 hipError_t launch_init(int lat, int nc, int store, const InitArgs& a, hipStream_t s);
+hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 __host__ __device__ int reduce_record_len(int N);
 size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);

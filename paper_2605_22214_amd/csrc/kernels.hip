@@ -233,6 +233,16 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Typed view of a global-memory pointer of the argument structs.
+template <class E>
+__device__ __forceinline__ E* gptr(const NFLBM_GLOBAL void* p) {
+  return (E*)(p);
+}
+template <class E>
+__device__ __forceinline__ E* gptr(const E* p) {
+  return const_cast<E*>(p);
+}
+
 // Element idx of an array addressed with a 32-bit byte offset from a uniform
 // base: the load/store can then take the base in scalar registers.
 template <class E>
@@ -247,20 +257,20 @@ __device__ __forceinline__ E* at(E* base, uint32_t idx) {
 // ------------------------------------------------------------------ k_conc
 // One node per thread over TX x TY tiles of one z plane: C of the evolved
 // components from the gathered g, and the bulk free energy E_B(C), which the
-// update reads for its gradient.
+// update reads for its gradient.  b is the workgroup's tile index within the
+// simulation (x fastest, then y, then z).
 template <class L, int NE, int ST, bool WALLS>
-__global__ void __launch_bounds__(256)
-k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+__device__ __forceinline__ void conc_tile(const StepArgs& a,
+                                          const DevParams<typename StoreT<ST>::T>* __restrict__ Pp, int b) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
   using G0S = typename S::G0S;
   constexpr int Q = L::Q;
   constexpr int NC = NE + 1;
-  const DevParams<T>& P = *Pp;
+  const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
   const int TX = 1 << a.tx_log2;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> a.tx_log2;
-  int b = static_cast<int>(blockIdx.x);
   const int tile_x = b % a.tiles_x;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
@@ -270,8 +280,8 @@ k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   const size_t n = static_cast<size_t>(a.n);
   const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
   const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
-  const G0S* g0 = static_cast<const G0S*>(a.g0_src);
-  const FS* gk = static_cast<const FS*>(a.gk_src);
+  const G0S* g0 = gptr<const G0S>(a.g0_src);
+  const FS* gk = gptr<const FS>(a.gk_src);
   // The small moving populations are summed first and the O(1) rest
   // population added last: one rounding at the scale of C per node.  Adding
   // them one by one onto the rest population would round every addition at
@@ -296,7 +306,7 @@ k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
 #pragma unroll
     for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]) + s[e];
   }
-  vst<T, NE>(at(static_cast<T*>(a.conc), node * NE), s);
+  vst<T, NE>(at(gptr<T>(a.conc), node * NE), s);
   T c[NC];
   T rest = T(0);
 #pragma unroll
@@ -305,7 +315,24 @@ k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
     rest += s[e];
   }
   c[NE] = T(1) - rest;
-  *at(static_cast<T*>(a.eb), node) = bulk_energy<NC, T>(c, P);
+  *at(gptr<T>(a.eb), node) = bulk_energy<NC, T>(c, P);
+}
+
+template <class L, int NE, int ST, bool WALLS>
+__global__ void __launch_bounds__(256)
+k_conc(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+  conc_tile<L, NE, ST, WALLS>(a, Pp, static_cast<int>(blockIdx.x));
+}
+
+// Batch form: workgroup w works on tile work[w].y of simulation m = work[w].x,
+// whose arguments are args[m] and coefficient tables params[m].
+template <class L, int NE, int ST, bool WALLS>
+__global__ void __launch_bounds__(256)
+k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
+             const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const StepArgs a = args[w.x];
+  conc_tile<L, NE, ST, WALLS>(a, params + w.x, w.y);
 }
 
 // ---------------------------------------------------------------- k_update
@@ -317,9 +344,12 @@ constexpr int update_waves() {
   return (ST != kStoreF64 && (L::DIM == 2 || NC <= 5)) ? 3 : 1;
 }
 
+// One workgroup's share of the update: tile b of the simulation (x fastest,
+// then y, then the z run), with the LDS window at smem_raw.
 template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL>
-__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
-k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+__device__ __forceinline__ void update_tile(const StepArgs& a,
+                                            const DevParams<typename StoreT<ST>::T>* __restrict__ Pp,
+                                            int b, unsigned char* smem_raw) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
@@ -327,9 +357,8 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   constexpr int Q = L::Q;
   constexpr int NE = NC - 1;
   constexpr bool D3 = (L::DIM == 3);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const DevParams<T>& P = *Pp;
+  const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
 
   // tile width as a compile-time constant: every LDS access of the stencil
   // is then an immediate offset from one base address
@@ -342,8 +371,6 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   const int tx = tid & (TX - 1);
   const int ty = tid >> TXL;
 
-  const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
-  int b = xcd_remap(static_cast<int>(blockIdx.x), nblocks);
   const int tile_x = b % a.tiles_x;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
@@ -355,9 +382,9 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   const bool active = (x < a.nx) && (y < a.ny);
   const size_t n = static_cast<size_t>(a.n);
   const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
-  const T* conc = static_cast<const T*>(a.conc);
-  const T* eb = static_cast<const T*>(a.eb);
-  const FS* fsrc = static_cast<const FS*>(a.f_src);
+  const T* conc = gptr<const T>(a.conc);
+  const T* eb = gptr<const T>(a.eb);
+  const FS* fsrc = gptr<const FS>(a.f_src);
 
   // Each thread fills at most two positions of the (TX+2) x (TY+2) LDS window
   // of every plane; their in-plane node offsets are fixed for the workgroup.
@@ -578,7 +605,7 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
     const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + s0);
 
     if constexpr (FIELDS) {
-      double* out = a.fields;
+      double* out = gptr<double>(a.fields);
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
         out[size_t(P.uidx[i]) * n + node] = static_cast<double>(c[i]);
@@ -608,10 +635,10 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
       }
     }
 
-    FS* fdst = static_cast<FS*>(a.f_dst);
-    FS* gkdst = static_cast<FS*>(a.gk_dst);
-    G0S* g0dst = static_cast<G0S*>(a.g0_dst);
-    const FS* gksrc = static_cast<const FS*>(a.gk_src);
+    FS* fdst = gptr<FS>(a.f_dst);
+    FS* gkdst = gptr<FS>(a.gk_dst);
+    G0S* g0dst = gptr<G0S>(a.g0_dst);
+    const FS* gksrc = gptr<const FS>(a.gk_src);
     const T vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
     const T cP = T(3) * Pn;
     const T hp = T(0.5) * (T(1) - T(0.5) * wp);
@@ -706,6 +733,27 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
     __syncthreads();
     if (active) process(0, 0, 0, 0);
   }
+}
+
+template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL>
+__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
+k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
+  update_tile<L, NC, ST, FIELDS, WALLS, TXL>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks), smem_raw);
+}
+
+// Batch form (see k_conc_batch).  The work list holds each simulation's
+// tiles contiguously, so the XCD remap keeps a simulation's neighbouring tiles
+// on one XCD.
+template <class L, int NC, int ST, bool WALLS, int TXL>
+__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
+k_update_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
+               const int2* __restrict__ work, int nblocks) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 w = work[xcd_remap(static_cast<int>(blockIdx.x), nblocks)];
+  const StepArgs a = args[w.x];
+  update_tile<L, NC, ST, false, WALLS, TXL>(a, params + w.x, w.y, smem_raw);
 }
 
 // ------------------------------------------------------------------ k_init
@@ -886,6 +934,9 @@ hipError_t init_st2(int lat, int nc, const InitArgs& a, hipStream_t s);
 hipError_t conc_st0(int lat, int nc, const StepArgs& a, hipStream_t s);
 hipError_t conc_st1(int lat, int nc, const StepArgs& a, hipStream_t s);
 hipError_t conc_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
+hipError_t batch_st0(int lat, int nc, const BatchLaunch& b, hipStream_t s);
+hipError_t batch_st1(int lat, int nc, const BatchLaunch& b, hipStream_t s);
+hipError_t batch_st2(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 
 #if defined(NFLBM_UNIT_STORE) && NFLBM_UNIT_STORE >= 0
 
@@ -905,7 +956,7 @@ inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_
 
 template <class L, int NC, int ST>
 hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
-  const auto* P = static_cast<const DevParams<TT<ST>>*>(a0.params);
+  const auto* P = (const DevParams<TT<ST>>*)(a0.params);
   if (fields) {
     // diagnostics only: one variant (16-wide tiles, walls handled at run time)
     StepArgs a = a0;
@@ -944,10 +995,45 @@ hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
 template <class L, int NC, int ST>
 hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
   const int blocks = a.tiles_x * a.tiles_y * a.nz;
-  const auto* P = static_cast<const DevParams<TT<ST>>*>(a.params);
+  const auto* P = (const DevParams<TT<ST>>*)(a.params);
   if (any_wall(a)) hipLaunchKernelGGL((k_conc<L, NC - 1, ST, true>), dim3(blocks), dim3(256), 0, s, a, P);
   else hipLaunchKernelGGL((k_conc<L, NC - 1, ST, false>), dim3(blocks), dim3(256), 0, s, a, P);
   return hipGetLastError();
+}
+
+// One time step of every simulation of a batch: the reconstruction over all
+// their tiles, then the update over all their tiles.
+template <class L, int NC, int ST>
+hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
+  const auto* P = static_cast<const DevParams<TT<ST>>*>(b.params);
+  if (b.walls)
+    hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, true>), dim3(b.blocks_conc), dim3(256), 0, s, b.args, P,
+                       b.work_conc);
+  else
+    hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, false>), dim3(b.blocks_conc), dim3(256), 0, s, b.args, P,
+                       b.work_conc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
+  const dim3 grid(b.blocks_update), blk(256);
+  const int nb = b.blocks_update;
+  if (b.tx_log2 == 6) {
+    if (b.walls) hipLaunchKernelGGL((k_update_batch<L, NC, ST, true, 6>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    else hipLaunchKernelGGL((k_update_batch<L, NC, ST, false, 6>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+  } else if (b.tx_log2 == 4) {
+    if (b.walls) hipLaunchKernelGGL((k_update_batch<L, NC, ST, true, 4>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    else hipLaunchKernelGGL((k_update_batch<L, NC, ST, false, 4>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t batch_nc(int nc, const BatchLaunch& b, hipStream_t s) {
+#define CALL_B(K) launch_batch_t<L, K, ST>(b, s)
+  NFLBM_NC_SWITCH(nc, CALL_B)
+#undef CALL_B
 }
 
 template <class L, int ST>
@@ -984,6 +1070,9 @@ hipError_t NFLBM_CAT(init_st, NFLBM_ST)(int lat, int nc, const InitArgs& a, hipS
 hipError_t NFLBM_CAT(conc_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
   return lat == 0 ? conc_nc<D2Q9, NFLBM_ST>(nc, a, s) : conc_nc<D3Q19, NFLBM_ST>(nc, a, s);
 }
+hipError_t NFLBM_CAT(batch_st, NFLBM_ST)(int lat, int nc, const BatchLaunch& b, hipStream_t s) {
+  return lat == 0 ? batch_nc<D2Q9, NFLBM_ST>(nc, b, s) : batch_nc<D3Q19, NFLBM_ST>(nc, b, s);
+}
 
 #else  // common unit
 
@@ -1018,6 +1107,15 @@ hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_
     case kStoreF64: return conc_st0(lat, nc, a, s);
     case kStoreF32: return conc_st1(lat, nc, a, s);
     case kStoreF16S: return conc_st2(lat, nc, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, hipStream_t s) {
+  switch (store) {
+    case kStoreF64: return batch_st0(lat, nc, b, s);
+    case kStoreF32: return batch_st1(lat, nc, b, s);
+    case kStoreF16S: return batch_st2(lat, nc, b, s);
   }
   return hipErrorInvalidValue;
 }

@@ -25,7 +25,10 @@ def test_exports_every_header_function(L):
     assert len(names) >= 15
     for name in names:
         assert hasattr(L, name), name
-    assert L.nflbm_abi_version() == 1
+    import re
+    with open(nf.HEADER) as fh:
+        ver = int(re.search(r"#define NFLBM_ABI_VERSION (\d+)", fh.read()).group(1))
+    assert L.nflbm_abi_version() == ver
 
 
 def random_sigma(N, rng, lo=0.003, hi=0.009):
@@ -105,3 +108,25 @@ def test_unstable_mobility_rejected(L):
 def test_coefficients_invalid_sigma(L):
     with pytest.raises(nf.NflbmError):
         nf.coefficients(np.array([[0.0, -1.0], [-1.0, 0.0]]))
+
+
+def test_batch_rejects_mixed_members_before_the_device(L):
+    """Members of a batch must share lattice, ncomp and precision; the check
+    runs before any member is created, so no GPU is needed."""
+    sig3 = np.full((3, 3), 0.005)
+    np.fill_diagonal(sig3, 0.0)
+    sig4 = np.full((4, 4), 0.005)
+    np.fill_diagonal(sig4, 0.0)
+    a = nf._Problem("D2Q9", (32, 32, 1), sig3, 1.0, m=0.05, precision=nf.FP32)
+    b = nf._Problem("D2Q9", (32, 32, 1), sig4, 1.0, m=0.05, precision=nf.FP32)
+    c = nf._Problem("D2Q9", (32, 32, 1), sig3, 1.0, m=0.05, precision=nf.FP64)
+    for pair in ((a, b), (a, c)):
+        arr = (nf.Config * 2)(pair[0].cfg, pair[1].cfg)
+        h = ctypes.c_void_p()
+        assert L.nflbm_batch_create(arr, 2, ctypes.byref(h)) == -1
+        assert b"share lattice" in L.nflbm_batch_last_error(None)
+        assert not h.value
+    h = ctypes.c_void_p()
+    assert L.nflbm_batch_create((nf.Config * 1)(a.cfg), 0, ctypes.byref(h)) == -1
+    assert L.nflbm_batch_count(None) == 0
+    assert L.nflbm_batch_member(None, 0) is None
