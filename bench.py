@@ -109,6 +109,35 @@ def run_form(nf, w, form, steps, warmup, timing_steps):
     return out
 
 
+def run_batch(nf, count, steps, per_sim_steps, seed=0):
+    """Batch of independent D2Q9 N=3 lens / Janus problems (sides 64..512 in
+    steps of 32, sigma_13 and sigma_23 drawn from U[0.0025, 0.01]), FP32
+    storage: graph replay of whole-batch steps against each member's own
+    launch sequence.  MLUPS counts the nodes of all members."""
+    import workloads as W
+    ws = W.batch_members(count=count, seed=seed)
+    b = nf.Batch.from_workloads(ws, precision=nf.FP32)
+    for i, w in enumerate(ws):
+        b.members[i].set_fields(w["C0"])
+    nodes = b.nodes()
+    tx, graph_steps, blocks = b.autotune()
+    b.step(2 * graph_steps, "graph")
+    ms_graph = b.step_timed(steps, "graph")
+    ms_launch = b.step_timed(max(2, steps // 10), "launch")
+    b.step(2, "per_sim")
+    ms_per = b.step_timed(per_sim_steps, "per_sim")
+    absent_nan = max(m.diagnostics(check=False)["nan"] for m in b.members[:8])
+    b.close()
+    graph = nodes * steps / (ms_graph * 1e-3) / 1e6
+    per = nodes * per_sim_steps / (ms_per * 1e-3) / 1e6
+    return {"workload": f"{count} independent D2Q9 N=3 lens/Janus problems, sides 64..512, FP32",
+            "nodes": nodes, "tile_x": 1 << tx, "graph_steps": graph_steps, "workgroups": blocks,
+            "graph_mlups": graph, "graph_steps_timed": steps,
+            "launch_mlups": nodes * max(2, steps // 10) / (ms_launch * 1e-3) / 1e6,
+            "per_sim_mlups": per, "per_sim_steps_timed": per_sim_steps,
+            "speedup_graph_vs_per_sim": graph / per, "nan_in_first_8": absent_nan}
+
+
 def cpu_baseline(sample_n=64, steps=60):
     """The FP64 oracle (not tuned) on a sample_n^3 lattice of the same recipe."""
     import workloads as W
@@ -137,6 +166,9 @@ def main():
     ap.add_argument("--forms", default="fp32,fp16s,fp64")
     ap.add_argument("--timing-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="members of the batch measurement (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB, 3 times (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -168,6 +200,12 @@ def main():
         print(f"bench: timing {form} ({args.n}^3, {args.steps} steps)", file=sys.stderr, flush=True)
         results[form] = run_form(nf, w, form, args.steps, args.warmup, args.timing_steps)
         print(f"bench: {form} {results[form]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+    batch = None
+    if args.batch_count > 0:
+        print(f"bench: batch of {args.batch_count} D2Q9 problems", file=sys.stderr, flush=True)
+        batch = run_batch(nf, args.batch_count, args.batch_steps, max(2, args.batch_steps // 10))
+        print(f"bench: batch {batch['graph_mlups']:.0f} MLUPS (graph) vs {batch['per_sim_mlups']:.0f} "
+              "(per simulation)", file=sys.stderr, flush=True)
     main_form = forms[0]
     r = results[main_form]
     traffic = None
@@ -202,6 +240,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": results,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

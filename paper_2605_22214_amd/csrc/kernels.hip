@@ -141,6 +141,77 @@ __device__ __forceinline__ void vst(E* p, const E (&v)[NE]) {
   }
 }
 
+// Nontemporal forms for streams touched once per step: the populations the
+// reconstruction gathers and the post-collision populations the update
+// writes (re-read only by the next step's reconstruction).  Streaming stores
+// also leave L2 free of dirty lines for the reconstruction that follows.
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
+template <class E, int NE>
+__device__ __forceinline__ void vld_nt(const E* p, E (&o)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    const unsigned t = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
+    __builtin_memcpy(o, &t, 4);
+  } else if constexpr (B == 8) {
+    const nt_u2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
+    __builtin_memcpy(o, &t, 8);
+  } else if constexpr (B == 16) {
+    const nt_u4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+    __builtin_memcpy(o, &t, 16);
+  } else {
+    // wider records move as two 16-byte halves from different instructions;
+    // a streaming hint would drop the line between them (measured: FP64
+    // reconstruction 10% slower), so they take the cached path
+    vld<E, NE>(p, o);
+  }
+}
+
+template <class E, int NE>
+__device__ __forceinline__ void vst_nt(E* p, const E (&v)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    unsigned t;
+    __builtin_memcpy(&t, v, 4);
+    __builtin_nontemporal_store(t, reinterpret_cast<unsigned*>(p));
+  } else if constexpr (B == 8) {
+    nt_u2 t;
+    __builtin_memcpy(&t, v, 8);
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u2*>(p));
+  } else if constexpr (B == 16) {
+    nt_u4 t;
+    __builtin_memcpy(&t, v, 16);
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u4*>(p));
+  } else {
+    vst<E, NE>(p, v);   // as in vld_nt
+  }
+}
+
+// A uniform value the compiler must treat as new at this point: direction
+// offsets derived from it are formed where they are used instead of being
+// hoisted out of the z loop, where dozens of 64-bit bases would stay live in
+// scalar registers and spill.
+__device__ __forceinline__ size_t fresh(size_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+// Read-only tables seen through the constant address space: uniform reads
+// become scalar loads with immediate offsets, and the pointer is fresh at the
+// point of use (see above).
+#define NFLBM_CONST __attribute__((address_space(4)))
+template <class E>
+__device__ __forceinline__ const NFLBM_CONST E* fresh_const(const E* p) {
+  const NFLBM_CONST E* c = (const NFLBM_CONST E*)(const NFLBM_GLOBAL E*)p;
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
+template <class E>
+__device__ __forceinline__ void st_nt(E* p, E v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 template <class T>
 __device__ __forceinline__ T fpoly(T c) {
   const T d = T(1) - c;
@@ -294,15 +365,15 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   for (int k = 1; k < Q; ++k) {
     FS v[NE];
     if (pulled_from_wall<L, WALLS>(nb, k))
-      vld<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
+      vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
     else
-      vld<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
+      vld_nt<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
 #pragma unroll
     for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
   }
   {
     G0S r[NE];
-    vld<G0S, NE>(at(g0, node * NE), r);
+    vld_nt<G0S, NE>(at(g0, node * NE), r);
 #pragma unroll
     for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]) + s[e];
   }
@@ -358,7 +429,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   constexpr int NE = NC - 1;
   constexpr bool D3 = (L::DIM == 3);
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
+  const DevParams<T>* P0 = gptr<const DevParams<T>>(Pp);
 
   // tile width as a compile-time constant: every LDS access of the stencil
   // is then an immediate offset from one base address
@@ -439,17 +510,21 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     {
       const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
       const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+      const size_t nn = fresh(n);
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         if (pulled_from_wall<L, WALLS>(nb, k))
-          f[k] = S::ld(at(fsrc + size_t(opposite(k) - 1) * n, node), 0);
+          f[k] = S::ld(at(fsrc + size_t(opposite(k) - 1) * nn, node), 0);
         else
-          f[k] = S::ld(at(fsrc + size_t(k - 1) * n, upstream<L>(nb, k)), 0);
+          f[k] = S::ld(at(fsrc + size_t(k - 1) * nn, upstream<L>(nb, k)), 0);
       }
     }
   };
 
   auto process = [&](int z, int s_dn, int s_c, int s_up) {
+    // the coefficient tables as seen from this plane: their loads take
+    // immediate offsets from one base instead of hoisted per-entry addresses
+    const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
     const int li = (ty + 1) * PX + (tx + 1);
     const T* Cc = sm + s_c * plane_stride;
     T c[NC];
@@ -649,6 +724,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     for (int i = 0; i < NE; ++i) moved[i] = T(0);
     Nbr nb;
     if (a.flags & kFlagNeedG) nb = neighbours<WALLS, D3>(x, y, z, a);
+    const size_t nn = fresh(n);
 
     // ---- per direction pair: TRT collision of f with forcing and BGK
     // collision of every evolved g; stores go to this node (pull layout)
@@ -675,20 +751,20 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       const T ep = T(0.5) * (feq_k + feq_b), em = T(0.5) * (feq_k - feq_b);
       const T sym = fma(-wp, fp - ep, hp * (Fk + Fb));
       const T asym = fma(-wm, fm - em, hm * (Fk - Fb));
-      *at(fdst + size_t(k - 1) * n, node) = S::pack(f[k] + sym + asym);
-      *at(fdst + size_t(kb - 1) * n, node) = S::pack(f[kb] + sym - asym);
+      st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(f[k] + sym + asym));
+      st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(f[kb] + sym - asym));
       const T mw = wk * P.m;
       FS qk[NE], qb[NE];
       FS ok[NE], ob[NE];
       if (a.flags & kFlagNeedG) {
         if (pulled_from_wall<L, WALLS>(nb, k))
-          vld<FS, NE>(at(gksrc + size_t(kb - 1) * n * NE, node * NE), ok);
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * nn * NE, node * NE), ok);
         else
-          vld<FS, NE>(at(gksrc + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), ok);
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * nn * NE, upstream<L>(nb, k) * NE), ok);
         if (pulled_from_wall<L, WALLS>(nb, kb))
-          vld<FS, NE>(at(gksrc + size_t(k - 1) * n * NE, node * NE), ob);
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * nn * NE, node * NE), ob);
         else
-          vld<FS, NE>(at(gksrc + size_t(kb - 1) * n * NE, upstream<L>(nb, kb) * NE), ob);
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * nn * NE, upstream<L>(nb, kb) * NE), ob);
       }
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
@@ -704,13 +780,13 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         qb[i] = S::pack(gb);
         moved[i] += S::unpack(qk[i]) + S::unpack(qb[i]);
       }
-      vst<FS, NE>(at(gkdst + size_t(k - 1) * n * NE, node * NE), qk);
-      vst<FS, NE>(at(gkdst + size_t(kb - 1) * n * NE, node * NE), qb);
+      vst_nt<FS, NE>(at(gkdst + size_t(k - 1) * nn * NE, node * NE), qk);
+      vst_nt<FS, NE>(at(gkdst + size_t(kb - 1) * nn * NE, node * NE), qb);
     }
     G0S r0[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) r0[i] = static_cast<G0S>(c[i] - moved[i]);
-    vst<G0S, NE>(at(g0dst, node * NE), r0);
+    vst_nt<G0S, NE>(at(g0dst, node * NE), r0);
   };
 
   if constexpr (D3) {

@@ -1,0 +1,117 @@
+"""Quaternary phase separation at full size (D2Q9, N = 4, 512 x 512).
+
+* FP64 after 1000 steps, in the default launch shape, against the oracle's
+  state at sampled nodes (tests/golden/quaternary_512_1000.txt, written by
+  make_quaternary_512.py from the oracle alone).  C and the g populations,
+  whose scale is set by C ~ 1/4, agree to 1e-12 of that scale.  v, P and the
+  f populations are O(1e-6) quantities formed from O(1) ones: two oracle
+  runs whose inputs differ by 1e-16 relative already differ by ~2e-12 of
+  max |v| after 1000 steps here, so they are held to 1e-10 of their scale.
+* 20000 steps (the full run) in FP64 and FP32: per-component mass, total
+  momentum and sum_i C_i = 1 hold to rounding; the FP32 / FP64 difference of
+  the concentration field is recorded.
+
+Measured values go to gpurun_out/quaternary.json.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "quaternary_512_1000.txt")
+RESULTS = {}
+C_FULL = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def record():
+    yield
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "quaternary.json"), "w") as fh:
+        json.dump(RESULTS, fh, indent=1, sort_keys=True)
+
+
+def load_golden():
+    masses = None
+    rows = []
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.startswith("# total mass per component:"):
+                masses = np.array([float(v) for v in line.split(":")[1].split()])
+            elif not line.startswith("#") and line.strip():
+                rows.append([float(v) for v in line.split()])
+    return masses, np.array(rows)
+
+
+def test_fp64_sampled_nodes_after_1000_steps():
+    masses, rows = load_golden()
+    xs, ys = rows[:, 0].astype(int), rows[:, 1].astype(int)
+    ref_C, ref_v, ref_P = rows[:, 2:6], rows[:, 6:8], rows[:, 8]
+    ref_f, ref_g = rows[:, 9:17], rows[:, 17:44].reshape(-1, 3, 9)
+    w = W.quaternary_2d(512)
+    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:
+        sim.set_fields(w["C0"])
+        sim.step(1000)
+        C = sim.get_field("C")[:, 0]
+        V = sim.get_field("V")[:, 0]
+        P = sim.get_field("P")[0]
+        F = sim.get_field("F_RAW")[:, 0]
+        G = sim.get_field("G_RAW")[:, :, 0]
+        d = sim.diagnostics()
+    got_C = C[:, ys, xs].T
+    got_v = V[:2, ys, xs].T
+    got_P = P[ys, xs]
+    got_f = F[:, ys, xs].T
+    got_g = np.transpose(G[:3, :, ys, xs], (2, 0, 1))
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    errs = {"C": rel(got_C, ref_C), "g": rel(got_g, ref_g), "v": rel(got_v, ref_v),
+            "P": rel(got_P, ref_P), "f": rel(got_f, ref_f),
+            "mass": float(np.max(np.abs(np.array(d["mass"]) - masses) / masses))}
+    RESULTS["fp64_1000_sampled_rel_err"] = errs
+    assert errs["C"] <= 1e-12
+    assert errs["g"] <= 1e-12
+    assert errs["mass"] <= 1e-13
+    for k in ("v", "P", "f"):
+        assert errs[k] <= 1e-10, k
+
+
+@pytest.mark.parametrize("name,prec", [("fp64", nf.FP64), ("fp32", nf.FP32)])
+def test_full_run_conservation(name, prec):
+    w = W.quaternary_2d(512)
+    with nf.Simulation.from_workload(w, precision=prec) as sim:
+        sim.set_fields(w["C0"])
+        d0 = sim.diagnostics()
+        sim.step(20000)
+        d1 = sim.diagnostics()
+        C = sim.get_field("C")[:, 0]
+    RESULTS.setdefault("full_run", {})[name] = {
+        "mass_rel_drift": [abs(b - a) / a for a, b in zip(d0["mass"], d1["mass"])],
+        "momentum": d1["momentum"], "max_sum_dev": d1["max_sum_dev"],
+        "C_max": [float(C[i].max()) for i in range(4)],
+        "C_min": [float(C[i].min()) for i in range(4)],
+    }
+    C_FULL[name] = C
+    if name == "fp32" and "fp64" in C_FULL:
+        ref = C_FULL["fp64"]
+        RESULTS["full_run"]["fp32_vs_fp64_rel_L2_C"] = float(np.linalg.norm(C - ref) / np.linalg.norm(ref))
+    drift = max(abs(b - a) / a for a, b in zip(d0["mass"], d1["mass"]))
+    mom = max(abs(v) for v in d1["momentum"])
+    if prec == nf.FP64:
+        assert drift < 1e-12
+        assert mom < 1e-12
+        assert d1["max_sum_dev"] < 1e-13
+    else:
+        assert drift < 1e-5
+        assert mom < 1e-4
+        assert d1["max_sum_dev"] < 1e-6
