@@ -9,7 +9,9 @@
   max |v| after 1000 steps here, so they are held to 1e-10 of their scale.
 * 20000 steps (the full run) in FP64 and FP32: per-component mass, total
   momentum and sum_i C_i = 1 hold to rounding; the FP32 / FP64 difference of
-  the concentration field is recorded.
+  the concentration field is recorded.  The surface-tension force sums to
+  zero over the lattice only in exact arithmetic (Eq. Fsnew), so the total
+  momentum is held to a rounding-sized budget per node and step.
 
 Measured values go to gpurun_out/quaternary.json.
 """
@@ -107,11 +109,12 @@ def test_full_run_conservation(name, prec):
         RESULTS["full_run"]["fp32_vs_fp64_rel_L2_C"] = float(np.linalg.norm(C - ref) / np.linalg.norm(ref))
     drift = max(abs(b - a) / a for a, b in zip(d0["mass"], d1["mass"]))
     mom = max(abs(v) for v in d1["momentum"])
+    node_steps = 512 * 512 * 20000
     if prec == nf.FP64:
         assert drift < 1e-12
-        assert mom < 1e-12
+        assert mom < 1e-18 * node_steps
         assert d1["max_sum_dev"] < 1e-13
     else:
         assert drift < 1e-5
-        assert mom < 1e-4
+        assert mom < 1e-11 * node_steps
         assert d1["max_sum_dev"] < 1e-6
