@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 2
+#define NFLBM_ABI_VERSION 3
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -79,8 +79,19 @@ enum {
   NFLBM_FLAG_POTENTIAL_FORCE = 1, /* F_s = sum_i mu_i grad C_i (Eq. ststand)
                                      instead of the conservative Eq. Fsnew;
                                      a negative control that drifts          */
-  NFLBM_FLAG_ALLOW_UNSTABLE = 2   /* skip the mobility stability check      */
+  NFLBM_FLAG_ALLOW_UNSTABLE = 2,  /* skip the mobility stability check      */
+  NFLBM_FLAG_G_POPULATIONS = 4    /* keep the populations of g even when every
+                                     tau_g = 1 (see "Storage of g" below)      */
 };
+
+/* Storage of g.  With every tau_g = 1 a post-collision population of g is
+ * its equilibrium, C_i s_k(v) - w_k m mu~_i (Eqs. glbe, geq), so by default
+ * the library keeps per node only the C_i the collision used, mu~_i, v and
+ * v.v, and the reconstruction of the next step re-forms the populations from
+ * them, in the same operations and storage rounding as the population form:
+ * both forms give bit-identical results.  Some tau_g != 1, or
+ * NFLBM_FLAG_G_POPULATIONS, keeps the 19 (N - 1) populations per node.
+ * nflbm_storage_form tells which form a simulation uses. */
 
 /*
  * Problem statement (Sec. II-III).
@@ -184,7 +195,8 @@ int nflbm_step_timed(nflbm_sim *sim, long long nsteps, double *ms, double *ms_up
 int nflbm_get_field(nflbm_sim *sim, int field, double *host_out);
 
 /* Raw state checkpoint: nflbm_state_bytes gives the size, get_state copies
- * the device state (both population sets, storage precision) to host_raw,
+ * the device state (storage precision: f_1..f_{Q-1}, then the populations of
+ * g or, in the moment form, the node records C, mu~, (v, v.v)) to host_raw,
  * set_state restores it bit for bit.  Synchronise. */
 int nflbm_state_bytes(nflbm_sim *sim, size_t *bytes);
 int nflbm_get_state(nflbm_sim *sim, void *host_raw);
@@ -214,6 +226,9 @@ int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, doub
  * device's LDS bytes per workgroup (any output pointer may be NULL). */
 int nflbm_set_launch(nflbm_sim *sim, int tx_log2, int zchunk);
 int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
+
+/* 1 if sim keeps g in the moment form, 0 for populations, negative on error. */
+int nflbm_storage_form(const nflbm_sim *sim);
 
 /* Bytes moved per lattice-node update by the reconstruction and update
  * kernels together, counting every stored population once read and once

@@ -22,6 +22,7 @@ D2Q9, D3Q19 = 0, 1
 FP64, FP32, FP16S = 0, 1, 2
 FLAG_POTENTIAL_FORCE = 1
 FLAG_ALLOW_UNSTABLE = 2
+FLAG_G_POPULATIONS = 4
 FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 BATCH_MODES = {"launch": 0, "graph": 1, "per_sim": 2}
@@ -100,6 +101,7 @@ def lib():
             "nflbm_last_error": (ctypes.c_char_p, [P]),
             "nflbm_abi_version": (I, []),
             "nflbm_autotune": (I, [P, ctypes.c_char_p]),
+            "nflbm_storage_form": (I, [P]),
             "nflbm_batch_create": (I, [ctypes.POINTER(Config), I, ctypes.POINTER(P)]),
             "nflbm_batch_destroy": (None, [P]),
             "nflbm_batch_count": (I, [P]),
@@ -322,6 +324,13 @@ class Simulation:
         b = ctypes.c_double()
         _check(lib().nflbm_bytes_per_node(self._handle(), ctypes.byref(b)), self._h)
         return b.value
+
+    def storage_form(self):
+        """'moments' (g kept as C, mu~, v per node; every tau_g = 1) or 'populations'."""
+        r = lib().nflbm_storage_form(self._handle())
+        if r < 0:
+            _check(r, self._h)
+        return "moments" if r == 1 else "populations"
 
     def autotune(self, cache_path=None):
         """Time the launch shapes and keep the fastest (state unchanged)."""

@@ -20,7 +20,10 @@ ARCH = os.environ.get("NFLBM_OFFLOAD_ARCH", "gfx950")
 
 # Device-code flags: gfx950 only; packed FP32 instructions are kept out of the
 # generated code (the compiler would otherwise form them from float code).
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# No implicit contraction of a*b + c: the kernels spell their fused
+# multiply-adds as fma(), so every instantiation of a kernel body (single or
+# batch launch, either storage form of g) rounds identically.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
           "-Wall", "-Wno-unused-function"]
 

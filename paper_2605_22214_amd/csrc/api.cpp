@@ -47,7 +47,12 @@ struct nflbm_sim {
   void* f[2] = {nullptr, nullptr};
   void* g0[2] = {nullptr, nullptr};
   void* gk[2] = {nullptr, nullptr};
-  void* conc = nullptr;
+  // reconstructed C: one array (population form), or the two records of the
+  // moment form (the collision's C of the current state, and the next C)
+  void* conc[2] = {nullptr, nullptr};
+  void* mu = nullptr;    // moment form: mu~ [node][i]
+  void* vel = nullptr;   // moment form: (v, v.v) [node][4]
+  int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
   void* eb = nullptr;
   void* params = nullptr;
   double* fields = nullptr;
@@ -147,12 +152,18 @@ void free_device(nflbm_sim* s) {
     if (s->gk[b]) (void)hipFree(s->gk[b]);
     s->f[b] = s->g0[b] = s->gk[b] = nullptr;
   }
-  if (s->conc) (void)hipFree(s->conc);
+  for (int b = 0; b < 2; ++b) {
+    if (s->conc[b]) (void)hipFree(s->conc[b]);
+    s->conc[b] = nullptr;
+  }
+  if (s->mu) (void)hipFree(s->mu);
+  if (s->vel) (void)hipFree(s->vel);
+  s->mu = s->vel = nullptr;
   if (s->eb) (void)hipFree(s->eb);
   if (s->params) (void)hipFree(s->params);
   if (s->fields) (void)hipFree(s->fields);
   if (s->red) (void)hipFree(s->red);
-  s->conc = s->params = s->eb = nullptr;
+  s->params = s->eb = nullptr;
   s->fields = s->red = nullptr;
 }
 
@@ -178,6 +189,7 @@ bool apply_launch(nflbm_sim* s, int l, int zc) {
   if (zc < 1) return false;
   if (zc > s->nz) zc = s->nz;
   if (update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
+  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
   const int TX = 1 << l, TY = 256 >> l;
   s->tx_log2 = l;
   s->zchunk = zc;
@@ -192,9 +204,13 @@ bool apply_launch(nflbm_sim* s, int l, int zc) {
 // workgroups (1024 in FP64, where longer runs measured faster).
 int choose_launch(nflbm_sim* s) {
   s->lds_max = device_lds_max();
+  auto fits = [&](int t) {
+    return update_lds_bytes(s->lat, s->N, s->store, t) <= s->lds_max &&
+           (!s->gform || conc_m_lds_bytes(s->lat, s->N, s->store, t) <= s->lds_max);
+  };
   int l = s->nx <= 16 ? 4 : 6;
-  if (l == 6 && update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) l = 4;
-  if (update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return -1;
+  if (l == 6 && !fits(l)) l = 4;
+  if (!fits(l)) return -1;
   int zc = 1;
   if (s->lat == NFLBM_D3Q19) {
     const int TX = 1 << l, TY = 256 >> l;
@@ -213,11 +229,18 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   StepArgs a{};
   a.f_src = s->f[src];
   a.f_dst = s->f[1 - src];
-  a.g0_src = s->g0[src];
-  a.g0_dst = s->g0[1 - src];
-  a.gk_src = s->gk[src];
-  a.gk_dst = s->gk[1 - src];
-  a.conc = s->conc;
+  if (s->gform) {
+    a.cprev = s->conc[src];
+    a.conc = s->conc[1 - src];
+    a.mu = s->mu;
+    a.vel = s->vel;
+  } else {
+    a.g0_src = s->g0[src];
+    a.g0_dst = s->g0[1 - src];
+    a.gk_src = s->gk[src];
+    a.gk_dst = s->gk[1 - src];
+    a.conc = s->conc[0];
+  }
   a.eb = s->eb;
   a.fields = s->fields;
   a.params = s->params;
@@ -258,6 +281,24 @@ int compute_fields(nflbm_sim* s) {
   return NFLBM_OK;
 }
 
+
+// Device arrays that make up the current state, in checkpoint order:
+// f_1..f_{Q-1}, then the populations g_{i,0}, g_{i,k} (population form) or
+// the node records C, mu~, (v, v.v) (moment form).
+std::vector<std::pair<void*, size_t>> state_segments(nflbm_sim* s) {
+  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  std::vector<std::pair<void*, size_t>> v;
+  v.emplace_back(s->f[s->cur], Qm * n * s->fs);
+  if (s->gform) {
+    v.emplace_back(s->conc[s->cur], NE * n * s->ts);
+    v.emplace_back(s->mu, NE * n * s->ts);
+    v.emplace_back(s->vel, 4 * n * s->ts);
+  } else {
+    v.emplace_back(s->g0[s->cur], NE * n * s->g0s);
+    v.emplace_back(s->gk[s->cur], NE * Qm * n * s->fs);
+  }
+  return v;
+}
 
 // ------------------------------------------------------------ batches
 int bfail(nflbm_batch* b, int code, const std::string& msg) {
@@ -360,6 +401,12 @@ int batch_half(nflbm_batch* b, int* half) {
   return build_batch_tables(b, false);
 }
 
+bool batch_tile_fits(const nflbm_batch* b, int l) {
+  const size_t lim = b->members[0]->lds_max;
+  return update_lds_bytes(b->lat, b->N, b->store, l) <= lim &&
+         (!b->members[0]->gform || conc_m_lds_bytes(b->lat, b->N, b->store, l) <= lim);
+}
+
 hipError_t launch_half(nflbm_batch* b, int half) {
   BatchLaunch bl{};
   bl.args = b->args + size_t(half) * b->members.size();
@@ -370,6 +417,7 @@ hipError_t launch_half(nflbm_batch* b, int half) {
   bl.blocks_update = b->blocks_update;
   bl.tx_log2 = b->tx_log2;
   bl.walls = b->walls;
+  bl.moments = b->members[0]->gform;
   return launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
 }
 
@@ -480,41 +528,32 @@ std::string sim_key(const nflbm_sim* s) {
   return o.str();
 }
 
-// Device copy of the current population set of s (restored after timing).
+// Device copy of the current state of s (restored after timing).
 struct SavedState {
-  void* f = nullptr;
-  void* g0 = nullptr;
-  void* gk = nullptr;
+  std::vector<void*> copies;
   int cur = 0;
 };
 
 int save_state(nflbm_sim* s, SavedState* st) {
-  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
   st->cur = s->cur;
-  bool ok = hipMalloc(&st->f, Qm * n * s->fs) == hipSuccess;
-  ok = ok && hipMalloc(&st->g0, NE * n * s->g0s) == hipSuccess;
-  ok = ok && hipMalloc(&st->gk, NE * Qm * n * s->fs) == hipSuccess;
-  if (!ok) return fail(s, NFLBM_ENOMEM, "cannot allocate the autotuner's state copy");
-  HIPCHK(s, hipMemcpyAsync(st->f, s->f[s->cur], Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream));
-  HIPCHK(s, hipMemcpyAsync(st->g0, s->g0[s->cur], NE * n * s->g0s, hipMemcpyDeviceToDevice, s->stream));
-  HIPCHK(s, hipMemcpyAsync(st->gk, s->gk[s->cur], NE * Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream));
+  for (const auto& seg : state_segments(s)) {
+    void* c = nullptr;
+    if (hipMalloc(&c, seg.second) != hipSuccess) return fail(s, NFLBM_ENOMEM, "cannot allocate the autotuner's state copy");
+    st->copies.push_back(c);
+    HIPCHK(s, hipMemcpyAsync(c, seg.first, seg.second, hipMemcpyDeviceToDevice, s->stream));
+  }
   return NFLBM_OK;
 }
 
 int restore_state(nflbm_sim* s, SavedState* st) {
-  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
   s->cur = st->cur;
+  const auto segs = state_segments(s);
   hipError_t e = hipSuccess;
-  if (st->f) e = hipMemcpyAsync(s->f[s->cur], st->f, Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess && st->g0)
-    e = hipMemcpyAsync(s->g0[s->cur], st->g0, NE * n * s->g0s, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess && st->gk)
-    e = hipMemcpyAsync(s->gk[s->cur], st->gk, NE * Qm * n * s->fs, hipMemcpyDeviceToDevice, s->stream);
+  for (size_t i = 0; i < st->copies.size() && i < segs.size() && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(segs[i].first, st->copies[i], segs[i].second, hipMemcpyDeviceToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (st->f) (void)hipFree(st->f);
-  if (st->g0) (void)hipFree(st->g0);
-  if (st->gk) (void)hipFree(st->gk);
-  st->f = st->g0 = st->gk = nullptr;
+  for (void* c : st->copies) (void)hipFree(c);
+  st->copies.clear();
   if (e != hipSuccess) return hip_fail(s, e, "autotune: restoring the state");
   return NFLBM_OK;
 }
@@ -640,6 +679,11 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
     if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
   if (cfg->flags & NFLBM_FLAG_POTENTIAL_FORCE) s->step_flags |= kFlagPotential;
   if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
+  // With every tau_g = 1 the post-collision g are equilibria of (C, mu~, v):
+  // store those per node instead of the populations, unless asked not to.
+  s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS)) ? 1 : 0;
+  if (s->gform && choose_launch(s) != 0) s->gform = 0;   // its LDS window does not fit
+  if (s->gform) s->step_flags |= kFlagMoments;
   if (choose_launch(s) != 0) {
     delete s;
     return fail(nullptr, NFLBM_ENOTSUP, "LDS window does not fit the device for this N and precision");
@@ -654,10 +698,19 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   bool ok = true;
   for (int b = 0; b < 2 && ok; ++b) {
     ok &= hipMalloc(&s->f[b], Qm * n * s->fs) == hipSuccess;
-    ok &= hipMalloc(&s->g0[b], NE * n * s->g0s) == hipSuccess;
-    ok &= hipMalloc(&s->gk[b], NE * Qm * n * s->fs) == hipSuccess;
+    if (s->gform) {
+      ok = ok && hipMalloc(&s->conc[b], NE * n * s->ts) == hipSuccess;
+    } else {
+      ok = ok && hipMalloc(&s->g0[b], NE * n * s->g0s) == hipSuccess;
+      ok = ok && hipMalloc(&s->gk[b], NE * Qm * n * s->fs) == hipSuccess;
+    }
   }
-  ok = ok && hipMalloc(&s->conc, NE * n * s->ts) == hipSuccess;
+  if (s->gform) {
+    ok = ok && hipMalloc(&s->mu, NE * n * s->ts) == hipSuccess;
+    ok = ok && hipMalloc(&s->vel, 4 * n * s->ts) == hipSuccess;
+  } else {
+    ok = ok && hipMalloc(&s->conc[0], NE * n * s->ts) == hipSuccess;
+  }
   ok = ok && hipMalloc(&s->eb, n * s->ts) == hipSuccess;
   const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
   ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
@@ -725,8 +778,8 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
   if (e == hipSuccess) {
     InitArgs a{};
     a.f = sim->f[sim->cur];
-    a.g0 = sim->g0[sim->cur];
-    a.gk = sim->gk[sim->cur];
+    a.g0 = sim->g0[sim->cur];   // population form (null in the moment form, whose
+    a.gk = sim->gk[sim->cur];   // records are reached through a.sa)
     a.C = dC;
     a.v = dv;
     a.P = dP;
@@ -824,8 +877,30 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     } else {
       g0buf.resize(size_t(NE) * n * sim->g0s);
       gkbuf.resize(size_t(NE) * Qm * n * sim->fs);
-      HIPCHK(sim, hipMemcpyAsync(g0buf.data(), sim->g0[sim->cur], g0buf.size(), hipMemcpyDeviceToHost, sim->stream));
-      HIPCHK(sim, hipMemcpyAsync(gkbuf.data(), sim->gk[sim->cur], gkbuf.size(), hipMemcpyDeviceToHost, sim->stream));
+      const void* g0dev = sim->g0[sim->cur];
+      const void* gkdev = sim->gk[sim->cur];
+      void* tmp = nullptr;
+      if (sim->gform) {
+        // the moment form holds no populations: write them out from the
+        // node records, as the population form would have stored them
+        if (hipMalloc(&tmp, g0buf.size() + gkbuf.size()) != hipSuccess)
+          return fail(sim, NFLBM_ENOMEM, "cannot allocate the population read-back buffer");
+        StepArgs a = make_args(sim, sim->cur);
+        a.g0_dst = tmp;
+        a.gk_dst = static_cast<unsigned char*>(tmp) + g0buf.size();
+        const hipError_t e = launch_expand(sim->lat, sim->N, sim->store, a, sim->stream);
+        if (e != hipSuccess) {
+          (void)hipFree(tmp);
+          return hip_fail(sim, e, "launch_expand");
+        }
+        g0dev = a.g0_dst;
+        gkdev = a.gk_dst;
+      }
+      hipError_t e = hipMemcpyAsync(g0buf.data(), g0dev, g0buf.size(), hipMemcpyDeviceToHost, sim->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(gkbuf.data(), gkdev, gkbuf.size(), hipMemcpyDeviceToHost, sim->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+      if (tmp) (void)hipFree(tmp);
+      if (e != hipSuccess) return hip_fail(sim, e, "G_RAW read-back");
     }
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
     auto val = [&](const unsigned char* base, size_t idx, size_t bytes, bool moving) -> double {
@@ -878,33 +953,30 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
 
 int nflbm_state_bytes(nflbm_sim* sim, size_t* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
-  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
-  *bytes = Qm * n * sim->fs + NE * n * sim->g0s + NE * Qm * n * sim->fs;
+  size_t b = 0;
+  for (const auto& seg : state_segments(sim)) b += seg.second;
+  *bytes = b;
   return NFLBM_OK;
 }
 
 int nflbm_get_state(nflbm_sim* sim, void* host_raw) {
   if (!sim || !host_raw) return fail(sim, NFLBM_EINVAL, "NULL argument");
-  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
   unsigned char* p = static_cast<unsigned char*>(host_raw);
-  HIPCHK(sim, hipMemcpyAsync(p, sim->f[sim->cur], Qm * n * sim->fs, hipMemcpyDeviceToHost, sim->stream));
-  p += Qm * n * sim->fs;
-  HIPCHK(sim, hipMemcpyAsync(p, sim->g0[sim->cur], NE * n * sim->g0s, hipMemcpyDeviceToHost, sim->stream));
-  p += NE * n * sim->g0s;
-  HIPCHK(sim, hipMemcpyAsync(p, sim->gk[sim->cur], NE * Qm * n * sim->fs, hipMemcpyDeviceToHost, sim->stream));
+  for (const auto& seg : state_segments(sim)) {
+    HIPCHK(sim, hipMemcpyAsync(p, seg.first, seg.second, hipMemcpyDeviceToHost, sim->stream));
+    p += seg.second;
+  }
   HIPCHK(sim, hipStreamSynchronize(sim->stream));
   return NFLBM_OK;
 }
 
 int nflbm_set_state(nflbm_sim* sim, const void* host_raw) {
   if (!sim || !host_raw) return fail(sim, NFLBM_EINVAL, "NULL argument");
-  const size_t n = sim->n, Qm = sim->Q - 1, NE = sim->NE;
   const unsigned char* p = static_cast<const unsigned char*>(host_raw);
-  HIPCHK(sim, hipMemcpyAsync(sim->f[sim->cur], p, Qm * n * sim->fs, hipMemcpyHostToDevice, sim->stream));
-  p += Qm * n * sim->fs;
-  HIPCHK(sim, hipMemcpyAsync(sim->g0[sim->cur], p, NE * n * sim->g0s, hipMemcpyHostToDevice, sim->stream));
-  p += NE * n * sim->g0s;
-  HIPCHK(sim, hipMemcpyAsync(sim->gk[sim->cur], p, NE * Qm * n * sim->fs, hipMemcpyHostToDevice, sim->stream));
+  for (const auto& seg : state_segments(sim)) {
+    HIPCHK(sim, hipMemcpyAsync(seg.first, p, seg.second, hipMemcpyHostToDevice, sim->stream));
+    p += seg.second;
+  }
   HIPCHK(sim, hipStreamSynchronize(sim->stream));
   return NFLBM_OK;
 }
@@ -970,11 +1042,20 @@ int nflbm_get_launch(nflbm_sim* sim, int* tx_log2, int* zchunk, int* lds_limit) 
   return NFLBM_OK;
 }
 
+int nflbm_storage_form(const nflbm_sim* sim) { return sim ? sim->gform : NFLBM_EINVAL; }
+
 int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const double Qm = sim->Q - 1, NE = sim->NE;
-  double b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;
-  if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;
+  double b;
+  if (sim->gform) {
+    // f read and written; reconstruction reads C, mu~, (v, v.v) and writes
+    // C, E_B; the update reads C, E_B and writes mu~, (v, v.v)
+    b = 2.0 * Qm * sim->fs + (NE + NE + 4 + NE + 1 + NE + 1 + NE + 4) * double(sim->ts);
+  } else {
+    b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;
+    if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;
+  }
   *bytes = b;
   return NFLBM_OK;
 }
@@ -1036,6 +1117,17 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
     if (cfgs[i].lattice != cfgs[0].lattice || cfgs[i].ncomp != cfgs[0].ncomp ||
         cfgs[i].precision != cfgs[0].precision)
       return bfail(nullptr, NFLBM_EINVAL, "batch members must share lattice, ncomp and precision");
+  // one storage form of g for every member: populations if any member needs
+  // them (some tau_g != 1, or asked for)
+  std::vector<nflbm_config> cc(cfgs, cfgs + count);
+  bool pop = false;
+  for (const auto& c : cc) {
+    if (c.flags & NFLBM_FLAG_G_POPULATIONS) pop = true;
+    for (int i = 0; c.tau_g && i < c.ncomp; ++i)
+      if (c.tau_g[i] != 1.0) pop = true;
+  }
+  if (pop)
+    for (auto& c : cc) c.flags |= NFLBM_FLAG_G_POPULATIONS;
   nflbm_batch* b = new nflbm_batch();
   b->lat = cfgs[0].lattice;
   b->N = cfgs[0].ncomp;
@@ -1047,11 +1139,22 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
     delete b;
     return bfail(nullptr, code, msg);
   };
-  for (int i = 0; i < count; ++i) {
-    nflbm_sim* m = nullptr;
-    const int rc = nflbm_create(&cfgs[i], &m);
-    if (rc != NFLBM_OK) return cleanup(rc, "member " + std::to_string(i) + ": " + nflbm_last_error(nullptr));
-    b->members.push_back(m);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    for (int i = 0; i < count; ++i) {
+      nflbm_sim* m = nullptr;
+      const int rc = nflbm_create(&cc[i], &m);
+      if (rc != NFLBM_OK) return cleanup(rc, "member " + std::to_string(i) + ": " + nflbm_last_error(nullptr));
+      b->members.push_back(m);
+    }
+    bool same = true;
+    for (nflbm_sim* m : b->members) same = same && m->gform == b->members[0]->gform;
+    if (same) break;
+    // a member fell back to populations (its LDS window): all do
+    for (nflbm_sim* m : b->members) nflbm_destroy(m);
+    b->members.clear();
+    for (auto& c : cc) c.flags |= NFLBM_FLAG_G_POPULATIONS;
+  }
+  for (nflbm_sim* m : b->members) {
     b->nodes += static_cast<long long>(m->n);
     if (m->wall[0] || m->wall[1] || m->wall[2]) b->walls = 1;
   }
@@ -1076,7 +1179,7 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
   int l = 6;
   for (nflbm_sim* m : b->members)
     if (m->nx <= 16) l = 4;
-  if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max) l = 4;
+  if (!batch_tile_fits(b, l)) l = 4;
   b->tx_log2 = l;
   const int rc = build_batch_tables(b, true);
   if (rc != NFLBM_OK) {
@@ -1170,8 +1273,7 @@ int nflbm_batch_set_launch(nflbm_batch* b, int tx_log2, int graph_steps) {
   const int g = graph_steps > 0 ? graph_steps : b->graph_steps;
   if (l != 4 && l != 6) return bfail(b, NFLBM_EINVAL, "tx_log2 must be 4 or 6");
   if (g < 2 || (g & 1)) return bfail(b, NFLBM_EINVAL, "graph_steps must be even and >= 2");
-  if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max)
-    return bfail(b, NFLBM_EINVAL, "LDS window too large for this tile");
+  if (!batch_tile_fits(b, l)) return bfail(b, NFLBM_EINVAL, "LDS window too large for this tile");
   const bool shape = l != b->tx_log2 || g != b->graph_steps;
   b->tx_log2 = l;
   b->graph_steps = g;
@@ -1219,7 +1321,7 @@ int nflbm_batch_autotune(nflbm_batch* b, const char* cache_path) {
   best = {b->tx_log2};
   for (int l : {4, 6}) {
     if (rc != NFLBM_OK) break;
-    if (update_lds_bytes(b->lat, b->N, b->store, l) > b->members[0]->lds_max) continue;
+    if (!batch_tile_fits(b, l)) continue;
     rc = nflbm_batch_set_launch(b, l, 0);
     double ms = 0.0;
     if (rc == NFLBM_OK) rc = batch_run(b, b->graph_steps, NFLBM_BATCH_GRAPH);  // warm-up and capture

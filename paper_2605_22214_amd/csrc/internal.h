@@ -39,7 +39,8 @@ struct DevParams {
 enum StepFlags {
   kFlagNeedG = 1,         // some tau_g != 1: the update reads g
   kFlagPotential = 2,     // potential-form surface tension
-  kFlagOmega = 4          // Omega != 0
+  kFlagOmega = 4,         // Omega != 0
+  kFlagMoments = 8        // moment form of g (tau_g = 1): C, mu~, v, v.v per node
 };
 
 // Device code sees the pointers in the argument structs as pointers to global
@@ -63,6 +64,11 @@ struct StepArgs {
   const NFLBM_GLOBAL void* gk_src;    // moving populations of evolved components
   NFLBM_GLOBAL void* gk_dst;
   NFLBM_GLOBAL void* conc;            // reconstructed C (compute precision)
+  // moment form: the node records of the previous step (C the collision
+  // used, mu~ [node][i], and (v, v.v) [node][4]); the populations are unused
+  const NFLBM_GLOBAL void* cprev;
+  NFLBM_GLOBAL void* mu;
+  NFLBM_GLOBAL void* vel;
   NFLBM_GLOBAL void* eb;              // E_B per node (compute precision)
   NFLBM_GLOBAL double* fields;        // fields-mode output [2N+7][n]
   const NFLBM_GLOBAL void* params;    // DevParams<T>
@@ -95,11 +101,14 @@ struct InitArgs {
 struct BatchLaunch {
   const StepArgs* args;               // device [count]
   const void* params;                 // device DevParams<T>[count]
-  const int2* work_conc;              // device [blocks_conc]
+  const int2* work_conc;              // device [blocks_conc] (population form)
   const int2* work_update;            // device [blocks_update]
   int blocks_conc, blocks_update;
   int tx_log2;
   int walls;                          // some member has a wall
+  int moments;                        // members use the moment form; the
+                                      // reconstruction then runs over the
+                                      // update's tiles
 };
 
 struct ReduceArgs {
@@ -117,6 +126,8 @@ hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s);
 hipError_t launch_init(int lat, int nc, int store, const InitArgs& a, hipStream_t s);
 hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, hipStream_t s);
+hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
+size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 __host__ __device__ int reduce_record_len(int N);
 size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);

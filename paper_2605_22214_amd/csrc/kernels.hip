@@ -199,7 +199,11 @@ __device__ __forceinline__ size_t fresh(size_t v) {
 // Read-only tables seen through the constant address space: uniform reads
 // become scalar loads with immediate offsets, and the pointer is fresh at the
 // point of use (see above).
+#if defined(__HIP_DEVICE_COMPILE__)
 #define NFLBM_CONST __attribute__((address_space(4)))
+#else
+#define NFLBM_CONST
+#endif
 template <class E>
 __device__ __forceinline__ const NFLBM_CONST E* fresh_const(const E* p) {
   const NFLBM_CONST E* c = (const NFLBM_CONST E*)(const NFLBM_GLOBAL E*)p;
@@ -219,12 +223,12 @@ __device__ __forceinline__ T fpoly(T c) {
 }
 template <class T>
 __device__ __forceinline__ T fprime(T c) {
-  return T(2) * c * (T(1) - T(3) * c + T(2) * c * c);
+  return (T(2) * c) * fma(T(2) * c, c, fma(-T(3), c, T(1)));
 }
 
 // E_B = sum_{i<j} beta_ij [f(C_i) + f(C_j) - f(C_i + C_j)]  (Eq. FreeEnergy)
-template <int NC, class T>
-__device__ __forceinline__ T bulk_energy(const T (&c)[NC], const DevParams<T>& P) {
+template <int NC, class T, class PT>
+__device__ __forceinline__ T bulk_energy(const T (&c)[NC], const PT& P) {
   T fi[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) fi[i] = fpoly(c[i]);
@@ -232,13 +236,49 @@ __device__ __forceinline__ T bulk_energy(const T (&c)[NC], const DevParams<T>& P
 #pragma unroll
   for (int i = 0; i < NC; ++i)
 #pragma unroll
-    for (int j = i + 1; j < NC; ++j) e += P.beta[i][j] * (fi[i] + fi[j] - fpoly(c[i] + c[j]));
+    for (int j = i + 1; j < NC; ++j) e = fma(P.beta[i][j], fi[i] + fi[j] - fpoly(c[i] + c[j]), e);
   return e;
 }
 
 __device__ __forceinline__ int wrap(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+
+// ------------------------------------------------- equilibrium pair terms
+// e_k . a for a 3-vector a, accumulated over the nonzero components of e_k.
+template <class L, class T>
+__device__ __forceinline__ T proj(int k, const T (&a)[3]) {
+  T r = T(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (L::e[k][d] != 0) r += (L::e[k][d] > 0) ? a[d] : -a[d];
+  return r;
+}
+
+// s_k(v) = w_k [3 e_k.v + 4.5 (e_k.v)^2 - 1.5 v.v] (Eqs. feq, geq) for
+// direction kd, formed through the odd member k of its pair {k, k+1} so that
+// both members come from the same ev = e_k.v and quad; base_s = -1.5 v.v.
+// Every kernel that forms s_k goes through here: the reconstruction of the
+// moment form re-forms the update's post-collision populations bit for bit.
+template <class L, class T>
+__device__ __forceinline__ T quad_term(T ev, T base_s) {
+  return fma(T(4.5) * ev, ev, base_s);
+}
+template <class L, class T>
+__device__ __forceinline__ T s_pair_member(int kd, T ev, T quad) {
+  return static_cast<T>(L::w[kd]) * fma((kd & 1) ? T(3) : -T(3), ev, quad);
+}
+
+// Post-collision population of an evolved component for tau_g = 1, i.e. its
+// equilibrium C s_k - w_k m mu~ (Eq. geq, rest-population reading), as the
+// update forms it.  The moment form keeps it in the compute precision: with
+// FP32 and FP64 storage that is the stored value of the population form, bit
+// for bit; with FP16S (binary16 moving populations) the moment form skips
+// that rounding, since it stores no populations of g.
+template <class T>
+__device__ __forceinline__ T g_post(T c, T s, T mmu) {
+  return fma(c, s, -mmu);
 }
 
 // ------------------------------------------------------- streaming sources
@@ -406,6 +446,270 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
   conc_tile<L, NE, ST, WALLS>(a, params + w.x, w.y);
 }
 
+// --------------------------------------------------- k_conc, moment form
+// With tau_g = 1 the post-collision populations of every evolved component
+// are its equilibria, C_i s_k(v) - w_k m mu~_i (Eq. glbe with tau_g = 1,
+// Eq. geq), so the state holds, per node, the C_i the collision used, mu~_i,
+// v and v.v instead of the 19 (N - 1) populations.  This kernel re-forms them
+// where they are needed:
+//   C_i(x, t+1) = [C_i(x) - sum_{k>=1} g*_{i,k}(x)] + sum_{k>=1} g*_{i,k}(x - e_k)
+// (rest population plus streamed moving populations, halfway bounce-back at
+// walls), in the order in which the population form sums them and in the
+// compute precision, so with FP32 and FP64 storage both forms give identical
+// bits.  The per-node records of
+// the tile and a one-node halo sit in LDS (three planes in D3Q19, marched
+// along z like the update).
+template <class L, int NE>
+constexpr int moment_record() { return 2 * NE + 4; }   // C[NE], mu~[NE], v[3], v.v
+
+template <class L, int NE, int ST, bool WALLS, int TXL>
+__device__ __forceinline__ void conc_tile_m(const StepArgs& a,
+                                            const DevParams<typename StoreT<ST>::T>* __restrict__ Pp, int b,
+                                            unsigned char* smem_raw) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
+  using G0S = typename S::G0S;
+  constexpr int Q = L::Q;
+  constexpr int NC = NE + 1;
+  constexpr bool D3 = (L::DIM == 3);
+  constexpr int REC = moment_record<L, NE>();
+  constexpr int TX = 1 << TXL;
+  constexpr int TY = 256 >> TXL;
+  constexpr int PX = TX + 2;
+  constexpr int PXY = PX * (TY + 2);
+  constexpr int plane_stride = REC * PXY;
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const DevParams<T>* P0 = gptr<const DevParams<T>>(Pp);
+  const int tid = threadIdx.x;
+  const int tx = tid & (TX - 1);
+  const int ty = tid >> TXL;
+  const int tile_x = b % a.tiles_x;
+  b /= a.tiles_x;
+  const int tile_y = b % a.tiles_y;
+  const int chunk = b / a.tiles_y;
+  const int x0 = tile_x * TX, y0 = tile_y * TY;
+  const int z0 = chunk * a.zchunk;
+  const int z1 = min(z0 + a.zchunk, a.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool active = (x < a.nx) && (y < a.ny);
+  const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
+  const T* cprev = gptr<const T>(a.cprev);
+  const T* mus = gptr<const T>(a.mu);
+  const T* vels = gptr<const T>(a.vel);
+
+  uint32_t fill_off[2];
+  bool fill_ok[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int idx = tid + 256 * r;
+    fill_ok[r] = idx < PXY;
+    fill_off[r] = 0;
+    if (fill_ok[r]) {
+      const int ly = idx / PX;
+      const int lx = idx - ly * PX;
+      int gx = x0 + lx - 1, gy = y0 + ly - 1;
+      if (gx < 0 || gx >= a.nx) {
+        if (WALLS && a.wall_x) fill_ok[r] = false;
+        else gx = wrap(gx, a.nx);
+      }
+      if (gy < 0 || gy >= a.ny) {
+        if (WALLS && a.wall_y) fill_ok[r] = false;
+        else gy = wrap(gy, a.ny);
+      }
+      fill_off[r] = uint32_t(gx) + nx * uint32_t(gy);
+    }
+  }
+
+  // Records of plane gz into an LDS slot, one field after another.  Positions
+  // inside a wall stay unfilled: a population pulled from a wall is this
+  // node's own, so they are never read.
+  auto load_plane = [&](int slot, int gz) {
+    T* base = sm + slot * plane_stride;
+    if (gz < 0 || gz >= a.nz) {
+      if (WALLS && a.wall_z) return;
+      gz = (gz < 0) ? gz + a.nz : gz - a.nz;
+    }
+    const uint32_t zoff = uint32_t(gz) * nxy;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!fill_ok[r]) continue;
+      const int idx = tid + 256 * r;
+      const uint32_t node = fill_off[r] + zoff;
+      T cc[NE], mm[NE], vv[4];
+      vld<T, NE>(at(cprev, node * NE), cc);
+      vld<T, NE>(at(mus, node * NE), mm);
+      vld<T, 4>(at(vels, node * 4), vv);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        base[e * PXY + idx] = cc[e];
+        base[(NE + e) * PXY + idx] = mm[e];
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) base[(2 * NE + d) * PXY + idx] = vv[d];
+    }
+  };
+
+  auto process = [&](int z, int s_dn, int s_c, int s_up) {
+    const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
+    const T m = P.m;
+    const int li = (ty + 1) * PX + (tx + 1);
+    const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
+    const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+    // this node's record
+    const T* own = sm + s_c * plane_stride + li;
+    T c[NE], mu[NE], v[3];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      c[e] = own[e * PXY];
+      mu[e] = own[(NE + e) * PXY];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[d] = own[(2 * NE + d) * PXY];
+    const T base_s = -T(1.5) * own[(2 * NE + 3) * PXY];
+    // rest population: C minus the stored moving populations, summed pair by
+    // pair as the population form does
+    T moved[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) moved[e] = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const T ev = proj<L>(k, v);
+      const T quad = quad_term<L>(ev, base_s);
+      const T sk = s_pair_member<L>(k, ev, quad);
+      const T sb = s_pair_member<L>(k + 1, ev, quad);
+      const T mw = static_cast<T>(L::w[k]) * m;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const T mmu = mw * mu[e];
+        moved[e] += g_post(c[e], sk, mmu) + g_post(c[e], sb, mmu);
+      }
+    }
+    // moving populations streamed in along e_k from x - e_k (or this node's
+    // own opposite one where x - e_k lies in a wall), in direction order
+    T sum[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) sum[e] = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
+      const bool wall = pulled_from_wall<L, WALLS>(nb, k);
+      const T* src;
+      int kd = k;
+      if (wall) {
+        src = own;
+        kd = opposite(k);
+      } else {
+        const int slot = (ez == 0) ? s_c : (ez > 0 ? s_dn : s_up);
+        src = sm + slot * plane_stride + li - ey * PX - ex;
+      }
+      const int kp = (kd & 1) ? kd : kd - 1;
+      T vs[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) vs[d] = src[(2 * NE + d) * PXY];
+      const T ev = proj<L>(kp, vs);
+      const T quad = quad_term<L>(ev, -T(1.5) * src[(2 * NE + 3) * PXY]);
+      const T sk = s_pair_member<L>(kd, ev, quad);
+      const T mw = static_cast<T>(L::w[kp]) * m;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) sum[e] += g_post(src[e * PXY], sk, mw * src[(NE + e) * PXY]);
+    }
+    T cn[NC];
+    T rest = T(0);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      sum[e] = static_cast<T>(static_cast<G0S>(c[e] - moved[e])) + sum[e];
+      cn[e] = sum[e];
+      rest += sum[e];
+    }
+    cn[NE] = T(1) - rest;
+    vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
+    *at(gptr<T>(a.eb), node) = bulk_energy<NC, T>(cn, P);
+  };
+
+  if constexpr (D3) {
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    for (int z = z0; z < z1; ++z) {
+      const int r = z - z0;
+      const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
+      asm volatile("" ::: "memory");
+      load_plane(s_up, z + 1);
+      __syncthreads();
+      if (active) process(z, s_dn, s_c, s_up);
+      __syncthreads();
+    }
+  } else {
+    load_plane(0, 0);
+    __syncthreads();
+    if (active) process(0, 0, 0, 0);
+  }
+}
+
+template <class L, int NE, int ST, bool WALLS, int TXL>
+__global__ void __launch_bounds__(256)
+k_conc_m(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
+  conc_tile_m<L, NE, ST, WALLS, TXL>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks), smem_raw);
+}
+
+template <class L, int NE, int ST, bool WALLS, int TXL>
+__global__ void __launch_bounds__(256)
+k_conc_m_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
+               const int2* __restrict__ work, int nblocks) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 w = work[xcd_remap(static_cast<int>(blockIdx.x), nblocks)];
+  const StepArgs a = args[w.x];
+  conc_tile_m<L, NE, ST, WALLS, TXL>(a, params + w.x, w.y, smem_raw);
+}
+
+// Post-collision populations of the moment form written out in the
+// population layout (g0 [node][i], gk [k-1][node][i] of the population form),
+// for read-back; one node per thread.  With FP16S the moving ones are
+// rounded to binary16 there, as that layout stores them.
+template <class L, int NE, int ST>
+__global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
+  using FS = typename S::FS;
+  using G0S = typename S::G0S;
+  constexpr int Q = L::Q;
+  const size_t n = static_cast<size_t>(a.n);
+  const size_t node = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n) return;
+  const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
+  T c[NE], mu[NE], vel[4];
+  vld<T, NE>(gptr<const T>(a.cprev) + node * NE, c);
+  vld<T, NE>(gptr<const T>(a.mu) + node * NE, mu);
+  vld<T, 4>(gptr<const T>(a.vel) + node * 4, vel);
+  const T v[3] = {vel[0], vel[1], vel[2]};
+  const T base_s = -T(1.5) * vel[3];
+  T moved[NE];
+  for (int e = 0; e < NE; ++e) moved[e] = T(0);
+  FS* gk = gptr<FS>(a.gk_dst);
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const T ev = proj<L>(k, v);
+    const T quad = quad_term<L>(ev, base_s);
+    const T sk = s_pair_member<L>(k, ev, quad);
+    const T sb = s_pair_member<L>(k + 1, ev, quad);
+    const T mw = static_cast<T>(L::w[k]) * P.m;
+    FS qk[NE], qb[NE];
+    for (int e = 0; e < NE; ++e) {
+      const T mmu = mw * mu[e];
+      const T gk = g_post(c[e], sk, mmu), gb = g_post(c[e], sb, mmu);
+      qk[e] = S::pack(gk);   // read-back layout of the population form
+      qb[e] = S::pack(gb);
+      moved[e] += gk + gb;
+    }
+    vst<FS, NE>(gk + (size_t(k - 1) * n + node) * NE, qk);
+    vst<FS, NE>(gk + (size_t(k) * n + node) * NE, qb);
+  }
+  G0S r0[NE];
+  for (int e = 0; e < NE; ++e) r0[e] = static_cast<G0S>(c[e] - moved[e]);
+  vst<G0S, NE>(gptr<G0S>(a.g0_dst) + node * NE, r0);
+}
+
 // ---------------------------------------------------------------- k_update
 // Occupancy target of the update kernel: three waves per SIMD (at most 168
 // VGPRs) where that needs no spilling (float compute, D3Q19 with N <= 5, all
@@ -417,7 +721,7 @@ constexpr int update_waves() {
 
 // One workgroup's share of the update: tile b of the simulation (x fastest,
 // then y, then the z run), with the LDS window at smem_raw.
-template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL>
+template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL, bool GM>
 __device__ __forceinline__ void update_tile(const StepArgs& a,
                                             const DevParams<typename StoreT<ST>::T>* __restrict__ Pp,
                                             int b, unsigned char* smem_raw) {
@@ -605,14 +909,14 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           if (m != i) row = fma(P.psi[i][l][m], c[m], row);
         br = fma(row, c[l], br);
       }
-      T val = P.k34D * lap[i] + P.k12D * c[i] * br;
+      T val = fma(P.k34D, lap[i], (P.k12D * c[i]) * br);
       if (a.flags & kFlagOmega) {
         T sx = T(0);
 #pragma unroll
         for (int k2 = 0; k2 < NC; ++k2)
 #pragma unroll
           for (int l = k2 + 1; l < NC; ++l)
-            if (k2 != i && l != i) sx += P.xt[i][k2][l] * (c[k2] * c[k2]) * (c[l] * c[l]);
+            if (k2 != i && l != i) sx = fma(P.xt[i][k2][l], (c[k2] * c[k2]) * (c[l] * c[l]), sx);
         T sy = T(0);
 #pragma unroll
         for (int l = 0; l < NC; ++l) {
@@ -620,10 +924,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           T inner = T(0);
 #pragma unroll
           for (int m = 0; m < NC; ++m)
-            if (m != i && m != l) inner += P.zt[i][l][m] * c[m];
-          sy += c[l] * c[l] * inner;
+            if (m != i && m != l) inner = fma(P.zt[i][l][m], c[m], inner);
+          sy = fma(c[l] * c[l], inner, sy);
         }
-        val += P.k12D * P.omega_stab * c[i] * (sx + c[i] * sy);
+        val = fma((P.k12D * P.omega_stab) * c[i], fma(c[i], sy, sx), val);
       }
       mu[i] = val;
     }
@@ -638,9 +942,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
         for (int k2 = 0; k2 < NC; ++k2)
           if (k2 != i)
-            mraw += P.beta[i][k2] * (fprime(c[i]) - fprime(c[i] + c[k2])) + P.kappa[i][k2] * lap[k2];
+            mraw += fma(P.kappa[i][k2], lap[k2], P.beta[i][k2] * (fprime(c[i]) - fprime(c[i] + c[k2])));
 #pragma unroll
-        for (int d = 0; d < 3; ++d) F[d] += mraw * gC[i][d];
+        for (int d = 0; d < 3; ++d) F[d] = fma(mraw, gC[i][d], F[d]);
       }
     } else {
       F[0] = gE[0];
@@ -675,7 +979,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
-    const T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const T vv = fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0]));
     const T s0 = static_cast<T>(L::w[0]) * (-T(1.5) * vv);
     const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + s0);
 
@@ -714,16 +1018,22 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     FS* gkdst = gptr<FS>(a.gk_dst);
     G0S* g0dst = gptr<G0S>(a.g0_dst);
     const FS* gksrc = gptr<const FS>(a.gk_src);
-    const T vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+    if constexpr (GM) {
+      // moment form: the reconstruction re-forms g* from mu~, v and v.v
+      vst_nt<T, NE>(at(gptr<T>(a.mu), node * NE), mu);
+      const T vel[4] = {v[0], v[1], v[2], vv};
+      vst_nt<T, 4>(at(gptr<T>(a.vel), node * 4), vel);
+    }
+    const T vF = fma(v[2], F[2], fma(v[1], F[1], v[0] * F[0]));
     const T cP = T(3) * Pn;
-    const T hp = T(0.5) * (T(1) - T(0.5) * wp);
-    const T hm = T(0.5) * (T(1) - T(0.5) * wm);
+    const T hp = T(0.5) * fma(-T(0.5), wp, T(1));
+    const T hm = T(0.5) * fma(-T(0.5), wm, T(1));
     const T base_s = -T(1.5) * vv;
     T moved[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) moved[i] = T(0);
     Nbr nb;
-    if (a.flags & kFlagNeedG) nb = neighbours<WALLS, D3>(x, y, z, a);
+    if (!GM && (a.flags & kFlagNeedG)) nb = neighbours<WALLS, D3>(x, y, z, a);
     const size_t nn = fresh(n);
 
     // ---- per direction pair: TRT collision of f with forcing and BGK
@@ -732,16 +1042,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     for (int k = 1; k < Q; k += 2) {
       const int kb = k + 1;
       const T wk = static_cast<T>(L::w[k]);
-      T ev = T(0), eF = T(0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (L::e[k][d] != 0) {
-          ev += (L::e[k][d] > 0) ? v[d] : -v[d];
-          eF += (L::e[k][d] > 0) ? F[d] : -F[d];
-        }
-      const T quad = fma(T(4.5) * ev, ev, base_s);
-      const T sk_k = wk * fma(T(3), ev, quad);
-      const T sk_b = wk * fma(-T(3), ev, quad);
+      const T ev = proj<L>(k, v), eF = proj<L>(k, F);
+      const T quad = quad_term<L>(ev, base_s);
+      const T sk_k = s_pair_member<L>(k, ev, quad);
+      const T sk_b = s_pair_member<L>(kb, ev, quad);
       const T feq_k = fma(wk, cP, sk_k);
       const T feq_b = fma(wk, cP, sk_b);
       const T fodd = wk * fma(T(9) * ev, eF, -T(3) * vF);
@@ -753,6 +1057,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       const T asym = fma(-wm, fm - em, hm * (Fk - Fb));
       st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(f[k] + sym + asym));
       st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(f[kb] + sym - asym));
+      if constexpr (GM) continue;
       const T mw = wk * P.m;
       FS qk[NE], qb[NE];
       FS ok[NE], ob[NE];
@@ -783,10 +1088,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       vst_nt<FS, NE>(at(gkdst + size_t(k - 1) * nn * NE, node * NE), qk);
       vst_nt<FS, NE>(at(gkdst + size_t(kb - 1) * nn * NE, node * NE), qb);
     }
-    G0S r0[NE];
+    if constexpr (!GM) {
+      G0S r0[NE];
 #pragma unroll
-    for (int i = 0; i < NE; ++i) r0[i] = static_cast<G0S>(c[i] - moved[i]);
-    vst_nt<G0S, NE>(at(g0dst, node * NE), r0);
+      for (int i = 0; i < NE; ++i) r0[i] = static_cast<G0S>(c[i] - moved[i]);
+      vst_nt<G0S, NE>(at(g0dst, node * NE), r0);
+    }
   };
 
   if constexpr (D3) {
@@ -811,33 +1118,35 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   }
 }
 
-template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL>
+template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL, bool GM>
 __global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
 k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
-  update_tile<L, NC, ST, FIELDS, WALLS, TXL>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks), smem_raw);
+  update_tile<L, NC, ST, FIELDS, WALLS, TXL, GM>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks),
+                                                 smem_raw);
 }
 
 // Batch form (see k_conc_batch).  The work list holds each simulation's
 // tiles contiguously, so the XCD remap keeps a simulation's neighbouring tiles
 // on one XCD.
-template <class L, int NC, int ST, bool WALLS, int TXL>
+template <class L, int NC, int ST, bool WALLS, int TXL, bool GM>
 __global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
 k_update_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
                const int2* __restrict__ work, int nblocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 w = work[xcd_remap(static_cast<int>(blockIdx.x), nblocks)];
   const StepArgs a = args[w.x];
-  update_tile<L, NC, ST, false, WALLS, TXL>(a, params + w.x, w.y, smem_raw);
+  update_tile<L, NC, ST, false, WALLS, TXL, GM>(a, params + w.x, w.y, smem_raw);
 }
 
 // ------------------------------------------------------------------ k_init
 // Writes the post-collision arrays so that the first gather yields
 // f_k = f^eq_k(P0, v0) (k >= 1), g_{i,0} = C_i, g_{i,k>=1} = 0: the value a
 // node must receive along e_k is stored where that node will pull it from.
-// Every slot is written exactly once.
-template <class L, int NC, int ST, bool WALLS>
+// Every slot is written exactly once.  In the moment form the same g follows
+// from the record C = C0, mu~ = 0, v = 0 (every s_k(0) is 0).
+template <class L, int NC, int ST, bool WALLS, bool GM>
 __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   using S = StoreT<ST>;
   using T = typename S::T;
@@ -874,17 +1183,29 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     const FS val = S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s));
     if (pulled_from_wall<L, WALLS>(nb, k)) {
       f[size_t(opposite(k) - 1) * n + node] = val;
-      vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, zero);
+      if (!GM) vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, zero);
     } else {
       const uint32_t src = upstream<L>(nb, k);
       f[size_t(k - 1) * n + src] = val;
-      vst<FS, NE>(gk + (size_t(k - 1) * n + src) * NE, zero);
+      if (!GM) vst<FS, NE>(gk + (size_t(k - 1) * n + src) * NE, zero);
     }
   }
-  G0S c0[NE];
+  if constexpr (GM) {
+    T c0[NE], z0[NE], z4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-  for (int i = 0; i < NE; ++i) c0[i] = static_cast<G0S>(a.C[size_t(P.uidx[i]) * n + node]);
-  vst<G0S, NE>(g0 + size_t(node) * NE, c0);
+    for (int i = 0; i < NE; ++i) {
+      c0[i] = static_cast<T>(a.C[size_t(P.uidx[i]) * n + node]);
+      z0[i] = T(0);
+    }
+    vst<T, NE>(gptr<T>(a.sa.cprev) + size_t(node) * NE, c0);
+    vst<T, NE>(gptr<T>(a.sa.mu) + size_t(node) * NE, z0);
+    vst<T, 4>(gptr<T>(a.sa.vel) + size_t(node) * 4, z4);
+  } else {
+    G0S c0[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) c0[i] = static_cast<G0S>(a.C[size_t(P.uidx[i]) * n + node]);
+    vst<G0S, NE>(g0 + size_t(node) * NE, c0);
+  }
 }
 
 // ---------------------------------------------------------------- k_reduce
@@ -993,12 +1314,22 @@ __global__ void __launch_bounds__(64) k_reduce_final(ReduceArgs a) {
 template <int ST>
 using TT = typename StoreT<ST>::T;
 
+// LDS of the update: NE concentrations + E_B per position, 1 or 3 planes.
 template <int ST>
 size_t lds_bytes_for(int lat, int nc, int tx_log2) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
   const int npl = lat == 1 ? 3 : 1;
-  return npl * size_t(nc) * pxy * sizeof(TT<ST>);   // NE concentrations + E_B per slot
+  return npl * size_t(nc) * pxy * sizeof(TT<ST>);
+}
+
+// LDS of the moment-form reconstruction: 2 NE + 4 values per position.
+template <int ST>
+size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
+  const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
+  const size_t pxy = size_t(TX + 2) * (TY + 2);
+  const int npl = lat == 1 ? 3 : 1;
+  return npl * size_t(2 * (nc - 1) + 4) * pxy * sizeof(TT<ST>);
 }
 
 hipError_t update_st0(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
@@ -1013,6 +1344,9 @@ hipError_t conc_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
 hipError_t batch_st0(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 hipError_t batch_st1(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 hipError_t batch_st2(int lat, int nc, const BatchLaunch& b, hipStream_t s);
+hipError_t expand_st0(int lat, int nc, const StepArgs& a, hipStream_t s);
+hipError_t expand_st1(int lat, int nc, const StepArgs& a, hipStream_t s);
+hipError_t expand_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
 
 #if defined(NFLBM_UNIT_STORE) && NFLBM_UNIT_STORE >= 0
 
@@ -1029,6 +1363,7 @@ hipError_t batch_st2(int lat, int nc, const BatchLaunch& b, hipStream_t s);
   }
 
 inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z; }
+inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
 
 template <class L, int NC, int ST>
 hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
@@ -1041,39 +1376,76 @@ hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
     a.tiles_y = (a.ny + 15) / 16;
     const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
     const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, 4);
-    hipLaunchKernelGGL((k_update<L, NC, ST, true, true, 4>), dim3(blocks), dim3(256), lds, s, a, P);
+    hipLaunchKernelGGL((k_update<L, NC, ST, true, true, 4, false>), dim3(blocks), dim3(256), lds, s, a, P);
     return hipGetLastError();
   }
   const StepArgs& a = a0;
-  const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
+  const dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z);
   const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
-  const bool w = any_wall(a);
-  if (a.tx_log2 == 6) {
-    if (w) hipLaunchKernelGGL((k_update<L, NC, ST, false, true, 6>), dim3(blocks), dim3(256), lds, s, a, P);
-    else hipLaunchKernelGGL((k_update<L, NC, ST, false, false, 6>), dim3(blocks), dim3(256), lds, s, a, P);
-  } else if (a.tx_log2 == 4) {
-    if (w) hipLaunchKernelGGL((k_update<L, NC, ST, false, true, 4>), dim3(blocks), dim3(256), lds, s, a, P);
-    else hipLaunchKernelGGL((k_update<L, NC, ST, false, false, 4>), dim3(blocks), dim3(256), lds, s, a, P);
-  } else {
-    return hipErrorInvalidValue;
+#define K_UPD(W, T, G) k_update<L, NC, ST, false, W, T, G>
+  {
+    const bool w_ = any_wall(a), m_ = moments(a);
+    if (a.tx_log2 == 6) {
+      if (w_) { if (m_) hipLaunchKernelGGL((K_UPD(true, 6, true)), grid, dim3(256), lds, s, a, P);
+                else hipLaunchKernelGGL((K_UPD(true, 6, false)), grid, dim3(256), lds, s, a, P); }
+      else { if (m_) hipLaunchKernelGGL((K_UPD(false, 6, true)), grid, dim3(256), lds, s, a, P);
+             else hipLaunchKernelGGL((K_UPD(false, 6, false)), grid, dim3(256), lds, s, a, P); }
+    } else if (a.tx_log2 == 4) {
+      if (w_) { if (m_) hipLaunchKernelGGL((K_UPD(true, 4, true)), grid, dim3(256), lds, s, a, P);
+                else hipLaunchKernelGGL((K_UPD(true, 4, false)), grid, dim3(256), lds, s, a, P); }
+      else { if (m_) hipLaunchKernelGGL((K_UPD(false, 4, true)), grid, dim3(256), lds, s, a, P);
+             else hipLaunchKernelGGL((K_UPD(false, 4, false)), grid, dim3(256), lds, s, a, P); }
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
+#undef K_UPD
   return hipGetLastError();
 }
 
 template <class L, int NC, int ST>
-hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
-  const dim3 grid((a.sa.nx + 63) / 64, (a.sa.ny + 3) / 4, a.sa.nz);
-  if (any_wall(a.sa)) hipLaunchKernelGGL((k_init<L, NC, ST, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_init<L, NC, ST, false>), grid, dim3(256), 0, s, a);
+hipError_t launch_init_t(const InitArgs& ia, hipStream_t s) {
+  const StepArgs& a = ia.sa;
+  const dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
+  const bool w_ = any_wall(a), m_ = moments(a);
+  if (w_) { if (m_) hipLaunchKernelGGL((k_init<L, NC, ST, true, true>), grid, dim3(256), 0, s, ia);
+            else hipLaunchKernelGGL((k_init<L, NC, ST, true, false>), grid, dim3(256), 0, s, ia); }
+  else { if (m_) hipLaunchKernelGGL((k_init<L, NC, ST, false, true>), grid, dim3(256), 0, s, ia);
+         else hipLaunchKernelGGL((k_init<L, NC, ST, false, false>), grid, dim3(256), 0, s, ia); }
   return hipGetLastError();
 }
 
 template <class L, int NC, int ST>
 hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
-  const int blocks = a.tiles_x * a.tiles_y * a.nz;
   const auto* P = (const DevParams<TT<ST>>*)(a.params);
-  if (any_wall(a)) hipLaunchKernelGGL((k_conc<L, NC - 1, ST, true>), dim3(blocks), dim3(256), 0, s, a, P);
+  const bool w_ = any_wall(a);
+  if (moments(a)) {
+    const dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z);
+    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
+#define K_CM(W, T) k_conc_m<L, NC - 1, ST, W, T>
+    if (a.tx_log2 == 6) {
+      if (w_) hipLaunchKernelGGL((K_CM(true, 6)), grid, dim3(256), lds, s, a, P);
+      else hipLaunchKernelGGL((K_CM(false, 6)), grid, dim3(256), lds, s, a, P);
+    } else if (a.tx_log2 == 4) {
+      if (w_) hipLaunchKernelGGL((K_CM(true, 4)), grid, dim3(256), lds, s, a, P);
+      else hipLaunchKernelGGL((K_CM(false, 4)), grid, dim3(256), lds, s, a, P);
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef K_CM
+    return hipGetLastError();
+  }
+  const int blocks = a.tiles_x * a.tiles_y * a.nz;
+  if (w_) hipLaunchKernelGGL((k_conc<L, NC - 1, ST, true>), dim3(blocks), dim3(256), 0, s, a, P);
   else hipLaunchKernelGGL((k_conc<L, NC - 1, ST, false>), dim3(blocks), dim3(256), 0, s, a, P);
+  return hipGetLastError();
+}
+
+template <class L, int NC, int ST>
+hipError_t launch_expand_t(const StepArgs& a, hipStream_t s) {
+  const auto* P = (const DevParams<TT<ST>>*)(a.params);
+  const unsigned blocks = static_cast<unsigned>((a.n + 255) / 256);
+  hipLaunchKernelGGL((k_expand_g<L, NC - 1, ST>), dim3(blocks), dim3(256), 0, s, a, P);
   return hipGetLastError();
 }
 
@@ -1082,26 +1454,49 @@ hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
 template <class L, int NC, int ST>
 hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   const auto* P = static_cast<const DevParams<TT<ST>>*>(b.params);
-  if (b.walls)
-    hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, true>), dim3(b.blocks_conc), dim3(256), 0, s, b.args, P,
-                       b.work_conc);
-  else
-    hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, false>), dim3(b.blocks_conc), dim3(256), 0, s, b.args, P,
-                       b.work_conc);
-  hipError_t e = hipGetLastError();
+  const dim3 blk(256);
+  hipError_t e;
+  if (b.moments) {
+    const dim3 grid(b.blocks_update);
+    const int nb = b.blocks_update;
+    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
+#define K_CMB(W, T) k_conc_m_batch<L, NC - 1, ST, W, T>
+    if (b.tx_log2 == 6) {
+      if (b.walls) hipLaunchKernelGGL((K_CMB(true, 6)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+      else hipLaunchKernelGGL((K_CMB(false, 6)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    } else if (b.tx_log2 == 4) {
+      if (b.walls) hipLaunchKernelGGL((K_CMB(true, 4)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+      else hipLaunchKernelGGL((K_CMB(false, 4)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef K_CMB
+  } else {
+    if (b.walls)
+      hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, true>), dim3(b.blocks_conc), blk, 0, s, b.args, P, b.work_conc);
+    else
+      hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, false>), dim3(b.blocks_conc), blk, 0, s, b.args, P, b.work_conc);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
-  const dim3 grid(b.blocks_update), blk(256);
+  const dim3 grid(b.blocks_update);
   const int nb = b.blocks_update;
+#define K_UB(W, T, G) k_update_batch<L, NC, ST, W, T, G>
   if (b.tx_log2 == 6) {
-    if (b.walls) hipLaunchKernelGGL((k_update_batch<L, NC, ST, true, 6>), grid, blk, lds, s, b.args, P, b.work_update, nb);
-    else hipLaunchKernelGGL((k_update_batch<L, NC, ST, false, 6>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    if (b.walls) { if (b.moments) hipLaunchKernelGGL((K_UB(true, 6, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+                   else hipLaunchKernelGGL((K_UB(true, 6, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
+    else { if (b.moments) hipLaunchKernelGGL((K_UB(false, 6, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+           else hipLaunchKernelGGL((K_UB(false, 6, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
   } else if (b.tx_log2 == 4) {
-    if (b.walls) hipLaunchKernelGGL((k_update_batch<L, NC, ST, true, 4>), grid, blk, lds, s, b.args, P, b.work_update, nb);
-    else hipLaunchKernelGGL((k_update_batch<L, NC, ST, false, 4>), grid, blk, lds, s, b.args, P, b.work_update, nb);
+    if (b.walls) { if (b.moments) hipLaunchKernelGGL((K_UB(true, 4, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+                   else hipLaunchKernelGGL((K_UB(true, 4, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
+    else { if (b.moments) hipLaunchKernelGGL((K_UB(false, 4, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+           else hipLaunchKernelGGL((K_UB(false, 4, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
   } else {
     return hipErrorInvalidValue;
   }
+#undef K_UB
   return hipGetLastError();
 }
 
@@ -1133,6 +1528,13 @@ hipError_t init_nc(int nc, const InitArgs& a, hipStream_t s) {
 #undef CALL_I
 }
 
+template <class L, int ST>
+hipError_t expand_nc(int nc, const StepArgs& a, hipStream_t s) {
+#define CALL_E(K) launch_expand_t<L, K, ST>(a, s)
+  NFLBM_NC_SWITCH(nc, CALL_E)
+#undef CALL_E
+}
+
 #define NFLBM_CAT2(a, b) a##b
 #define NFLBM_CAT(a, b) NFLBM_CAT2(a, b)
 #define NFLBM_ST NFLBM_UNIT_STORE
@@ -1149,6 +1551,9 @@ hipError_t NFLBM_CAT(conc_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipS
 hipError_t NFLBM_CAT(batch_st, NFLBM_ST)(int lat, int nc, const BatchLaunch& b, hipStream_t s) {
   return lat == 0 ? batch_nc<D2Q9, NFLBM_ST>(nc, b, s) : batch_nc<D3Q19, NFLBM_ST>(nc, b, s);
 }
+hipError_t NFLBM_CAT(expand_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
+  return lat == 0 ? expand_nc<D2Q9, NFLBM_ST>(nc, a, s) : expand_nc<D3Q19, NFLBM_ST>(nc, a, s);
+}
 
 #else  // common unit
 
@@ -1158,6 +1563,23 @@ size_t update_lds_bytes(int lat, int nc, int store, int tx_log2) {
     case kStoreF32: return lds_bytes_for<kStoreF32>(lat, nc, tx_log2);
     default: return lds_bytes_for<kStoreF16S>(lat, nc, tx_log2);
   }
+}
+
+size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2) {
+  switch (store) {
+    case kStoreF64: return conc_m_lds_bytes_for<kStoreF64>(lat, nc, tx_log2);
+    case kStoreF32: return conc_m_lds_bytes_for<kStoreF32>(lat, nc, tx_log2);
+    default: return conc_m_lds_bytes_for<kStoreF16S>(lat, nc, tx_log2);
+  }
+}
+
+hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s) {
+  switch (store) {
+    case kStoreF64: return expand_st0(lat, nc, a, s);
+    case kStoreF32: return expand_st1(lat, nc, a, s);
+    case kStoreF16S: return expand_st2(lat, nc, a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s) {

@@ -1,0 +1,124 @@
+"""The two storage forms of g give identical bits.
+
+With every tau_g = 1 the library keeps g as the node records (C, mu~, v, v.v)
+and re-forms the post-collision populations in the reconstruction; with
+FLAG_G_POPULATIONS it stores the populations.  In FP64 and FP32 both round
+and sum the same values in the same order, so f, C, every derived field and
+the read-back populations must agree bit for bit, on both lattices, with
+walls, TRT, Omega > 0, the potential force, an absent component, and in
+batches.  With FP16S the population form rounds g to binary16 and the moment
+form does not, so there the two agree to the FP16S tolerance and the moment
+form is the closer one to FP64.
+"""
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+import workloads as W
+from oracle.coeffs import equal_sigma
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [nf.FP64, nf.FP32, nf.FP16S]
+
+
+def cases():
+    lens = W.lens_2d(37, 29, radius=7.0)
+    walls = W.noise("D2Q9", (45, 21, 1), 4, amp=0.15, seed=11, sigma=0.006, m=0.05)
+    walls.update(walls=(False, True, False), trt_magic=3.0 / 16.0, body_force=(2e-6, -1e-6, 0.0),
+                 tau=np.array([0.6, 0.9, 1.3, 1.1]))
+    sig = equal_sigma(4, 0.005)
+    sig[0, 3] = sig[3, 0] = 0.012
+    janus = W.janus_2d(30, 26, radius=6.0, offset=7.0, sigma=sig)
+    janus["omega_stab"] = 1.0 / 18.0
+    d3 = W.noise("D3Q19", (19, 13, 11), 4, 5, amp=0.1, seed=4)
+    layered = W.layered_3d(5, 3, 40, nlayers=4, force=1e-5)
+    rng = np.random.default_rng(2)
+    layered["C0"] = layered["C0"] + 0.02 * rng.uniform(size=layered["C0"].shape)
+    layered["C0"] /= layered["C0"].sum(axis=0)
+    d3w = W.noise("D3Q19", (17, 9, 12), 3, amp=0.2, seed=8, m=0.05)
+    d3w["walls"] = (True, False, True)
+    return [("lens", lens, -1, 0), ("walls_trt", walls, -1, 0), ("omega", janus, 0, 0),
+            ("potential", janus, 0, nf.FLAG_POTENTIAL_FORCE), ("d3_absent", d3, 0, 0),
+            ("d3_layered", layered, -1, 0), ("d3_walls_xz", d3w, -1, 0)]
+
+
+def run(w, prec, implicit, flags, steps):
+    sim = nf.Simulation.from_workload(w, precision=prec, implicit=implicit, flags=flags)
+    sim.set_fields(w["C0"], w.get("v0"))
+    sim.step(steps)
+    out = {k: sim.get_field(k) for k in ("C", "V", "P", "F", "MU", "F_RAW", "G_RAW")}
+    form = sim.storage_form()
+    sim.close()
+    return form, out
+
+
+@pytest.mark.parametrize("prec", [nf.FP64, nf.FP32])
+@pytest.mark.parametrize("idx", range(7))
+def test_forms_bitwise_equal(idx, prec):
+    name, w, implicit, flags = cases()[idx]
+    steps = 23
+    fm, a = run(w, prec, implicit, flags, steps)
+    fp, b = run(w, prec, implicit, flags | nf.FLAG_G_POPULATIONS, steps)
+    assert (fm, fp) == ("moments", "populations")
+    for k in a:
+        assert np.array_equal(a[k], b[k]), f"{name} {k}"
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_fp16s_forms_agree(idx):
+    name, w, implicit, flags = cases()[idx]
+    steps = 23
+    _, ref = run(w, nf.FP64, implicit, flags, steps)
+    _, a = run(w, nf.FP16S, implicit, flags, steps)
+    _, b = run(w, nf.FP16S, implicit, flags | nf.FLAG_G_POPULATIONS, steps)
+    for k in ("C", "V", "P"):
+        assert rel(a[k], b[k]) < 2e-2, (name, k)
+    assert rel(a["C"], ref["C"]) <= rel(b["C"], ref["C"]) * 1.5 + 1e-6, name
+
+
+def test_moment_form_checkpoint_roundtrip():
+    w = W.noise("D3Q19", (20, 16, 12), 4, seed=3)
+    with nf.Simulation.from_workload(w, precision=nf.FP32) as s:
+        assert s.storage_form() == "moments"
+        s.set_fields(w["C0"])
+        s.step(7)
+        st = s.get_state()
+        s.step(5)
+        ref = s.get_state()
+        s.set_state(st)
+        s.step(5)
+        assert np.array_equal(s.get_state(), ref)
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_batch_in_both_forms_matches_standalone(forced):
+    ws = W.batch_members(count=4, seed=21, sides=[40, 33, 64, 50])
+    ws[1]["walls"] = (False, True, False)
+    flags = nf.FLAG_G_POPULATIONS if forced else 0
+    ref = []
+    for w in ws:
+        s = nf.Simulation.from_workload(w, precision=nf.FP32, flags=flags)
+        s.set_fields(w["C0"])
+        s.step(17)
+        ref.append(s.get_field("C"))
+        s.close()
+    with nf.Batch.from_workloads(ws, precision=nf.FP32, flags=flags) as b:
+        assert b.members[0].storage_form() == ("populations" if forced else "moments")
+        b.set_launch(graph_steps=4)
+        for i, w in enumerate(ws):
+            b.members[i].set_fields(w["C0"])
+        b.step(17, "graph")
+        for i in range(len(ws)):
+            assert np.array_equal(b.members[i].get_field("C"), ref[i]), i
+
+
+def test_batch_with_one_tau_g_member_uses_populations():
+    ws = W.batch_members(count=3, seed=5, sides=[32, 40, 36])
+    ws[2]["tau_g"] = np.array([1.0, 0.9, 1.1])
+    with nf.Batch.from_workloads(ws, precision=nf.FP32) as b:
+        assert all(m.storage_form() == "populations" for m in b.members)

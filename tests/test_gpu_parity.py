@@ -104,10 +104,13 @@ def case_d3_layered_walls():
     ("d3_absent", case_d3_absent, 10, 0, 0),
     ("d3_layered_walls", case_d3_layered_walls, 15, -1, 0),
 ])
-def test_fp64_parity_small(name, mk, steps, implicit, flags):
+@pytest.mark.parametrize("form", ["moments", "populations"])
+def test_fp64_parity_small(name, mk, steps, implicit, flags, form):
     w = mk()
     okw = {"force_form": "potential"} if flags & nf.FLAG_POTENTIAL_FORCE else {}
-    sim, f, g, par = run_both(w, steps, implicit=implicit, flags=flags, okw=okw)
+    extra = nf.FLAG_G_POPULATIONS if form == "populations" else 0
+    sim, f, g, par = run_both(w, steps, implicit=implicit, flags=flags | extra, okw=okw)
+    assert sim.storage_form() == form
     compare(sim, f, g, par, 1e-12, name)
 
 
@@ -115,6 +118,7 @@ def test_fp64_parity_tau_g_not_one():
     w = W.lens_2d(33, 17, radius=5.0)
     w["tau_g"] = np.array([0.8, 1.2, 1.0])
     sim, f, g, par = run_both(w, 15)
+    assert sim.storage_form() == "populations"
     compare(sim, f, g, par, 1e-12, "tau_g")
 
 
