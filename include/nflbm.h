@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 3
+#define NFLBM_ABI_VERSION 4
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -193,6 +193,26 @@ int nflbm_step_timed(nflbm_sim *sim, long long nsteps, double *ms, double *ms_up
 /* Copy one field (NFLBM_FIELD_*) of the current state to host_out (sizes in
  * the field list above).  Synchronises. */
 int nflbm_get_field(nflbm_sim *sim, int field, double *host_out);
+
+/* Device memory the state of a simulation with configuration cfg occupies
+ * (every array the steps read or write: both f sets, g or the node records,
+ * the reconstructed C and E_B), each array rounded up to 256 bytes.  Host-only
+ * planning: validates cfg as nflbm_create does (same errors), allocates
+ * nothing.  For callers that provide the memory, e.g. a torch tensor. */
+int nflbm_device_bytes(const nflbm_config *cfg, size_t *bytes);
+
+/* Move the device state of sim into caller memory: dev_ptr (256-byte
+ * aligned) of at least nflbm_device_bytes bytes on sim's device.  The
+ * current state is copied over and the library's own arrays are freed; from
+ * then on the caller keeps the buffer alive until nflbm_destroy (which does
+ * not free it).  Binding again to the same pointer does nothing; binding to
+ * another copies the state there.  EINVAL for batch members, a NULL or
+ * misaligned pointer, or a short buffer.  Synchronises. */
+int nflbm_bind_state(nflbm_sim *sim, void *dev_ptr, size_t bytes);
+
+/* alpha (N*N row-major) and gamma (N) of sim (Eqs. alpha1, alpha2), FP64, in
+ * user component order; either pointer may be NULL. */
+int nflbm_get_coeffs(const nflbm_sim *sim, double *alpha, double *gamma);
 
 /* Raw state checkpoint: nflbm_state_bytes gives the size, get_state copies
  * the device state (storage precision: f_1..f_{Q-1}, then the populations of

@@ -102,6 +102,9 @@ def lib():
             "nflbm_abi_version": (I, []),
             "nflbm_autotune": (I, [P, ctypes.c_char_p]),
             "nflbm_storage_form": (I, [P]),
+            "nflbm_device_bytes": (I, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
+            "nflbm_bind_state": (I, [P, P, ctypes.c_size_t]),
+            "nflbm_get_coeffs": (I, [P, DP, DP]),
             "nflbm_batch_create": (I, [ctypes.POINTER(Config), I, ctypes.POINTER(P)]),
             "nflbm_batch_destroy": (None, [P]),
             "nflbm_batch_count": (I, [P]),
@@ -324,6 +327,26 @@ class Simulation:
         b = ctypes.c_double()
         _check(lib().nflbm_bytes_per_node(self._handle(), ctypes.byref(b)), self._h)
         return b.value
+
+    @staticmethod
+    def device_bytes(lattice, shape, sigma, tau, **kw):
+        """Device bytes the state of such a simulation occupies (no GPU use)."""
+        prob = _Problem(lattice, shape, sigma, tau, **kw)
+        b = ctypes.c_size_t()
+        _check(lib().nflbm_device_bytes(ctypes.byref(prob.cfg), ctypes.byref(b)))
+        return b.value
+
+    def bind_state(self, dev_ptr, nbytes):
+        """Keep the state in caller memory (e.g. tensor.data_ptr()); the caller
+        keeps that memory alive while the simulation exists."""
+        _check(lib().nflbm_bind_state(self._handle(), ctypes.c_void_p(dev_ptr), ctypes.c_size_t(nbytes)),
+               self._h)
+
+    def get_coeffs(self):
+        a = np.zeros((self.N, self.N))
+        g = np.zeros(self.N)
+        _check(lib().nflbm_get_coeffs(self._handle(), _dptr(a), _dptr(g)), self._h)
+        return a, g
 
     def storage_form(self):
         """'moments' (g kept as C, mu~, v per node; every tau_g = 1) or 'populations'."""

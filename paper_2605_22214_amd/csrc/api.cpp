@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -53,6 +54,8 @@ struct nflbm_sim {
   void* mu = nullptr;    // moment form: mu~ [node][i]
   void* vel = nullptr;   // moment form: (v, v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
+  bool borrowed = false; // state arrays live in caller memory (nflbm_bind_state)
+  bool in_batch = false;
   void* eb = nullptr;
   void* params = nullptr;
   double* fields = nullptr;
@@ -146,20 +149,12 @@ void fill_params(const nflbm_sim& s, const double* tau, const double* tau_g, dou
 }
 
 void free_device(nflbm_sim* s) {
-  for (int b = 0; b < 2; ++b) {
-    if (s->f[b]) (void)hipFree(s->f[b]);
-    if (s->g0[b]) (void)hipFree(s->g0[b]);
-    if (s->gk[b]) (void)hipFree(s->gk[b]);
-    s->f[b] = s->g0[b] = s->gk[b] = nullptr;
+  void** arrays[] = {&s->f[0], &s->f[1], &s->g0[0], &s->g0[1], &s->gk[0], &s->gk[1],
+                     &s->conc[0], &s->conc[1], &s->mu, &s->vel, &s->eb};
+  for (void** a : arrays) {
+    if (*a && !s->borrowed) (void)hipFree(*a);
+    *a = nullptr;
   }
-  for (int b = 0; b < 2; ++b) {
-    if (s->conc[b]) (void)hipFree(s->conc[b]);
-    s->conc[b] = nullptr;
-  }
-  if (s->mu) (void)hipFree(s->mu);
-  if (s->vel) (void)hipFree(s->vel);
-  s->mu = s->vel = nullptr;
-  if (s->eb) (void)hipFree(s->eb);
   if (s->params) (void)hipFree(s->params);
   if (s->fields) (void)hipFree(s->fields);
   if (s->red) (void)hipFree(s->red);
@@ -567,6 +562,122 @@ long long tune_steps(double nodes, double bytes_per_node) {
   return k & ~1LL;
 }
 
+// Validate cfg and fill every host-side field of s: sizes, coefficient
+// tables, storage form of g, launch shape.  Allocates nothing.
+int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
+  if (cfg->lattice != NFLBM_D2Q9 && cfg->lattice != NFLBM_D3Q19)
+    return fail(nullptr, NFLBM_EINVAL, "unknown lattice");
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+    return fail(nullptr, NFLBM_EINVAL, "lattice dimensions must be >= 1");
+  if (cfg->lattice == NFLBM_D2Q9 && cfg->nz != 1)
+    return fail(nullptr, NFLBM_EINVAL, "D2Q9 needs nz == 1");
+  const long long nn = 1LL * cfg->nx * cfg->ny * cfg->nz;
+  if (nn >= (1LL << 31)) return fail(nullptr, NFLBM_EINVAL, "more than 2^31-1 nodes");
+  const int N = cfg->ncomp;
+  if (N < 2 || N > NFLBM_MAX_COMP) return fail(nullptr, NFLBM_EINVAL, "ncomp outside 2..8");
+  if (!cfg->sigma || !cfg->tau) return fail(nullptr, NFLBM_EINVAL, "sigma and tau are required");
+  if (cfg->precision < NFLBM_FP64 || cfg->precision > NFLBM_FP16S)
+    return fail(nullptr, NFLBM_EINVAL, "unknown precision");
+  const int imp = cfg->implicit_comp < 0 ? N - 1 : cfg->implicit_comp;
+  if (imp >= N) return fail(nullptr, NFLBM_EINVAL, "implicit_comp out of range");
+  for (int i = 0; i < N; ++i) {
+    if (!(cfg->tau[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau must exceed 1/2");
+    if (cfg->tau_g && !(cfg->tau_g[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau_g must exceed 1/2");
+  }
+  if (!(cfg->m > 0.0)) return fail(nullptr, NFLBM_EINVAL, "m must be positive");
+  if (!(cfg->omega_stab >= 0.0)) return fail(nullptr, NFLBM_EINVAL, "omega_stab must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (cfg->wall[a] != 0 && cfg->wall[a] != 1) return fail(nullptr, NFLBM_EINVAL, "wall flags are 0 or 1");
+  if (cfg->lattice == NFLBM_D2Q9 && cfg->wall[2])
+    return fail(nullptr, NFLBM_EINVAL, "D2Q9 has no z walls");
+
+  s->lat = cfg->lattice;
+  s->N = N;
+  s->NE = N - 1;
+  s->Q = s->lat == NFLBM_D2Q9 ? 9 : 19;
+  s->store = cfg->precision;
+  s->flags = cfg->flags;
+  s->nx = cfg->nx;
+  s->ny = cfg->ny;
+  s->nz = cfg->nz;
+  for (int a = 0; a < 3; ++a) s->wall[a] = cfg->wall[a];
+  s->implicit = imp;
+  s->n = static_cast<size_t>(nn);
+  {
+    int q = 0;
+    for (int u = 0; u < N; ++u)
+      if (u != imp) s->uidx[q++] = u;
+    s->uidx[N - 1] = imp;
+  }
+  char msg[256] = {0};
+  const int rc = compute_coeffs(N, cfg->sigma, cfg->width_D, &s->co, msg);
+  if (rc) {
+    return fail(nullptr, rc == -1 ? NFLBM_EINVAL : NFLBM_ESINGULAR, msg);
+  }
+  // Linear stability of the explicit Cahn-Hilliard update in a pure phase:
+  // a mode of -lap eigenvalue lam grows by 1 + M lam (a - (3D/4) lam) per step
+  // with a = -12/D; |growth| <= 1 up to lam_max = 16/3 needs the bound below.
+  if (!(cfg->flags & NFLBM_FLAG_ALLOW_UNSTABLE)) {
+    const double lam = 16.0 / 3.0;
+    for (int i = 0; i < N; ++i) {
+      const double tg = cfg->tau_g ? cfg->tau_g[i] : 1.0;
+      const double M = cfg->m * (tg - 0.5) / 3.0;
+      if (M * lam * (0.75 * cfg->width_D * lam + 12.0 / cfg->width_D) >= 2.0) {
+            return fail(nullptr, NFLBM_EUNSTABLE,
+                    "mobility M = c_s^2 m (tau_g - 1/2) exceeds the linear stability bound");
+      }
+    }
+  }
+  switch (s->store) {
+    case NFLBM_FP64: s->fs = 8; s->g0s = 8; s->ts = 8; break;
+    case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; break;
+    default: s->fs = 2; s->g0s = 4; s->ts = 4; break;
+  }
+  s->step_flags = 0;
+  for (int i = 0; i < N; ++i)
+    if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
+  if (cfg->flags & NFLBM_FLAG_POTENTIAL_FORCE) s->step_flags |= kFlagPotential;
+  if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
+  // With every tau_g = 1 the post-collision g are equilibria of (C, mu~, v):
+  // store those per node instead of the populations, unless asked not to.
+  s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS)) ? 1 : 0;
+  if (s->gform && choose_launch(s) != 0) s->gform = 0;   // its LDS window does not fit
+  if (s->gform) s->step_flags |= kFlagMoments;
+  if (choose_launch(s) != 0) {
+    return fail(nullptr, NFLBM_ENOTSUP, "LDS window does not fit the device for this N and precision");
+  }
+
+  const size_t n = s->n, NE = s->NE;
+  if (double(n) * double(NE) * double(s->fs > s->ts ? s->fs : s->ts) >= 4294967296.0 ||
+      double(n) * double(NE) * double(s->g0s) >= 4294967296.0) {
+    return fail(nullptr, NFLBM_ENOTSUP, "lattice too large: in-plane byte offsets must fit 32 bits");
+  }
+  return NFLBM_OK;
+}
+
+// Device arrays of the state (pointer slot, bytes) in a fixed order: both f
+// sets, then g (population form) or the node records (moment form), then
+// the reconstructed C and E_B.
+std::vector<std::pair<void**, size_t>> state_arrays(nflbm_sim* s) {
+  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
+  std::vector<std::pair<void**, size_t>> v;
+  for (int b = 0; b < 2; ++b) v.emplace_back(&s->f[b], Qm * n * s->fs);
+  if (s->gform) {
+    for (int b = 0; b < 2; ++b) v.emplace_back(&s->conc[b], NE * n * s->ts);
+    v.emplace_back(&s->mu, NE * n * s->ts);
+    v.emplace_back(&s->vel, 4 * n * s->ts);
+  } else {
+    for (int b = 0; b < 2; ++b) v.emplace_back(&s->g0[b], NE * n * s->g0s);
+    for (int b = 0; b < 2; ++b) v.emplace_back(&s->gk[b], NE * Qm * n * s->fs);
+    v.emplace_back(&s->conc[0], NE * n * s->ts);
+  }
+  v.emplace_back(&s->eb, n * s->ts);
+  return v;
+}
+
+constexpr size_t kBindAlign = 256;
+size_t align_up(size_t v) { return (v + kBindAlign - 1) / kBindAlign * kBindAlign; }
+
 }  // namespace
 
 extern "C" {
@@ -603,115 +714,16 @@ int nflbm_coefficients(int N, const double* sigma, double D, double* alpha, doub
 int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   if (!cfg || !out) return fail(nullptr, NFLBM_EINVAL, "NULL argument");
   *out = nullptr;
-  if (cfg->lattice != NFLBM_D2Q9 && cfg->lattice != NFLBM_D3Q19)
-    return fail(nullptr, NFLBM_EINVAL, "unknown lattice");
-  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
-    return fail(nullptr, NFLBM_EINVAL, "lattice dimensions must be >= 1");
-  if (cfg->lattice == NFLBM_D2Q9 && cfg->nz != 1)
-    return fail(nullptr, NFLBM_EINVAL, "D2Q9 needs nz == 1");
-  const long long nn = 1LL * cfg->nx * cfg->ny * cfg->nz;
-  if (nn >= (1LL << 31)) return fail(nullptr, NFLBM_EINVAL, "more than 2^31-1 nodes");
-  const int N = cfg->ncomp;
-  if (N < 2 || N > NFLBM_MAX_COMP) return fail(nullptr, NFLBM_EINVAL, "ncomp outside 2..8");
-  if (!cfg->sigma || !cfg->tau) return fail(nullptr, NFLBM_EINVAL, "sigma and tau are required");
-  if (cfg->precision < NFLBM_FP64 || cfg->precision > NFLBM_FP16S)
-    return fail(nullptr, NFLBM_EINVAL, "unknown precision");
-  const int imp = cfg->implicit_comp < 0 ? N - 1 : cfg->implicit_comp;
-  if (imp >= N) return fail(nullptr, NFLBM_EINVAL, "implicit_comp out of range");
-  for (int i = 0; i < N; ++i) {
-    if (!(cfg->tau[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau must exceed 1/2");
-    if (cfg->tau_g && !(cfg->tau_g[i] > 0.5)) return fail(nullptr, NFLBM_EINVAL, "tau_g must exceed 1/2");
-  }
-  if (!(cfg->m > 0.0)) return fail(nullptr, NFLBM_EINVAL, "m must be positive");
-  if (!(cfg->omega_stab >= 0.0)) return fail(nullptr, NFLBM_EINVAL, "omega_stab must be >= 0");
-  for (int a = 0; a < 3; ++a)
-    if (cfg->wall[a] != 0 && cfg->wall[a] != 1) return fail(nullptr, NFLBM_EINVAL, "wall flags are 0 or 1");
-  if (cfg->lattice == NFLBM_D2Q9 && cfg->wall[2])
-    return fail(nullptr, NFLBM_EINVAL, "D2Q9 has no z walls");
-
   nflbm_sim* s = new nflbm_sim();
-  s->lat = cfg->lattice;
-  s->N = N;
-  s->NE = N - 1;
-  s->Q = s->lat == NFLBM_D2Q9 ? 9 : 19;
-  s->store = cfg->precision;
-  s->flags = cfg->flags;
-  s->nx = cfg->nx;
-  s->ny = cfg->ny;
-  s->nz = cfg->nz;
-  for (int a = 0; a < 3; ++a) s->wall[a] = cfg->wall[a];
-  s->implicit = imp;
-  s->n = static_cast<size_t>(nn);
-  {
-    int q = 0;
-    for (int u = 0; u < N; ++u)
-      if (u != imp) s->uidx[q++] = u;
-    s->uidx[N - 1] = imp;
-  }
-  char msg[256] = {0};
-  const int rc = compute_coeffs(N, cfg->sigma, cfg->width_D, &s->co, msg);
-  if (rc) {
+  const int prc = plan_sim(cfg, s);
+  if (prc != NFLBM_OK) {
     delete s;
-    return fail(nullptr, rc == -1 ? NFLBM_EINVAL : NFLBM_ESINGULAR, msg);
+    return prc;
   }
-  // Linear stability of the explicit Cahn-Hilliard update in a pure phase:
-  // a mode of -lap eigenvalue lam grows by 1 + M lam (a - (3D/4) lam) per step
-  // with a = -12/D; |growth| <= 1 up to lam_max = 16/3 needs the bound below.
-  if (!(cfg->flags & NFLBM_FLAG_ALLOW_UNSTABLE)) {
-    const double lam = 16.0 / 3.0;
-    for (int i = 0; i < N; ++i) {
-      const double tg = cfg->tau_g ? cfg->tau_g[i] : 1.0;
-      const double M = cfg->m * (tg - 0.5) / 3.0;
-      if (M * lam * (0.75 * cfg->width_D * lam + 12.0 / cfg->width_D) >= 2.0) {
-        delete s;
-        return fail(nullptr, NFLBM_EUNSTABLE,
-                    "mobility M = c_s^2 m (tau_g - 1/2) exceeds the linear stability bound");
-      }
-    }
-  }
-  switch (s->store) {
-    case NFLBM_FP64: s->fs = 8; s->g0s = 8; s->ts = 8; break;
-    case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; break;
-    default: s->fs = 2; s->g0s = 4; s->ts = 4; break;
-  }
-  s->step_flags = 0;
-  for (int i = 0; i < N; ++i)
-    if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
-  if (cfg->flags & NFLBM_FLAG_POTENTIAL_FORCE) s->step_flags |= kFlagPotential;
-  if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
-  // With every tau_g = 1 the post-collision g are equilibria of (C, mu~, v):
-  // store those per node instead of the populations, unless asked not to.
-  s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS)) ? 1 : 0;
-  if (s->gform && choose_launch(s) != 0) s->gform = 0;   // its LDS window does not fit
-  if (s->gform) s->step_flags |= kFlagMoments;
-  if (choose_launch(s) != 0) {
-    delete s;
-    return fail(nullptr, NFLBM_ENOTSUP, "LDS window does not fit the device for this N and precision");
-  }
-
-  const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
-  if (double(n) * double(NE) * double(s->fs > s->ts ? s->fs : s->ts) >= 4294967296.0 ||
-      double(n) * double(NE) * double(s->g0s) >= 4294967296.0) {
-    delete s;
-    return fail(nullptr, NFLBM_ENOTSUP, "lattice too large: in-plane byte offsets must fit 32 bits");
-  }
+  const int N = s->N;
+  const size_t n = s->n;
   bool ok = true;
-  for (int b = 0; b < 2 && ok; ++b) {
-    ok &= hipMalloc(&s->f[b], Qm * n * s->fs) == hipSuccess;
-    if (s->gform) {
-      ok = ok && hipMalloc(&s->conc[b], NE * n * s->ts) == hipSuccess;
-    } else {
-      ok = ok && hipMalloc(&s->g0[b], NE * n * s->g0s) == hipSuccess;
-      ok = ok && hipMalloc(&s->gk[b], NE * Qm * n * s->fs) == hipSuccess;
-    }
-  }
-  if (s->gform) {
-    ok = ok && hipMalloc(&s->mu, NE * n * s->ts) == hipSuccess;
-    ok = ok && hipMalloc(&s->vel, 4 * n * s->ts) == hipSuccess;
-  } else {
-    ok = ok && hipMalloc(&s->conc[0], NE * n * s->ts) == hipSuccess;
-  }
-  ok = ok && hipMalloc(&s->eb, n * s->ts) == hipSuccess;
+  for (auto& a : state_arrays(s)) ok = ok && hipMalloc(a.first, a.second) == hipSuccess;
   const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
   ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
   if (!ok) {
@@ -1144,6 +1156,7 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
       nflbm_sim* m = nullptr;
       const int rc = nflbm_create(&cc[i], &m);
       if (rc != NFLBM_OK) return cleanup(rc, "member " + std::to_string(i) + ": " + nflbm_last_error(nullptr));
+      m->in_batch = true;
       b->members.push_back(m);
     }
     bool same = true;
@@ -1345,5 +1358,56 @@ int nflbm_batch_autotune(nflbm_batch* b, const char* cache_path) {
 }
 
 const char* nflbm_batch_last_error(const nflbm_batch* b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
+
+
+int nflbm_device_bytes(const nflbm_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return fail(nullptr, NFLBM_EINVAL, "NULL argument");
+  nflbm_sim s;
+  const int rc = plan_sim(cfg, &s);
+  if (rc != NFLBM_OK) return rc;
+  size_t total = 0;
+  for (const auto& a : state_arrays(&s)) total += align_up(a.second);
+  *bytes = total;
+  return NFLBM_OK;
+}
+
+int nflbm_bind_state(nflbm_sim* sim, void* dev_ptr, size_t bytes) {
+  if (!sim || !dev_ptr) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  if (sim->in_batch) return fail(sim, NFLBM_EINVAL, "batch members keep library memory");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kBindAlign != 0)
+    return fail(sim, NFLBM_EINVAL, "dev_ptr must be 256-byte aligned");
+  auto arrays = state_arrays(sim);
+  size_t total = 0;
+  for (const auto& a : arrays) total += align_up(a.second);
+  if (bytes < total) return fail(sim, NFLBM_EINVAL, "buffer smaller than nflbm_device_bytes");
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  unsigned char* base = static_cast<unsigned char*>(dev_ptr);
+  if (base == static_cast<unsigned char*>(*arrays[0].first)) return NFLBM_OK;   // already bound here
+  size_t off = 0;
+  std::vector<void*> old;
+  for (auto& a : arrays) {
+    void* dst = base + off;
+    HIPCHK(sim, hipMemcpyAsync(dst, *a.first, a.second, hipMemcpyDeviceToDevice, sim->stream));
+    old.push_back(*a.first);
+    *a.first = dst;
+    off += align_up(a.second);
+  }
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  if (!sim->borrowed)
+    for (void* p : old) (void)hipFree(p);
+  sim->borrowed = true;
+  return NFLBM_OK;
+}
+
+int nflbm_get_coeffs(const nflbm_sim* sim, double* alpha, double* gamma) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  const int N = sim->N;
+  for (int i = 0; i < N; ++i) {
+    if (gamma) gamma[i] = sim->co.gamma[i];
+    for (int j = 0; j < N; ++j)
+      if (alpha) alpha[i * N + j] = sim->co.alpha[i][j];
+  }
+  return NFLBM_OK;
+}
 
 }  // extern "C"

@@ -130,3 +130,24 @@ def test_batch_rejects_mixed_members_before_the_device(L):
     assert L.nflbm_batch_create((nf.Config * 1)(a.cfg), 0, ctypes.byref(h)) == -1
     assert L.nflbm_batch_count(None) == 0
     assert L.nflbm_batch_member(None, 0) is None
+
+
+def test_device_bytes_plans_without_a_device(L):
+    """nflbm_device_bytes validates like nflbm_create and sums the state
+    arrays (each rounded to 256 bytes) of the storage form it would pick."""
+    def al(v):
+        return (v + 255) // 256 * 256
+    sig = equal_sigma(5, 0.01)
+    nx, ny, nz = 20, 16, 12
+    n = nx * ny * nz
+    mom = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32)
+    assert mom == 2 * al(18 * n * 4) + 2 * al(4 * n * 4) + al(4 * n * 4) + al(4 * n * 4) + al(n * 4)
+    pop = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32,
+                                     flags=nf.FLAG_G_POPULATIONS)
+    assert pop == 2 * al(18 * n * 4) + 2 * al(4 * n * 4) + 2 * al(4 * 18 * n * 4) + al(4 * n * 4) + al(n * 4)
+    tg = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP16S,
+                                    tau_g=[1.0, 1.0, 0.8, 1.0, 1.0])
+    assert tg == 2 * al(18 * n * 2) + 2 * al(4 * n * 4) + 2 * al(4 * 18 * n * 2) + al(4 * n * 4) + al(n * 4)
+    with pytest.raises(nf.NflbmError) as e:
+        nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 0.4, m=0.1)
+    assert e.value.code == -1

@@ -67,6 +67,38 @@ def lens_2d(nx=64, ny=64, radius=12.0, sigma=None, m=0.05, tau=1.0):
                  y_interface=yc)
 
 
+def table1_lens(s, nx=300, ny=150, radius=35.0, m=0.05, ncomp=6):
+    """Four-fluid lens of Table I inside an N = 6 model (Sec. IV A): fluid 1
+    fills the lower band and fluid 2 the upper (periodic), a disc of radius R
+    centred on the middle 1|2 interface holds fluid 3 in its left half and
+    fluid 4 in its right half, and fluids 5, 6 are exactly 0.  sigma_12 =
+    0.005, sigma_13 = sigma_14 = sigma_23 = sigma_24 = sigma_34 = s, and every
+    tension of fluids 5, 6 is 0.005.  tau = 1 (eta = 1/6), tau_g = 1."""
+    j = np.arange(ny, dtype=np.float64)[:, None]
+    i = np.arange(nx, dtype=np.float64)[None, :]
+    half = ny / 2.0
+    yc = half - 0.5
+    xc = nx / 2.0 - 0.5
+    band_centre = half / 2.0 - 0.5
+    dist = ((j - band_centre + half) % ny) - half
+    c1r = _smooth(half / 2.0 - np.abs(dist)) * np.ones((ny, nx))
+    disc = _smooth(-(np.sqrt((i - xc) ** 2 + (j - yc) ** 2) - radius))
+    right = _smooth(i - xc) * np.ones((ny, nx))
+    c3 = disc * (1 - right)
+    c4 = disc * right
+    c1 = (1 - disc) * c1r
+    c2 = (1 - disc) * (1 - c1r)
+    zero = np.zeros((ny, nx))
+    C0 = np.stack([c1, c2, c3, c4] + [zero] * (ncomp - 4))[:, None, :, :]
+    sigma = np.full((ncomp, ncomp), 0.005)
+    for a in range(4):
+        for b in range(4):
+            sigma[a, b] = s
+    sigma[0, 1] = sigma[1, 0] = 0.005
+    np.fill_diagonal(sigma, 0.0)
+    return _base("D2Q9", (nx, ny, 1), sigma, 1.0, m, C0=C0, name="table1_lens", y_interface=yc)
+
+
 def janus_2d(nx=100, ny=100, radius=20.0, offset=25.0, sigma=None, m=0.05, tau=1.0,
              ncomp=4):
     """Janus droplet (Sec. IV A): a disc of fluid 2 at the centre and discs of
