@@ -153,3 +153,40 @@ def lens_angles(C_lens, y_interface, margin=3.0):
     res["above"] = 180.0 - a_top
     res["below"] = 180.0 - a_bot
     return res
+
+
+def janus_lens_angles(C_a, C_b, y_interface, x_split, margin=3.0):
+    """Angles at the outer triple points of a Janus lens: fluids a (left of
+    x = x_split) and b (right) together form a lens on a flat horizontal
+    interface between an upper and a lower fluid (Sec. IV A, Table I).
+
+    For each lens fluid, the part of its C = 0.5 contour away from the a|b
+    interface (|x - x_split| > margin) and from the flat interface
+    (|y - y_interface| > margin) is fitted with one circle above and one below
+    the interface, as in lens_angles; the interior angle is the one filled by
+    the lens fluid at its outer triple point.  Returns the interior angle and
+    the angles filled by the upper and lower fluids, averaged over a and b,
+    plus the per-fluid values."""
+    res = {}
+    for name, C, side in (("a", C_a, -1.0), ("b", C_b, 1.0)):
+        pts = contour_points(C)
+        pts = pts[side * (pts[:, 0] - x_split) > margin]
+        top = pts[pts[:, 1] > y_interface + margin]
+        bot = pts[pts[:, 1] < y_interface - margin]
+        xt, yt, rt = _fit_circle(top[:, 0], top[:, 1])
+        xb, yb, rb = _fit_circle(bot[:, 0], bot[:, 1])
+        a_top = _cap_angle(yt, rt, y_interface, True)
+        a_bot = _cap_angle(yb, rb, y_interface, False)
+        res[name] = {"interior": a_top + a_bot, "above": 180.0 - a_top, "below": 180.0 - a_bot}
+    for key in ("interior", "above", "below"):
+        res[key] = 0.5 * (res["a"][key] + res["b"][key])
+    return res
+
+
+def _cap_angle(yc, r, y_interface, above):
+    """Angle between a circular arc and the horizontal line y = y_interface at
+    their crossing, measured inside the cap on the given side of the line."""
+    dy = y_interface - yc
+    ang = math.degrees(math.acos(max(-1.0, min(1.0, abs(dy) / r))))
+    centre_on_far_side = (yc < y_interface) if above else (yc > y_interface)
+    return ang if centre_on_far_side else 180.0 - ang

@@ -375,6 +375,31 @@ def test_lens_angle_measurement_on_exact_caps():
     assert res["above"] == pytest.approx(120.0, abs=1.0)
 
 
+@pytest.mark.parametrize("psi_top,psi_bot", [(30.0, 45.0), (60.0, 60.0), (80.0, 20.0)])
+def test_janus_lens_angle_measurement_on_exact_caps(psi_top, psi_bot):
+    """The per-fluid measurement of a Janus lens (Table I geometry: left half
+    fluid a, right half fluid b) recovers the angles of exact circular caps
+    meeting the interface at psi_top and psi_bot: interior psi_top + psi_bot,
+    upper 180 - psi_top, lower 180 - psi_bot."""
+    ny, nx = 150, 300
+    yi, xs = 74.5, 149.5
+    j = np.arange(ny, dtype=np.float64)[:, None]
+    i = np.arange(nx, dtype=np.float64)[None, :]
+    half = 40.0
+    rt = half / math.sin(math.radians(psi_top))
+    yt = yi - rt * math.cos(math.radians(psi_top))
+    rb = half / math.sin(math.radians(psi_bot))
+    yb = yi + rb * math.cos(math.radians(psi_bot))
+    dt = rt - np.sqrt((i - xs) ** 2 + (j - yt) ** 2)
+    db = rb - np.sqrt((i - xs) ** 2 + (j - yb) ** 2)
+    lens = 0.5 * (1 + np.tanh(np.where(j >= yi, dt, db) / 2))
+    right = 0.5 * (1 + np.tanh((i - xs) / 2))
+    res = A.janus_lens_angles(lens * (1 - right), lens * right, yi, xs)
+    assert res["interior"] == pytest.approx(psi_top + psi_bot, abs=0.5)
+    assert res["above"] == pytest.approx(180.0 - psi_top, abs=0.5)
+    assert res["below"] == pytest.approx(180.0 - psi_bot, abs=0.5)
+
+
 # ---------------------------------------------------------------- stability
 def test_mobility_stability_bound():
     """The checkerboard mode of a nearly pure phase decays for M = m/6 below
