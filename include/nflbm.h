@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 4
+#define NFLBM_ABI_VERSION 5
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -80,8 +80,11 @@ enum {
                                      instead of the conservative Eq. Fsnew;
                                      a negative control that drifts          */
   NFLBM_FLAG_ALLOW_UNSTABLE = 2,  /* skip the mobility stability check      */
-  NFLBM_FLAG_G_POPULATIONS = 4    /* keep the populations of g even when every
+  NFLBM_FLAG_G_POPULATIONS = 4,   /* keep the populations of g even when every
                                      tau_g = 1 (see "Storage of g" below)      */
+  NFLBM_FLAG_NO_HYDRO = 8         /* diffusive-only (Sec. IV B): the LBE of f is
+                                     not evolved, v = 0 and P = 0 everywhere;
+                                     only the Cahn-Hilliard LBEs of g step     */
 };
 
 /* Storage of g.  With every tau_g = 1 a post-collision population of g is
@@ -226,6 +229,15 @@ int nflbm_set_state(nflbm_sim *sim, const void *host_raw);
  * centre-of-mass velocity (Sec. V A).  ENUMERIC if a NaN/Inf was found.
  * Synchronises. */
 int nflbm_diagnostics(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
+
+/* Characteristic domain size L_i of every component (Eq. L, Sec. IV B) of
+ * the current state: lambda_i = H(C_i - 1/2) (taken as C_i > 1/2),
+ * S_i(k) = |FFT(lambda_i)|^2 over the lattice's wave vectors k = 2 pi m / n
+ * (k = 0 left out), L_i = 2 pi sum S_i / sum |k| S_i, in lattice units.
+ * L (N doubles, user order) receives the values; a component with no
+ * interface gets 0.  FP64 FFT (hipFFT); buffers and plan are made on the
+ * first call and kept.  Synchronises. */
+int nflbm_domain_size(nflbm_sim *sim, double *L);
 
 /* Host-only (no device needed): the coefficient tables for N tensions sigma
  * (N*N row-major) and width D.  Any output pointer may be NULL.

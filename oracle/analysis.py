@@ -190,3 +190,29 @@ def _cap_angle(yc, r, y_interface, above):
     ang = math.degrees(math.acos(max(-1.0, min(1.0, abs(dy) / r))))
     centre_on_far_side = (yc < y_interface) if above else (yc > y_interface)
     return ang if centre_on_far_side else 180.0 - ang
+
+
+def domain_size(C, level=0.5):
+    """Characteristic length L_i of each component (Eq. L, Sec. IV B).
+
+    C: [N, nz, ny, nx] (or [N, ny, nx]).  lambda_i = H(C_i - level), taken as
+    C_i > level; S_i(k) = |sum_x lambda_i(x) exp(-i k.x)|^2 on the periodic
+    lattice's wave vectors k = 2 pi (m_x/nx, m_y/ny, m_z/nz).  The integrals
+    of Eq. L become sums over the full k grid (circular averaging followed by
+    integration over d^2k visits every k once); k = 0, which carries only the
+    mean of lambda, is left out of both.  L_i = 2 pi sum S_i / sum |k| S_i."""
+    C = np.asarray(C, dtype=np.float64)
+    if C.ndim == 3:
+        C = C[:, None]
+    N = C.shape[0]
+    shape = C.shape[1:]
+    freqs = [2.0 * np.pi * np.fft.fftfreq(n) for n in shape]
+    kz, ky, kx = np.meshgrid(*freqs, indexing="ij")
+    kmag = np.sqrt(kx * kx + ky * ky + kz * kz)
+    nonzero = kmag > 0
+    out = np.empty(N)
+    for i in range(N):
+        lam = (C[i] > level).astype(np.float64)
+        S = np.abs(np.fft.fftn(lam)) ** 2
+        out[i] = 2.0 * np.pi * S[nonzero].sum() / (kmag[nonzero] * S[nonzero]).sum()
+    return out

@@ -23,6 +23,7 @@ FP64, FP32, FP16S = 0, 1, 2
 FLAG_POTENTIAL_FORCE = 1
 FLAG_ALLOW_UNSTABLE = 2
 FLAG_G_POPULATIONS = 4
+FLAG_NO_HYDRO = 8
 FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 BATCH_MODES = {"launch": 0, "graph": 1, "per_sim": 2}
@@ -105,6 +106,7 @@ def lib():
             "nflbm_device_bytes": (I, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
             "nflbm_bind_state": (I, [P, P, ctypes.c_size_t]),
             "nflbm_get_coeffs": (I, [P, DP, DP]),
+            "nflbm_domain_size": (I, [P, DP]),
             "nflbm_batch_create": (I, [ctypes.POINTER(Config), I, ctypes.POINTER(P)]),
             "nflbm_batch_destroy": (None, [P]),
             "nflbm_batch_count": (I, [P]),
@@ -347,6 +349,12 @@ class Simulation:
         g = np.zeros(self.N)
         _check(lib().nflbm_get_coeffs(self._handle(), _dptr(a), _dptr(g)), self._h)
         return a, g
+
+    def domain_size(self):
+        """L_i of Eq. L for every component (lattice units)."""
+        out = np.zeros(self.N)
+        _check(lib().nflbm_domain_size(self._handle(), _dptr(out)), self._h)
+        return out
 
     def storage_form(self):
         """'moments' (g kept as C, mu~, v per node; every tau_g = 1) or 'populations'."""

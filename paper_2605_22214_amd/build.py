@@ -74,7 +74,7 @@ def build(verbose=True, jobs=None):
                     print(w, flush=True)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
-          [os.path.join(BUILD, u[1]) for u in UNITS]
+          [os.path.join(BUILD, u[1]) for u in UNITS] + ["-L/opt/rocm/lib", "-lhipfft"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -2,6 +2,7 @@
 #include "nflbm.h"
 
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <chrono>
@@ -55,6 +56,12 @@ struct nflbm_sim {
   void* vel = nullptr;   // moment form: (v, v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
   bool borrowed = false; // state arrays live in caller memory (nflbm_bind_state)
+  // domain-size diagnostic: batched R2C plan and its buffers (made on first use)
+  hipfftHandle fft = 0;
+  bool fft_made = false;
+  double* lam = nullptr;
+  void* spec = nullptr;
+  double* spart = nullptr;
   bool in_batch = false;
   void* eb = nullptr;
   void* params = nullptr;
@@ -156,6 +163,14 @@ void free_device(nflbm_sim* s) {
     *a = nullptr;
   }
   if (s->params) (void)hipFree(s->params);
+  if (s->fft_made) (void)hipfftDestroy(s->fft);
+  s->fft_made = false;
+  if (s->lam) (void)hipFree(s->lam);
+  if (s->spec) (void)hipFree(s->spec);
+  if (s->spart) (void)hipFree(s->spart);
+  s->lam = nullptr;
+  s->spec = nullptr;
+  s->spart = nullptr;
   if (s->fields) (void)hipFree(s->fields);
   if (s->red) (void)hipFree(s->red);
   s->params = s->eb = nullptr;
@@ -637,6 +652,7 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
   for (int i = 0; i < N; ++i)
     if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
   if (cfg->flags & NFLBM_FLAG_POTENTIAL_FORCE) s->step_flags |= kFlagPotential;
+  if (cfg->flags & NFLBM_FLAG_NO_HYDRO) s->step_flags |= kFlagNoHydro;
   if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
   // With every tau_g = 1 the post-collision g are equilibria of (C, mu~, v):
   // store those per node instead of the populations, unless asked not to.
@@ -800,6 +816,10 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
     a.sa = make_args(sim, sim->cur);
     e = launch_init(sim->lat, sim->N, sim->store, a, sim->stream);
   }
+  if (e == hipSuccess && (sim->step_flags & kFlagNoHydro))
+    // f is never written in diffusive-only runs: both sets hold the initial f
+    e = hipMemcpyAsync(sim->f[1 - sim->cur], sim->f[sim->cur], size_t(sim->Q - 1) * n * sim->fs,
+                       hipMemcpyDeviceToDevice, sim->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(sim, e, "set_fields");
@@ -1406,6 +1426,48 @@ int nflbm_get_coeffs(const nflbm_sim* sim, double* alpha, double* gamma) {
     if (gamma) gamma[i] = sim->co.gamma[i];
     for (int j = 0; j < N; ++j)
       if (alpha) alpha[i * N + j] = sim->co.alpha[i][j];
+  }
+  return NFLBM_OK;
+}
+
+
+int nflbm_domain_size(nflbm_sim* sim, double* L) {
+  if (!sim || !L) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  int rc = compute_fields(sim);
+  if (rc) return rc;
+  const int N = sim->N;
+  const long long n = static_cast<long long>(sim->n);
+  const long long nc = static_cast<long long>(sim->nz) * sim->ny * (sim->nx / 2 + 1);
+  const int blocks = 256;
+  if (!sim->fft_made) {
+    bool ok = hipMalloc(reinterpret_cast<void**>(&sim->lam), size_t(N) * n * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&sim->spec, size_t(N) * nc * 2 * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&sim->spart), size_t(N) * blocks * 2 * sizeof(double)) == hipSuccess;
+    if (!ok) return fail(sim, NFLBM_ENOMEM, "cannot allocate the domain-size buffers");
+    int dims3[3] = {sim->nz, sim->ny, sim->nx};
+    int dims2[2] = {sim->ny, sim->nx};
+    const bool three = sim->nz > 1;
+    hipfftResult r = hipfftPlanMany(&sim->fft, three ? 3 : 2, three ? dims3 : dims2, nullptr, 1, static_cast<int>(n),
+                                    nullptr, 1, static_cast<int>(nc), HIPFFT_D2Z, N);
+    if (r != HIPFFT_SUCCESS) return fail(sim, NFLBM_EDEVICE, "hipfftPlanMany failed");
+    sim->fft_made = true;
+  }
+  if (hipfftSetStream(sim->fft, sim->stream) != HIPFFT_SUCCESS) return fail(sim, NFLBM_EDEVICE, "hipfftSetStream failed");
+  HIPCHK(sim, launch_lambda(sim->fields, sim->lam, static_cast<long long>(N) * n, sim->stream));
+  if (hipfftExecD2Z(sim->fft, sim->lam, static_cast<hipfftDoubleComplex*>(sim->spec)) != HIPFFT_SUCCESS)
+    return fail(sim, NFLBM_EDEVICE, "hipfftExecD2Z failed");
+  HIPCHK(sim, launch_spectrum(sim->spec, N, sim->nx, sim->ny, sim->nz, nc, blocks, sim->spart, sim->stream));
+  std::vector<double> part(size_t(N) * blocks * 2);
+  HIPCHK(sim, hipMemcpyAsync(part.data(), sim->spart, part.size() * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  const double two_pi = 6.283185307179586;
+  for (int i = 0; i < N; ++i) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < blocks; ++k) {
+      a += part[(size_t(i) * blocks + k) * 2];
+      b += part[(size_t(i) * blocks + k) * 2 + 1];
+    }
+    L[i] = b > 0.0 ? two_pi * a / b : 0.0;
   }
   return NFLBM_OK;
 }

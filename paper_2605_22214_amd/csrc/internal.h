@@ -40,7 +40,8 @@ enum StepFlags {
   kFlagNeedG = 1,         // some tau_g != 1: the update reads g
   kFlagPotential = 2,     // potential-form surface tension
   kFlagOmega = 4,         // Omega != 0
-  kFlagMoments = 8        // moment form of g (tau_g = 1): C, mu~, v, v.v per node
+  kFlagMoments = 8,       // moment form of g (tau_g = 1): C, mu~, v, v.v per node
+  kFlagNoHydro = 16       // diffusive-only: f not evolved, v = 0
 };
 
 // Device code sees the pointers in the argument structs as pointers to global
@@ -129,6 +130,11 @@ hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, h
 hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
 size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+// Domain size (Eq. L): lambda = H(C - 1/2) over [N][n], and partial sums
+// [N][blocks][2] of |X|^2 and |k| |X|^2 over an R2C spectrum [N][nc].
+hipError_t launch_lambda(const double* C, double* lam, long long total, hipStream_t s);
+hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long long nc, int blocks,
+                           double* partial, hipStream_t s);
 __host__ __device__ int reduce_record_len(int N);
 size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
 

@@ -246,13 +246,19 @@ __device__ __forceinline__ int wrap(int v, int n) {
 }
 
 // ------------------------------------------------- equilibrium pair terms
-// e_k . a for a 3-vector a, accumulated over the nonzero components of e_k.
+// e_k . a for a 3-vector a, summed over the nonzero components of e_k from
+// the first one on.
 template <class L, class T>
 __device__ __forceinline__ T proj(int k, const T (&a)[3]) {
   T r = T(0);
+  bool first = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    if (L::e[k][d] != 0) r += (L::e[k][d] > 0) ? a[d] : -a[d];
+    if (L::e[k][d] != 0) {
+      const T t = (L::e[k][d] > 0) ? a[d] : -a[d];
+      r = first ? t : r + t;
+      first = false;
+    }
   return r;
 }
 
@@ -459,8 +465,19 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
 // bits.  The per-node records of
 // the tile and a one-node halo sit in LDS (three planes in D3Q19, marched
 // along z like the update).
-template <class L, int NE>
-constexpr int moment_record() { return 2 * NE + 4; }   // C[NE], mu~[NE], v[3], v.v
+// LDS record of one position: C in [0, NEP), mu~ in [NEP, 2 NEP), then v and
+// v.v, with NEP = NE rounded up to 4 so every group starts 16-byte aligned and
+// moves with vector reads.  The record is padded to an odd multiple of 16
+// bytes (12 or 20 floats, 14 or 22 doubles): consecutive positions then start
+// in different 16-byte bank groups, so a wavefront's reads of a row of
+// positions do not collide on banks.
+template <int NE>
+constexpr int moment_nep() { return (NE + 3) / 4 * 4; }
+template <int NE, class T>
+constexpr int moment_record() {
+  const int r = 2 * moment_nep<NE>() + 4;
+  return (r * int(sizeof(T)) / 16) % 2 == 1 ? r : r + 16 / int(sizeof(T));
+}
 
 template <class L, int NE, int ST, bool WALLS, int TXL>
 __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
@@ -472,7 +489,8 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   constexpr int Q = L::Q;
   constexpr int NC = NE + 1;
   constexpr bool D3 = (L::DIM == 3);
-  constexpr int REC = moment_record<L, NE>();
+  constexpr int NEP = moment_nep<NE>();
+  constexpr int REC = moment_record<NE, T>();
   constexpr int TX = 1 << TXL;
   constexpr int TY = 256 >> TXL;
   constexpr int PX = TX + 2;
@@ -520,9 +538,9 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     }
   }
 
-  // Records of plane gz into an LDS slot, one field after another.  Positions
-  // inside a wall stay unfilled: a population pulled from a wall is this
-  // node's own, so they are never read.
+  // Records of plane gz into an LDS slot, one record per position.
+  // Positions inside a wall stay unfilled: a population pulled from a wall is
+  // this node's own, so they are never read.
   auto load_plane = [&](int slot, int gz) {
     T* base = sm + slot * plane_stride;
     if (gz < 0 || gz >= a.nz) {
@@ -535,17 +553,16 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       if (!fill_ok[r]) continue;
       const int idx = tid + 256 * r;
       const uint32_t node = fill_off[r] + zoff;
-      T cc[NE], mm[NE], vv[4];
-      vld<T, NE>(at(cprev, node * NE), cc);
-      vld<T, NE>(at(mus, node * NE), mm);
+      T cc[NEP], mm[NEP], vv[4];
+#pragma unroll
+      for (int e = NE; e < NEP; ++e) cc[e] = mm[e] = T(0);
+      vld<T, NE>(at(cprev, node * NE), reinterpret_cast<T(&)[NE]>(cc));
+      vld<T, NE>(at(mus, node * NE), reinterpret_cast<T(&)[NE]>(mm));
       vld<T, 4>(at(vels, node * 4), vv);
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        base[e * PXY + idx] = cc[e];
-        base[(NE + e) * PXY + idx] = mm[e];
-      }
-#pragma unroll
-      for (int d = 0; d < 4; ++d) base[(2 * NE + d) * PXY + idx] = vv[d];
+      T* rec = base + idx * REC;
+      vst<T, NEP>(rec, cc);
+      vst<T, NEP>(rec + NEP, mm);
+      vst<T, 4>(rec + 2 * NEP, vv);
     }
   };
 
@@ -555,17 +572,24 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const int li = (ty + 1) * PX + (tx + 1);
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
-    // this node's record
-    const T* own = sm + s_c * plane_stride + li;
-    T c[NE], mu[NE], v[3];
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      c[e] = own[e * PXY];
-      mu[e] = own[(NE + e) * PXY];
+    // records of the 3 x 3 neighbourhood are reached from its lowest corner
+    // with non-negative immediate offsets
+    const T* corner_dn = sm + s_dn * plane_stride + (li - PX - 1) * REC;
+    const T* corner_c = sm + s_c * plane_stride + (li - PX - 1) * REC;
+    const T* corner_up = sm + s_up * plane_stride + (li - PX - 1) * REC;
+    auto rec_at = [&](const T* corner, int ex, int ey) { return corner + ((1 + ey) * PX + (1 + ex)) * REC; };
+    const T* own = rec_at(corner_c, 0, 0);
+    T c[NEP], mu[NEP], v[3];
+    {
+      T v4[4];
+      vld<T, NEP>(own, c);
+      vld<T, NEP>(own + NEP, mu);
+      vld<T, 4>(own + 2 * NEP, v4);
+      v[0] = v4[0];
+      v[1] = v4[1];
+      v[2] = v4[2];
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) v[d] = own[(2 * NE + d) * PXY];
-    const T base_s = -T(1.5) * own[(2 * NE + 3) * PXY];
+    const T base_s = -T(1.5) * own[2 * NEP + 3];
     // rest population: C minus the stored moving populations, summed pair by
     // pair as the population form does
     T moved[NE];
@@ -599,19 +623,21 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
         src = own;
         kd = opposite(k);
       } else {
-        const int slot = (ez == 0) ? s_c : (ez > 0 ? s_dn : s_up);
-        src = sm + slot * plane_stride + li - ey * PX - ex;
+        const T* corner = (ez == 0) ? corner_c : (ez > 0 ? corner_dn : corner_up);
+        src = rec_at(corner, -ex, -ey);
       }
       const int kp = (kd & 1) ? kd : kd - 1;
-      T vs[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) vs[d] = src[(2 * NE + d) * PXY];
+      T cs[NEP], ms[NEP], v4[4];
+      vld<T, NEP>(src, cs);
+      vld<T, NEP>(src + NEP, ms);
+      vld<T, 4>(src + 2 * NEP, v4);
+      const T vs[3] = {v4[0], v4[1], v4[2]};
       const T ev = proj<L>(kp, vs);
-      const T quad = quad_term<L>(ev, -T(1.5) * src[(2 * NE + 3) * PXY]);
+      const T quad = quad_term<L>(ev, -T(1.5) * v4[3]);
       const T sk = s_pair_member<L>(kd, ev, quad);
       const T mw = static_cast<T>(L::w[kp]) * m;
 #pragma unroll
-      for (int e = 0; e < NE; ++e) sum[e] += g_post(src[e * PXY], sk, mw * src[(NE + e) * PXY]);
+      for (int e = 0; e < NE; ++e) sum[e] += g_post(cs[e], sk, mw * ms[e]);
     }
     T cn[NC];
     T rest = T(0);
@@ -862,8 +888,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
       }
       if (!wall) {
+        // from the lowest corner of the 3 x 3 neighbourhood every offset is a
+        // non-negative immediate
         const int slot = (ez == 0) ? s_c : (ez > 0 ? s_up : s_dn);
-        const T* Cn = sm + slot * plane_stride + li + ey * PX + ex;
+        const T* Cn = sm + slot * plane_stride + (li - PX - 1) + (1 + ey) * PX + (1 + ex);
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
           const T d = Cn[i * PXY] - c[i];
@@ -967,18 +995,22 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     // only now: loading it before the stencil would keep Q-1 more registers
     // live through it and cost occupancy.
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
-    load_f(z);
+    // diffusive-only runs (Sec. IV B) do not evolve f: v = 0 and P = 0
+    const bool hydro = !(a.flags & kFlagNoHydro);
     T v[3] = {T(0), T(0), T(0)};
     T fsum = T(0);
+    if (hydro) {
+      load_f(z);
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      fsum += f[k];
+      for (int k = 1; k < Q; ++k) {
+        fsum += f[k];
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? f[k] : -f[k];
+        for (int d = 0; d < 3; ++d)
+          if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? f[k] : -f[k];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
     const T vv = fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0]));
     const T s0 = static_cast<T>(L::w[0]) * (-T(1.5) * vv);
     const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + s0);
@@ -1055,8 +1087,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       const T ep = T(0.5) * (feq_k + feq_b), em = T(0.5) * (feq_k - feq_b);
       const T sym = fma(-wp, fp - ep, hp * (Fk + Fb));
       const T asym = fma(-wm, fm - em, hm * (Fk - Fb));
-      st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(f[k] + sym + asym));
-      st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(f[kb] + sym - asym));
+      if (hydro) {
+        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(f[k] + sym + asym));
+        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(f[kb] + sym - asym));
+      }
       if constexpr (GM) continue;
       const T mw = wk * P.m;
       FS qk[NE], qb[NE];
@@ -1289,6 +1323,52 @@ __global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
   }
 }
 
+// ------------------------------------------------------------ domain size
+// lambda_i = H(C_i - 1/2) of every component from the fields-mode C [N][n].
+__global__ void __launch_bounds__(256) k_lambda(const double* __restrict__ C, double* __restrict__ lam,
+                                                long long total) {
+  const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < total) lam[i] = C[i] > 0.5 ? 1.0 : 0.0;
+}
+
+// Partial sums of S(k) = |X(k)|^2 and |k| S(k) over the half spectrum of an
+// R2C transform (nz x ny x (nx/2 + 1) per component, component blockIdx.y),
+// k = 0 left out; wave vectors kept once stand for their conjugates too.
+__global__ void __launch_bounds__(256) k_spectrum(const double2* __restrict__ X, int nx, int ny, int nz,
+                                                  long long nc, double* __restrict__ partial) {
+  __shared__ double scratch[4];
+  const int comp = blockIdx.y;
+  X += static_cast<long long>(comp) * nc;
+  const int nxh = nx / 2 + 1;
+  double as = 0.0, ak = 0.0;
+  const double two_pi = 6.283185307179586;
+  for (long long idx = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; idx < nc;
+       idx += static_cast<long long>(gridDim.x) * 256) {
+    const int ix = static_cast<int>(idx % nxh);
+    const long long t = idx / nxh;
+    const int iy = static_cast<int>(t % ny);
+    const int iz = static_cast<int>(t / ny);
+    if (ix == 0 && iy == 0 && iz == 0) continue;
+    const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
+    const double fx = double(ix) / nx;
+    const double fy = double(iy <= ny / 2 ? iy : iy - ny) / ny;
+    const double fz = double(iz <= nz / 2 ? iz : iz - nz) / nz;
+    const double kmag = two_pi * sqrt(fx * fx + fy * fy + fz * fz);
+    const double2 c = X[idx];
+    const double S = c.x * c.x + c.y * c.y;
+    as += w * S;
+    ak += w * kmag * S;
+  }
+  as = block_reduce<0>(as, scratch);
+  __syncthreads();
+  ak = block_reduce<0>(ak, scratch);
+  if (threadIdx.x == 0) {
+    double* out = partial + (static_cast<long long>(comp) * gridDim.x + blockIdx.x) * 2;
+    out[0] = as;
+    out[1] = ak;
+  }
+}
+
 __global__ void __launch_bounds__(64) k_reduce_final(ReduceArgs a) {
   const int N = a.N;
   const int rec = reduce_record_len(N);
@@ -1323,13 +1403,15 @@ size_t lds_bytes_for(int lat, int nc, int tx_log2) {
   return npl * size_t(nc) * pxy * sizeof(TT<ST>);
 }
 
-// LDS of the moment-form reconstruction: 2 NE + 4 values per position.
+// LDS of the moment-form reconstruction: one padded record per position.
 template <int ST>
 size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
   const int npl = lat == 1 ? 3 : 1;
-  return npl * size_t(2 * (nc - 1) + 4) * pxy * sizeof(TT<ST>);
+  size_t rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4;
+  if ((rec * sizeof(TT<ST>) / 16) % 2 == 0) rec += 16 / sizeof(TT<ST>);
+  return npl * rec * pxy * sizeof(TT<ST>);
 }
 
 hipError_t update_st0(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
@@ -1616,6 +1698,19 @@ hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, h
     case kStoreF16S: return batch_st2(lat, nc, b, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_lambda(const double* C, double* lam, long long total, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  hipLaunchKernelGGL(k_lambda, dim3(blocks), dim3(256), 0, s, C, lam, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long long nc, int blocks,
+                           double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3(blocks, N), dim3(256), 0, s, static_cast<const double2*>(X), nx, ny, nz, nc,
+                     partial);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {

@@ -217,8 +217,8 @@ def test_reduction_trajectory():
 
 
 # ---------------------------------------------------------- linear dispersion
-@pytest.mark.parametrize("N,a", [(2, 1.5), (4, None)])
-def test_linear_dispersion(N, a):
+@pytest.mark.parametrize("N,a,hydro", [(2, 1.5, True), (4, None, True), (4, None, False)])
+def test_linear_dispersion(N, a, hydro):
     """Small noise about the uniform mixture grows per Fourier mode as G(k)^t.
 
     N = 2: a = 6/D by hand (mu~_1 = -(12/D) C (1 - 3C + 2C^2) linearised at 1/2).
@@ -226,7 +226,7 @@ def test_linear_dispersion(N, a):
     zero-sum direction (finite difference), independent of the factored form."""
     from oracle import potential as pot
     n, m, D, T = 32, 0.05, 4.0, 200
-    par = S.Params(D2Q9, (n, n, 1), equal_sigma(N, 0.005), np.ones(N), m=m)
+    par = S.Params(D2Q9, (n, n, 1), equal_sigma(N, 0.005), np.ones(N), m=m, hydro=hydro)
     if a is None:
         eps = 1e-6
         Cu = np.full((N, 1), 1.0 / N)
@@ -420,3 +420,51 @@ def test_mobility_stability_bound():
         amp[fac] = np.abs(C[1] - C[1].mean()).max()
     assert amp[0.9] < 1e-9
     assert amp[1.5] > 1e-4
+
+
+# ------------------------------------------------------------- domain size
+def _brute_force_L(lam):
+    """Eq. L by a direct double sum over x and k (tiny grids only)."""
+    ny, nx = lam.shape
+    num = den = 0.0
+    for my in range(ny):
+        for mx in range(nx):
+            if mx == 0 and my == 0:
+                continue
+            ky = 2 * math.pi * (my if my <= ny // 2 else my - ny) / ny
+            kx = 2 * math.pi * (mx if mx <= nx // 2 else mx - nx) / nx
+            if ny % 2 == 0 and my == ny // 2:
+                ky = -math.pi   # fftfreq puts the Nyquist row at -1/2
+            if nx % 2 == 0 and mx == nx // 2:
+                kx = -math.pi
+            amp = 0j
+            for y in range(ny):
+                for x in range(nx):
+                    amp += lam[y, x] * complex(math.cos(kx * x + ky * y), -math.sin(kx * x + ky * y))
+            S = abs(amp) ** 2
+            num += S
+            den += math.hypot(kx, ky) * S
+    return 2 * math.pi * num / den
+
+
+def test_domain_size_matches_direct_sum():
+    rng = np.random.default_rng(5)
+    C = rng.uniform(size=(2, 1, 6, 10))
+    L = A.domain_size(C)
+    for i in range(2):
+        assert L[i] == pytest.approx(_brute_force_L((C[i, 0] > 0.5).astype(float)), rel=1e-12)
+
+
+def test_domain_size_invariances():
+    """Translations leave L unchanged; repeating a pattern periodically 2 x 2
+    times leaves it unchanged (its spectrum only gains empty wave vectors)."""
+    rng = np.random.default_rng(6)
+    C = rng.uniform(size=(1, 1, 12, 16))
+    L0 = A.domain_size(C)[0]
+    assert A.domain_size(np.roll(C, (3, 5), axis=(2, 3)))[0] == pytest.approx(L0, rel=1e-12)
+    assert A.domain_size(np.tile(C, (1, 1, 2, 2)))[0] == pytest.approx(L0, rel=1e-12)
+    # stripes of half-period 8 along x: a square wave, L ~ the half-period
+    x = np.arange(64)
+    stripes = ((x // 8) % 2).astype(float)[None, None, None, :] * np.ones((1, 1, 4, 64))
+    Ls = A.domain_size(stripes)[0]
+    assert 4.0 < Ls < 16.0

@@ -153,6 +153,16 @@ def noise(lattice, shape, ncomp_present, ncomp_total=None, amp=0.02, seed=0,
                  name=f"noise_{lattice}_{ncomp_present}of{ncomp_total}")
 
 
+def coarsening_2d(n=400, ncomp=4, seed=0, sigma=0.005, m=0.1):
+    """Phase separation from the recipe of Sec. IV B: every C_i drawn from
+    U[0, 2/N] at each node, then normalised to sum 1; all sigma equal, eta =
+    1/6 (tau = 1), tau_g = 1."""
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 2.0 / ncomp, size=(ncomp, 1, n, n))
+    C /= C.sum(axis=0, keepdims=True)
+    return _base("D2Q9", (n, n, 1), _equal_sigma(ncomp, sigma), 1.0, m, C0=C, name="coarsening_2d")
+
+
 def quaternary_2d(n=512, seed=0):
     """D2Q9, N = 4, n x n periodic, 0.25 + U(-0.02, 0.02) renormalised;
     sigma = 0.01, tau = tau_g = 1, m = 0.1."""
