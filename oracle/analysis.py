@@ -82,6 +82,36 @@ def linear_growth(lam, M, a, D):
     return 1.0 + M * lam * (a - 0.75 * D * lam)
 
 
+def gradient_symbol(lat, kvec):
+    """s(k) = sum_{q>=1} w_q e_q sin(k . e_q) -> [3]: the isotropic gradient
+    (1/c_s^2) sum_q w_q e_q [psi(x + e_q) - psi(x)] acts on exp(i k.x) as
+    3 i s(k)."""
+    out = np.zeros(3)
+    for q in range(1, lat.Q):
+        ke = sum(kvec[a] * lat.e[q, a] for a in range(3))
+        out = out + lat.w[q] * lat.e[q] * np.sin(ke)
+    return out
+
+
+def source_mobility_growth(lat, kvec, alpha0, A, kappa, m_star, tau_g=1.0):
+    """Per-step growth matrix of a Fourier mode of C about a uniform state in
+    the concentration-dependent mobility scheme of Appendix C, tau_g = 1,
+    v = 0.  With g^eq carrying no mobility term, C(x, t+1) = C(x, t) +
+    sum_k S_k(x - e_k) for the source S_k = (1/2) w_k m* e_k.G, and G =
+    alpha0 grad Phi; streaming turns the sum into (3/2) m* |s(k)|^2 times G's
+    amplitude over 3 i s(k).  Phi linearises as (A - K lam(k)) dC with A the
+    Jacobian of the bulk part of mu + phi + xi and K_jk = kappa_jk (j != k)
+    from the gradient part of mu_j.  Returns the N x N matrix."""
+    if tau_g != 1.0:
+        raise ValueError("closed form holds for tau_g = 1")
+    s = gradient_symbol(lat, kvec)
+    lam = laplacian_symbol(lat, kvec)
+    K = np.array(kappa, dtype=np.float64).copy()
+    np.fill_diagonal(K, 0.0)
+    N = K.shape[0]
+    return np.eye(N) + 1.5 * m_star * float(s @ s) * (alpha0 @ (A - K * lam))
+
+
 def laplace_pressure_2d(sigma, R):
     return sigma / R
 

@@ -124,6 +124,27 @@ def mu_tilde_literal(C, lapC, co, omega=0.0, with_phi=True, with_xi=True):
     return out
 
 
+def flux_potentials(C, lapC, co, omega=0.0):
+    """mu_j + phi_j + xi_j for every component j: the quantity that Eq. MU
+    contracts with alpha, and whose gradient the concentration-dependent
+    mobility of Appendix C contracts with the per-node alpha."""
+    return mu_full(C, lapC, co) + phi(C, co) + xi(C, co, omega)
+
+
+def alpha_c2c2(C):
+    """Concentration-dependent mobility matrix of Appendix C at every node:
+    alpha_ij = C_i^2 C_j^2 for i != j and alpha_ii = -sum_{j != i} alpha_ij,
+    so that every row (and column) sums to zero -> [N, N, ...]."""
+    N = C.shape[0]
+    a = np.zeros((N, N) + C.shape[1:])
+    for i in range(N):
+        for j in range(N):
+            if j != i:
+                a[i, j] = C[i] ** 2 * C[j] ** 2
+                a[i, i] = a[i, i] - a[i, j]
+    return a
+
+
 def bulk_flux_potential_eq_fluxwrong(C, co):
     """The right-hand side of Eq. fluxwrong without the gradient:
     (12/D) [ -C_i (1 - 3C_i + 2C_i^2) + 6 sum_{j<k<l} T_{i;jkl} C_j C_k C_l ].

@@ -42,6 +42,14 @@ Readings (where the printed text is garbled or silent):
     adds w_k C_i to every direction, which adds a Fickian c_s^2 C_i I to the
     second moment.
   * rho = 1 exactly (rho_i = 1 for every component), so grad rho terms vanish.
+  * Concentration-dependent mobility (Appendix C, ``mobility="c2c2"``): the
+    per-node alpha_ij = C_i^2 C_j^2, alpha_ii = -sum_{j != i} alpha_ij replaces
+    the constant alpha inside the flux only.  g^eq takes m = 0 and every
+    evolved g gains the source (1 - 1/(2 tau_g)) w_k m* e_k.G_i after its BGK
+    relaxation, with G_i = sum_j alpha_ij grad(mu_j + phi_j + xi_j) from the
+    same isotropic gradient stencil as every other gradient; the mobility is
+    M = c_s^2 m* (tau_g - 1/2).  alpha_ij is evaluated with all N
+    concentrations of the node (the implicit one included).
 """
 import numpy as np
 
@@ -56,7 +64,7 @@ class Params:
                  trt_magic=0.0, tau_g=None, m=0.02, body_force=(0.0, 0.0, 0.0),
                  walls=(False, False, False), mu_form="factored",
                  force_form="conservative", geq_form="rest", hydro=True,
-                 implicit=None):
+                 implicit=None, mobility="constant", m_star=10.0):
         from .coeffs import Coefficients
         self.lat = lattice
         nx, ny, nz = shape
@@ -77,6 +85,10 @@ class Params:
         self.force_form = force_form
         self.geq_form = geq_form
         self.hydro = hydro
+        if mobility not in ("constant", "c2c2"):
+            raise ValueError(mobility)
+        self.mobility = mobility
+        self.m_star = float(m_star)
         self.implicit = self.N - 1 if implicit is None else int(implicit)
         if not 0 <= self.implicit < self.N:
             raise ValueError("implicit component out of range")
@@ -206,8 +218,29 @@ def macroscopic(f, g, par):
         wm = 1.0 / (0.5 + par.trt_magic / (tau - 0.5))
     else:
         wm = wp.copy()
-    return dict(C=C, EB=EB, gradC=gradC, lapC=lapC, gradEB=gradEB, mu_tilde=mut,
-                F=F, v=v, P=P, s=s, tau=tau, omega_plus=wp, omega_minus=wm)
+    out = dict(C=C, EB=EB, gradC=gradC, lapC=lapC, gradEB=gradEB, mu_tilde=mut,
+               F=F, v=v, P=P, s=s, tau=tau, omega_plus=wp, omega_minus=wm)
+    if par.mobility == "c2c2":
+        Phi = potential.flux_potentials(C, lapC, co, par.omega_stab)
+        gradPhi = np.stack([gradient(Phi[j], par) for j in range(N)])   # [N, 3, ...]
+        A = potential.alpha_c2c2(C)
+        G = np.zeros_like(gradPhi)
+        for i in range(N):
+            for j in range(N):
+                G[i] = G[i] + A[i, j] * gradPhi[j]
+        out.update(Phi=Phi, alpha=A, G=G)
+    return out
+
+
+def mobility_source(lat, G, tau_g, m_star):
+    """Source of the g-LBE in Appendix C: (1 - 1/(2 tau_g)) w_k m* e_k.G
+    -> [Q, ...] for one component."""
+    pre = (1.0 - 0.5 / tau_g) * m_star
+    out = np.empty((lat.Q,) + G.shape[1:])
+    for k in range(lat.Q):
+        eG = sum(lat.e[k, a] * G[a] for a in range(3))
+        out[k] = pre * lat.w[k] * eG
+    return out
 
 
 def f_equilibrium(lat, P, s):
@@ -267,8 +300,12 @@ def collide(f, g, par, mac=None):
                      + 0.5 * (1.0 - 0.5 * wm) * (Fk[k] - Fk[kb]))
     else:
         fs = f.copy()
-    geq = g_equilibrium(lat, mac["C"], s, mac["mu_tilde"], par.m, par.geq_form)
+    m_geq = 0.0 if par.mobility == "c2c2" else par.m
+    geq = g_equilibrium(lat, mac["C"], s, mac["mu_tilde"], m_geq, par.geq_form)
     gs = g - (g - geq) / par.tau_g.reshape(-1, 1, 1, 1, 1)
+    if par.mobility == "c2c2":
+        for i in par.evolved:
+            gs[i] = gs[i] + mobility_source(lat, mac["G"][i], par.tau_g[i], par.m_star)
     gs[par.implicit] = 0.0
     return fs, gs, mac
 
