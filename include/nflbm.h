@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 5
+#define NFLBM_ABI_VERSION 6
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -82,10 +82,27 @@ enum {
   NFLBM_FLAG_ALLOW_UNSTABLE = 2,  /* skip the mobility stability check      */
   NFLBM_FLAG_G_POPULATIONS = 4,   /* keep the populations of g even when every
                                      tau_g = 1 (see "Storage of g" below)      */
-  NFLBM_FLAG_NO_HYDRO = 8         /* diffusive-only (Sec. IV B): the LBE of f is
+  NFLBM_FLAG_NO_HYDRO = 8,        /* diffusive-only (Sec. IV B): the LBE of f is
                                      not evolved, v = 0 and P = 0 everywhere;
                                      only the Cahn-Hilliard LBEs of g step     */
+  NFLBM_FLAG_C2C2_MOBILITY = 16   /* concentration-dependent mobility of
+                                     Appendix C, see below                     */
 };
+
+/* Concentration-dependent mobility (Appendix C, Eqs. mobilconc and
+ * glbesource), the comparison variant of Fig. 3(d).  The flux uses the
+ * per-node alpha_ij = C_i^2 C_j^2 (i != j), alpha_ii = -sum_{j != i} alpha_ij
+ * instead of the constant alpha of Eqs. alpha1/alpha2: g^eq carries no
+ * mobility term, and each evolved g gains after its relaxation the source
+ * (1 - 1/(2 tau_g,i)) w_k m* e_k.G_i with G_i = sum_j alpha_ij
+ * grad(mu_j + phi_j + xi_j) (the same isotropic gradient stencil and wall
+ * rule as every other gradient).  Under this flag the config field m is m*
+ * (the paper uses 10; M = c_s^2 m* (tau_g - 1/2)), g is kept as populations,
+ * the constant-mobility stability check is skipped (alpha is at most 1/16
+ * in magnitude per entry here), and the library allocates a scratch array of
+ * N values per node in the compute precision for the potentials.  The MU
+ * field still reports the constant-alpha flux potential, which this variant
+ * does not use.  Batches do not take members with this flag (NFLBM_ENOTSUP). */
 
 /* Storage of g.  With every tau_g = 1 a post-collision population of g is
  * its equilibrium, C_i s_k(v) - w_k m mu~_i (Eqs. glbe, geq), so by default
@@ -262,9 +279,12 @@ int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
 /* 1 if sim keeps g in the moment form, 0 for populations, negative on error. */
 int nflbm_storage_form(const nflbm_sim *sim);
 
-/* Bytes moved per lattice-node update by the reconstruction and update
- * kernels together, counting every stored population once read and once
- * written plus the reconstructed concentrations (written once, read once). */
+/* Bytes moved per lattice-node update by the kernels of one step together,
+ * counting every stored population once read and once written plus the
+ * reconstructed concentrations (written once, read once); f is left out of a
+ * diffusive-only run (it is neither read nor written), and the
+ * concentration-dependent mobility adds its potentials (written once, read
+ * once), a second read of C and the re-write of the moving populations of g. */
 int nflbm_bytes_per_node(nflbm_sim *sim, double *bytes);
 
 /* Launch-shape autotuner: times every shape nflbm_set_launch accepts (tile

@@ -24,6 +24,7 @@ FLAG_POTENTIAL_FORCE = 1
 FLAG_ALLOW_UNSTABLE = 2
 FLAG_G_POPULATIONS = 4
 FLAG_NO_HYDRO = 8
+FLAG_C2C2_MOBILITY = 16
 FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 BATCH_MODES = {"launch": 0, "graph": 1, "per_sim": 2}

@@ -35,6 +35,7 @@ UNITS = [
     ("kernels.hip", "kernels_f32.o", True, ["-DNFLBM_UNIT_STORE=1"]),
     ("kernels.hip", "kernels_f16s.o", True, ["-DNFLBM_UNIT_STORE=2"]),
     ("kernels.hip", "kernels_common.o", True, ["-DNFLBM_UNIT_STORE=-1"]),
+    ("mobility.hip", "mobility.o", True, []),
 ]
 
 

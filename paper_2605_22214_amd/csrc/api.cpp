@@ -55,6 +55,10 @@ struct nflbm_sim {
   void* mu = nullptr;    // moment form: mu~ [node][i]
   void* vel = nullptr;   // moment form: (v, v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
+  // concentration-dependent mobility: MobParams and the potential scratch
+  bool c2c2 = false;
+  void* mob = nullptr;
+  void* phi = nullptr;
   bool borrowed = false; // state arrays live in caller memory (nflbm_bind_state)
   // domain-size diagnostic: batched R2C plan and its buffers (made on first use)
   hipfftHandle fft = 0;
@@ -163,6 +167,9 @@ void free_device(nflbm_sim* s) {
     *a = nullptr;
   }
   if (s->params) (void)hipFree(s->params);
+  if (s->mob) (void)hipFree(s->mob);
+  if (s->phi) (void)hipFree(s->phi);
+  s->mob = s->phi = nullptr;
   if (s->fft_made) (void)hipfftDestroy(s->fft);
   s->fft_made = false;
   if (s->lam) (void)hipFree(s->lam);
@@ -278,6 +285,63 @@ int ensure_fields(nflbm_sim* s) {
       return fail(s, NFLBM_ENOMEM, "cannot allocate the readback field buffer");
     }
   }
+  return NFLBM_OK;
+}
+
+// Tables of the concentration-dependent mobility in internal component order:
+// Lambda and Theta are symmetric in their index sets, so every ordering of a
+// set is filled from the sorted user-index entry.
+template <class T>
+void fill_mob(const nflbm_sim& s, const double* tau_g, double m_star, MobParams<T>* p) {
+  std::memset(p, 0, sizeof(*p));
+  const int N = s.N;
+  const Coeffs& c = s.co;
+  auto srt = [](int* v, int n) {
+    for (int x = 0; x < n; ++x)
+      for (int y = x + 1; y < n; ++y)
+        if (v[y] < v[x]) std::swap(v[x], v[y]);
+  };
+  for (int j = 0; j < N; ++j)
+    for (int k = 0; k < N; ++k)
+      for (int l = 0; l < N; ++l)
+        for (int m = 0; m < N; ++m) {
+          const int uj = s.uidx[j];
+          int t[3] = {s.uidx[k], s.uidx[l], s.uidx[m]};
+          if (k != l && k != m && l != m && j != k && j != l && j != m) {
+            srt(t, 3);
+            p->lam[j][k][l][m] = static_cast<T>(c.lam[uj][t[0]][t[1]][t[2]]);
+          }
+          // theta[k][l][j][m]: pair {k, l}, then j and m outside it
+          if (k != l && j != k && j != l && m != k && m != l && m != j) {
+            int pr[2] = {s.uidx[k], s.uidx[l]};
+            srt(pr, 2);
+            p->theta[k][l][j][m] = static_cast<T>(c.theta[pr[0]][pr[1]][uj][s.uidx[m]]);
+          }
+        }
+  for (int i = 0; i < N; ++i) {
+    const double tg = tau_g ? tau_g[s.uidx[i]] : 1.0;
+    p->pre[i] = static_cast<T>((1.0 - 0.5 / tg) * m_star);
+  }
+}
+
+MobArgs mob_args(const nflbm_sim* s, const StepArgs& a) {
+  MobArgs m{};
+  m.sa = a;
+  m.mob = s->mob;
+  m.phi = s->phi;
+  return m;
+}
+
+// One time step from state set `cur`; ev (optional) brackets the update.
+int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1) {
+  StepArgs a = make_args(s, s->cur);
+  HIPCHK(s, launch_conc(s->lat, s->N, s->store, a, s->stream));
+  if (s->c2c2) HIPCHK(s, launch_mob_potentials(s->lat, s->N, s->store, mob_args(s, a), s->stream));
+  if (ev0) HIPCHK(s, hipEventRecord(ev0, s->stream));
+  HIPCHK(s, launch_update(s->lat, s->N, s->store, a, false, s->stream));
+  if (ev1) HIPCHK(s, hipEventRecord(ev1, s->stream));
+  if (s->c2c2) HIPCHK(s, launch_mob_source(s->lat, s->N, s->store, mob_args(s, a), s->stream));
+  s->cur ^= 1;
   return NFLBM_OK;
 }
 
@@ -632,7 +696,7 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
   // Linear stability of the explicit Cahn-Hilliard update in a pure phase:
   // a mode of -lap eigenvalue lam grows by 1 + M lam (a - (3D/4) lam) per step
   // with a = -12/D; |growth| <= 1 up to lam_max = 16/3 needs the bound below.
-  if (!(cfg->flags & NFLBM_FLAG_ALLOW_UNSTABLE)) {
+  if (!(cfg->flags & (NFLBM_FLAG_ALLOW_UNSTABLE | NFLBM_FLAG_C2C2_MOBILITY))) {
     const double lam = 16.0 / 3.0;
     for (int i = 0; i < N; ++i) {
       const double tg = cfg->tau_g ? cfg->tau_g[i] : 1.0;
@@ -656,7 +720,8 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
   if (cfg->omega_stab != 0.0) s->step_flags |= kFlagOmega;
   // With every tau_g = 1 the post-collision g are equilibria of (C, mu~, v):
   // store those per node instead of the populations, unless asked not to.
-  s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS)) ? 1 : 0;
+  s->c2c2 = (cfg->flags & NFLBM_FLAG_C2C2_MOBILITY) != 0;
+  s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS) && !s->c2c2) ? 1 : 0;
   if (s->gform && choose_launch(s) != 0) s->gform = 0;   // its LDS window does not fit
   if (s->gform) s->step_flags |= kFlagMoments;
   if (choose_launch(s) != 0) {
@@ -742,19 +807,39 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   for (auto& a : state_arrays(s)) ok = ok && hipMalloc(a.first, a.second) == hipSuccess;
   const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
   ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
+  if (s->c2c2) {
+    const size_t msize = s->ts == 8 ? sizeof(MobParams<double>) : sizeof(MobParams<float>);
+    ok = ok && hipMalloc(&s->mob, msize) == hipSuccess;
+    ok = ok && hipMalloc(&s->phi, size_t(N) * n * s->ts) == hipSuccess;
+  }
   if (!ok) {
     free_device(s);
     delete s;
     return fail(nullptr, NFLBM_ENOMEM, "device allocation failed");
   }
+  // the concentration-dependent mobility takes m = 0 in g^eq; cfg->m is its m*
+  const double m_geq = s->c2c2 ? 0.0 : cfg->m;
   if (s->ts == 8) {
     DevParams<double> p;
-    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, cfg->m, cfg->omega_stab, cfg->body_force, &p);
+    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, m_geq, cfg->omega_stab, cfg->body_force, &p);
     if (hipMemcpy(s->params, &p, sizeof(p), hipMemcpyHostToDevice) != hipSuccess) ok = false;
   } else {
     DevParams<float> p;
-    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, cfg->m, cfg->omega_stab, cfg->body_force, &p);
+    fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, m_geq, cfg->omega_stab, cfg->body_force, &p);
     if (hipMemcpy(s->params, &p, sizeof(p), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+  }
+  if (ok && s->c2c2) {
+    if (s->ts == 8) {
+      auto* mp = new MobParams<double>();
+      fill_mob(*s, cfg->tau_g, cfg->m, mp);
+      if (hipMemcpy(s->mob, mp, sizeof(*mp), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+      delete mp;
+    } else {
+      auto* mp = new MobParams<float>();
+      fill_mob(*s, cfg->tau_g, cfg->m, mp);
+      if (hipMemcpy(s->mob, mp, sizeof(*mp), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+      delete mp;
+    }
   }
   // rest state with C_1 = 1 everywhere until set_fields is called
   if (ok) {
@@ -830,10 +915,8 @@ int nflbm_step(nflbm_sim* sim, long long nsteps) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (nsteps < 0) return fail(sim, NFLBM_EINVAL, "nsteps < 0");
   for (long long t = 0; t < nsteps; ++t) {
-    StepArgs a = make_args(sim, sim->cur);
-    HIPCHK(sim, launch_conc(sim->lat, sim->N, sim->store, a, sim->stream));
-    HIPCHK(sim, launch_update(sim->lat, sim->N, sim->store, a, false, sim->stream));
-    sim->cur ^= 1;
+    const int rc = launch_step(sim, nullptr, nullptr);
+    if (rc != NFLBM_OK) return rc;
   }
   return NFLBM_OK;
 }
@@ -850,12 +933,8 @@ int nflbm_step_timed(nflbm_sim* sim, long long nsteps, double* ms, double* ms_up
   }
   HIPCHK(sim, hipEventRecord(e0, sim->stream));
   for (long long t = 0; t < nsteps; ++t) {
-    StepArgs a = make_args(sim, sim->cur);
-    HIPCHK(sim, launch_conc(sim->lat, sim->N, sim->store, a, sim->stream));
-    if (ms_update) HIPCHK(sim, hipEventRecord(ev[2 * t], sim->stream));
-    HIPCHK(sim, launch_update(sim->lat, sim->N, sim->store, a, false, sim->stream));
-    if (ms_update) HIPCHK(sim, hipEventRecord(ev[2 * t + 1], sim->stream));
-    sim->cur ^= 1;
+    const int rc = ms_update ? launch_step(sim, ev[2 * t], ev[2 * t + 1]) : launch_step(sim, nullptr, nullptr);
+    if (rc != NFLBM_OK) return rc;
   }
   HIPCHK(sim, hipEventRecord(e1, sim->stream));
   HIPCHK(sim, hipEventSynchronize(e1));
@@ -1087,7 +1166,11 @@ int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   } else {
     b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;
     if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;
+    // concentration-dependent mobility: potentials read C and write N values;
+    // the source reads them and C, rewrites the moving populations and g0
+    if (sim->c2c2) b += (NE + sim->N) * sim->ts + (sim->N + NE) * sim->ts + 2.0 * NE * Qm * sim->fs + NE * sim->g0s;
   }
+  if (sim->step_flags & kFlagNoHydro) b -= 2.0 * Qm * sim->fs;   // f neither read nor written
   *bytes = b;
   return NFLBM_OK;
 }
@@ -1151,6 +1234,9 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
       return bfail(nullptr, NFLBM_EINVAL, "batch members must share lattice, ncomp and precision");
   // one storage form of g for every member: populations if any member needs
   // them (some tau_g != 1, or asked for)
+  for (int i = 0; i < count; ++i)
+    if (cfgs[i].flags & NFLBM_FLAG_C2C2_MOBILITY)
+      return bfail(nullptr, NFLBM_ENOTSUP, "batch members cannot use the concentration-dependent mobility");
   std::vector<nflbm_config> cc(cfgs, cfgs + count);
   bool pop = false;
   for (const auto& c : cc) {

@@ -127,8 +127,8 @@ int compute_coeffs(int N, const double* sigma, double D, Coeffs* out, char* msg)
   };
 
   // --- Lambda[j][triple] for every triple k<l<m (Eq. ngamma)
-  static thread_local double lam[kMaxComp][kMaxComp][kMaxComp][kMaxComp];
-  static thread_local double th[kMaxComp][kMaxComp][kMaxComp][kMaxComp];  // [k][l][j][m]
+  auto& lam = c.lam;
+  auto& th = c.theta;   // [k][l][j][m]
   for (int k = 0; k < N; ++k)
     for (int l = k + 1; l < N; ++l)
       for (int m = l + 1; m < N; ++m) {

@@ -22,6 +22,11 @@ struct Coeffs {
   double psi[kMaxComp][kMaxComp][kMaxComp] = {};
   double xt[kMaxComp][kMaxComp][kMaxComp] = {};
   double zt[kMaxComp][kMaxComp][kMaxComp] = {};
+  // The solved coefficients themselves (user indices; 0 outside the index
+  // sets): lam[j][k][l][m] = Lambda_{j;klm} for k<l<m without j (Eq. ngamma),
+  // theta[k][l][j][m] = Theta_{kl;j;m} for k<l, j and m outside {k,l}, j != m.
+  double lam[kMaxComp][kMaxComp][kMaxComp][kMaxComp] = {};
+  double theta[kMaxComp][kMaxComp][kMaxComp][kMaxComp] = {};
   bool any_positive_spreading = false;    // some S_ij;k = s_ij - s_ik - s_jk > 0
 };
 

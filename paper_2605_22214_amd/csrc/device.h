@@ -1,0 +1,344 @@
+// Device-side building blocks shared by the kernel sources: the lattices,
+// the storage types of each precision, vector and nontemporal node
+// accesses, the free-energy polynomials, the equilibrium pair terms and the
+// pull-streaming neighbour rules.  Included by device code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace nflbm {
+
+// ---------------------------------------------------------------- lattices
+struct D2Q9 {
+  static constexpr int Q = 9, DIM = 2;
+  static constexpr int e[9][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                  {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+struct D3Q19 {
+  static constexpr int Q = 19, DIM = 3;
+  static constexpr int e[19][3] = {
+      {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+      {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+      {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+// In both sets the opposite of direction k (k >= 1) is k + 1 for odd k.
+__host__ __device__ constexpr int opposite(int k) { return (k & 1) ? k + 1 : k - 1; }
+
+// ----------------------------------------------------------- storage types
+template <int ST> struct StoreT;
+template <> struct StoreT<kStoreF64> {
+  using T = double; using FS = double; using G0S = double;
+  static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ FS pack(T v) { return v; }
+  static __device__ __forceinline__ T unpack(FS v) { return v; }
+};
+template <> struct StoreT<kStoreF32> {
+  using T = float; using FS = float; using G0S = float;
+  static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ FS pack(T v) { return v; }
+  static __device__ __forceinline__ T unpack(FS v) { return v; }
+};
+template <> struct StoreT<kStoreF16S> {
+  using T = float; using FS = _Float16; using G0S = float;
+  static __device__ __forceinline__ T ld(const FS* p, size_t i) {
+    return static_cast<float>(p[i]) * (1.0f / kHalfScale);
+  }
+  static __device__ __forceinline__ FS pack(T v) { return static_cast<_Float16>(v * kHalfScale); }
+  static __device__ __forceinline__ T unpack(FS v) { return static_cast<float>(v) * (1.0f / kHalfScale); }
+};
+
+// ------------------------------------------------- per-node vector access
+// The NE values a node holds for one direction are contiguous; groups of 4,
+// 8, 16 or 32 bytes move with single vector instructions.  Node offsets are
+// multiples of the group size, so these accesses are aligned.
+template <class E, int NE>
+__device__ __forceinline__ void vld(const E* p, E (&o)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+    __builtin_memcpy(o, &t, 4);
+  } else if constexpr (B == 8) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);
+    __builtin_memcpy(o, &t, 8);
+  } else if constexpr (B == 16) {
+    const uint4 t = *reinterpret_cast<const uint4*>(p);
+    __builtin_memcpy(o, &t, 16);
+  } else if constexpr (B == 32) {
+    uint4 t[2];
+    t[0] = reinterpret_cast<const uint4*>(p)[0];
+    t[1] = reinterpret_cast<const uint4*>(p)[1];
+    __builtin_memcpy(o, t, 32);
+  } else {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) o[e] = p[e];
+  }
+}
+
+template <class E, int NE>
+__device__ __forceinline__ void vst(E* p, const E (&v)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    uint32_t t;
+    __builtin_memcpy(&t, v, 4);
+    *reinterpret_cast<uint32_t*>(p) = t;
+  } else if constexpr (B == 8) {
+    uint2 t;
+    __builtin_memcpy(&t, v, 8);
+    *reinterpret_cast<uint2*>(p) = t;
+  } else if constexpr (B == 16) {
+    uint4 t;
+    __builtin_memcpy(&t, v, 16);
+    *reinterpret_cast<uint4*>(p) = t;
+  } else if constexpr (B == 32) {
+    uint4 t[2];
+    __builtin_memcpy(t, v, 32);
+    reinterpret_cast<uint4*>(p)[0] = t[0];
+    reinterpret_cast<uint4*>(p)[1] = t[1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) p[e] = v[e];
+  }
+}
+
+// Nontemporal forms for streams touched once per step: the populations the
+// reconstruction gathers and the post-collision populations the update
+// writes (re-read only by the next step's reconstruction).  Streaming stores
+// also leave L2 free of dirty lines for the reconstruction that follows.
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
+template <class E, int NE>
+__device__ __forceinline__ void vld_nt(const E* p, E (&o)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    const unsigned t = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
+    __builtin_memcpy(o, &t, 4);
+  } else if constexpr (B == 8) {
+    const nt_u2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
+    __builtin_memcpy(o, &t, 8);
+  } else if constexpr (B == 16) {
+    const nt_u4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+    __builtin_memcpy(o, &t, 16);
+  } else {
+    // wider records move as two 16-byte halves from different instructions;
+    // a streaming hint would drop the line between them (measured: FP64
+    // reconstruction 10% slower), so they take the cached path
+    vld<E, NE>(p, o);
+  }
+}
+
+template <class E, int NE>
+__device__ __forceinline__ void vst_nt(E* p, const E (&v)[NE]) {
+  constexpr int B = int(sizeof(E)) * NE;
+  if constexpr (B == 4) {
+    unsigned t;
+    __builtin_memcpy(&t, v, 4);
+    __builtin_nontemporal_store(t, reinterpret_cast<unsigned*>(p));
+  } else if constexpr (B == 8) {
+    nt_u2 t;
+    __builtin_memcpy(&t, v, 8);
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u2*>(p));
+  } else if constexpr (B == 16) {
+    nt_u4 t;
+    __builtin_memcpy(&t, v, 16);
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u4*>(p));
+  } else {
+    vst<E, NE>(p, v);   // as in vld_nt
+  }
+}
+
+// A uniform value the compiler must treat as new at this point: direction
+// offsets derived from it are formed where they are used instead of being
+// hoisted out of the z loop, where dozens of 64-bit bases would stay live in
+// scalar registers and spill.
+__device__ __forceinline__ size_t fresh(size_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+// Read-only tables seen through the constant address space: uniform reads
+// become scalar loads with immediate offsets, and the pointer is fresh at the
+// point of use (see above).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NFLBM_CONST __attribute__((address_space(4)))
+#else
+#define NFLBM_CONST
+#endif
+template <class E>
+__device__ __forceinline__ const NFLBM_CONST E* fresh_const(const E* p) {
+  const NFLBM_CONST E* c = (const NFLBM_CONST E*)(const NFLBM_GLOBAL E*)p;
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
+template <class E>
+__device__ __forceinline__ void st_nt(E* p, E v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <class T>
+__device__ __forceinline__ T fpoly(T c) {
+  const T d = T(1) - c;
+  return c * c * d * d;
+}
+template <class T>
+__device__ __forceinline__ T fprime(T c) {
+  return (T(2) * c) * fma(T(2) * c, c, fma(-T(3), c, T(1)));
+}
+
+// E_B = sum_{i<j} beta_ij [f(C_i) + f(C_j) - f(C_i + C_j)]  (Eq. FreeEnergy)
+template <int NC, class T, class PT>
+__device__ __forceinline__ T bulk_energy(const T (&c)[NC], const PT& P) {
+  T fi[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) fi[i] = fpoly(c[i]);
+  T e = T(0);
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NC; ++j) e = fma(P.beta[i][j], fi[i] + fi[j] - fpoly(c[i] + c[j]), e);
+  return e;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// ------------------------------------------------- equilibrium pair terms
+// e_k . a for a 3-vector a, summed over the nonzero components of e_k from
+// the first one on.
+template <class L, class T>
+__device__ __forceinline__ T proj(int k, const T (&a)[3]) {
+  T r = T(0);
+  bool first = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (L::e[k][d] != 0) {
+      const T t = (L::e[k][d] > 0) ? a[d] : -a[d];
+      r = first ? t : r + t;
+      first = false;
+    }
+  return r;
+}
+
+// s_k(v) = w_k [3 e_k.v + 4.5 (e_k.v)^2 - 1.5 v.v] (Eqs. feq, geq) for
+// direction kd, formed through the odd member k of its pair {k, k+1} so that
+// both members come from the same ev = e_k.v and quad; base_s = -1.5 v.v.
+// Every kernel that forms s_k goes through here: the reconstruction of the
+// moment form re-forms the update's post-collision populations bit for bit.
+template <class L, class T>
+__device__ __forceinline__ T quad_term(T ev, T base_s) {
+  return fma(T(4.5) * ev, ev, base_s);
+}
+template <class L, class T>
+__device__ __forceinline__ T s_pair_member(int kd, T ev, T quad) {
+  return static_cast<T>(L::w[kd]) * fma((kd & 1) ? T(3) : -T(3), ev, quad);
+}
+
+// Post-collision population of an evolved component for tau_g = 1, i.e. its
+// equilibrium C s_k - w_k m mu~ (Eq. geq, rest-population reading), as the
+// update forms it.  The moment form keeps it in the compute precision: with
+// FP32 and FP64 storage that is the stored value of the population form, bit
+// for bit; with FP16S (binary16 moving populations) the moment form skips
+// that rounding, since it stores no populations of g.
+template <class T>
+__device__ __forceinline__ T g_post(T c, T s, T mmu) {
+  return fma(c, s, -mmu);
+}
+
+// ------------------------------------------------------- streaming sources
+// Offsets of the neighbour rows of a node: x-1, x, x+1 with periodic wrap
+// (y and z pre-multiplied by the row and plane strides), and which faces of
+// the node are walls.
+struct Nbr {
+  uint32_t xo[3], yo[3], zo[3];
+  bool wlo[3], whi[3];
+};
+
+template <bool WALLS, bool D3>
+__device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a) {
+  Nbr b;
+  const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
+  b.xo[0] = x - 1; b.xo[1] = x; b.xo[2] = x + 1;
+  b.yo[0] = y - 1; b.yo[1] = y; b.yo[2] = y + 1;
+  b.zo[0] = z - 1; b.zo[1] = z; b.zo[2] = z + 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) b.wlo[d] = b.whi[d] = false;
+  if (x == 0) { if (WALLS && a.wall_x) b.wlo[0] = true; else b.xo[0] = a.nx - 1; }
+  if (x == a.nx - 1) { if (WALLS && a.wall_x) b.whi[0] = true; else b.xo[2] = 0; }
+  if (y == 0) { if (WALLS && a.wall_y) b.wlo[1] = true; else b.yo[0] = a.ny - 1; }
+  if (y == a.ny - 1) { if (WALLS && a.wall_y) b.whi[1] = true; else b.yo[2] = 0; }
+  if (D3) {
+    if (z == 0) { if (WALLS && a.wall_z) b.wlo[2] = true; else b.zo[0] = a.nz - 1; }
+    if (z == a.nz - 1) { if (WALLS && a.wall_z) b.whi[2] = true; else b.zo[2] = 0; }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b.yo[d] *= nx;
+    b.zo[d] *= nxy;
+  }
+  return b;
+}
+
+// The population streaming into this node along e_k comes from x - e_k; if
+// that node lies inside a wall it is this node's own post-collision
+// population of the opposite direction (halfway bounce-back, Sec. III C).
+template <class L, bool WALLS>
+__device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
+  if (!WALLS) return false;
+  bool w = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (L::e[k][d] > 0) w = w || b.wlo[d];
+    if (L::e[k][d] < 0) w = w || b.whi[d];
+  }
+  return w;
+}
+template <class L>
+__device__ __forceinline__ uint32_t upstream(const Nbr& b, int k) {
+  return b.xo[1 - L::e[k][0]] + b.yo[1 - L::e[k][1]] + b.zo[1 - L::e[k][2]];
+}
+
+// Workgroup -> tile.  Consecutive workgroup ids are dealt round-robin to the
+// 8 XCDs, each with its own L2; the remap hands every XCD a contiguous run of
+// tiles, so the halo rows and planes a workgroup re-reads were mostly fetched
+// into the same L2 by its neighbours.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Typed view of a global-memory pointer of the argument structs.
+template <class E>
+__device__ __forceinline__ E* gptr(const NFLBM_GLOBAL void* p) {
+  return (E*)(p);
+}
+template <class E>
+__device__ __forceinline__ E* gptr(const E* p) {
+  return const_cast<E*>(p);
+}
+
+// Element idx of an array addressed with a 32-bit byte offset from a uniform
+// base: the load/store can then take the base in scalar registers.
+template <class E>
+__device__ __forceinline__ const E* at(const E* base, uint32_t idx) {
+  return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(E)));
+}
+template <class E>
+__device__ __forceinline__ E* at(E* base, uint32_t idx) {
+  return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(E)));
+}
+
+}  // namespace nflbm

@@ -36,6 +36,17 @@ struct DevParams {
   int uidx[kMaxComp];     // user index of internal component i
 };
 
+// Tables of the concentration-dependent mobility variant (Appendix C), in
+// internal component order and the compute precision T.  The literal flux
+// potentials mu_j + phi_j + xi_j need the Lambda and Theta coefficients
+// themselves, which the factored tables of DevParams fold away.
+template <class T>
+struct MobParams {
+  T lam[kMaxComp][kMaxComp][kMaxComp][kMaxComp];    // Lambda_{j;klm}: [j][k][l][m], any order of k,l,m
+  T theta[kMaxComp][kMaxComp][kMaxComp][kMaxComp];  // Theta_{kl;j;m}: [k][l][j][m], either order of k,l
+  T pre[kMaxComp];                                  // (1 - 1/(2 tau_g,i)) m*
+};
+
 enum StepFlags {
   kFlagNeedG = 1,         // some tau_g != 1: the update reads g
   kFlagPotential = 2,     // potential-form surface tension
@@ -122,6 +133,16 @@ struct ReduceArgs {
   int blocks;
 };
 
+// Arguments of the two kernels of the concentration-dependent mobility
+// variant: sa supplies the lattice, walls, the reconstructed C, the new
+// population set (gk_dst, g0_dst) and the DevParams; phi is scratch
+// [node][N] in the compute precision.
+struct MobArgs {
+  StepArgs sa;
+  const void* mob;                    // MobParams<T>
+  void* phi;
+};
+
 // Launchers: lat 0 = D2Q9, 1 = D3Q19; nc = N; store = StoreKind.
 hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s);
@@ -137,5 +158,10 @@ hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long lo
                            double* partial, hipStream_t s);
 __host__ __device__ int reduce_record_len(int N);
 size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
+// Concentration-dependent mobility: the literal flux potentials of every node
+// (after the reconstruction), and the source term added to the update's
+// post-collision populations (after the update).
+hipError_t launch_mob_potentials(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
+hipError_t launch_mob_source(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
 
 }  // namespace nflbm

@@ -38,338 +38,9 @@
 
 #include <cstdint>
 
-#include "internal.h"
+#include "device.h"
 
 namespace nflbm {
-
-// ---------------------------------------------------------------- lattices
-struct D2Q9 {
-  static constexpr int Q = 9, DIM = 2;
-  static constexpr int e[9][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
-                                  {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
-  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-};
-
-struct D3Q19 {
-  static constexpr int Q = 19, DIM = 3;
-  static constexpr int e[19][3] = {
-      {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
-      {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-      {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
-                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-};
-// In both sets the opposite of direction k (k >= 1) is k + 1 for odd k.
-__host__ __device__ constexpr int opposite(int k) { return (k & 1) ? k + 1 : k - 1; }
-
-// ----------------------------------------------------------- storage types
-template <int ST> struct StoreT;
-template <> struct StoreT<kStoreF64> {
-  using T = double; using FS = double; using G0S = double;
-  static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
-  static __device__ __forceinline__ FS pack(T v) { return v; }
-  static __device__ __forceinline__ T unpack(FS v) { return v; }
-};
-template <> struct StoreT<kStoreF32> {
-  using T = float; using FS = float; using G0S = float;
-  static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
-  static __device__ __forceinline__ FS pack(T v) { return v; }
-  static __device__ __forceinline__ T unpack(FS v) { return v; }
-};
-template <> struct StoreT<kStoreF16S> {
-  using T = float; using FS = _Float16; using G0S = float;
-  static __device__ __forceinline__ T ld(const FS* p, size_t i) {
-    return static_cast<float>(p[i]) * (1.0f / kHalfScale);
-  }
-  static __device__ __forceinline__ FS pack(T v) { return static_cast<_Float16>(v * kHalfScale); }
-  static __device__ __forceinline__ T unpack(FS v) { return static_cast<float>(v) * (1.0f / kHalfScale); }
-};
-
-// ------------------------------------------------- per-node vector access
-// The NE values a node holds for one direction are contiguous; groups of 4,
-// 8, 16 or 32 bytes move with single vector instructions.  Node offsets are
-// multiples of the group size, so these accesses are aligned.
-template <class E, int NE>
-__device__ __forceinline__ void vld(const E* p, E (&o)[NE]) {
-  constexpr int B = int(sizeof(E)) * NE;
-  if constexpr (B == 4) {
-    const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
-    __builtin_memcpy(o, &t, 4);
-  } else if constexpr (B == 8) {
-    const uint2 t = *reinterpret_cast<const uint2*>(p);
-    __builtin_memcpy(o, &t, 8);
-  } else if constexpr (B == 16) {
-    const uint4 t = *reinterpret_cast<const uint4*>(p);
-    __builtin_memcpy(o, &t, 16);
-  } else if constexpr (B == 32) {
-    uint4 t[2];
-    t[0] = reinterpret_cast<const uint4*>(p)[0];
-    t[1] = reinterpret_cast<const uint4*>(p)[1];
-    __builtin_memcpy(o, t, 32);
-  } else {
-#pragma unroll
-    for (int e = 0; e < NE; ++e) o[e] = p[e];
-  }
-}
-
-template <class E, int NE>
-__device__ __forceinline__ void vst(E* p, const E (&v)[NE]) {
-  constexpr int B = int(sizeof(E)) * NE;
-  if constexpr (B == 4) {
-    uint32_t t;
-    __builtin_memcpy(&t, v, 4);
-    *reinterpret_cast<uint32_t*>(p) = t;
-  } else if constexpr (B == 8) {
-    uint2 t;
-    __builtin_memcpy(&t, v, 8);
-    *reinterpret_cast<uint2*>(p) = t;
-  } else if constexpr (B == 16) {
-    uint4 t;
-    __builtin_memcpy(&t, v, 16);
-    *reinterpret_cast<uint4*>(p) = t;
-  } else if constexpr (B == 32) {
-    uint4 t[2];
-    __builtin_memcpy(t, v, 32);
-    reinterpret_cast<uint4*>(p)[0] = t[0];
-    reinterpret_cast<uint4*>(p)[1] = t[1];
-  } else {
-#pragma unroll
-    for (int e = 0; e < NE; ++e) p[e] = v[e];
-  }
-}
-
-// Nontemporal forms for streams touched once per step: the populations the
-// reconstruction gathers and the post-collision populations the update
-// writes (re-read only by the next step's reconstruction).  Streaming stores
-// also leave L2 free of dirty lines for the reconstruction that follows.
-typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
-typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
-
-template <class E, int NE>
-__device__ __forceinline__ void vld_nt(const E* p, E (&o)[NE]) {
-  constexpr int B = int(sizeof(E)) * NE;
-  if constexpr (B == 4) {
-    const unsigned t = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
-    __builtin_memcpy(o, &t, 4);
-  } else if constexpr (B == 8) {
-    const nt_u2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
-    __builtin_memcpy(o, &t, 8);
-  } else if constexpr (B == 16) {
-    const nt_u4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
-    __builtin_memcpy(o, &t, 16);
-  } else {
-    // wider records move as two 16-byte halves from different instructions;
-    // a streaming hint would drop the line between them (measured: FP64
-    // reconstruction 10% slower), so they take the cached path
-    vld<E, NE>(p, o);
-  }
-}
-
-template <class E, int NE>
-__device__ __forceinline__ void vst_nt(E* p, const E (&v)[NE]) {
-  constexpr int B = int(sizeof(E)) * NE;
-  if constexpr (B == 4) {
-    unsigned t;
-    __builtin_memcpy(&t, v, 4);
-    __builtin_nontemporal_store(t, reinterpret_cast<unsigned*>(p));
-  } else if constexpr (B == 8) {
-    nt_u2 t;
-    __builtin_memcpy(&t, v, 8);
-    __builtin_nontemporal_store(t, reinterpret_cast<nt_u2*>(p));
-  } else if constexpr (B == 16) {
-    nt_u4 t;
-    __builtin_memcpy(&t, v, 16);
-    __builtin_nontemporal_store(t, reinterpret_cast<nt_u4*>(p));
-  } else {
-    vst<E, NE>(p, v);   // as in vld_nt
-  }
-}
-
-// A uniform value the compiler must treat as new at this point: direction
-// offsets derived from it are formed where they are used instead of being
-// hoisted out of the z loop, where dozens of 64-bit bases would stay live in
-// scalar registers and spill.
-__device__ __forceinline__ size_t fresh(size_t v) {
-  asm volatile("" : "+s"(v));
-  return v;
-}
-// Read-only tables seen through the constant address space: uniform reads
-// become scalar loads with immediate offsets, and the pointer is fresh at the
-// point of use (see above).
-#if defined(__HIP_DEVICE_COMPILE__)
-#define NFLBM_CONST __attribute__((address_space(4)))
-#else
-#define NFLBM_CONST
-#endif
-template <class E>
-__device__ __forceinline__ const NFLBM_CONST E* fresh_const(const E* p) {
-  const NFLBM_CONST E* c = (const NFLBM_CONST E*)(const NFLBM_GLOBAL E*)p;
-  asm volatile("" : "+s"(c));
-  return c;
-}
-
-template <class E>
-__device__ __forceinline__ void st_nt(E* p, E v) {
-  __builtin_nontemporal_store(v, p);
-}
-
-template <class T>
-__device__ __forceinline__ T fpoly(T c) {
-  const T d = T(1) - c;
-  return c * c * d * d;
-}
-template <class T>
-__device__ __forceinline__ T fprime(T c) {
-  return (T(2) * c) * fma(T(2) * c, c, fma(-T(3), c, T(1)));
-}
-
-// E_B = sum_{i<j} beta_ij [f(C_i) + f(C_j) - f(C_i + C_j)]  (Eq. FreeEnergy)
-template <int NC, class T, class PT>
-__device__ __forceinline__ T bulk_energy(const T (&c)[NC], const PT& P) {
-  T fi[NC];
-#pragma unroll
-  for (int i = 0; i < NC; ++i) fi[i] = fpoly(c[i]);
-  T e = T(0);
-#pragma unroll
-  for (int i = 0; i < NC; ++i)
-#pragma unroll
-    for (int j = i + 1; j < NC; ++j) e = fma(P.beta[i][j], fi[i] + fi[j] - fpoly(c[i] + c[j]), e);
-  return e;
-}
-
-__device__ __forceinline__ int wrap(int v, int n) {
-  v %= n;
-  return v < 0 ? v + n : v;
-}
-
-// ------------------------------------------------- equilibrium pair terms
-// e_k . a for a 3-vector a, summed over the nonzero components of e_k from
-// the first one on.
-template <class L, class T>
-__device__ __forceinline__ T proj(int k, const T (&a)[3]) {
-  T r = T(0);
-  bool first = true;
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (L::e[k][d] != 0) {
-      const T t = (L::e[k][d] > 0) ? a[d] : -a[d];
-      r = first ? t : r + t;
-      first = false;
-    }
-  return r;
-}
-
-// s_k(v) = w_k [3 e_k.v + 4.5 (e_k.v)^2 - 1.5 v.v] (Eqs. feq, geq) for
-// direction kd, formed through the odd member k of its pair {k, k+1} so that
-// both members come from the same ev = e_k.v and quad; base_s = -1.5 v.v.
-// Every kernel that forms s_k goes through here: the reconstruction of the
-// moment form re-forms the update's post-collision populations bit for bit.
-template <class L, class T>
-__device__ __forceinline__ T quad_term(T ev, T base_s) {
-  return fma(T(4.5) * ev, ev, base_s);
-}
-template <class L, class T>
-__device__ __forceinline__ T s_pair_member(int kd, T ev, T quad) {
-  return static_cast<T>(L::w[kd]) * fma((kd & 1) ? T(3) : -T(3), ev, quad);
-}
-
-// Post-collision population of an evolved component for tau_g = 1, i.e. its
-// equilibrium C s_k - w_k m mu~ (Eq. geq, rest-population reading), as the
-// update forms it.  The moment form keeps it in the compute precision: with
-// FP32 and FP64 storage that is the stored value of the population form, bit
-// for bit; with FP16S (binary16 moving populations) the moment form skips
-// that rounding, since it stores no populations of g.
-template <class T>
-__device__ __forceinline__ T g_post(T c, T s, T mmu) {
-  return fma(c, s, -mmu);
-}
-
-// ------------------------------------------------------- streaming sources
-// Offsets of the neighbour rows of a node: x-1, x, x+1 with periodic wrap
-// (y and z pre-multiplied by the row and plane strides), and which faces of
-// the node are walls.
-struct Nbr {
-  uint32_t xo[3], yo[3], zo[3];
-  bool wlo[3], whi[3];
-};
-
-template <bool WALLS, bool D3>
-__device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a) {
-  Nbr b;
-  const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
-  b.xo[0] = x - 1; b.xo[1] = x; b.xo[2] = x + 1;
-  b.yo[0] = y - 1; b.yo[1] = y; b.yo[2] = y + 1;
-  b.zo[0] = z - 1; b.zo[1] = z; b.zo[2] = z + 1;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) b.wlo[d] = b.whi[d] = false;
-  if (x == 0) { if (WALLS && a.wall_x) b.wlo[0] = true; else b.xo[0] = a.nx - 1; }
-  if (x == a.nx - 1) { if (WALLS && a.wall_x) b.whi[0] = true; else b.xo[2] = 0; }
-  if (y == 0) { if (WALLS && a.wall_y) b.wlo[1] = true; else b.yo[0] = a.ny - 1; }
-  if (y == a.ny - 1) { if (WALLS && a.wall_y) b.whi[1] = true; else b.yo[2] = 0; }
-  if (D3) {
-    if (z == 0) { if (WALLS && a.wall_z) b.wlo[2] = true; else b.zo[0] = a.nz - 1; }
-    if (z == a.nz - 1) { if (WALLS && a.wall_z) b.whi[2] = true; else b.zo[2] = 0; }
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    b.yo[d] *= nx;
-    b.zo[d] *= nxy;
-  }
-  return b;
-}
-
-// The population streaming into this node along e_k comes from x - e_k; if
-// that node lies inside a wall it is this node's own post-collision
-// population of the opposite direction (halfway bounce-back, Sec. III C).
-template <class L, bool WALLS>
-__device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
-  if (!WALLS) return false;
-  bool w = false;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (L::e[k][d] > 0) w = w || b.wlo[d];
-    if (L::e[k][d] < 0) w = w || b.whi[d];
-  }
-  return w;
-}
-template <class L>
-__device__ __forceinline__ uint32_t upstream(const Nbr& b, int k) {
-  return b.xo[1 - L::e[k][0]] + b.yo[1 - L::e[k][1]] + b.zo[1 - L::e[k][2]];
-}
-
-// Workgroup -> tile.  Consecutive workgroup ids are dealt round-robin to the
-// 8 XCDs, each with its own L2; the remap hands every XCD a contiguous run of
-// tiles, so the halo rows and planes a workgroup re-reads were mostly fetched
-// into the same L2 by its neighbours.
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-  const int per = nblocks >> 3;
-  if (b >= per * 8) return b;
-  return (b & 7) * per + (b >> 3);
-}
-
-// Typed view of a global-memory pointer of the argument structs.
-template <class E>
-__device__ __forceinline__ E* gptr(const NFLBM_GLOBAL void* p) {
-  return (E*)(p);
-}
-template <class E>
-__device__ __forceinline__ E* gptr(const E* p) {
-  return const_cast<E*>(p);
-}
-
-// Element idx of an array addressed with a 32-bit byte offset from a uniform
-// base: the load/store can then take the base in scalar registers.
-template <class E>
-__device__ __forceinline__ const E* at(const E* base, uint32_t idx) {
-  return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(E)));
-}
-template <class E>
-__device__ __forceinline__ E* at(E* base, uint32_t idx) {
-  return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(E)));
-}
 
 // ------------------------------------------------------------------ k_conc
 // One node per thread over TX x TY tiles of one z plane: C of the evolved
@@ -471,11 +142,18 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
 // bytes (12 or 20 floats, 14 or 22 doubles): consecutive positions then start
 // in different 16-byte bank groups, so a wavefront's reads of a row of
 // positions do not collide on banks.
-template <int NE>
-constexpr int moment_nep() { return (NE + 3) / 4 * 4; }
+// In FP64 the fields are stored field-major instead (field f of position p at
+// f * PXY + p, NEP = NE, no padding): its 8-byte reads of consecutive
+// positions are conflict-free, and the FP64 reconstruction measured faster
+// that way, while FP32 and FP16S measured faster with records.
+template <class T>
+constexpr bool moment_aos() { return sizeof(T) == 4; }
+template <int NE, class T>
+constexpr int moment_nep() { return moment_aos<T>() ? (NE + 3) / 4 * 4 : NE; }
 template <int NE, class T>
 constexpr int moment_record() {
-  const int r = 2 * moment_nep<NE>() + 4;
+  const int r = 2 * moment_nep<NE, T>() + 4;
+  if (!moment_aos<T>()) return r;
   return (r * int(sizeof(T)) / 16) % 2 == 1 ? r : r + 16 / int(sizeof(T));
 }
 
@@ -489,7 +167,8 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   constexpr int Q = L::Q;
   constexpr int NC = NE + 1;
   constexpr bool D3 = (L::DIM == 3);
-  constexpr int NEP = moment_nep<NE>();
+  constexpr bool AOS = moment_aos<T>();
+  constexpr int NEP = moment_nep<NE, T>();
   constexpr int REC = moment_record<NE, T>();
   constexpr int TX = 1 << TXL;
   constexpr int TY = 256 >> TXL;
@@ -559,12 +238,40 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       vld<T, NE>(at(cprev, node * NE), reinterpret_cast<T(&)[NE]>(cc));
       vld<T, NE>(at(mus, node * NE), reinterpret_cast<T(&)[NE]>(mm));
       vld<T, 4>(at(vels, node * 4), vv);
-      T* rec = base + idx * REC;
-      vst<T, NEP>(rec, cc);
-      vst<T, NEP>(rec + NEP, mm);
-      vst<T, 4>(rec + 2 * NEP, vv);
+      if constexpr (AOS) {
+        T* rec = base + idx * REC;
+        vst<T, NEP>(rec, cc);
+        vst<T, NEP>(rec + NEP, mm);
+        vst<T, 4>(rec + 2 * NEP, vv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          base[e * PXY + idx] = cc[e];
+          base[(NE + e) * PXY + idx] = mm[e];
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) base[(2 * NE + d) * PXY + idx] = vv[d];
+      }
     }
   };
+  // C, mu~ and (v, v.v) of the position at rec (a record start, or in the
+  // field-major layout the position's slot in the first field)
+  auto read_pos = [&](const T* rec, T (&cs)[NEP], T (&ms)[NEP], T (&v4)[4]) {
+    if constexpr (AOS) {
+      vld<T, NEP>(rec, cs);
+      vld<T, NEP>(rec + NEP, ms);
+      vld<T, 4>(rec + 2 * NEP, v4);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        cs[e] = rec[e * PXY];
+        ms[e] = rec[(NE + e) * PXY];
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v4[d] = rec[(2 * NE + d) * PXY];
+    }
+  };
+  constexpr int PSTEP = AOS ? REC : 1;   // distance between positions
 
   auto process = [&](int z, int s_dn, int s_c, int s_up) {
     const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
@@ -574,22 +281,21 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
     // records of the 3 x 3 neighbourhood are reached from its lowest corner
     // with non-negative immediate offsets
-    const T* corner_dn = sm + s_dn * plane_stride + (li - PX - 1) * REC;
-    const T* corner_c = sm + s_c * plane_stride + (li - PX - 1) * REC;
-    const T* corner_up = sm + s_up * plane_stride + (li - PX - 1) * REC;
-    auto rec_at = [&](const T* corner, int ex, int ey) { return corner + ((1 + ey) * PX + (1 + ex)) * REC; };
+    const T* corner_dn = sm + s_dn * plane_stride + (li - PX - 1) * PSTEP;
+    const T* corner_c = sm + s_c * plane_stride + (li - PX - 1) * PSTEP;
+    const T* corner_up = sm + s_up * plane_stride + (li - PX - 1) * PSTEP;
+    auto rec_at = [&](const T* corner, int ex, int ey) { return corner + ((1 + ey) * PX + (1 + ex)) * PSTEP; };
     const T* own = rec_at(corner_c, 0, 0);
     T c[NEP], mu[NEP], v[3];
+    T base_s;
     {
       T v4[4];
-      vld<T, NEP>(own, c);
-      vld<T, NEP>(own + NEP, mu);
-      vld<T, 4>(own + 2 * NEP, v4);
+      read_pos(own, c, mu, v4);
       v[0] = v4[0];
       v[1] = v4[1];
       v[2] = v4[2];
+      base_s = -T(1.5) * v4[3];
     }
-    const T base_s = -T(1.5) * own[2 * NEP + 3];
     // rest population: C minus the stored moving populations, summed pair by
     // pair as the population form does
     T moved[NE];
@@ -628,9 +334,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       }
       const int kp = (kd & 1) ? kd : kd - 1;
       T cs[NEP], ms[NEP], v4[4];
-      vld<T, NEP>(src, cs);
-      vld<T, NEP>(src + NEP, ms);
-      vld<T, 4>(src + 2 * NEP, v4);
+      read_pos(src, cs, ms, v4);
       const T vs[3] = {v4[0], v4[1], v4[2]};
       const T ev = proj<L>(kp, vs);
       const T quad = quad_term<L>(ev, -T(1.5) * v4[3]);
@@ -1409,8 +1113,13 @@ size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
   const int npl = lat == 1 ? 3 : 1;
-  size_t rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4;
-  if ((rec * sizeof(TT<ST>) / 16) % 2 == 0) rec += 16 / sizeof(TT<ST>);
+  size_t rec;
+  if (sizeof(TT<ST>) == 4) {
+    rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4;
+    if ((rec * sizeof(TT<ST>) / 16) % 2 == 0) rec += 16 / sizeof(TT<ST>);
+  } else {
+    rec = size_t(nc - 1) * 2 + 4;   // field-major, no padding
+  }
   return npl * rec * pxy * sizeof(TT<ST>);
 }
 

@@ -151,3 +151,40 @@ def test_device_bytes_plans_without_a_device(L):
     with pytest.raises(nf.NflbmError) as e:
         nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 0.4, m=0.1)
     assert e.value.code == -1
+
+
+def test_flag_values_match_header():
+    import re
+    with open(nf.HEADER) as fh:
+        text = fh.read()
+    flags = dict((m.group(1), int(m.group(2)))
+                 for m in re.finditer(r"NFLBM_FLAG_(\w+)\s*=\s*(\d+)", text))
+    assert flags
+    for name, val in flags.items():
+        assert getattr(nf, "FLAG_" + name) == val, name
+
+
+def test_c2c2_mobility_plans_populations_and_skips_the_constant_bound(L):
+    """Under the concentration-dependent mobility flag m is m* (10 in the
+    paper), which the constant-mobility bound would reject; the plan keeps g
+    as populations."""
+    def al(v):
+        return (v + 255) // 256 * 256
+    sig = equal_sigma(4, 0.005)
+    nx, ny = 40, 24
+    n = nx * ny
+    with pytest.raises(nf.NflbmError):
+        nf.Simulation.device_bytes("D2Q9", (nx, ny, 1), sig, 1.0, m=10.0, precision=nf.FP32)
+    got = nf.Simulation.device_bytes("D2Q9", (nx, ny, 1), sig, 1.0, m=10.0, precision=nf.FP32,
+                                     flags=nf.FLAG_C2C2_MOBILITY)
+    assert got == 2 * al(8 * n * 4) + 2 * al(3 * n * 4) + 2 * al(3 * 8 * n * 4) + al(3 * n * 4) + al(n * 4)
+
+
+def test_batch_rejects_c2c2_members_before_the_device(L):
+    sig = equal_sigma(3, 0.005)
+    a = nf._Problem("D2Q9", (32, 32, 1), sig, 1.0, m=10.0, precision=nf.FP32,
+                    flags=nf.FLAG_C2C2_MOBILITY)
+    arr = (nf.Config * 2)(a.cfg, a.cfg)
+    h = ctypes.c_void_p()
+    assert L.nflbm_batch_create(arr, 2, ctypes.byref(h)) == -7
+    assert not h.value
