@@ -108,8 +108,9 @@ enum {
  * its equilibrium, C_i s_k(v) - w_k m mu~_i (Eqs. glbe, geq), so by default
  * the library keeps per node only the C_i the collision used, mu~_i, v and
  * v.v, and the reconstruction of the next step re-forms the populations from
- * them, in the same operations and storage rounding as the population form:
- * both forms give bit-identical results.  Some tau_g != 1, or
+ * them and takes the rest population directly from Eq. geq: the two forms
+ * agree to rounding (the population form writes the rest population as C_i
+ * minus its stored moving populations).  Some tau_g != 1, or
  * NFLBM_FLAG_G_POPULATIONS, keeps the 19 (N - 1) populations per node.
  * nflbm_storage_form tells which form a simulation uses. */
 

@@ -235,8 +235,8 @@ __device__ __forceinline__ T proj(int k, const T (&a)[3]) {
 // s_k(v) = w_k [3 e_k.v + 4.5 (e_k.v)^2 - 1.5 v.v] (Eqs. feq, geq) for
 // direction kd, formed through the odd member k of its pair {k, k+1} so that
 // both members come from the same ev = e_k.v and quad; base_s = -1.5 v.v.
-// Every kernel that forms s_k goes through here: the reconstruction of the
-// moment form re-forms the update's post-collision populations bit for bit.
+// Every kernel that forms s_k goes through here, so the reconstruction of the
+// moment form forms each s_k exactly as the update does.
 template <class L, class T>
 __device__ __forceinline__ T quad_term(T ev, T base_s) {
   return fma(T(4.5) * ev, ev, base_s);
@@ -248,13 +248,32 @@ __device__ __forceinline__ T s_pair_member(int kd, T ev, T quad) {
 
 // Post-collision population of an evolved component for tau_g = 1, i.e. its
 // equilibrium C s_k - w_k m mu~ (Eq. geq, rest-population reading), as the
-// update forms it.  The moment form keeps it in the compute precision: with
-// FP32 and FP64 storage that is the stored value of the population form, bit
-// for bit; with FP16S (binary16 moving populations) the moment form skips
-// that rounding, since it stores no populations of g.
+// update forms it.  The moment form keeps it in the compute precision; with
+// FP16S (binary16 moving populations) it thereby skips that rounding, since
+// it stores no populations of g.
 template <class T>
 __device__ __forceinline__ T g_post(T c, T s, T mmu) {
   return fma(c, s, -mmu);
+}
+// Post-collision rest population for tau_g = 1: g^eq_0 = C_i (1 + s_0) +
+// (1 - w_0) m mu~_i (Eq. geq, rest-population reading), with m0mu =
+// (1 - w_0) m mu~_i.  The moment form uses it directly; the population form
+// stores C_i minus its stored moving populations instead, which equals it in
+// exact arithmetic and keeps node mass to one rounding of binary16 storage.
+template <class T>
+__device__ __forceinline__ T g_rest(T c, T s0, T m0mu) {
+  return fma(c, s0, c) + m0mu;
+}
+// 1 - w_0 as the sum of the moving weights in precision T, in direction
+// order.  The moving populations carry -w_k m mu~ with w_k rounded to T; the
+// rest population must carry exactly their sum, or every step would shift the
+// mass of a component by m mu~ times the rounding of the weights (3e-8 per
+// step in float, measured as a drift against FP64).
+template <class L, class T>
+__host__ __device__ constexpr T moving_weight_sum() {
+  T s = T(0);
+  for (int k = 1; k < L::Q; ++k) s += static_cast<T>(L::w[k]);
+  return s;
 }
 
 // ------------------------------------------------------- streaming sources

@@ -129,11 +129,14 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
 // Eq. geq), so the state holds, per node, the C_i the collision used, mu~_i,
 // v and v.v instead of the 19 (N - 1) populations.  This kernel re-forms them
 // where they are needed:
-//   C_i(x, t+1) = [C_i(x) - sum_{k>=1} g*_{i,k}(x)] + sum_{k>=1} g*_{i,k}(x - e_k)
-// (rest population plus streamed moving populations, halfway bounce-back at
-// walls), in the order in which the population form sums them and in the
-// compute precision, so with FP32 and FP64 storage both forms give identical
-// bits.  The per-node records of
+//   C_i(x, t+1) = g^eq_{i,0}(x) + sum_{k>=1} g*_{i,k}(x - e_k)
+// (rest population of Eq. geq plus the streamed moving populations, halfway
+// bounce-back at walls), in the compute precision.  The incoming sum is
+// grouped as sum_k C s_k - m sum_k w_k mu~, and the rest population is formed
+// directly rather than as C minus the node's own outgoing populations: the
+// two forms of g then agree to rounding instead of bit for bit, for a third
+// of this kernel's arithmetic.  Mass is kept to the rounding of C at each
+// node (no systematic drift; see the comment at the final sum).  The per-node records of
 // the tile and a one-node halo sit in LDS (three planes in D3Q19, marched
 // along z like the update).
 // LDS record of one position: C in [0, NEP), mu~ in [NEP, 2 NEP), then v and
@@ -163,7 +166,6 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
                                             unsigned char* smem_raw) {
   using S = StoreT<ST>;
   using T = typename S::T;
-  using G0S = typename S::G0S;
   constexpr int Q = L::Q;
   constexpr int NC = NE + 1;
   constexpr bool D3 = (L::DIM == 3);
@@ -296,29 +298,13 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       v[2] = v4[2];
       base_s = -T(1.5) * v4[3];
     }
-    // rest population: C minus the stored moving populations, summed pair by
-    // pair as the population form does
-    T moved[NE];
-#pragma unroll
-    for (int e = 0; e < NE; ++e) moved[e] = T(0);
-#pragma unroll
-    for (int k = 1; k < Q; k += 2) {
-      const T ev = proj<L>(k, v);
-      const T quad = quad_term<L>(ev, base_s);
-      const T sk = s_pair_member<L>(k, ev, quad);
-      const T sb = s_pair_member<L>(k + 1, ev, quad);
-      const T mw = static_cast<T>(L::w[k]) * m;
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const T mmu = mw * mu[e];
-        moved[e] += g_post(c[e], sk, mmu) + g_post(c[e], sb, mmu);
-      }
-    }
     // moving populations streamed in along e_k from x - e_k (or this node's
-    // own opposite one where x - e_k lies in a wall), in direction order
-    T sum[NE];
+    // own opposite one where x - e_k lies in a wall): sum_k C s_k and
+    // sum_k w_k mu~ over the sources, kept apart, so that the incoming
+    // populations sum to sc - m sm
+    T sc[NE], smu[NE];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) sum[e] = T(0);
+    for (int e = 0; e < NE; ++e) sc[e] = smu[e] = T(0);
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
@@ -339,15 +325,27 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       const T ev = proj<L>(kp, vs);
       const T quad = quad_term<L>(ev, -T(1.5) * v4[3]);
       const T sk = s_pair_member<L>(kd, ev, quad);
-      const T mw = static_cast<T>(L::w[kp]) * m;
+      const T wk = static_cast<T>(L::w[kp]);
 #pragma unroll
-      for (int e = 0; e < NE; ++e) sum[e] += g_post(cs[e], sk, mw * ms[e]);
+      for (int e = 0; e < NE; ++e) {
+        sc[e] = fma(cs[e], sk, sc[e]);
+        smu[e] = fma(wk, ms[e], smu[e]);
+      }
     }
+    // rest population of this node (Eq. geq) plus the streamed-in ones, as
+    // C plus the net change: the small terms are summed first and meet C in
+    // one rounding.  Added to C on its own, C s_0 (never positive) would be
+    // lost below half an ulp at every node and step alike: a steady mass gain
+    // in float storage (1e-5 per step on the 64^2 lens).
+    const T s0 = static_cast<T>(L::w[0]) * base_s;
+    const T m0 = moving_weight_sum<L, T>() * m;
+    T sum[NE];
     T cn[NC];
     T rest = T(0);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      sum[e] = static_cast<T>(static_cast<G0S>(c[e] - moved[e])) + sum[e];
+      const T d = fma(c[e], s0, m0 * mu[e]) + fma(-m, smu[e], sc[e]);
+      sum[e] = c[e] + d;
       cn[e] = sum[e];
       rest += sum[e];
     }
@@ -414,8 +412,6 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
   vld<T, 4>(gptr<const T>(a.vel) + node * 4, vel);
   const T v[3] = {vel[0], vel[1], vel[2]};
   const T base_s = -T(1.5) * vel[3];
-  T moved[NE];
-  for (int e = 0; e < NE; ++e) moved[e] = T(0);
   FS* gk = gptr<FS>(a.gk_dst);
 #pragma unroll
   for (int k = 1; k < Q; k += 2) {
@@ -430,13 +426,15 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
       const T gk = g_post(c[e], sk, mmu), gb = g_post(c[e], sb, mmu);
       qk[e] = S::pack(gk);   // read-back layout of the population form
       qb[e] = S::pack(gb);
-      moved[e] += gk + gb;
     }
     vst<FS, NE>(gk + (size_t(k - 1) * n + node) * NE, qk);
     vst<FS, NE>(gk + (size_t(k) * n + node) * NE, qb);
   }
+  // the rest population as the reconstruction uses it (Eq. geq)
+  const T s0 = static_cast<T>(L::w[0]) * base_s;
+  const T m0 = moving_weight_sum<L, T>() * P.m;
   G0S r0[NE];
-  for (int e = 0; e < NE; ++e) r0[e] = static_cast<G0S>(c[e] - moved[e]);
+  for (int e = 0; e < NE; ++e) r0[e] = static_cast<G0S>(g_rest(c[e], s0, m0 * mu[e]));
   vst<G0S, NE>(gptr<G0S>(a.g0_dst) + node * NE, r0);
 }
 

@@ -1,15 +1,22 @@
-"""The two storage forms of g give identical bits.
+"""The two storage forms of g agree to rounding.
 
 With every tau_g = 1 the library keeps g as the node records (C, mu~, v, v.v)
 and re-forms the post-collision populations in the reconstruction; with
-FLAG_G_POPULATIONS it stores the populations.  In FP64 and FP32 both round
-and sum the same values in the same order, so f, C, every derived field and
-the read-back populations must agree bit for bit, on both lattices, with
-walls, TRT, Omega > 0, the potential force, an absent component, and in
-batches.  With FP16S the population form rounds g to binary16 and the moment
-form does not, so there the two agree to the FP16S tolerance and the moment
-form is the closer one to FP64.
+FLAG_G_POPULATIONS it stores the populations.  The moment form takes the rest
+population directly from Eq. geq and groups the incoming sum differently, the
+population form writes the rest population as C minus its stored moving
+populations: the results differ by rounding only.  After 23 steps, on both
+lattices, with walls, TRT, Omega > 0, the potential force and an absent
+component (exactly 0.0 in both), FP64 agrees to 1e-13 of each field's scale
+for C and g and 1e-10 for the O(1e-6) derived fields (v, P, F, f); FP32 to
+the bounds in test_forms_agree_to_rounding.  With FP16S the population form
+also rounds g to binary16 and the moment form does not, so there the two
+agree to the FP16S tolerance.  Measured differences go to
+gpurun_out/forms.json.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -53,20 +60,46 @@ def run(w, prec, implicit, flags, steps):
     return form, out
 
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RESULTS = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def record():
+    yield
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "forms.json"), "w") as fh:
+        json.dump(RESULTS, fh, indent=1, sort_keys=True)
+
+
+def rel(a, b):
+    scale = np.abs(b).max()
+    if scale == 0.0:
+        return 0.0 if np.all(a == 0.0) else np.inf
+    return float(np.abs(a - b).max() / scale)
+
+
+# per field: (FP64, FP32) bound on max |moment - population| / max |population|
+TOL = {"C": (1e-13, 1e-5), "G_RAW": (1e-13, 1e-5), "MU": (1e-10, 1e-3),
+       "V": (1e-10, 1e-2), "P": (1e-10, 1e-2), "F": (1e-10, 1e-2), "F_RAW": (1e-10, 1e-2)}
+
+
 @pytest.mark.parametrize("prec", [nf.FP64, nf.FP32])
 @pytest.mark.parametrize("idx", range(7))
-def test_forms_bitwise_equal(idx, prec):
+def test_forms_agree_to_rounding(idx, prec):
     name, w, implicit, flags = cases()[idx]
     steps = 23
     fm, a = run(w, prec, implicit, flags, steps)
     fp, b = run(w, prec, implicit, flags | nf.FLAG_G_POPULATIONS, steps)
     assert (fm, fp) == ("moments", "populations")
-    for k in a:
-        assert np.array_equal(a[k], b[k]), f"{name} {k}"
-
-
-def rel(a, b):
-    return float(np.abs(a - b).max() / np.abs(b).max())
+    errs = {k: rel(a[k], b[k]) for k in a}
+    RESULTS.setdefault("fp64" if prec == nf.FP64 else "fp32", {})[name] = errs
+    col = 0 if prec == nf.FP64 else 1
+    bad = {k: v for k, v in errs.items() if not v <= TOL[k][col]}
+    assert not bad, (name, errs)
+    if name == "d3_absent":
+        assert np.all(a["C"][4] == 0.0) and np.all(b["C"][4] == 0.0)
 
 
 @pytest.mark.parametrize("idx", range(7))
