@@ -578,34 +578,75 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       lap[i] = T(0);
       gC[i][0] = gC[i][1] = gC[i][2] = T(0);
     }
-    // ---- isotropic stencils (Eq. gradstencil and the Laplacian after it)
+    // ---- isotropic stencils (Eq. gradstencil and the Laplacian after it).
+    // From the lowest corner of the 3 x 3 neighbourhood every LDS offset is a
+    // non-negative immediate.
+    auto nbr = [&](int ex, int ey, int ez) {
+      const int slot = (ez == 0) ? s_c : (ez > 0 ? s_up : s_dn);
+      return sm + slot * plane_stride + (li - PX - 1) + (1 + ey) * PX + (1 + ex);
+    };
+    // A node next to a wall face goes direction by direction; every other
+    // node, in every kernel variant and tile shape alike, goes by pairs, so a
+    // node's result depends only on its position.
+    bool near_wall = false;
+    if constexpr (WALLS) {
+      near_wall = (a.wall_x && (x == 0 || x == a.nx - 1)) || (a.wall_y && (y == 0 || y == a.ny - 1)) ||
+                  (a.wall_z && (z == 0 || z == a.nz - 1));
+    }
+    if (!near_wall) {
+      // over the opposite pairs {k, k+1}, with psi+ = psi(x + e_k) and
+      // psi- = psi(x - e_k) the gradient takes w_k e_k (psi+ - psi-) and the
+      // Laplacian w_k (psi+ + psi-), less (sum of the moving weights) psi(x)
+      // at the end: a tenth fewer instructions than direction by direction
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
-      const T wk = static_cast<T>(L::w[k]);
-      bool wall = false;
-      if (WALLS) {
-        if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
-        if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
-        if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
-      }
-      if (!wall) {
-        // from the lowest corner of the 3 x 3 neighbourhood every offset is a
-        // non-negative immediate
-        const int slot = (ez == 0) ? s_c : (ez > 0 ? s_up : s_dn);
-        const T* Cn = sm + slot * plane_stride + (li - PX - 1) + (1 + ey) * PX + (1 + ex);
+      for (int k = 1; k < Q; k += 2) {
+        const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
+        const T wk = static_cast<T>(L::w[k]);
+        const T* Cp = nbr(ex, ey, ez);
+        const T* Cm = nbr(-ex, -ey, -ez);
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-          const T d = Cn[i * PXY] - c[i];
-          lap[i] = fma(wk, d, lap[i]);
-          if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, d, gC[i][0]);
-          if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, d, gC[i][1]);
-          if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, d, gC[i][2]);
+          const T vp = Cp[i * PXY], vm = Cm[i * PXY];
+          const T dd = vp - vm;
+          lap[i] = fma(wk, vp + vm, lap[i]);
+          if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, dd, gC[i][0]);
+          if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, dd, gC[i][1]);
+          if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, dd, gC[i][2]);
         }
-        const T dE = Cn[NE * PXY] - E0;
+        const T dE = Cp[NE * PXY] - Cm[NE * PXY];
         if (ex != 0) gE[0] = fma((ex > 0) ? wk : -wk, dE, gE[0]);
         if (ey != 0) gE[1] = fma((ey > 0) ? wk : -wk, dE, gE[1]);
         if (ez != 0) gE[2] = fma((ez > 0) ? wk : -wk, dE, gE[2]);
+      }
+      constexpr T wsum = moving_weight_sum<L, T>();
+#pragma unroll
+      for (int i = 0; i < NE; ++i) lap[i] = fma(-wsum, c[i], lap[i]);
+    } else {
+      // next to a wall, direction by direction: a neighbour inside a wall
+      // takes the centre value, i.e. contributes nothing
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
+        const T wk = static_cast<T>(L::w[k]);
+        bool wall = false;
+        if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
+        if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
+        if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+        if (!wall) {
+          const T* Cn = nbr(ex, ey, ez);
+#pragma unroll
+          for (int i = 0; i < NE; ++i) {
+            const T d = Cn[i * PXY] - c[i];
+            lap[i] = fma(wk, d, lap[i]);
+            if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, d, gC[i][0]);
+            if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, d, gC[i][1]);
+            if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, d, gC[i][2]);
+          }
+          const T dE = Cn[NE * PXY] - E0;
+          if (ex != 0) gE[0] = fma((ex > 0) ? wk : -wk, dE, gE[0]);
+          if (ey != 0) gE[1] = fma((ey > 0) ? wk : -wk, dE, gE[1]);
+          if (ez != 0) gE[2] = fma((ez > 0) ? wk : -wk, dE, gE[2]);
+        }
       }
     }
     // the implicit component is 1 - sum of the others, so each of its stencil
