@@ -23,8 +23,12 @@ def _dfp(c):
     return 2 * c * (1 - 3 * c + 2 * c * c)
 
 
+def _is_solid(par, x, y, z):
+    return par.solid is not None and bool(par.solid[z, y, x])
+
+
 def _node_neighbour(par, x, y, z, e):
-    """Index of x + e, or None if it is inside a wall."""
+    """Index of x + e, or None if it is inside a wall or a solid node."""
     nx, ny, nz = par.shape
     p = [x + int(e[0]), y + int(e[1]), z + int(e[2])]
     n = (nx, ny, nz)
@@ -33,6 +37,8 @@ def _node_neighbour(par, x, y, z, e):
             if par.walls[a]:
                 return None
             p[a] %= n[a]
+    if _is_solid(par, p[0], p[1], p[2]):
+        return None
     return p[0], p[1], p[2]
 
 
@@ -55,6 +61,8 @@ def step(f, g, par):
                     C[i, z, y, x] = s
                     others += s
                 C[par.implicit, z, y, x] = 1.0 - others
+                if _is_solid(par, x, y, z):
+                    C[:, z, y, x] = 0.0
     EB = np.zeros((nz, ny, nx))
     for z in range(nz):
         for y in range(ny):
@@ -71,6 +79,8 @@ def step(f, g, par):
     for z in range(nz):
         for y in range(ny):
             for x in range(nx):
+                if _is_solid(par, x, y, z):
+                    continue              # no fluid, nothing collides or streams
                 nb = [_node_neighbour(par, x, y, z, lat.e[k]) for k in range(Q)]
                 c0 = [C[i, z, y, x] for i in range(N)]
                 grad = [[0.0, 0.0, 0.0] for _ in range(N)]

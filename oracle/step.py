@@ -64,7 +64,7 @@ class Params:
                  trt_magic=0.0, tau_g=None, m=0.02, body_force=(0.0, 0.0, 0.0),
                  walls=(False, False, False), mu_form="factored",
                  force_form="conservative", geq_form="rest", hydro=True,
-                 implicit=None, mobility="constant", m_star=10.0):
+                 implicit=None, mobility="constant", m_star=10.0, solid=None):
         from .coeffs import Coefficients
         self.lat = lattice
         nx, ny, nz = shape
@@ -85,6 +85,12 @@ class Params:
         self.force_form = force_form
         self.geq_form = geq_form
         self.hydro = hydro
+        if solid is None:
+            self.solid = None
+        else:
+            self.solid = np.asarray(solid, dtype=bool).reshape(self.grid)
+            if self.solid.all():
+                raise ValueError("no fluid node")
         if mobility not in ("constant", "c2c2"):
             raise ValueError(mobility)
         self.mobility = mobility
@@ -106,7 +112,9 @@ def _axis(a):
 
 
 def wall_mask(par, e):
-    """True at nodes whose neighbour x + e lies inside a wall."""
+    """True at nodes whose neighbour x + e lies inside a wall: beyond a wall
+    face, or a solid node (Sec. III C: halfway bounce-back at every solid
+    boundary, and the stencil takes psi(x) for a neighbour inside a solid)."""
     nz, ny, nx = par.grid
     mask = np.zeros((nz, ny, nx), dtype=bool)
     n = (nx, ny, nz)
@@ -116,6 +124,8 @@ def wall_mask(par, e):
         idx = [slice(None)] * 3
         idx[_axis(a) + 3] = n[a] - 1 if e[a] > 0 else 0
         mask[tuple(idx)] = True
+    if par.solid is not None:
+        mask |= np.roll(par.solid, shift=(-int(e[2]), -int(e[1]), -int(e[0])), axis=(0, 1, 2))
     return mask
 
 
@@ -167,6 +177,8 @@ def concentrations(g, par):
     for i in par.evolved:
         rest = rest + C[i]
     C[par.implicit] = 1.0 - rest
+    if par.solid is not None:
+        C[:, par.solid] = 0.0
     return C
 
 
@@ -218,6 +230,10 @@ def macroscopic(f, g, par):
         wm = 1.0 / (0.5 + par.trt_magic / (tau - 0.5))
     else:
         wm = wp.copy()
+    if par.solid is not None:
+        # solid nodes hold no fluid: every node field is zero there
+        for a in (EB, gradC, lapC, gradEB, mut, F, v, P, s):
+            a[..., par.solid] = 0.0
     out = dict(C=C, EB=EB, gradC=gradC, lapC=lapC, gradEB=gradEB, mu_tilde=mut,
                F=F, v=v, P=P, s=s, tau=tau, omega_plus=wp, omega_minus=wm)
     if par.mobility == "c2c2":
@@ -328,6 +344,8 @@ def stream(post, par):
             kb = lat.opp[k]
             out[..., kb, :, :, :] = np.where(mask, post[..., k, :, :, :],
                                              out[..., kb, :, :, :])
+    if par.solid is not None:
+        out[..., par.solid] = 0.0       # nothing streams into a solid node
     return out
 
 
@@ -362,4 +380,7 @@ def initial_state(par, C0, v0=None, P0=None):
     g = np.zeros((par.N, lat.Q) + par.grid)
     g[:, 0] = C0
     g[par.implicit] = 0.0
+    if par.solid is not None:
+        f[..., par.solid] = 0.0
+        g[..., par.solid] = 0.0
     return f, g
