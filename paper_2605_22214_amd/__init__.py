@@ -81,6 +81,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2605_22214_amd.build`")
+        # One HIP runtime per process: PyTorch for ROCm ships its own copy of
+        # the HIP and HSA runtimes under the same library names.  Loaded first,
+        # it is the one this library binds to; loaded after this library it
+        # would start a second runtime that finds no GPU.  So torch, where
+        # installed, is imported before the library is opened.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
         DP = ctypes.POINTER(ctypes.c_double)

@@ -188,3 +188,18 @@ def test_batch_rejects_c2c2_members_before_the_device(L):
     h = ctypes.c_void_p()
     assert L.nflbm_batch_create(arr, 2, ctypes.byref(h)) == -7
     assert not h.value
+
+
+def test_single_hip_runtime_in_process(L):
+    """The binding loads PyTorch's HIP runtime (where torch is installed)
+    before the library, so the process holds one HIP and one HSA runtime: a
+    second copy would find no GPU."""
+    pytest.importorskip("torch")
+    mapped = set()
+    with open("/proc/self/maps") as fh:
+        for line in fh:
+            path = line.split()[-1]
+            if "libamdhip64" in path or "libhsa-runtime64" in path:
+                mapped.add(path)
+    assert len([p for p in mapped if "libamdhip64" in p]) == 1, mapped
+    assert len([p for p in mapped if "libhsa-runtime64" in p]) == 1, mapped
