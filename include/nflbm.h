@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 6
+#define NFLBM_ABI_VERSION 7
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -276,6 +276,12 @@ int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, doub
  * device's LDS bytes per workgroup (any output pointer may be NULL). */
 int nflbm_set_launch(nflbm_sim *sim, int tx_log2, int zchunk);
 int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
+/* The same for the reconstruction kernel (zeroth moment of g, Sec. III B),
+ * which has a launch shape of its own: in D3Q19 with float records it
+ * defaults to 16 x 16 tiles, whose smaller LDS window lets three workgroups
+ * share a CU, while the update keeps 64 x 4.  Results do not depend on it. */
+int nflbm_set_conc_launch(nflbm_sim *sim, int tx_log2, int zchunk);
+int nflbm_get_conc_launch(nflbm_sim *sim, int *tx_log2, int *zchunk);
 
 /* 1 if sim keeps g in the moment form, 0 for populations, negative on error. */
 int nflbm_storage_form(const nflbm_sim *sim);
@@ -290,13 +296,16 @@ int nflbm_bytes_per_node(nflbm_sim *sim, double *bytes);
 
 /* Launch-shape autotuner: times every shape nflbm_set_launch accepts (tile
  * width 16 or 64; in D3Q19 z runs of 1, 2, 4, ... planes and the whole
- * height) for a few steps each and keeps the fastest.  The halo is one node
+ * height) for a few steps each and keeps the one with the fastest update
+ * launches, then does the same for the reconstruction's shape
+ * (nflbm_set_conc_launch) by the rest of the step.  The halo is one node
  * wide in every shape: the stencils (Eq. gradstencil) reach nearest
  * neighbours only.  The state is copied on the device before the trials and
  * restored afterwards, so results are unchanged.  cache_path (may be NULL)
  * names a text file of earlier choices, one "<key>|<values>" line each, keyed
- * by lattice, N, precision, shape, walls, options and device; a cached
- * choice is applied without timing, a new one is appended.  Synchronises. */
+ * by lattice, N, precision, shape, walls, options and device, with the four
+ * values "tx_log2 zchunk conc_tx_log2 conc_zchunk"; a cached choice is
+ * applied without timing, a new one is appended.  Synchronises. */
 int nflbm_autotune(nflbm_sim *sim, const char *cache_path);
 
 /* ------------------------------------------------------------------------

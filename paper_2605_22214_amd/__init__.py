@@ -99,6 +99,8 @@ def lib():
             "nflbm_set_stream": (I, [P, P]),
             "nflbm_set_fields": (I, [P, DP, DP, DP]),
             "nflbm_step": (I, [P, LL]),
+            "nflbm_set_conc_launch": (I, [P, I, I]),
+            "nflbm_get_conc_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_step_timed": (I, [P, LL, DP, DP]),
             "nflbm_get_field": (I, [P, I, DP]),
             "nflbm_state_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
@@ -335,6 +337,14 @@ class Simulation:
                                       ctypes.byref(c)), self._h)
         return a.value, b.value, c.value
 
+    def set_conc_launch(self, tx_log2=0, zchunk=0):
+        _check(lib().nflbm_set_conc_launch(self._handle(), int(tx_log2), int(zchunk)), self._h)
+
+    def get_conc_launch(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().nflbm_get_conc_launch(self._handle(), ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
+
     def bytes_per_node(self):
         b = ctypes.c_double()
         _check(lib().nflbm_bytes_per_node(self._handle(), ctypes.byref(b)), self._h)
@@ -377,7 +387,7 @@ class Simulation:
         """Time the launch shapes and keep the fastest (state unchanged)."""
         _check(lib().nflbm_autotune(self._handle(), None if cache_path is None
                                     else os.fsencode(cache_path)), self._h)
-        return self.get_launch()
+        return self.get_launch() + self.get_conc_launch()
 
     def close(self):
         if getattr(self, "_h", None) is not None:

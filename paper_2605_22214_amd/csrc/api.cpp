@@ -74,8 +74,10 @@ struct nflbm_sim {
   int red_blocks = 0;
   int cur = 0;
   hipStream_t stream = nullptr;
-  // launch shape
+  // launch shape of the update, and of the reconstruction (its own: the two
+  // kernels measured fastest with different tiles)
   int tx_log2 = 6, zchunk = 1, tiles_x = 1, tiles_y = 1, chunks_z = 1;
+  int ctx_log2 = 6, czchunk = 1, ctiles_x = 1, ctiles_y = 1, cchunks_z = 1;
   size_t lds_max = 65536;
   int step_flags = 0;
   std::string err;
@@ -216,9 +218,42 @@ bool apply_launch(nflbm_sim* s, int l, int zc) {
   return true;
 }
 
-// Default shape: tiles 64 x 4 (16 x 16 when nx <= 16 or when the wider LDS
-// window does not fit); in 3-D a z run per workgroup that leaves about 4096
-// workgroups (1024 in FP64, where longer runs measured faster).
+// Launch shape of the reconstruction; false if invalid or its LDS does not fit.
+bool apply_conc_launch(nflbm_sim* s, int l, int zc) {
+  if (l != 4 && l != 6) return false;
+  if (s->lat != NFLBM_D3Q19) zc = 1;
+  if (zc < 1) return false;
+  if (zc > s->nz) zc = s->nz;
+  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
+  const int TX = 1 << l, TY = 256 >> l;
+  s->ctx_log2 = l;
+  s->czchunk = zc;
+  s->ctiles_x = (s->nx + TX - 1) / TX;
+  s->ctiles_y = (s->ny + TY - 1) / TY;
+  s->cchunks_z = s->lat == NFLBM_D3Q19 ? (s->nz + zc - 1) / zc : 1;
+  return true;
+}
+
+// z run per workgroup that leaves about `target` workgroups for tile width 1 << l.
+int zchunk_for(const nflbm_sim* s, int l, long long target) {
+  if (s->lat != NFLBM_D3Q19) return 1;
+  const int TX = 1 << l, TY = 256 >> l;
+  const long long xy = static_cast<long long>((s->nx + TX - 1) / TX) * ((s->ny + TY - 1) / TY);
+  long long chunks = target / (xy > 0 ? xy : 1);
+  if (chunks < 1) chunks = 1;
+  if (chunks > s->nz) chunks = s->nz;
+  int zc = static_cast<int>((s->nz + chunks - 1) / chunks);
+  if (zc < 4) zc = s->nz < 4 ? s->nz : 4;
+  return zc;
+}
+
+// Default shapes.  Update: tiles 64 x 4 (16 x 16 when nx <= 16 or when the
+// wider LDS window does not fit), in 3-D a z run per workgroup that leaves
+// about 8192 workgroups (1024 in FP64, where longer runs measured faster).
+// Moment-form reconstruction in 3-D with float records: 16 x 16 tiles and
+// about 4096 workgroups (its LDS window then allows three workgroups per CU);
+// otherwise the update's shape (the population form's pointwise gather reads
+// rows of 64 nodes better than rows of 16).
 int choose_launch(nflbm_sim* s) {
   s->lds_max = device_lds_max();
   auto fits = [&](int t) {
@@ -228,18 +263,21 @@ int choose_launch(nflbm_sim* s) {
   int l = s->nx <= 16 ? 4 : 6;
   if (l == 6 && !fits(l)) l = 4;
   if (!fits(l)) return -1;
-  int zc = 1;
-  if (s->lat == NFLBM_D3Q19) {
-    const int TX = 1 << l, TY = 256 >> l;
-    const long long xy = static_cast<long long>((s->nx + TX - 1) / TX) * ((s->ny + TY - 1) / TY);
-    const long long target = s->store == NFLBM_FP64 ? 1024 : 4096;
-    long long chunks = target / (xy > 0 ? xy : 1);
-    if (chunks < 1) chunks = 1;
-    if (chunks > s->nz) chunks = s->nz;
-    zc = static_cast<int>((s->nz + chunks - 1) / chunks);
-    if (zc < 4) zc = s->nz < 4 ? s->nz : 4;
-  }
-  return apply_launch(s, l, zc) ? 0 : -1;
+  const bool f64 = s->store == NFLBM_FP64;
+  if (!apply_launch(s, l, zchunk_for(s, l, f64 ? 1024 : 8192))) return -1;
+  if (s->lat == NFLBM_D3Q19 && !f64 && s->gform && apply_conc_launch(s, 4, zchunk_for(s, 4, 4096))) return 0;
+  return apply_conc_launch(s, l, zchunk_for(s, l, f64 ? 1024 : 4096)) ? 0 : -1;
+}
+
+// The step arguments with the reconstruction's launch shape.
+StepArgs conc_args(const nflbm_sim* s, const StepArgs& a) {
+  StepArgs c = a;
+  c.tx_log2 = s->ctx_log2;
+  c.zchunk = s->czchunk;
+  c.tiles_x = s->ctiles_x;
+  c.tiles_y = s->ctiles_y;
+  c.chunks_z = s->cchunks_z;
+  return c;
 }
 
 StepArgs make_args(const nflbm_sim* s, int src) {
@@ -335,7 +373,7 @@ MobArgs mob_args(const nflbm_sim* s, const StepArgs& a) {
 // One time step from state set `cur`; ev (optional) brackets the update.
 int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1) {
   StepArgs a = make_args(s, s->cur);
-  HIPCHK(s, launch_conc(s->lat, s->N, s->store, a, s->stream));
+  HIPCHK(s, launch_conc(s->lat, s->N, s->store, conc_args(s, a), s->stream));
   if (s->c2c2) HIPCHK(s, launch_mob_potentials(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   if (ev0) HIPCHK(s, hipEventRecord(ev0, s->stream));
   HIPCHK(s, launch_update(s->lat, s->N, s->store, a, false, s->stream));
@@ -350,7 +388,7 @@ int compute_fields(nflbm_sim* s) {
   int rc = ensure_fields(s);
   if (rc) return rc;
   StepArgs a = make_args(s, s->cur);
-  HIPCHK(s, launch_conc(s->lat, s->N, s->store, a, s->stream));
+  HIPCHK(s, launch_conc(s->lat, s->N, s->store, conc_args(s, a), s->stream));
   HIPCHK(s, launch_update(s->lat, s->N, s->store, a, true, s->stream));
   return NFLBM_OK;
 }
@@ -1145,6 +1183,21 @@ int nflbm_set_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
   return NFLBM_OK;
 }
 
+int nflbm_set_conc_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  const int l = tx_log2 > 0 ? tx_log2 : sim->ctx_log2;
+  const int zc = zchunk > 0 ? zchunk : sim->czchunk;
+  if (!apply_conc_launch(sim, l, zc)) return fail(sim, NFLBM_EINVAL, "invalid launch shape or LDS too large");
+  return NFLBM_OK;
+}
+
+int nflbm_get_conc_launch(nflbm_sim* sim, int* tx_log2, int* zchunk) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (tx_log2) *tx_log2 = sim->ctx_log2;
+  if (zchunk) *zchunk = sim->czchunk;
+  return NFLBM_OK;
+}
+
 int nflbm_get_launch(nflbm_sim* sim, int* tx_log2, int* zchunk, int* lds_limit) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (tx_log2) *tx_log2 = sim->tx_log2;
@@ -1179,13 +1232,12 @@ int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
 int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   const std::string key = sim_key(sim);
-  std::vector<int> best = {sim->tx_log2, sim->zchunk};
+  std::vector<int> best = {sim->tx_log2, sim->zchunk, sim->ctx_log2, sim->czchunk};
   if (cache_lookup(cache_path, key, &best)) {
-    if (apply_launch(sim, best[0], best[1])) return NFLBM_OK;
+    if (apply_launch(sim, best[0], best[1]) && apply_conc_launch(sim, best[2], best[3])) return NFLBM_OK;
   }
   std::vector<std::pair<int, int>> cands;
   for (int l : {4, 6}) {
-    if (update_lds_bytes(sim->lat, sim->N, sim->store, l) > sim->lds_max) continue;
     if (sim->lat == NFLBM_D3Q19) {
       for (int zc = 1; zc <= sim->nz; zc *= 2) cands.emplace_back(l, zc);
       if ((sim->nz & (sim->nz - 1)) != 0) cands.emplace_back(l, sim->nz);
@@ -1193,7 +1245,6 @@ int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
       cands.emplace_back(l, 1);
     }
   }
-  if (cands.empty()) return fail(sim, NFLBM_ENOTSUP, "no launch shape fits the device");
   SavedState st;
   int rc = save_state(sim, &st);
   if (rc != NFLBM_OK) {
@@ -1203,22 +1254,31 @@ int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
   double bpn = 0.0;
   (void)nflbm_bytes_per_node(sim, &bpn);
   const long long K = tune_steps(double(sim->n), bpn);
-  double best_ms = 1e300;
-  const int keep_l = sim->tx_log2, keep_zc = sim->zchunk;
-  best = {keep_l, keep_zc};
-  for (const auto& c : cands) {
-    if (!apply_launch(sim, c.first, c.second)) continue;
-    rc = nflbm_step(sim, 2);
-    double ms = 0.0;
-    if (rc == NFLBM_OK) rc = nflbm_step_timed(sim, K, &ms, nullptr);
-    if (rc != NFLBM_OK) break;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = {c.first, c.second};
+  const int keep[4] = {sim->tx_log2, sim->zchunk, sim->ctx_log2, sim->czchunk};
+  best = {keep[0], keep[1], keep[2], keep[3]};
+  // the update's shape by the update's own time, then the reconstruction's
+  // by the rest of the step, the other kernel's shape held fixed
+  for (int pass = 0; pass < 2 && rc == NFLBM_OK; ++pass) {
+    double best_ms = 1e300;
+    for (const auto& c : cands) {
+      const bool ok = pass == 0 ? apply_launch(sim, c.first, c.second) : apply_conc_launch(sim, c.first, c.second);
+      if (!ok) continue;
+      rc = nflbm_step(sim, 2);
+      double ms = 0.0, mu = 0.0;
+      if (rc == NFLBM_OK) rc = nflbm_step_timed(sim, K, &ms, &mu);
+      if (rc != NFLBM_OK) break;
+      const double t = pass == 0 ? mu : ms - mu;
+      if (t < best_ms) {
+        best_ms = t;
+        best[2 * pass] = c.first;
+        best[2 * pass + 1] = c.second;
+      }
     }
+    if (pass == 0 && !apply_launch(sim, best[0], best[1])) (void)apply_launch(sim, keep[0], keep[1]);
   }
   const int rc2 = restore_state(sim, &st);
-  if (!apply_launch(sim, best[0], best[1])) (void)apply_launch(sim, keep_l, keep_zc);
+  if (!apply_launch(sim, best[0], best[1])) (void)apply_launch(sim, keep[0], keep[1]);
+  if (!apply_conc_launch(sim, best[2], best[3])) (void)apply_conc_launch(sim, keep[2], keep[3]);
   if (rc != NFLBM_OK) return rc;
   if (rc2 != NFLBM_OK) return rc2;
   cache_store(cache_path, key, best);

@@ -172,16 +172,18 @@ def test_autotune_keeps_state_and_caches(tmp_path):
         before = s.get_state()
         shape = s.autotune(cache)
         assert shape[0] in (4, 6) and 1 <= shape[1] <= 32
+        assert shape[3] in (4, 6) and 1 <= shape[4] <= 32
         assert np.array_equal(s.get_state(), before)
         s.step(5)
         after_tuned = s.get_state()
     with open(cache) as fh:
         lines = fh.read().splitlines()
-    assert len(lines) == 1 and lines[0].endswith(f"|{shape[0]} {shape[1]}")
+    assert len(lines) == 1 and lines[0].endswith(f"|{shape[0]} {shape[1]} {shape[3]} {shape[4]}")
     with nf.Simulation.from_workload(w, precision=nf.FP32, implicit=0) as s:
         s.set_fields(w["C0"])
         s.step(3)
-        assert s.autotune(cache)[:2] == shape[:2]      # from the cache
+        again = s.autotune(cache)                      # from the cache
+        assert again[:2] == shape[:2] and again[3:] == shape[3:]
         s.step(5)
         assert np.array_equal(s.get_state(), after_tuned)
     with open(cache) as fh:
@@ -203,3 +205,19 @@ def test_batch_autotune_keeps_state(tmp_path):
     for i in range(len(ws)):
         assert np.array_equal(got[i], ref[i])
     assert os.path.getsize(cache) > 0
+
+
+def test_reconstruction_launch_shapes_agree():
+    """The reconstruction's own launch shape changes no bit of the result."""
+    w = W.quaternary_3d(24, nz=19)
+    ref = None
+    for tx, zc in ((6, 1), (4, 4), (4, 19), (6, 7)):
+        with nf.Simulation.from_workload(w, precision=nf.FP32, implicit=0) as s:
+            s.set_conc_launch(tx, zc)
+            assert s.get_conc_launch() == (tx, zc)
+            s.set_fields(w["C0"])
+            s.step(11)
+            st = s.get_state()
+        if ref is None:
+            ref = st
+        assert np.array_equal(st, ref), (tx, zc)
