@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 7
+#define NFLBM_ABI_VERSION 8
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -193,6 +193,19 @@ void nflbm_destroy(nflbm_sim *sim);
 /* Run all subsequent device work of sim on this hipStream_t (NULL = the
  * default stream), e.g. torch.cuda.current_stream().cuda_stream. */
 int nflbm_set_stream(nflbm_sim *sim, void *hip_stream);
+
+/* Solid geometry (Sec. III C): solid[n] (node order x fastest, copied; 1 =
+ * solid, 0 = fluid) marks nodes of any shape as solid, in addition to the wall
+ * faces of the configuration.  Every population a fluid node would pull from
+ * a solid node is its own opposite post-collision one instead (halfway
+ * bounce-back: the solid surface lies half a link beyond the last fluid
+ * node), and every stencil neighbour inside a solid takes the node's own
+ * value.  Solid nodes hold no fluid: their concentrations and every field
+ * read back as 0, and diagnostics leave them out.  Call before
+ * nflbm_set_fields (which fills only the fluid nodes); NULL removes the
+ * geometry.  Takes 4 bytes per node of device memory besides the state.
+ * EINVAL if every node is solid, ENOTSUP for a batch member.  Synchronises. */
+int nflbm_set_solid(nflbm_sim *sim, const unsigned char *solid);
 
 /* Initialise the state from host fields: C (N n, required), v (3 n or NULL
  * for rest), P (n or NULL for 0).  f = f^eq(P, v) for k >= 1; g_{i,0} = C_i,

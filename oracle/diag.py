@@ -21,15 +21,17 @@ def diagnostics(f, g, par, vcm_component=1):
     mac = macroscopic(f, g, par)
     C, v = mac["C"], mac["v"]
     N = par.N
+    # solid nodes hold no fluid (all fields 0 there) and are left out
+    fl = np.ones(C.shape[1:], dtype=bool) if par.solid is None else ~par.solid
     out = {
-        "mass": [fsum(C[i]) for i in range(N)],
-        "momentum": [fsum(v[a]) for a in range(3)],
-        "max_abs_c": [float(np.abs(C[i]).max()) for i in range(N)],
-        "min_c": [float(C[i].min()) for i in range(N)],
-        "max_sum_dev": float(np.abs(C.sum(axis=0) - 1.0).max()),
+        "mass": [fsum(C[i][fl]) for i in range(N)],
+        "momentum": [fsum(v[a][fl]) for a in range(3)],
+        "max_abs_c": [float(np.abs(C[i][fl]).max()) for i in range(N)],
+        "min_c": [float(C[i][fl].min()) for i in range(N)],
+        "max_sum_dev": float(np.abs(C.sum(axis=0)[fl] - 1.0).max()),
     }
     c = C[vcm_component]
     den = fsum(c)
-    out["vcm"] = [fsum(c * v[a]) / den if den != 0.0 else 0.0 for a in range(3)]
+    out["vcm"] = [fsum((c * v[a])[fl]) / den if den != 0.0 else 0.0 for a in range(3)]
     out["nan"] = int(not (np.isfinite(f).all() and np.isfinite(g).all()))
     return out

@@ -100,6 +100,7 @@ def lib():
             "nflbm_set_fields": (I, [P, DP, DP, DP]),
             "nflbm_step": (I, [P, LL]),
             "nflbm_set_conc_launch": (I, [P, I, I]),
+            "nflbm_set_solid": (I, [P, ctypes.c_void_p]),
             "nflbm_get_conc_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_step_timed": (I, [P, LL, DP, DP]),
             "nflbm_get_field": (I, [P, I, DP]),
@@ -336,6 +337,17 @@ class Simulation:
         _check(lib().nflbm_get_launch(self._handle(), ctypes.byref(a), ctypes.byref(b),
                                       ctypes.byref(c)), self._h)
         return a.value, b.value, c.value
+
+    def set_solid(self, solid):
+        """Solid nodes (bool or 0/1 array in [nz][ny][nx] order, or None to
+        remove them); call before set_fields."""
+        if solid is None:
+            _check(lib().nflbm_set_solid(self._handle(), None), self._h)
+            return
+        m = np.ascontiguousarray(np.asarray(solid).reshape(-1) != 0, dtype=np.uint8)
+        if m.size != int(np.prod(self.shape)):
+            raise ValueError("solid mask must have one entry per node")
+        _check(lib().nflbm_set_solid(self._handle(), m.ctypes.data), self._h)
 
     def set_conc_launch(self, tx_log2=0, zchunk=0):
         _check(lib().nflbm_set_conc_launch(self._handle(), int(tx_log2), int(zchunk)), self._h)

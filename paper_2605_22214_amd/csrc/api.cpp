@@ -55,6 +55,9 @@ struct nflbm_sim {
   void* mu = nullptr;    // moment form: mu~ [node][i]
   void* vel = nullptr;   // moment form: (v, v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
+  // solid geometry: per-node pull masks (StepArgs::bb) and the caller's mask
+  uint32_t* bb = nullptr;
+  std::vector<unsigned char> solid_host;
   // concentration-dependent mobility: MobParams and the potential scratch
   bool c2c2 = false;
   void* mob = nullptr;
@@ -169,6 +172,8 @@ void free_device(nflbm_sim* s) {
     *a = nullptr;
   }
   if (s->params) (void)hipFree(s->params);
+  if (s->bb) (void)hipFree(s->bb);
+  s->bb = nullptr;
   if (s->mob) (void)hipFree(s->mob);
   if (s->phi) (void)hipFree(s->phi);
   s->mob = s->phi = nullptr;
@@ -299,6 +304,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.eb = s->eb;
   a.fields = s->fields;
   a.params = s->params;
+  a.bb = s->bb;
   a.n = static_cast<long long>(s->n);
   a.nx = s->nx;
   a.ny = s->ny;
@@ -635,7 +641,8 @@ void cache_store(const char* path, const std::string& key, const std::vector<int
 std::string sim_key(const nflbm_sim* s) {
   std::ostringstream o;
   o << "sim lat=" << s->lat << " N=" << s->N << " store=" << s->store << " shape=" << s->nx << 'x' << s->ny
-    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " flags=" << s->step_flags
+    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " solid=" << (s->bb ? 1 : 0)
+    << " flags=" << s->step_flags
     << " dev=" << device_tag();
   return o.str();
 }
@@ -913,6 +920,35 @@ int nflbm_set_stream(nflbm_sim* sim, void* stream) {
   return NFLBM_OK;
 }
 
+int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (sim->in_batch) return fail(sim, NFLBM_ENOTSUP, "batch members take no solid geometry");
+  if (!solid) {
+    if (sim->bb) (void)hipFree(sim->bb);
+    sim->bb = nullptr;
+    sim->solid_host.clear();
+    return NFLBM_OK;
+  }
+  const size_t n = sim->n;
+  size_t fluid = 0;
+  for (size_t q = 0; q < n; ++q) fluid += solid[q] ? 0 : 1;
+  if (fluid == 0) return fail(sim, NFLBM_EINVAL, "every node is solid");
+  if (!sim->bb && hipMalloc(reinterpret_cast<void**>(&sim->bb), n * sizeof(uint32_t)) != hipSuccess) {
+    sim->bb = nullptr;
+    return fail(sim, NFLBM_ENOMEM, "cannot allocate the solid geometry");
+  }
+  unsigned char* dmask = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&dmask), n) != hipSuccess)
+    return fail(sim, NFLBM_ENOMEM, "cannot allocate the solid mask");
+  hipError_t e = hipMemcpyAsync(dmask, solid, n, hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess) e = launch_build_bb(sim->lat, dmask, sim->bb, make_args(sim, sim->cur), sim->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+  (void)hipFree(dmask);
+  if (e != hipSuccess) return hip_fail(sim, e, "set_solid");
+  sim->solid_host.assign(solid, solid + n);
+  return NFLBM_OK;
+}
+
 int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const double* P) {
   if (!sim || !C) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const size_t n = sim->n;
@@ -1061,25 +1097,37 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     const int (*E)[3] = sim->lat == NFLBM_D2Q9 ? kD2Q9 : kD3Q19;
     const int dims[3] = {sim->nx, sim->ny, sim->nz};
     // (direction, node) the population f_k of node q is read from
+    const bool geom = !sim->solid_host.empty();
     auto source = [&](int k, int x, int y, int z, int& dir) -> size_t {
+      const size_t self = size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
       int c[3] = {x - E[k][0], y - E[k][1], z - E[k][2]};
       for (int d = 0; d < 3; ++d) {
         if (c[d] < 0 || c[d] >= dims[d]) {
           if (sim->wall[d]) {
             dir = (k & 1) ? k + 1 : k - 1;
-            return size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
+            return self;
           }
           c[d] = (c[d] + dims[d]) % dims[d];
         }
       }
+      const size_t src = size_t(c[0]) + size_t(sim->nx) * (size_t(c[1]) + size_t(sim->ny) * c[2]);
+      if (geom && sim->solid_host[src]) {   // bounced back from a solid node
+        dir = (k & 1) ? k + 1 : k - 1;
+        return self;
+      }
       dir = k;
-      return size_t(c[0]) + size_t(sim->nx) * (size_t(c[1]) + size_t(sim->ny) * c[2]);
+      return src;
     };
     if (field == NFLBM_FIELD_G_RAW) std::memset(host_out, 0, size_t(N) * sim->Q * n * sizeof(double));
     for (int z = 0; z < sim->nz; ++z)
       for (int y = 0; y < sim->ny; ++y)
         for (int x = 0; x < sim->nx; ++x) {
           const size_t q = size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
+          if (geom && sim->solid_host[q]) {         // no fluid: every population 0
+            if (field == NFLBM_FIELD_F_RAW)
+              for (int k = 1; k <= Qm; ++k) host_out[size_t(k - 1) * n + q] = 0.0;
+            continue;
+          }
           if (field == NFLBM_FIELD_G_RAW)
             for (int i = 0; i < NE; ++i)
               host_out[size_t(sim->uidx[i]) * sim->Q * n + q] = val(g0buf.data(), q * NE + i, sim->g0s, false);
@@ -1155,6 +1203,7 @@ int nflbm_diagnostics(nflbm_sim* sim, int vcm_component, nflbm_diag* out) {
   a.N = N;
   a.vcm_comp = vcm_component;
   a.blocks = sim->red_blocks;
+  a.bb = sim->bb;
   HIPCHK(sim, launch_reduce(a, sim->stream));
   std::vector<double> r(rec);
   HIPCHK(sim, hipMemcpyAsync(r.data(), a.out, rec * sizeof(double), hipMemcpyDeviceToHost, sim->stream));

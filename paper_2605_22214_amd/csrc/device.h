@@ -283,6 +283,8 @@ __host__ __device__ constexpr T moving_weight_sum() {
 struct Nbr {
   uint32_t xo[3], yo[3], zo[3];
   bool wlo[3], whi[3];
+  bool geom;      // solid geometry given: pm decides, the faces are folded in
+  uint32_t pm;    // its pull mask (StepArgs::bb) of this node
 };
 
 template <bool WALLS, bool D3>
@@ -307,6 +309,12 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a
     b.yo[d] *= nx;
     b.zo[d] *= nxy;
   }
+  b.geom = false;
+  b.pm = 0u;
+  if (WALLS && a.bb) {
+    b.geom = true;
+    b.pm = a.bb[uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)];
+  }
   return b;
 }
 
@@ -316,6 +324,7 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a
 template <class L, bool WALLS>
 __device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
   if (!WALLS) return false;
+  if (b.geom) return (b.pm >> k) & 1u;
   bool w = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -323,6 +332,13 @@ __device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
     if (L::e[k][d] < 0) w = w || b.whi[d];
   }
   return w;
+}
+// A solid node holds no fluid: the reconstruction writes C = 0 there and the
+// fields read back as 0; what the update stores there is read by no fluid
+// node (every pull from it is bounced back).
+template <bool WALLS>
+__device__ __forceinline__ bool solid_node(const Nbr& b) {
+  return WALLS && b.geom && (b.pm & 1u);
 }
 template <class L>
 __device__ __forceinline__ uint32_t upstream(const Nbr& b, int k) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 #include "coeffs.h"
 
@@ -84,6 +85,10 @@ struct StepArgs {
   NFLBM_GLOBAL void* eb;              // E_B per node (compute precision)
   NFLBM_GLOBAL double* fields;        // fields-mode output [2N+7][n]
   const NFLBM_GLOBAL void* params;    // DevParams<T>
+  // Solid geometry (null without): per node, bit k (1 <= k < Q) set when the
+  // population arriving along e_k would come from a solid node or from
+  // beyond a wall face, bit 0 set at solid nodes themselves.
+  const NFLBM_GLOBAL uint32_t* bb;
   long long n;
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
@@ -131,6 +136,7 @@ struct ReduceArgs {
   int N;
   int vcm_comp;                       // user index
   int blocks;
+  const uint32_t* bb;                 // solid geometry or null: solid nodes are skipped
 };
 
 // Arguments of the two kernels of the concentration-dependent mobility
@@ -161,6 +167,10 @@ size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
 // Concentration-dependent mobility: the literal flux potentials of every node
 // (after the reconstruction), and the source term added to the update's
 // post-collision populations (after the update).
+// Per-node pull masks of StepArgs::bb from a byte mask solid[n] (1 = solid)
+// and the wall faces of a.
+hipError_t launch_build_bb(int lat, const unsigned char* solid, uint32_t* bb, const StepArgs& a,
+                           hipStream_t s);
 hipError_t launch_mob_potentials(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
 hipError_t launch_mob_source(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
 

@@ -68,6 +68,14 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   const size_t n = static_cast<size_t>(a.n);
   const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
   const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
+  if (solid_node<WALLS>(nb)) {
+    T zero[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) zero[e] = T(0);
+    vst<T, NE>(at(gptr<T>(a.conc), node * NE), zero);
+    *at(gptr<T>(a.eb), node) = T(0);
+    return;
+  }
   const G0S* g0 = gptr<const G0S>(a.g0_src);
   const FS* gk = gptr<const FS>(a.gk_src);
   // The small moving populations are summed first and the O(1) rest
@@ -281,6 +289,14 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const int li = (ty + 1) * PX + (tx + 1);
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+    if (solid_node<WALLS>(nb)) {
+      T zero[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) zero[e] = T(0);
+      vst<T, NE>(at(gptr<T>(a.conc), node * NE), zero);
+      *at(gptr<T>(a.eb), node) = T(0);
+      return;
+    }
     // records of the 3 x 3 neighbourhood are reached from its lowest corner
     // with non-negative immediate offsets
     const T* corner_dn = sm + s_dn * plane_stride + (li - PX - 1) * PSTEP;
@@ -558,6 +574,16 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     // immediate offsets from one base instead of hoisted per-entry addresses
     const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
     const int li = (ty + 1) * PX + (tx + 1);
+    // solid geometry: this node's pull mask (bit k: the neighbour x - e_k is
+    // solid or beyond a wall face; bit 0: this node is solid)
+    bool geom = false;
+    uint32_t pm = 0u;
+    if constexpr (WALLS) {
+      if (a.bb) {
+        geom = true;
+        pm = a.bb[uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)];
+      }
+    }
     const T* Cc = sm + s_c * plane_stride;
     T c[NC];
     {
@@ -590,8 +616,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     // node's result depends only on its position.
     bool near_wall = false;
     if constexpr (WALLS) {
-      near_wall = (a.wall_x && (x == 0 || x == a.nx - 1)) || (a.wall_y && (y == 0 || y == a.ny - 1)) ||
-                  (a.wall_z && (z == 0 || z == a.nz - 1));
+      near_wall = geom ? (pm >> 1) != 0u
+                       : (a.wall_x && (x == 0 || x == a.nx - 1)) || (a.wall_y && (y == 0 || y == a.ny - 1)) ||
+                             (a.wall_z && (z == 0 || z == a.nz - 1));
     }
     if (!near_wall) {
       // over the opposite pairs {k, k+1}, with psi+ = psi(x + e_k) and
@@ -629,9 +656,13 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
         const T wk = static_cast<T>(L::w[k]);
         bool wall = false;
-        if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
-        if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
-        if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+        if (geom) {
+          wall = (pm >> opposite(k)) & 1u;      // x + e_k is x - e_(opposite k)
+        } else {
+          if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
+          if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
+          if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+        }
         if (!wall) {
           const T* Cn = nbr(ex, ey, ez);
 #pragma unroll
@@ -760,6 +791,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 
     if constexpr (FIELDS) {
       double* out = gptr<double>(a.fields);
+      if (pm & 1u) {          // a solid node: no fluid, every field 0
+#pragma unroll
+        for (int r = 0; r < 2 * NC + 7; ++r) out[size_t(r) * n + node] = 0.0;
+        return;
+      }
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
         out[size_t(P.uidx[i]) * n + node] = static_cast<double>(c[i]);
@@ -942,6 +978,31 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   if (x >= a.sa.nx || y >= a.sa.ny) return;
   const uint32_t node = uint32_t(x) + uint32_t(a.sa.nx) * (uint32_t(y) + uint32_t(a.sa.ny) * uint32_t(z));
   const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a.sa);
+  if (solid_node<WALLS>(nb)) {
+    // no fluid: this node's own stored values are 0 (no fluid node reads them)
+    FS zf[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) zf[e] = S::pack(T(0));
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      f[size_t(k - 1) * n + node] = S::pack(T(0));
+      if (!GM) vst<FS, NE>(gk + (size_t(k - 1) * n + node) * NE, zf);
+    }
+    T z0[NE], z4[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < NE; ++i) z0[i] = T(0);
+    if constexpr (GM) {
+      vst<T, NE>(gptr<T>(a.sa.cprev) + size_t(node) * NE, z0);
+      vst<T, NE>(gptr<T>(a.sa.mu) + size_t(node) * NE, z0);
+      vst<T, 4>(gptr<T>(a.sa.vel) + size_t(node) * 4, z4);
+    } else {
+      G0S g00[NE];
+#pragma unroll
+      for (int i = 0; i < NE; ++i) g00[i] = G0S(0);
+      vst<G0S, NE>(g0 + size_t(node) * NE, g00);
+    }
+    return;
+  }
   double v[3] = {0.0, 0.0, 0.0};
   double Pn = 0.0;
   if (a.v)
@@ -1034,6 +1095,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
     else if (q == 3 * N + 3) { acc = 0.0; op = 1; }
     else { acc = 0.0; }
     for (size_t node = lo + threadIdx.x; node < hi; node += 256) {
+      if (a.bb && (a.bb[node] & 1u)) continue;     // solid node: no fluid
       double val;
       if (q < N) val = f[size_t(q) * n + node];
       else if (q < N + 3) val = f[size_t(q) * n + node];
@@ -1064,6 +1126,36 @@ __global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
     if (threadIdx.x == 0) out[q] = r;
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------ solid geometry
+// StepArgs::bb of every node from the byte mask solid[n]: bit k set when
+// x - e_k lies beyond a wall face or is solid, bit 0 when x is solid.
+template <class L>
+__global__ void __launch_bounds__(256) k_build_bb(const unsigned char* __restrict__ solid,
+                                                  uint32_t* __restrict__ bb, StepArgs a) {
+  const size_t n = static_cast<size_t>(a.n);
+  const size_t node = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n) return;
+  const int x = int(node % size_t(a.nx));
+  const int y = int((node / size_t(a.nx)) % size_t(a.ny));
+  const int z = int(node / (size_t(a.nx) * size_t(a.ny)));
+  const int dims[3] = {a.nx, a.ny, a.nz};
+  const int walls[3] = {a.wall_x, a.wall_y, a.wall_z};
+  uint32_t m = solid[node] ? 1u : 0u;
+  for (int k = 1; k < L::Q; ++k) {
+    int c[3] = {x - L::e[k][0], y - L::e[k][1], z - L::e[k][2]};
+    bool blocked = false;
+    for (int d = 0; d < 3; ++d) {
+      if (c[d] < 0 || c[d] >= dims[d]) {
+        if (walls[d]) blocked = true;
+        c[d] = (c[d] + dims[d]) % dims[d];
+      }
+    }
+    if (!blocked) blocked = solid[size_t(c[0]) + size_t(a.nx) * (size_t(c[1]) + size_t(a.ny) * size_t(c[2]))] != 0;
+    if (blocked) m |= 1u << k;
+  }
+  bb[node] = m;
 }
 
 // ------------------------------------------------------------ domain size
@@ -1192,7 +1284,7 @@ hipError_t expand_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
     default: return hipErrorInvalidValue; \
   }
 
-inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z; }
+inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr; }
 inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
 
 template <class L, int NC, int ST>
@@ -1446,6 +1538,14 @@ hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, h
     case kStoreF16S: return batch_st2(lat, nc, b, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_build_bb(int lat, const unsigned char* solid, uint32_t* bb, const StepArgs& a,
+                           hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((a.n + 255) / 256);
+  if (lat == 0) hipLaunchKernelGGL(k_build_bb<D2Q9>, dim3(blocks), dim3(256), 0, s, solid, bb, a);
+  else hipLaunchKernelGGL(k_build_bb<D3Q19>, dim3(blocks), dim3(256), 0, s, solid, bb, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_lambda(const double* C, double* lam, long long total, hipStream_t s) {

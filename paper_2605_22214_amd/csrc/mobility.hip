@@ -243,7 +243,7 @@ namespace {
     default: return hipErrorInvalidValue; \
   }
 
-inline bool walls_of(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z; }
+inline bool walls_of(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr; }
 inline dim3 node_grid(const StepArgs& a) { return dim3(static_cast<unsigned>((a.n + 255) / 256)); }
 
 template <class L, int NC, class T>
