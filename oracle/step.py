@@ -50,6 +50,17 @@ Readings (where the printed text is garbled or silent):
     same isotropic gradient stencil as every other gradient; the mobility is
     M = c_s^2 m* (tau_g - 1/2).  alpha_ij is evaluated with all N
     concentrations of the node (the implicit one included).
+  * Open faces (Sec. III C, ``open_faces={face: (v_b, C_b)}``, face 0..5 =
+    x-, x+, y-, y+, z-, z+ of a walled axis): a population entering across
+    the face is the node's own opposite post-collision one plus 2 w_k
+    (e_k . v_b) / c_s^2 for f (velocity Dirichlet, rho_b = 1; the sign that
+    gives the fluid the face's momentum) and, for g, minus it plus
+    g^eq_k + g^eq_kbar of (C_b, v_b) (anti-bounce-back with the even part of
+    the equilibrium, which keeps a uniform state at the boundary values
+    fixed).  mu~ in that equilibrium is the bulk value of the uniform state
+    C_b.  Stencil neighbours beyond the face take the boundary values (C_b,
+    E_B(C_b)).  Where a link crosses a wall face and an open face (a corner),
+    the wall wins; where it crosses two open faces, the first axis's face.
 """
 import numpy as np
 
@@ -64,7 +75,8 @@ class Params:
                  trt_magic=0.0, tau_g=None, m=0.02, body_force=(0.0, 0.0, 0.0),
                  walls=(False, False, False), mu_form="factored",
                  force_form="conservative", geq_form="rest", hydro=True,
-                 implicit=None, mobility="constant", m_star=10.0, solid=None):
+                 implicit=None, mobility="constant", m_star=10.0, solid=None,
+                 open_faces=None):
         from .coeffs import Coefficients
         self.lat = lattice
         nx, ny, nz = shape
@@ -91,6 +103,14 @@ class Params:
             self.solid = np.asarray(solid, dtype=bool).reshape(self.grid)
             if self.solid.all():
                 raise ValueError("no fluid node")
+        self.open_faces = {}
+        for face, (vb, Cb) in (open_faces or {}).items():
+            if not 0 <= face < 6 or not self.walls[face // 2]:
+                raise ValueError("an open face must lie on a walled axis")
+            self.open_faces[int(face)] = (np.asarray(vb, dtype=np.float64).reshape(3),
+                                          np.asarray(Cb, dtype=np.float64).reshape(self.N))
+        if self.open_faces and (solid is not None or mobility != "constant"):
+            raise ValueError("open faces take neither solid nodes nor the mobility variant")
         if mobility not in ("constant", "c2c2"):
             raise ValueError(mobility)
         self.mobility = mobility
@@ -129,33 +149,63 @@ def wall_mask(par, e):
     return mask
 
 
-def neighbour(psi, e, par):
-    """psi(x + e) with periodic wrap, or psi(x) where x + e is inside a wall."""
+def open_face_masks(par, e):
+    """{face: nodes whose link to x + e leaves across that open face}, with a
+    wall face taking precedence and, between open faces, the first axis."""
+    out = {}
+    if not par.open_faces:
+        return out
+    nz, ny, nx = par.grid
+    n = (nx, ny, nz)
+    grid = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    idx = (grid[2], grid[1], grid[0])
+    plain = np.zeros((nz, ny, nx), dtype=bool)
+    decided = np.zeros((nz, ny, nx), dtype=bool)
+    for a in range(3):
+        if not par.walls[a] or e[a] == 0:
+            continue
+        face = 2 * a + (1 if e[a] > 0 else 0)
+        cross = (idx[a] + int(e[a]) < 0) | (idx[a] + int(e[a]) >= n[a])
+        if face in par.open_faces:
+            m = cross & ~decided
+            out[face] = out.get(face, np.zeros_like(m)) | m
+            decided |= cross
+        else:
+            plain |= cross
+    return {f: m & ~plain for f, m in out.items()}
+
+
+def neighbour(psi, e, par, bvals=None):
+    """psi(x + e) with periodic wrap, or psi(x) where x + e is inside a wall;
+    beyond an open face the face's value bvals[face] when given."""
     out = np.roll(psi, shift=(-int(e[2]), -int(e[1]), -int(e[0])), axis=(-3, -2, -1))
     mask = wall_mask(par, e)
     if mask.any():
         out = np.where(mask, psi, out)
+    if bvals is not None:
+        for face, m in open_face_masks(par, e).items():
+            out = np.where(m, bvals[face], out)
     return out
 
 
-def gradient(psi, par):
+def gradient(psi, par, bvals=None):
     """(1/c_s^2) sum_{k>=1} w_k e_k [psi(x+e_k) - psi(x)]  -> [3, ...]."""
     lat = par.lat
     out = np.zeros((3,) + psi.shape)
     for k in range(1, lat.Q):
-        d = neighbour(psi, lat.e[k], par) - psi
+        d = neighbour(psi, lat.e[k], par, bvals) - psi
         for a in range(3):
             if lat.e[k, a] != 0:
                 out[a] = out[a] + lat.w[k] * lat.e[k, a] * d
     return out / CS2
 
 
-def laplacian(psi, par):
+def laplacian(psi, par, bvals=None):
     """(2/c_s^2) sum_{k>=1} w_k [psi(x+e_k) - psi(x)]."""
     lat = par.lat
     out = np.zeros(psi.shape)
     for k in range(1, lat.Q):
-        out = out + lat.w[k] * (neighbour(psi, lat.e[k], par) - psi)
+        out = out + lat.w[k] * (neighbour(psi, lat.e[k], par, bvals) - psi)
     return 2.0 * out / CS2
 
 
@@ -187,9 +237,15 @@ def macroscopic(f, g, par):
     lat, co, N = par.lat, par.co, par.N
     C = concentrations(g, par)
     EB = potential.bulk_energy(C, co)
-    gradC = np.stack([gradient(C[i], par) for i in range(N)])      # [N, 3, ...]
-    lapC = np.stack([laplacian(C[i], par) for i in range(N)])      # [N, ...]
-    gradEB = gradient(EB, par)
+    bc = [None] * N
+    beb = None
+    if par.open_faces:
+        bc = [{f: Cb[i] for f, (vb, Cb) in par.open_faces.items()} for i in range(N)]
+        beb = {f: float(potential.bulk_energy(Cb.reshape(N, 1), co)[0])
+               for f, (vb, Cb) in par.open_faces.items()}
+    gradC = np.stack([gradient(C[i], par, bc[i]) for i in range(N)])      # [N, 3, ...]
+    lapC = np.stack([laplacian(C[i], par, bc[i]) for i in range(N)])      # [N, ...]
+    gradEB = gradient(EB, par, beb)
     if par.mu_form == "factored":
         mut = potential.mu_tilde_factored(C, lapC, co, par.omega_stab)
     elif par.mu_form == "literal":
@@ -326,8 +382,31 @@ def collide(f, g, par, mac=None):
     return fs, gs, mac
 
 
-def stream(post, par):
-    """Step 10 for one population array [..., Q, nz, ny, nx]."""
+def open_face_terms(par):
+    """Per open face: the f correction 2 w_k (e_k . v_b) / c_s^2 [Q] and, per
+    component, g^eq_k + g^eq_kbar of (C_b, v_b) [N, Q] (rest form, mu~ of the
+    uniform state C_b)."""
+    lat, N = par.lat, par.N
+    out = {}
+    for face, (vb, Cb) in par.open_faces.items():
+        v = vb.reshape(3, 1, 1, 1)
+        sk = s_k(lat, v)[:, 0, 0, 0]
+        mut = potential.mu_tilde_factored(Cb.reshape(N, 1), np.zeros((N, 1)), par.co,
+                                          par.omega_stab)[:, 0]
+        fc = np.array([lat.w[k] * (lat.e[k] @ vb) / CS2 * 2.0 for k in range(lat.Q)])
+        gs = np.zeros((N, lat.Q))
+        for i in range(N):
+            for k in range(1, lat.Q):
+                kb = lat.opp[k]
+                gs[i, k] = (Cb[i] * sk[k] - lat.w[k] * par.m * mut[i]
+                            + Cb[i] * sk[kb] - lat.w[kb] * par.m * mut[i])
+        out[face] = (fc, gs)
+    return out
+
+
+def stream(post, par, kind=None):
+    """Step 10 for one population array [..., Q, nz, ny, nx]; kind "f" or "g"
+    selects the open-face rule."""
     lat = par.lat
     out = np.empty_like(post)
     for k in range(lat.Q):
@@ -344,6 +423,19 @@ def stream(post, par):
             kb = lat.opp[k]
             out[..., kb, :, :, :] = np.where(mask, post[..., k, :, :, :],
                                              out[..., kb, :, :, :])
+    if par.open_faces:
+        terms = open_face_terms(par)
+        for k in range(1, lat.Q):
+            kb = lat.opp[k]
+            for face, m in open_face_masks(par, lat.e[k]).items():
+                fc, gs = terms[face]
+                if kind == "f":
+                    val = post[..., k, :, :, :] + fc[kb]
+                elif kind == "g":
+                    val = -post[..., k, :, :, :] + gs[:, kb].reshape((-1,) + (1,) * 3)
+                else:
+                    raise ValueError("open faces need kind='f' or 'g'")
+                out[..., kb, :, :, :] = np.where(m, val, out[..., kb, :, :, :])
     if par.solid is not None:
         out[..., par.solid] = 0.0       # nothing streams into a solid node
     return out
@@ -353,7 +445,9 @@ def step(f, g, par):
     """One full time step; returns (f, g, mac) with mac the macroscopic fields
     of the input state."""
     fs, gs, mac = collide(f, g, par)
-    return stream(fs, par), stream(gs, par), mac
+    gn = stream(gs, par, "g")
+    gn[par.implicit] = 0.0
+    return stream(fs, par, "f"), gn, mac
 
 
 def run(f, g, par, steps):
