@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 8
+#define NFLBM_ABI_VERSION 9
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -193,6 +193,24 @@ void nflbm_destroy(nflbm_sim *sim);
 /* Run all subsequent device work of sim on this hipStream_t (NULL = the
  * default stream), e.g. torch.cuda.current_stream().cuda_stream. */
 int nflbm_set_stream(nflbm_sim *sim, void *hip_stream);
+
+/* Open face (Sec. III C): turns the wall face `face` (0..5 = x-, x+, y-, y+,
+ * z-, z+; its axis must be walled in the configuration; 0..3 in D2Q9) into an
+ * inlet / outlet with velocity v_b[3] and concentrations C_b[N] (user order,
+ * summing to 1).  A population of f entering across it is the node's own
+ * opposite post-collision one plus 2 w_k (e_k . v_b) / c_s^2 (velocity
+ * Dirichlet with rho_b = 1, the sign that gives the fluid the face's
+ * momentum); one of g is minus its own opposite one plus g^eq_k + g^eq_kbar
+ * of (C_b, v_b) (anti-bounce-back with the even part of the equilibrium; the
+ * flux potential in it is the bulk one of the uniform state C_b); stencil
+ * neighbours beyond the face take C_b and E_B(C_b).  Where a link crosses a
+ * wall face and an open face the wall wins, between two open faces the first
+ * axis's face.  v_b = C_b = NULL makes the face a wall again.  Needs g as
+ * populations (create with NFLBM_FLAG_G_POPULATIONS: ENOTSUP otherwise) and
+ * takes neither solid nodes, the concentration-dependent mobility nor batch
+ * members (ENOTSUP).  Call before nflbm_set_fields.  EINVAL for a bad face,
+ * an unwalled axis, non-finite values or C_b not summing to 1. */
+int nflbm_set_open_face(nflbm_sim *sim, int face, const double *v_b, const double *C_b);
 
 /* Solid geometry (Sec. III C): solid[n] (node order x fastest, copied; 1 =
  * solid, 0 = fluid) marks nodes of any shape as solid, in addition to the wall

@@ -101,6 +101,7 @@ def lib():
             "nflbm_step": (I, [P, LL]),
             "nflbm_set_conc_launch": (I, [P, I, I]),
             "nflbm_set_solid": (I, [P, ctypes.c_void_p]),
+            "nflbm_set_open_face": (I, [P, I, DP, DP]),
             "nflbm_get_conc_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_step_timed": (I, [P, LL, DP, DP]),
             "nflbm_get_field": (I, [P, I, DP]),
@@ -348,6 +349,16 @@ class Simulation:
         if m.size != int(np.prod(self.shape)):
             raise ValueError("solid mask must have one entry per node")
         _check(lib().nflbm_set_solid(self._handle(), m.ctypes.data), self._h)
+
+    def set_open_face(self, face, v_b=None, C_b=None):
+        """Open face 0..5 (x-, x+, y-, y+, z-, z+) with velocity v_b and
+        concentrations C_b (user order), or a wall again with None."""
+        if v_b is None:
+            _check(lib().nflbm_set_open_face(self._handle(), int(face), None, None), self._h)
+            return
+        v = np.ascontiguousarray(v_b, dtype=np.float64).reshape(3)
+        c = np.ascontiguousarray(C_b, dtype=np.float64).reshape(self.N)
+        _check(lib().nflbm_set_open_face(self._handle(), int(face), _dptr(v), _dptr(c)), self._h)
 
     def set_conc_launch(self, tx_log2=0, zchunk=0):
         _check(lib().nflbm_set_conc_launch(self._handle(), int(tx_log2), int(zchunk)), self._h)

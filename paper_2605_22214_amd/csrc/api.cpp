@@ -32,6 +32,10 @@ constexpr int kD3Q19[19][3] = {
     {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
     {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+constexpr double kW2[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+constexpr double kW3[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
 }  // namespace
 
@@ -55,6 +59,12 @@ struct nflbm_sim {
   void* mu = nullptr;    // moment form: mu~ [node][i]
   void* vel = nullptr;   // moment form: (v, v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
+  // open faces: FaceBC<T> on the device, and the host's copy of each face
+  void* faces = nullptr;
+  int open_mask = 0;
+  double face_v[6][3] = {};
+  double face_c[6][kMaxComp] = {};   // user order
+  double m_geq = 0.0, omega = 0.0;
   // solid geometry: per-node pull masks (StepArgs::bb) and the caller's mask
   uint32_t* bb = nullptr;
   std::vector<unsigned char> solid_host;
@@ -174,6 +184,8 @@ void free_device(nflbm_sim* s) {
   if (s->params) (void)hipFree(s->params);
   if (s->bb) (void)hipFree(s->bb);
   s->bb = nullptr;
+  if (s->faces) (void)hipFree(s->faces);
+  s->faces = nullptr;
   if (s->mob) (void)hipFree(s->mob);
   if (s->phi) (void)hipFree(s->phi);
   s->mob = s->phi = nullptr;
@@ -305,6 +317,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.fields = s->fields;
   a.params = s->params;
   a.bb = s->bb;
+  a.faces = s->faces;
   a.n = static_cast<long long>(s->n);
   a.nx = s->nx;
   a.ny = s->ny;
@@ -387,6 +400,77 @@ int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1) {
   if (s->c2c2) HIPCHK(s, launch_mob_source(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   s->cur ^= 1;
   return NFLBM_OK;
+}
+
+// Bulk flux potential mu~_i of a uniform state C (user order, Laplacian 0):
+// the factored form of Eq. MU with the tables of coeffs.cpp.
+double mu_bulk(const Coeffs& c, const double* C, double omega, int i) {
+  const int N = c.N;
+  double br = -(1.0 - 3.0 * C[i] + 2.0 * C[i] * C[i]);
+  for (int l = 0; l < N; ++l)
+    for (int m = l + 1; m < N; ++m)
+      if (l != i && m != i) br += c.psi[i][l][m] * C[l] * C[m];
+  double val = (12.0 / c.D) * C[i] * br;
+  if (omega != 0.0) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < N; ++k)
+      for (int l = k + 1; l < N; ++l)
+        if (k != i && l != i) sx += c.xt[i][k][l] * C[k] * C[k] * C[l] * C[l];
+    for (int l = 0; l < N; ++l) {
+      if (l == i) continue;
+      double inner = 0.0;
+      for (int m = 0; m < N; ++m)
+        if (m != i && m != l) inner += c.zt[i][l][m] * C[m];
+      sy += C[l] * C[l] * inner;
+    }
+    val += (12.0 / c.D) * omega * C[i] * (sx + C[i] * sy);
+  }
+  return val;
+}
+
+double bulk_energy_host(const Coeffs& c, const double* C) {
+  auto fp = [](double x) { return x * x * (1.0 - x) * (1.0 - x); };
+  double e = 0.0;
+  for (int i = 0; i < c.N; ++i)
+    for (int j = i + 1; j < c.N; ++j) e += c.beta[i][j] * (fp(C[i]) + fp(C[j]) - fp(C[i] + C[j]));
+  return e;
+}
+
+// Open-face terms of fill_faces in FP64, for the host's read-back of the
+// post-streaming populations: f correction and g^eq_k + g^eq_kbar of
+// component u (user index) for the population entering along e_k.
+double face_fcorr(const nflbm_sim& s, int f, int k) {
+  const int (*E)[3] = s.lat == NFLBM_D2Q9 ? kD2Q9 : kD3Q19;
+  const double* W = s.lat == NFLBM_D2Q9 ? kW2 : kW3;
+  const double* v = s.face_v[f];
+  return 6.0 * W[k] * (E[k][0] * v[0] + E[k][1] * v[1] + E[k][2] * v[2]);
+}
+double face_gsum(const nflbm_sim& s, int f, int u, int k) {
+  const int (*E)[3] = s.lat == NFLBM_D2Q9 ? kD2Q9 : kD3Q19;
+  const double* W = s.lat == NFLBM_D2Q9 ? kW2 : kW3;
+  const double* v = s.face_v[f];
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double ev = E[k][0] * v[0] + E[k][1] * v[1] + E[k][2] * v[2];
+  // s_k + s_kbar = 2 w_k (4.5 (e_k . v)^2 - 1.5 v.v)
+  const double ssum = 2.0 * W[k] * (4.5 * ev * ev - 1.5 * vv);
+  return s.face_c[f][u] * ssum - 2.0 * W[k] * s.m_geq * mu_bulk(s.co, s.face_c[f], s.omega, u);
+}
+
+// The device table of the open faces (internal component order).
+template <class T>
+void fill_faces(const nflbm_sim& s, FaceBC<T>* p) {
+  std::memset(p, 0, sizeof(*p));
+  p->open = s.open_mask;
+  for (int f = 0; f < 6; ++f) {
+    if (!((s.open_mask >> f) & 1)) continue;
+    const double* Cu = s.face_c[f];
+    for (int k = 1; k < s.Q; ++k) {
+      p->fcorr[f][k] = static_cast<T>(face_fcorr(s, f, k));
+      for (int i = 0; i < s.NE; ++i) p->gsum[f][i][k] = static_cast<T>(face_gsum(s, f, s.uidx[i], k));
+    }
+    for (int i = 0; i < s.N; ++i) p->cb[f][i] = static_cast<T>(Cu[s.uidx[i]]);
+    p->eb[f] = static_cast<T>(bulk_energy_host(s.co, Cu));
+  }
 }
 
 // Reconstruct C and evaluate the node fields of the current state.
@@ -641,7 +725,7 @@ void cache_store(const char* path, const std::string& key, const std::vector<int
 std::string sim_key(const nflbm_sim* s) {
   std::ostringstream o;
   o << "sim lat=" << s->lat << " N=" << s->N << " store=" << s->store << " shape=" << s->nx << 'x' << s->ny
-    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " solid=" << (s->bb ? 1 : 0)
+    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " solid=" << (s->bb ? 1 : 0) << " open=" << s->open_mask
     << " flags=" << s->step_flags
     << " dev=" << device_tag();
   return o.str();
@@ -864,6 +948,8 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   }
   // the concentration-dependent mobility takes m = 0 in g^eq; cfg->m is its m*
   const double m_geq = s->c2c2 ? 0.0 : cfg->m;
+  s->m_geq = m_geq;
+  s->omega = cfg->omega_stab;
   if (s->ts == 8) {
     DevParams<double> p;
     fill_params(*s, cfg->tau, cfg->tau_g, cfg->trt_magic, m_geq, cfg->omega_stab, cfg->body_force, &p);
@@ -920,9 +1006,61 @@ int nflbm_set_stream(nflbm_sim* sim, void* stream) {
   return NFLBM_OK;
 }
 
+int nflbm_set_open_face(nflbm_sim* sim, int face, const double* v_b, const double* C_b) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (face < 0 || face >= 6 || (sim->lat == NFLBM_D2Q9 && face >= 4))
+    return fail(sim, NFLBM_EINVAL, "face is 0..5 (x-, x+, y-, y+, z-, z+; 0..3 in D2Q9)");
+  if (!sim->wall[face / 2]) return fail(sim, NFLBM_EINVAL, "an open face must lie on a walled axis");
+  if (sim->in_batch || sim->bb || sim->c2c2)
+    return fail(sim, NFLBM_ENOTSUP, "open faces take neither batches, solid nodes nor the mobility variant");
+  if (sim->gform)
+    return fail(sim, NFLBM_ENOTSUP, "open faces need g as populations (NFLBM_FLAG_G_POPULATIONS)");
+  if ((v_b == nullptr) != (C_b == nullptr)) return fail(sim, NFLBM_EINVAL, "v_b and C_b go together");
+  if (v_b) {
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(v_b[d])) return fail(sim, NFLBM_EINVAL, "v_b must be finite");
+    double sum = 0.0;
+    for (int i = 0; i < sim->N; ++i) {
+      if (!std::isfinite(C_b[i])) return fail(sim, NFLBM_EINVAL, "C_b must be finite");
+      sum += C_b[i];
+    }
+    if (std::fabs(sum - 1.0) > 1e-12) return fail(sim, NFLBM_EINVAL, "C_b must sum to 1");
+    for (int d = 0; d < 3; ++d) sim->face_v[face][d] = v_b[d];
+    for (int i = 0; i < sim->N; ++i) sim->face_c[face][i] = C_b[i];
+    sim->open_mask |= 1 << face;
+  } else {
+    sim->open_mask &= ~(1 << face);
+  }
+  if (!sim->open_mask) {
+    if (sim->faces) (void)hipFree(sim->faces);
+    sim->faces = nullptr;
+    return NFLBM_OK;
+  }
+  const size_t bytes = sim->ts == 8 ? sizeof(FaceBC<double>) : sizeof(FaceBC<float>);
+  if (!sim->faces && hipMalloc(&sim->faces, bytes) != hipSuccess) {
+    sim->faces = nullptr;
+    return fail(sim, NFLBM_ENOMEM, "cannot allocate the open-face table");
+  }
+  hipError_t e;
+  if (sim->ts == 8) {
+    auto* t = new FaceBC<double>();
+    fill_faces(*sim, t);
+    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
+    delete t;
+  } else {
+    auto* t = new FaceBC<float>();
+    fill_faces(*sim, t);
+    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
+    delete t;
+  }
+  if (e != hipSuccess) return hip_fail(sim, e, "set_open_face");
+  return NFLBM_OK;
+}
+
 int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (sim->in_batch) return fail(sim, NFLBM_ENOTSUP, "batch members take no solid geometry");
+  if (solid && sim->open_mask) return fail(sim, NFLBM_ENOTSUP, "open faces take no solid nodes");
   if (!solid) {
     if (sim->bb) (void)hipFree(sim->bb);
     sim->bb = nullptr;
@@ -1098,17 +1236,32 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     const int dims[3] = {sim->nx, sim->ny, sim->nz};
     // (direction, node) the population f_k of node q is read from
     const bool geom = !sim->solid_host.empty();
+    // open face a pull enters across (-1: none, or a wall face wins)
+    int entry = -1;
     auto source = [&](int k, int x, int y, int z, int& dir) -> size_t {
       const size_t self = size_t(x) + size_t(sim->nx) * (size_t(y) + size_t(sim->ny) * z);
       int c[3] = {x - E[k][0], y - E[k][1], z - E[k][2]};
+      entry = -1;
+      bool crossed = false, wall = false;
       for (int d = 0; d < 3; ++d) {
         if (c[d] < 0 || c[d] >= dims[d]) {
           if (sim->wall[d]) {
-            dir = (k & 1) ? k + 1 : k - 1;
-            return self;
+            const int face = 2 * d + (c[d] < 0 ? 0 : 1);
+            crossed = true;
+            if ((sim->open_mask >> face) & 1) {
+              if (entry < 0) entry = face;
+            } else {
+              wall = true;
+            }
+            continue;
           }
           c[d] = (c[d] + dims[d]) % dims[d];
         }
+      }
+      if (crossed) {
+        if (wall) entry = -1;
+        dir = (k & 1) ? k + 1 : k - 1;
+        return self;
       }
       const size_t src = size_t(c[0]) + size_t(sim->nx) * (size_t(c[1]) + size_t(sim->ny) * c[2]);
       if (geom && sim->solid_host[src]) {   // bounced back from a solid node
@@ -1135,11 +1288,15 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
             int dir = k;
             const size_t src = source(k, x, y, z, dir);
             if (field == NFLBM_FIELD_F_RAW) {
-              host_out[size_t(k - 1) * n + q] = val(fbuf.data(), size_t(dir - 1) * n + src, sim->fs, true);
+              double v = val(fbuf.data(), size_t(dir - 1) * n + src, sim->fs, true);
+              if (entry >= 0) v += face_fcorr(*sim, entry, k);
+              host_out[size_t(k - 1) * n + q] = v;
             } else {
-              for (int i = 0; i < NE; ++i)
-                host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] =
-                    val(gkbuf.data(), (size_t(dir - 1) * n + src) * NE + i, sim->fs, true);
+              for (int i = 0; i < NE; ++i) {
+                double v = val(gkbuf.data(), (size_t(dir - 1) * n + src) * NE + i, sim->fs, true);
+                if (entry >= 0) v = face_gsum(*sim, entry, sim->uidx[i], k) - v;
+                host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] = v;
+              }
             }
           }
         }

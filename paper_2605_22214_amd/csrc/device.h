@@ -287,8 +287,9 @@ struct Nbr {
   uint32_t pm;    // its pull mask (StepArgs::bb) of this node
 };
 
-template <bool WALLS, bool D3>
+template <class L, bool WALLS>
 __device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a) {
+  constexpr bool D3 = (L::DIM == 3);
   Nbr b;
   const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
   b.xo[0] = x - 1; b.xo[1] = x; b.xo[2] = x + 1;
@@ -309,11 +310,27 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a
     b.yo[d] *= nx;
     b.zo[d] *= nxy;
   }
+  // pull mask: bit k set when the population arriving along e_k comes from
+  // beyond a wall face or (with solid geometry) from a solid node; one bit
+  // test per direction in either case
   b.geom = false;
   b.pm = 0u;
-  if (WALLS && a.bb) {
-    b.geom = true;
-    b.pm = a.bb[uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)];
+  if (WALLS) {
+    if (a.bb) {
+      b.geom = true;
+      b.pm = a.bb[uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)];
+    } else {
+#pragma unroll
+      for (int k = 1; k < L::Q; ++k) {
+        bool w = false;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (L::e[k][d] > 0) w = w || b.wlo[d];
+          if (L::e[k][d] < 0) w = w || b.whi[d];
+        }
+        if (w) b.pm |= 1u << k;
+      }
+    }
   }
   return b;
 }
@@ -324,15 +341,31 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int z, const StepArgs& a
 template <class L, bool WALLS>
 __device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
   if (!WALLS) return false;
-  if (b.geom) return (b.pm >> k) & 1u;
-  bool w = false;
+  return (b.pm >> k) & 1u;
+}
+// The open face (0..5 = x-, x+, y-, y+, z-, z+) the population arriving along
+// e_k enters across, or -1: it crosses no face, or a wall face (a wall wins
+// at a corner; between two open faces the first axis's face).
+template <class L, bool WALLS>
+__device__ __forceinline__ int entry_face(const Nbr& b, int k, int open) {
+  if (!WALLS || !open) return -1;
+  int face = -1;
+  bool wall = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (L::e[k][d] > 0) w = w || b.wlo[d];
-    if (L::e[k][d] < 0) w = w || b.whi[d];
+    int fc = -1;
+    if (L::e[k][d] > 0 && b.wlo[d]) fc = 2 * d;
+    if (L::e[k][d] < 0 && b.whi[d]) fc = 2 * d + 1;
+    if (fc < 0) continue;
+    if ((open >> fc) & 1) {
+      if (face < 0) face = fc;
+    } else {
+      wall = true;
+    }
   }
-  return w;
+  return wall ? -1 : face;
 }
+
 // A solid node holds no fluid: the reconstruction writes C = 0 there and the
 // fields read back as 0; what the update stores there is read by no fluid
 // node (every pull from it is bounced back).

@@ -48,6 +48,17 @@ struct MobParams {
   T pre[kMaxComp];                                  // (1 - 1/(2 tau_g,i)) m*
 };
 
+// Open faces (velocity and concentration Dirichlet, Sec. III C), faces 0..5 =
+// x-, x+, y-, y+, z-, z+; internal component order; compute precision T.
+template <class T>
+struct FaceBC {
+  int open;                         // bit f: face f is open (else a wall)
+  T fcorr[6][19];                   // 2 w_k (e_k . v_b) / c_s^2, population entering along e_k
+  T gsum[6][kMaxComp][19];          // g^eq_k + g^eq_kbar of (C_b, v_b), evolved components
+  T cb[6][kMaxComp];                // C_b of every component (stencil value beyond the face)
+  T eb[6];                          // E_B(C_b)
+};
+
 enum StepFlags {
   kFlagNeedG = 1,         // some tau_g != 1: the update reads g
   kFlagPotential = 2,     // potential-form surface tension
@@ -89,6 +100,7 @@ struct StepArgs {
   // population arriving along e_k would come from a solid node or from
   // beyond a wall face, bit 0 set at solid nodes themselves.
   const NFLBM_GLOBAL uint32_t* bb;
+  const NFLBM_GLOBAL void* faces;     // FaceBC<T> when some face is open, else null
   long long n;
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;

@@ -67,7 +67,7 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   if (x >= a.nx || y >= a.ny) return;
   const size_t n = static_cast<size_t>(a.n);
   const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
-  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
+  const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
   if (solid_node<WALLS>(nb)) {
     T zero[NE];
 #pragma unroll
@@ -86,6 +86,10 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   T s[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) s[e] = T(0);
+  // open faces: a population entering across one is minus this node's own
+  // opposite one plus g^eq_k + g^eq_kbar of the face (anti-bounce-back)
+  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+  const int open = (WALLS && FB) ? FB->open : 0;
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
     FS v[NE];
@@ -93,8 +97,14 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
       vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
     else
       vld_nt<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
+    const int fc = entry_face<L, WALLS>(nb, k, open);
+    if (fc >= 0) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+      for (int e = 0; e < NE; ++e) s[e] += FB->gsum[fc][e][k] - S::unpack(v[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+    }
   }
   {
     G0S r[NE];
@@ -288,7 +298,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const T m = P.m;
     const int li = (ty + 1) * PX + (tx + 1);
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
-    const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+    const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
     if (solid_node<WALLS>(nb)) {
       T zero[NE];
 #pragma unroll
@@ -457,9 +467,11 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
 // ---------------------------------------------------------------- k_update
 // Occupancy target of the update kernel: three waves per SIMD (at most 168
 // VGPRs) where that needs no spilling (float compute, D3Q19 with N <= 5, all
-// D2Q9); otherwise the compiler's own choice.
-template <class L, int NC, int ST>
+// D2Q9, except the D3Q19 wall variant that collides stored g populations);
+// otherwise the compiler's own choice.
+template <class L, int NC, int ST, bool WALLS = false, bool GM = true>
 constexpr int update_waves() {
+  if (L::DIM == 3 && WALLS && !GM) return 1;
   return (ST != kStoreF64 && (L::DIM == 2 || NC <= 5)) ? 3 : 1;
 }
 
@@ -504,27 +516,46 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   const T* conc = gptr<const T>(a.conc);
   const T* eb = gptr<const T>(a.eb);
   const FS* fsrc = gptr<const FS>(a.f_src);
+  // open faces (velocity and concentration Dirichlet); null and 0 otherwise
+  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+  const int open = (WALLS && FB) ? FB->open : 0;
+  auto plain = [&](int face) { return !((open >> face) & 1); };   // a wall face
 
   // Each thread fills at most two positions of the (TX+2) x (TY+2) LDS window
   // of every plane; their in-plane node offsets are fixed for the workgroup.
+  // A position beyond an open face holds the face's values (fill_face).
   uint32_t fill_off[2];
   bool fill_ok[2];
+  int fill_face[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     const int idx = tid + 256 * r;
     fill_ok[r] = idx < PXY;
     fill_off[r] = 0;
+    fill_face[r] = -1;
     if (fill_ok[r]) {
       const int ly = idx / PX;
       const int lx = idx - ly * PX;
       int gx = x0 + lx - 1, gy = y0 + ly - 1;
       if (gx < 0 || gx >= a.nx) {
-        if (WALLS && a.wall_x) fill_ok[r] = false;
-        else gx = wrap(gx, a.nx);
+        if (WALLS && a.wall_x) {
+          const int face = gx < 0 ? 0 : 1;
+          if (plain(face)) fill_ok[r] = false;
+          else fill_face[r] = face;
+          gx = 0;
+        } else {
+          gx = wrap(gx, a.nx);
+        }
       }
       if (gy < 0 || gy >= a.ny) {
-        if (WALLS && a.wall_y) fill_ok[r] = false;
-        else gy = wrap(gy, a.ny);
+        if (WALLS && a.wall_y) {
+          const int face = gy < 0 ? 2 : 3;
+          if (plain(face)) fill_ok[r] = false;
+          else if (fill_face[r] < 0) fill_face[r] = face;
+          gy = 0;
+        } else {
+          gy = wrap(gy, a.ny);
+        }
       }
       fill_off[r] = uint32_t(gx) + nx * uint32_t(gy);
     }
@@ -534,15 +565,28 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   // Positions inside a wall are left unfilled: the stencil never reads them.
   auto load_plane = [&](int slot, int gz) {
     T* base = sm + slot * plane_stride;
+    int plane_face = -1;
     if (gz < 0 || gz >= a.nz) {
-      if (WALLS && a.wall_z) return;
-      gz = (gz < 0) ? gz + a.nz : gz - a.nz;
+      if (WALLS && a.wall_z) {
+        plane_face = gz < 0 ? 4 : 5;
+        if (plain(plane_face)) return;
+        gz = 0;
+      } else {
+        gz = (gz < 0) ? gz + a.nz : gz - a.nz;
+      }
     }
     const uint32_t zoff = uint32_t(gz) * nxy;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (!fill_ok[r]) continue;
       const int idx = tid + 256 * r;
+      const int face = fill_face[r] >= 0 ? fill_face[r] : plane_face;
+      if (WALLS && face >= 0) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) base[e * PXY + idx] = FB->cb[face][e];
+        base[NE * PXY + idx] = FB->eb[face];
+        continue;
+      }
       const uint32_t node = fill_off[r] + zoff;
       T ce[NE];
       vld<T, NE>(at(conc, node * NE), ce);
@@ -557,14 +601,18 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   auto load_f = [&](int z) {
     {
       const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
-      const Nbr nb = neighbours<WALLS, D3>(x, y, z, a);
+      const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
       const size_t nn = fresh(n);
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
-        if (pulled_from_wall<L, WALLS>(nb, k))
+        if (pulled_from_wall<L, WALLS>(nb, k)) {
           f[k] = S::ld(at(fsrc + size_t(opposite(k) - 1) * nn, node), 0);
-        else
+          // open face: velocity Dirichlet, bounce-back plus 2 w_k (e_k . v_b) / c_s^2
+          const int fc = entry_face<L, WALLS>(nb, k, open);
+          if (fc >= 0) f[k] += FB->fcorr[fc][k];
+        } else {
           f[k] = S::ld(at(fsrc + size_t(k - 1) * nn, upstream<L>(nb, k)), 0);
+        }
       }
     }
   };
@@ -617,8 +665,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     bool near_wall = false;
     if constexpr (WALLS) {
       near_wall = geom ? (pm >> 1) != 0u
-                       : (a.wall_x && (x == 0 || x == a.nx - 1)) || (a.wall_y && (y == 0 || y == a.ny - 1)) ||
-                             (a.wall_z && (z == 0 || z == a.nz - 1));
+                       : (a.wall_x && ((x == 0 && plain(0)) || (x == a.nx - 1 && plain(1)))) ||
+                             (a.wall_y && ((y == 0 && plain(2)) || (y == a.ny - 1 && plain(3)))) ||
+                             (a.wall_z && ((z == 0 && plain(4)) || (z == a.nz - 1 && plain(5))));
     }
     if (!near_wall) {
       // over the opposite pairs {k, k+1}, with psi+ = psi(x + e_k) and
@@ -659,9 +708,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         if (geom) {
           wall = (pm >> opposite(k)) & 1u;      // x + e_k is x - e_(opposite k)
         } else {
-          if (ex != 0 && a.wall_x) wall |= (x + ex < 0) || (x + ex >= a.nx);
-          if (ey != 0 && a.wall_y) wall |= (y + ey < 0) || (y + ey >= a.ny);
-          if (ez != 0 && a.wall_z) wall |= (z + ez < 0) || (z + ez >= a.nz);
+          // a neighbour beyond an open face is an ordinary LDS position
+          if (ex != 0 && a.wall_x) wall |= (x + ex < 0 && plain(0)) || (x + ex >= a.nx && plain(1));
+          if (ey != 0 && a.wall_y) wall |= (y + ey < 0 && plain(2)) || (y + ey >= a.ny && plain(3));
+          if (ez != 0 && a.wall_z) wall |= (z + ez < 0 && plain(4)) || (z + ez >= a.nz && plain(5));
         }
         if (!wall) {
           const T* Cn = nbr(ex, ey, ez);
@@ -844,7 +894,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
     for (int i = 0; i < NE; ++i) moved[i] = T(0);
     Nbr nb;
-    if (!GM && (a.flags & kFlagNeedG)) nb = neighbours<WALLS, D3>(x, y, z, a);
+    if (!GM && (a.flags & kFlagNeedG)) nb = neighbours<L, WALLS>(x, y, z, a);
     const size_t nn = fresh(n);
 
     // ---- per direction pair: TRT collision of f with forcing and BGK
@@ -874,6 +924,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       const T mw = wk * P.m;
       FS qk[NE], qb[NE];
       FS ok[NE], ob[NE];
+      // open faces: the pulled g are anti-bounced (see the reconstruction)
+      int fk = -1, fb = -1;
+      if (WALLS && open && (a.flags & kFlagNeedG)) {
+        fk = entry_face<L, WALLS>(nb, k, open);
+        fb = entry_face<L, WALLS>(nb, kb, open);
+      }
       if (a.flags & kFlagNeedG) {
         if (pulled_from_wall<L, WALLS>(nb, k))
           vld<FS, NE>(at(gksrc + size_t(kb - 1) * nn * NE, node * NE), ok);
@@ -890,7 +946,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         T gk = fma(c[i], sk_k, -mmu);
         T gb = fma(c[i], sk_b, -mmu);
         if (a.flags & kFlagNeedG) {
-          const T o1 = S::unpack(ok[i]), o2 = S::unpack(ob[i]);
+          T o1 = S::unpack(ok[i]), o2 = S::unpack(ob[i]);
+          if (fk >= 0) o1 = FB->gsum[fk][i][k] - o1;
+          if (fb >= 0) o2 = FB->gsum[fb][i][kb] - o2;
           gk = o1 - (o1 - gk) * P.inv_tau_g[i];
           gb = o2 - (o2 - gb) * P.inv_tau_g[i];
         }
@@ -932,7 +990,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 }
 
 template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL, bool GM>
-__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
+__global__ void __launch_bounds__(256, (update_waves<L, NC, ST, WALLS, GM>()))
 k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
@@ -944,7 +1002,7 @@ k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
 // tiles contiguously, so the XCD remap keeps a simulation's neighbouring tiles
 // on one XCD.
 template <class L, int NC, int ST, bool WALLS, int TXL, bool GM>
-__global__ void __launch_bounds__(256, (update_waves<L, NC, ST>()))
+__global__ void __launch_bounds__(256, (update_waves<L, NC, ST, WALLS, GM>()))
 k_update_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
                const int2* __restrict__ work, int nblocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -977,7 +1035,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   const int z = blockIdx.z;
   if (x >= a.sa.nx || y >= a.sa.ny) return;
   const uint32_t node = uint32_t(x) + uint32_t(a.sa.nx) * (uint32_t(y) + uint32_t(a.sa.ny) * uint32_t(z));
-  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a.sa);
+  const Nbr nb = neighbours<L, WALLS>(x, y, z, a.sa);
   if (solid_node<WALLS>(nb)) {
     // no fluid: this node's own stored values are 0 (no fluid node reads them)
     FS zf[NE];
@@ -1020,6 +1078,21 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     const double s = L::w[k] * (3.0 * ev + 4.5 * ev * ev - 1.5 * vv);
     const FS val = S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s));
     if (pulled_from_wall<L, WALLS>(nb, k)) {
+      // an open face adds its correction to the slot on the way in: store the
+      // value that the first step then reads as f_k = val and g_k = 0
+      const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.sa.faces);
+      const int fc = entry_face<L, WALLS>(nb, k, (WALLS && FB) ? FB->open : 0);
+      if (fc >= 0) {
+        f[size_t(opposite(k) - 1) * n + node] =
+            S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s) - FB->fcorr[fc][k]);
+        if (!GM) {
+          FS gs[NE];
+#pragma unroll
+          for (int e = 0; e < NE; ++e) gs[e] = S::pack(FB->gsum[fc][e][k]);
+          vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, gs);
+        }
+        continue;
+      }
       f[size_t(opposite(k) - 1) * n + node] = val;
       if (!GM) vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, zero);
     } else {

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) k_mob_potentials(MobArgs ma) {
   const T* conc = gptr<const T>(a.conc);
   int x, y, z;
   node_xyz(node, a, x, y, z);
-  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
+  const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
   T c[NC];
   node_conc<NC, T>(conc, node, c);
   T lap[NC];
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_mob_source(MobArgs ma) {
   const T* phi = static_cast<const T*>(ma.phi);
   int x, y, z;
   node_xyz(node, a, x, y, z);
-  const Nbr nb = neighbours<WALLS, (L::DIM == 3)>(x, y, z, a);
+  const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
   T p0[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) p0[j] = phi[size_t(node) * NC + j];

@@ -1,0 +1,147 @@
+"""Open faces (Sec. III C: velocity Dirichlet for f, anti-bounce-back
+concentration Dirichlet for g) through the C ABI (nflbm_set_open_face).
+
+* FP64 against the oracle with the same faces: a Couette cell (a wall and a
+  moving open face), an inlet/outlet channel of three components between
+  walls, tau_g != 1, and D3Q19 with inlet, outlet and a moving lid (links that
+  cross two faces at the edges).  Metric per field as in the parity tests:
+  C and g to 1e-12 of their scale, the O(1e-6) v, P, F and f to 1e-10.
+* FP32: the Couette profile u_x = U (y + 1/2) / n_y, exact for the scheme,
+  within float storage error.
+* Argument errors: moment form, an unwalled axis, C_b not summing to 1.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+import workloads as W
+from oracle import step as S
+from oracle.coeffs import equal_sigma
+from oracle.lattice import D2Q9, D3Q19
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RESULTS = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def record():
+    yield
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "openfaces.json"), "w") as fh:
+        json.dump(RESULTS, fh, indent=1, sort_keys=True)
+
+
+def rel(a, b, floor=0.0):
+    scale = max(np.abs(b).max(), floor)
+    if scale == 0.0:
+        return 0.0 if np.all(a == 0.0) else np.inf
+    return float(np.abs(a - b).max() / scale)
+
+
+def couette(nx=8, ny=12, U=1e-3):
+    N = 2
+    C0 = np.zeros((N, 1, ny, nx))
+    C0[0] = 1.0
+    w = W._base("D2Q9", (nx, ny, 1), equal_sigma(N, 0.005), 1.0, 0.05, C0=C0,
+                walls=(False, True, False))
+    return w, {3: ((U, 0.0, 0.0), (1.0, 0.0))}
+
+
+def case(name):
+    if name == "couette":
+        w, faces = couette()
+        return w, faces, 400, -1
+    if name == "channel_3":
+        w = W.noise("D2Q9", (40, 18, 1), 3, amp=0.1, seed=4, sigma=0.006, m=0.05)
+        w.update(walls=(True, True, False), trt_magic=3.0 / 16.0, tau=np.array([0.7, 1.0, 1.2]))
+        u = (2e-3, 0.0, 0.0)
+        faces = {0: (u, (0.8, 0.15, 0.05)), 1: (u, (1.0 / 3, 1.0 / 3, 1.0 / 3))}
+        return w, faces, 200, -1
+    if name == "tau_g":
+        w = W.noise("D2Q9", (30, 14, 1), 3, amp=0.1, seed=6, sigma=0.006, m=0.05)
+        w.update(walls=(True, False, False), tau_g=np.array([0.8, 1.0, 1.3]))
+        faces = {0: ((1e-3, 2e-4, 0.0), (0.5, 0.3, 0.2))}
+        return w, faces, 150, -1
+    if name == "d3_lid_inlet_outlet":
+        w = W.noise("D3Q19", (14, 9, 10), 3, amp=0.1, seed=7, sigma=0.006, m=0.05)
+        w.update(walls=(True, False, True))
+        u = (1e-3, 0.0, 0.0)
+        faces = {0: (u, (0.6, 0.3, 0.1)), 1: (u, (0.2, 0.3, 0.5)), 5: ((2e-3, 0.0, 0.0), (0.4, 0.4, 0.2))}
+        return w, faces, 60, -1
+    raise KeyError(name)
+
+
+def oracle_run(w, faces, steps, implicit):
+    lat = D2Q9 if w["lattice"] == "D2Q9" else D3Q19
+    N = w["sigma"].shape[0]
+    par = S.Params(lat, w["shape"], w["sigma"], w["tau"], D=w["D"], omega_stab=w["omega_stab"],
+                   trt_magic=w["trt_magic"], tau_g=w["tau_g"], m=w["m"], body_force=w["body_force"],
+                   walls=w["walls"], implicit=(N - 1 if implicit == -1 else implicit),
+                   open_faces=faces)
+    f, g = S.initial_state(par, w["C0"])
+    for _ in range(steps):
+        f, g, _ = S.step(f, g, par)
+    return f, g, par
+
+
+def gpu_sim(w, faces, precision):
+    sim = nf.Simulation.from_workload(w, precision=precision, flags=nf.FLAG_G_POPULATIONS)
+    for face, (vb, Cb) in faces.items():
+        sim.set_open_face(face, vb, Cb)
+    sim.set_fields(w["C0"])
+    return sim
+
+
+@pytest.mark.parametrize("name", ["couette", "channel_3", "tau_g", "d3_lid_inlet_outlet"])
+def test_fp64_matches_oracle_with_open_faces(name):
+    w, faces, steps, implicit = case(name)
+    f, g, par = oracle_run(w, faces, steps, implicit)
+    mac = S.macroscopic(f, g, par)
+    with gpu_sim(w, faces, nf.FP64) as sim:
+        sim.step(steps)
+        errs = {"C": rel(sim.get_field("C"), mac["C"]),
+                "G_RAW": rel(sim.get_field("G_RAW")[par.evolved], g[par.evolved]),
+                "V": rel(sim.get_field("V"), mac["v"]),
+                "P": rel(sim.get_field("P"), mac["P"]),
+                # F is rounding noise (1e-17) in the pure-phase Couette cell
+                "F": rel(sim.get_field("F"), mac["F"], floor=1e-12),
+                "F_RAW": rel(sim.get_field("F_RAW"), f[1:])}
+    RESULTS.setdefault("fp64_vs_oracle", {})[name] = errs
+    moved = float(np.abs(mac["C"] - w["C0"].reshape(mac["C"].shape)).max())
+    vmax = float(np.abs(mac["v"]).max())
+    assert moved > 1e-6 or vmax > 1e-5
+    assert errs["C"] <= 1e-12 and errs["G_RAW"] <= 1e-12, errs
+    for k in ("V", "P", "F", "F_RAW"):
+        assert errs[k] <= 1e-10, (k, errs)
+
+
+def test_fp32_couette_profile():
+    w, faces = couette(nx=8, ny=12, U=1e-3)
+    with gpu_sim(w, faces, nf.FP32) as sim:
+        sim.step(4000)
+        u = sim.get_field("V")[0, 0, :, 0]
+    y = np.arange(12) + 0.5
+    exact = 1e-3 * y / 12
+    err = float(np.abs(u - exact).max() / 1e-3)
+    RESULTS["fp32_couette_rel_err"] = err
+    assert err < 1e-4
+
+
+def test_open_face_argument_errors():
+    w, faces = couette()
+    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:        # moment form
+        with pytest.raises(nf.NflbmError):
+            sim.set_open_face(3, (1e-3, 0, 0), (1.0, 0.0))
+    with nf.Simulation.from_workload(w, precision=nf.FP64, flags=nf.FLAG_G_POPULATIONS) as sim:
+        with pytest.raises(nf.NflbmError):
+            sim.set_open_face(0, (1e-3, 0, 0), (1.0, 0.0))                 # x is periodic
+        with pytest.raises(nf.NflbmError):
+            sim.set_open_face(3, (1e-3, 0, 0), (0.7, 0.2))                 # sum != 1
+        sim.set_open_face(3, (1e-3, 0, 0), (1.0, 0.0))
+        sim.set_open_face(3)                                               # a wall again
