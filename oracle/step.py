@@ -61,6 +61,17 @@ Readings (where the printed text is garbled or silent):
     C_b.  Stencil neighbours beyond the face take the boundary values (C_b,
     E_B(C_b)).  Where a link crosses a wall face and an open face (a corner),
     the wall wins; where it crosses two open faces, the first axis's face.
+  * Convective outflow (Sec. III C, Eq. convect, ``outflow=face`` of a walled
+    axis): after streaming, every population (all k, f and g) of the boundary
+    plane N becomes (q(N, t) + U q(N-1, t+1)) / (1 + U), q(N, t) the plane's
+    post-streaming values of the previous step.  U is the mean over plane N-1
+    of the populations' normal momentum sum_k (e_k . n) f_k after streaming
+    (without the F/2 term, which would need the new state's stencils), and 0
+    if that mean points inwards.  Stencil neighbours beyond the face take
+    ghost values of C_i and E_B convected the same way, psi(N+1, t+1) =
+    (psi(N+1, t) + U psi(N, t+1)) / (1 + U), starting at psi(N, 0).  The
+    previous planes, U and the ghosts are state: they live in
+    ``par.outflow_state`` (set by initial_state, advanced by step).
 """
 import numpy as np
 
@@ -76,7 +87,7 @@ class Params:
                  walls=(False, False, False), mu_form="factored",
                  force_form="conservative", geq_form="rest", hydro=True,
                  implicit=None, mobility="constant", m_star=10.0, solid=None,
-                 open_faces=None):
+                 open_faces=None, outflow=None):
         from .coeffs import Coefficients
         self.lat = lattice
         nx, ny, nz = shape
@@ -111,6 +122,13 @@ class Params:
                                           np.asarray(Cb, dtype=np.float64).reshape(self.N))
         if self.open_faces and (solid is not None or mobility != "constant"):
             raise ValueError("open faces take neither solid nodes nor the mobility variant")
+        self.outflow = None if outflow is None else int(outflow)
+        if self.outflow is not None:
+            if not 0 <= self.outflow < 6 or not self.walls[self.outflow // 2]:
+                raise ValueError("the outflow face must lie on a walled axis")
+            if self.outflow in self.open_faces or solid is not None or mobility != "constant":
+                raise ValueError("the outflow face takes no open face, solid nodes or mobility variant")
+        self.outflow_state = None
         if mobility not in ("constant", "c2c2"):
             raise ValueError(mobility)
         self.mobility = mobility
@@ -153,7 +171,10 @@ def open_face_masks(par, e):
     """{face: nodes whose link to x + e leaves across that open face}, with a
     wall face taking precedence and, between open faces, the first axis."""
     out = {}
-    if not par.open_faces:
+    faces = set(par.open_faces)
+    if par.outflow is not None:
+        faces.add(par.outflow)
+    if not faces:
         return out
     nz, ny, nx = par.grid
     n = (nx, ny, nz)
@@ -166,7 +187,7 @@ def open_face_masks(par, e):
             continue
         face = 2 * a + (1 if e[a] > 0 else 0)
         cross = (idx[a] + int(e[a]) < 0) | (idx[a] + int(e[a]) >= n[a])
-        if face in par.open_faces:
+        if face in faces:
             m = cross & ~decided
             out[face] = out.get(face, np.zeros_like(m)) | m
             decided |= cross
@@ -184,7 +205,11 @@ def neighbour(psi, e, par, bvals=None):
         out = np.where(mask, psi, out)
     if bvals is not None:
         for face, m in open_face_masks(par, e).items():
-            out = np.where(m, bvals[face], out)
+            if face in bvals:
+                val = bvals[face]
+                if np.ndim(val) > 0:      # a ghost plane: the value where the link lands
+                    val = np.roll(val, shift=(-int(e[2]), -int(e[1]), -int(e[0])), axis=(-3, -2, -1))
+                out = np.where(m, val, out)
     return out
 
 
@@ -239,10 +264,15 @@ def macroscopic(f, g, par):
     EB = potential.bulk_energy(C, co)
     bc = [None] * N
     beb = None
-    if par.open_faces:
+    if par.open_faces or par.outflow is not None:
         bc = [{f: Cb[i] for f, (vb, Cb) in par.open_faces.items()} for i in range(N)]
         beb = {f: float(potential.bulk_energy(Cb.reshape(N, 1), co)[0])
                for f, (vb, Cb) in par.open_faces.items()}
+        if par.outflow is not None:
+            st = par.outflow_state
+            for i in range(N):
+                bc[i][par.outflow] = _plane_field(par, st["ghost_C"][i])
+            beb[par.outflow] = _plane_field(par, st["ghost_EB"])
     gradC = np.stack([gradient(C[i], par, bc[i]) for i in range(N)])      # [N, 3, ...]
     lapC = np.stack([laplacian(C[i], par, bc[i]) for i in range(N)])      # [N, ...]
     gradEB = gradient(EB, par, beb)
@@ -423,11 +453,13 @@ def stream(post, par, kind=None):
             kb = lat.opp[k]
             out[..., kb, :, :, :] = np.where(mask, post[..., k, :, :, :],
                                              out[..., kb, :, :, :])
-    if par.open_faces:
+    if par.open_faces or par.outflow is not None:
         terms = open_face_terms(par)
         for k in range(1, lat.Q):
             kb = lat.opp[k]
             for face, m in open_face_masks(par, lat.e[k]).items():
+                if face not in terms:
+                    continue          # the outflow face: replaced after streaming
                 fc, gs = terms[face]
                 if kind == "f":
                     val = post[..., k, :, :, :] + fc[kb]
@@ -441,13 +473,71 @@ def stream(post, par, kind=None):
     return out
 
 
+def _plane(par, k_off=0):
+    """Index tuple of the plane of the outflow face (k_off = 1: the plane
+    inside it) over [..., nz, ny, nx]."""
+    a = par.outflow // 2
+    n = par.shape[a]
+    pos = (n - 1 - k_off) if par.outflow % 2 == 1 else k_off
+    idx = [slice(None)] * 3
+    idx[2 - a] = pos
+    return (Ellipsis,) + tuple(idx)
+
+
+def _plane_field(par, plane):
+    """A plane array broadcast to the lattice (its values matter only beyond
+    the outflow face, where neighbour() reads them)."""
+    a = par.outflow // 2
+    shape = list(par.grid)
+    shape[2 - a] = 1
+    return np.broadcast_to(plane.reshape(shape), par.grid)
+
+
+def _outflow_start(f, g, par):
+    """Outflow state at t = 0: the boundary plane's populations, U = 0 and
+    ghosts equal to the boundary plane's C and E_B."""
+    if par.outflow is None:
+        return
+    C = concentrations(g, par)
+    EB = potential.bulk_energy(C, par.co)
+    bn = _plane(par)
+    par.outflow_state = {"f": f[bn].copy(), "g": g[bn].copy(), "U": 0.0,
+                         "ghost_C": C[bn].copy(), "ghost_EB": EB[bn].copy()}
+
+
+def _outflow_apply(f, g, par):
+    """Eq. convect on the streamed populations, then the ghosts."""
+    st = par.outflow_state
+    a = par.outflow // 2
+    sgn = 1.0 if par.outflow % 2 == 1 else -1.0
+    lat = par.lat
+    inner = _plane(par, 1)
+    mom = np.zeros(f[0][inner[1:]].shape)
+    for k in range(1, lat.Q):
+        if lat.e[k, a] != 0:
+            mom = mom + sgn * lat.e[k, a] * f[k][inner[1:]]
+    U = max(float(mom.mean()), 0.0)
+    bn = _plane(par)
+    f[bn] = (st["f"] + U * f[inner]) / (1.0 + U)
+    g[bn] = (st["g"] + U * g[inner]) / (1.0 + U)
+    g[par.implicit] = 0.0
+    st["f"], st["g"], st["U"] = f[bn].copy(), g[bn].copy(), U
+    C = concentrations(g, par)
+    EB = potential.bulk_energy(C, par.co)
+    st["ghost_C"] = (st["ghost_C"] + U * C[bn]) / (1.0 + U)
+    st["ghost_EB"] = (st["ghost_EB"] + U * EB[bn]) / (1.0 + U)
+
+
 def step(f, g, par):
     """One full time step; returns (f, g, mac) with mac the macroscopic fields
     of the input state."""
     fs, gs, mac = collide(f, g, par)
     gn = stream(gs, par, "g")
     gn[par.implicit] = 0.0
-    return stream(fs, par, "f"), gn, mac
+    fn = stream(fs, par, "f")
+    if par.outflow is not None:
+        _outflow_apply(fn, gn, par)
+    return fn, gn, mac
 
 
 def run(f, g, par, steps):
@@ -477,4 +567,5 @@ def initial_state(par, C0, v0=None, P0=None):
     if par.solid is not None:
         f[..., par.solid] = 0.0
         g[..., par.solid] = 0.0
+    _outflow_start(f, g, par)
     return f, g
