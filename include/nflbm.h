@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 9
+#define NFLBM_ABI_VERSION 10
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -207,10 +207,32 @@ int nflbm_set_stream(nflbm_sim *sim, void *hip_stream);
  * wall face and an open face the wall wins, between two open faces the first
  * axis's face.  v_b = C_b = NULL makes the face a wall again.  Needs g as
  * populations (create with NFLBM_FLAG_G_POPULATIONS: ENOTSUP otherwise) and
- * takes neither solid nodes, the concentration-dependent mobility nor batch
- * members (ENOTSUP).  Call before nflbm_set_fields.  EINVAL for a bad face,
+ * takes neither solid nodes, the concentration-dependent mobility, batch
+ * members, the outflow face itself nor, with an outflow face, a face on
+ * another axis (ENOTSUP).  Call before nflbm_set_fields.  EINVAL for a bad face,
  * an unwalled axis, non-finite values or C_b not summing to 1. */
 int nflbm_set_open_face(nflbm_sim *sim, int face, const double *v_b, const double *C_b);
+
+/* Convective outflow (Sec. III C, Eq. convect): turns the wall face `face`
+ * (numbered as for nflbm_set_open_face; its axis walled, at least 3 nodes
+ * long) into an outlet; -1 removes it.  After streaming, every population q
+ * (f and g, every direction) of the boundary plane N becomes
+ * (q(N, t) + U q(N-1, t+1)) / (1 + U), q(N, t) the plane's post-streaming
+ * values of the previous step and U the mean over plane N-1 of the normal
+ * momentum sum_k (e_k . n) f_k after streaming (n the outward normal,
+ * without the F/2 term; U = 0 where the mean points inwards).  Stencil
+ * neighbours beyond the face take ghost values of C_i and E_B convected the
+ * same way, psi(N+1, t+1) = (psi(N+1, t) + U psi(N, t+1)) / (1 + U), from
+ * psi(N, 0).  The plane N values, the ghosts and the previous U are state:
+ * nflbm_set_fields (and a call here after it) starts them from the current
+ * populations, and nflbm_get_state / nflbm_set_state include them (after the
+ * populations).  At most one outflow face.  Needs g as populations (ENOTSUP
+ * otherwise) and takes neither solid nodes, the concentration-dependent
+ * mobility, batch members, nor an open face on another axis (ENOTSUP; an
+ * inlet on the opposite face is fine).  Device memory: one plane of (Q-1) +
+ * (N-1) Q + N values in the compute precision.  EINVAL for a bad face, an
+ * unwalled or too short axis, or an open face there.  Synchronises. */
+int nflbm_set_outflow(nflbm_sim *sim, int face);
 
 /* Solid geometry (Sec. III C): solid[n] (node order x fastest, copied; 1 =
  * solid, 0 = fluid) marks nodes of any shape as solid, in addition to the wall
@@ -222,7 +244,8 @@ int nflbm_set_open_face(nflbm_sim *sim, int face, const double *v_b, const doubl
  * read back as 0, and diagnostics leave them out.  Call before
  * nflbm_set_fields (which fills only the fluid nodes); NULL removes the
  * geometry.  Takes 4 bytes per node of device memory besides the state.
- * EINVAL if every node is solid, ENOTSUP for a batch member.  Synchronises. */
+ * EINVAL if every node is solid, ENOTSUP for a batch member, open faces or an
+ * outflow face.  Synchronises. */
 int nflbm_set_solid(nflbm_sim *sim, const unsigned char *solid);
 
 /* Initialise the state from host fields: C (N n, required), v (3 n or NULL

@@ -102,6 +102,7 @@ def lib():
             "nflbm_set_conc_launch": (I, [P, I, I]),
             "nflbm_set_solid": (I, [P, ctypes.c_void_p]),
             "nflbm_set_open_face": (I, [P, I, DP, DP]),
+            "nflbm_set_outflow": (I, [P, I]),
             "nflbm_get_conc_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_step_timed": (I, [P, LL, DP, DP]),
             "nflbm_get_field": (I, [P, I, DP]),
@@ -359,6 +360,11 @@ class Simulation:
         v = np.ascontiguousarray(v_b, dtype=np.float64).reshape(3)
         c = np.ascontiguousarray(C_b, dtype=np.float64).reshape(self.N)
         _check(lib().nflbm_set_open_face(self._handle(), int(face), _dptr(v), _dptr(c)), self._h)
+
+    def set_outflow(self, face):
+        """Convective outflow on face 0..5 (x-, x+, y-, y+, z-, z+), or None
+        to remove it."""
+        _check(lib().nflbm_set_outflow(self._handle(), -1 if face is None else int(face)), self._h)
 
     def set_conc_launch(self, tx_log2=0, zchunk=0):
         _check(lib().nflbm_set_conc_launch(self._handle(), int(tx_log2), int(zchunk)), self._h)

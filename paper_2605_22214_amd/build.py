@@ -36,6 +36,7 @@ UNITS = [
     ("kernels.hip", "kernels_f16s.o", True, ["-DNFLBM_UNIT_STORE=2"]),
     ("kernels.hip", "kernels_common.o", True, ["-DNFLBM_UNIT_STORE=-1"]),
     ("mobility.hip", "mobility.o", True, []),
+    ("outflow.hip", "outflow.o", True, []),
 ]
 
 

@@ -65,6 +65,14 @@ struct nflbm_sim {
   double face_v[6][3] = {};
   double face_c[6][kMaxComp] = {};   // user order
   double m_geq = 0.0, omega = 0.0;
+  // convective outflow face (-1 none): one device block holding the plane
+  // buffers f [Q-1][P], g [N-1][Q][P] and the ghosts [N][P] (compute
+  // precision), and the per-workgroup momentum sums plus U (FP64)
+  int out_face = -1;
+  size_t out_plane = 0;
+  void* out_buf = nullptr;
+  double* out_red = nullptr;
+  int out_blocks = 0;
   // solid geometry: per-node pull masks (StepArgs::bb) and the caller's mask
   uint32_t* bb = nullptr;
   std::vector<unsigned char> solid_host;
@@ -186,6 +194,10 @@ void free_device(nflbm_sim* s) {
   s->bb = nullptr;
   if (s->faces) (void)hipFree(s->faces);
   s->faces = nullptr;
+  if (s->out_buf) (void)hipFree(s->out_buf);
+  if (s->out_red) (void)hipFree(s->out_red);
+  s->out_buf = nullptr;
+  s->out_red = nullptr;
   if (s->mob) (void)hipFree(s->mob);
   if (s->phi) (void)hipFree(s->phi);
   s->mob = s->phi = nullptr;
@@ -318,6 +330,14 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.params = s->params;
   a.bb = s->bb;
   a.faces = s->faces;
+  a.out_face = s->out_face;
+  if (s->out_face >= 0) {
+    const size_t P = s->out_plane;
+    unsigned char* b = static_cast<unsigned char*>(s->out_buf);
+    a.out_f = b;
+    a.out_g = b + size_t(s->Q - 1) * P * s->ts;
+    a.out_ghost = b + (size_t(s->Q - 1) + size_t(s->NE) * s->Q) * P * s->ts;
+  }
   a.n = static_cast<long long>(s->n);
   a.nx = s->nx;
   a.ny = s->ny;
@@ -381,6 +401,23 @@ void fill_mob(const nflbm_sim& s, const double* tau_g, double m_star, MobParams<
   }
 }
 
+// Convective outflow of the state set `cur` (start: capture its boundary
+// plane instead of convecting).
+int launch_outflow_step(nflbm_sim* s, bool start) {
+  OutflowArgs o{};
+  o.sa = make_args(s, s->cur);
+  o.partial = s->out_red;
+  o.u = s->out_red + s->out_blocks;
+  o.blocks = s->out_blocks;
+  o.start = start ? 1 : 0;
+  HIPCHK(s, launch_outflow(s->lat, s->N, s->store, o, s->stream));
+  return NFLBM_OK;
+}
+
+size_t out_buf_bytes(const nflbm_sim* s) {
+  return (size_t(s->Q - 1) + size_t(s->NE) * s->Q + size_t(s->N)) * s->out_plane * s->ts;
+}
+
 MobArgs mob_args(const nflbm_sim* s, const StepArgs& a) {
   MobArgs m{};
   m.sa = a;
@@ -399,6 +436,7 @@ int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev1) HIPCHK(s, hipEventRecord(ev1, s->stream));
   if (s->c2c2) HIPCHK(s, launch_mob_source(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   s->cur ^= 1;
+  if (s->out_face >= 0) return launch_outflow_step(s, false);
   return NFLBM_OK;
 }
 
@@ -460,7 +498,7 @@ double face_gsum(const nflbm_sim& s, int f, int u, int k) {
 template <class T>
 void fill_faces(const nflbm_sim& s, FaceBC<T>* p) {
   std::memset(p, 0, sizeof(*p));
-  p->open = s.open_mask;
+  p->open = s.open_mask | (s.out_face >= 0 ? 1 << s.out_face : 0);
   for (int f = 0; f < 6; ++f) {
     if (!((s.open_mask >> f) & 1)) continue;
     const double* Cu = s.face_c[f];
@@ -499,6 +537,7 @@ std::vector<std::pair<void*, size_t>> state_segments(nflbm_sim* s) {
     v.emplace_back(s->g0[s->cur], NE * n * s->g0s);
     v.emplace_back(s->gk[s->cur], NE * Qm * n * s->fs);
   }
+  if (s->out_face >= 0) v.emplace_back(s->out_buf, out_buf_bytes(s));
   return v;
 }
 
@@ -725,7 +764,7 @@ void cache_store(const char* path, const std::string& key, const std::vector<int
 std::string sim_key(const nflbm_sim* s) {
   std::ostringstream o;
   o << "sim lat=" << s->lat << " N=" << s->N << " store=" << s->store << " shape=" << s->nx << 'x' << s->ny
-    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " solid=" << (s->bb ? 1 : 0) << " open=" << s->open_mask
+    << 'x' << s->nz << " walls=" << s->wall[0] << s->wall[1] << s->wall[2] << " solid=" << (s->bb ? 1 : 0) << " open=" << s->open_mask << " out=" << s->out_face
     << " flags=" << s->step_flags
     << " dev=" << device_tag();
   return o.str();
@@ -885,6 +924,34 @@ std::vector<std::pair<void**, size_t>> state_arrays(nflbm_sim* s) {
   return v;
 }
 
+// The device table of the open and outflow faces (freed when there is none).
+int upload_faces(nflbm_sim* sim) {
+  if (!sim->open_mask && sim->out_face < 0) {
+    if (sim->faces) (void)hipFree(sim->faces);
+    sim->faces = nullptr;
+    return NFLBM_OK;
+  }
+  const size_t bytes = sim->ts == 8 ? sizeof(FaceBC<double>) : sizeof(FaceBC<float>);
+  if (!sim->faces && hipMalloc(&sim->faces, bytes) != hipSuccess) {
+    sim->faces = nullptr;
+    return fail(sim, NFLBM_ENOMEM, "cannot allocate the open-face table");
+  }
+  hipError_t e;
+  if (sim->ts == 8) {
+    auto* t = new FaceBC<double>();
+    fill_faces(*sim, t);
+    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
+    delete t;
+  } else {
+    auto* t = new FaceBC<float>();
+    fill_faces(*sim, t);
+    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
+    delete t;
+  }
+  if (e != hipSuccess) return hip_fail(sim, e, "set_open_face");
+  return NFLBM_OK;
+}
+
 constexpr size_t kBindAlign = 256;
 size_t align_up(size_t v) { return (v + kBindAlign - 1) / kBindAlign * kBindAlign; }
 
@@ -1016,6 +1083,8 @@ int nflbm_set_open_face(nflbm_sim* sim, int face, const double* v_b, const doubl
   if (sim->gform)
     return fail(sim, NFLBM_ENOTSUP, "open faces need g as populations (NFLBM_FLAG_G_POPULATIONS)");
   if ((v_b == nullptr) != (C_b == nullptr)) return fail(sim, NFLBM_EINVAL, "v_b and C_b go together");
+  if (v_b && sim->out_face >= 0 && (face == sim->out_face || face / 2 != sim->out_face / 2))
+    return fail(sim, NFLBM_ENOTSUP, "with an outflow face, an open face must be the opposite face of its axis");
   if (v_b) {
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(v_b[d])) return fail(sim, NFLBM_EINVAL, "v_b must be finite");
@@ -1031,29 +1100,69 @@ int nflbm_set_open_face(nflbm_sim* sim, int face, const double* v_b, const doubl
   } else {
     sim->open_mask &= ~(1 << face);
   }
-  if (!sim->open_mask) {
-    if (sim->faces) (void)hipFree(sim->faces);
-    sim->faces = nullptr;
-    return NFLBM_OK;
+  return upload_faces(sim);
+}
+
+int nflbm_set_outflow(nflbm_sim* sim, int face) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (face == -1) {
+    if (sim->out_face < 0) return NFLBM_OK;
+    sim->out_face = -1;
+    if (sim->out_buf) (void)hipFree(sim->out_buf);
+    if (sim->out_red) (void)hipFree(sim->out_red);
+    sim->out_buf = nullptr;
+    sim->out_red = nullptr;
+    return upload_faces(sim);
   }
-  const size_t bytes = sim->ts == 8 ? sizeof(FaceBC<double>) : sizeof(FaceBC<float>);
-  if (!sim->faces && hipMalloc(&sim->faces, bytes) != hipSuccess) {
-    sim->faces = nullptr;
-    return fail(sim, NFLBM_ENOMEM, "cannot allocate the open-face table");
+  if (face < 0 || face >= 6 || (sim->lat == NFLBM_D2Q9 && face >= 4))
+    return fail(sim, NFLBM_EINVAL, "face is 0..5 (x-, x+, y-, y+, z-, z+; 0..3 in D2Q9), or -1");
+  const int dims[3] = {sim->nx, sim->ny, sim->nz};
+  if (!sim->wall[face / 2]) return fail(sim, NFLBM_EINVAL, "an outflow face must lie on a walled axis");
+  if (dims[face / 2] < 3) return fail(sim, NFLBM_EINVAL, "the outflow axis needs at least 3 nodes");
+  if ((sim->open_mask >> face) & 1) return fail(sim, NFLBM_EINVAL, "the face is an open face");
+  if (sim->in_batch || sim->bb || sim->c2c2)
+    return fail(sim, NFLBM_ENOTSUP, "an outflow face takes neither batches, solid nodes nor the mobility variant");
+  if (sim->gform)
+    return fail(sim, NFLBM_ENOTSUP, "an outflow face needs g as populations (NFLBM_FLAG_G_POPULATIONS)");
+  for (int f = 0; f < 6; ++f)
+    if (((sim->open_mask >> f) & 1) && f / 2 != face / 2)
+      return fail(sim, NFLBM_ENOTSUP, "an outflow face takes no open face on another axis");
+  if (sim->out_face >= 0 && sim->out_face != face) {
+    const int rc = nflbm_set_outflow(sim, -1);
+    if (rc) return rc;
   }
-  hipError_t e;
-  if (sim->ts == 8) {
-    auto* t = new FaceBC<double>();
-    fill_faces(*sim, t);
-    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
-    delete t;
-  } else {
-    auto* t = new FaceBC<float>();
-    fill_faces(*sim, t);
-    e = hipMemcpy(sim->faces, t, sizeof(*t), hipMemcpyHostToDevice);
-    delete t;
+  const int ax = face / 2;
+  const size_t P = size_t(dims[ax == 0 ? 1 : 0]) * size_t(dims[ax == 2 ? 1 : 2]);
+  if (!sim->out_buf) {
+    sim->out_plane = P;
+    sim->out_face = face;   // sizes the buffer
+    const long long blocks = static_cast<long long>((P + 255) / 256);
+    if (blocks > (1LL << 30)) {
+      sim->out_face = -1;
+      return fail(sim, NFLBM_EINVAL, "outflow plane too large");
+    }
+    sim->out_blocks = static_cast<int>(blocks);
+    if (hipMalloc(&sim->out_buf, out_buf_bytes(sim)) != hipSuccess) {
+      sim->out_buf = nullptr;
+      sim->out_face = -1;
+      return fail(sim, NFLBM_ENOMEM, "cannot allocate the outflow plane buffers");
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&sim->out_red), size_t(sim->out_blocks + 1) * sizeof(double)) !=
+        hipSuccess) {
+      (void)hipFree(sim->out_buf);
+      sim->out_buf = nullptr;
+      sim->out_red = nullptr;
+      sim->out_face = -1;
+      return fail(sim, NFLBM_ENOMEM, "cannot allocate the outflow reduction buffer");
+    }
   }
-  if (e != hipSuccess) return hip_fail(sim, e, "set_open_face");
+  sim->out_face = face;
+  int rc = upload_faces(sim);
+  if (rc) return rc;
+  // start from the current state's boundary plane
+  rc = launch_outflow_step(sim, true);
+  if (rc) return rc;
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
   return NFLBM_OK;
 }
 
@@ -1061,6 +1170,7 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (sim->in_batch) return fail(sim, NFLBM_ENOTSUP, "batch members take no solid geometry");
   if (solid && sim->open_mask) return fail(sim, NFLBM_ENOTSUP, "open faces take no solid nodes");
+  if (solid && sim->out_face >= 0) return fail(sim, NFLBM_ENOTSUP, "an outflow face takes no solid nodes");
   if (!solid) {
     if (sim->bb) (void)hipFree(sim->bb);
     sim->bb = nullptr;
@@ -1117,6 +1227,15 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
     // f is never written in diffusive-only runs: both sets hold the initial f
     e = hipMemcpyAsync(sim->f[1 - sim->cur], sim->f[sim->cur], size_t(sim->Q - 1) * n * sim->fs,
                        hipMemcpyDeviceToDevice, sim->stream);
+  if (e == hipSuccess && sim->out_face >= 0) {
+    // the outflow plane and ghosts start from the new state
+    const int rc = launch_outflow_step(sim, true);
+    if (rc) {
+      (void)hipStreamSynchronize(sim->stream);
+      (void)hipFree(tmp);
+      return rc;
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(sim, e, "set_fields");
@@ -1272,6 +1391,22 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
       return src;
     };
     if (field == NFLBM_FIELD_G_RAW) std::memset(host_out, 0, size_t(N) * sim->Q * n * sizeof(double));
+    // convective outflow: plane N's post-streaming populations are the plane
+    // buffers (f [Q-1][P], then g [N-1][Q][P], compute precision)
+    std::vector<double> outv;
+    int oax = -1, opos = -1;
+    if (sim->out_face >= 0) {
+      const size_t cnt = (size_t(Qm) + size_t(NE) * sim->Q) * sim->out_plane;
+      std::vector<unsigned char> raw(cnt * sim->ts);
+      HIPCHK(sim, hipMemcpyAsync(raw.data(), sim->out_buf, raw.size(), hipMemcpyDeviceToHost, sim->stream));
+      HIPCHK(sim, hipStreamSynchronize(sim->stream));
+      outv.resize(cnt);
+      for (size_t i = 0; i < cnt; ++i)
+        outv[i] = sim->ts == 8 ? reinterpret_cast<const double*>(raw.data())[i]
+                               : static_cast<double>(reinterpret_cast<const float*>(raw.data())[i]);
+      oax = sim->out_face / 2;
+      opos = (sim->out_face & 1) ? dims[oax] - 1 : 0;
+    }
     for (int z = 0; z < sim->nz; ++z)
       for (int y = 0; y < sim->ny; ++y)
         for (int x = 0; x < sim->nx; ++x) {
@@ -1279,6 +1414,21 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
           if (geom && sim->solid_host[q]) {         // no fluid: every population 0
             if (field == NFLBM_FIELD_F_RAW)
               for (int k = 1; k <= Qm; ++k) host_out[size_t(k - 1) * n + q] = 0.0;
+            continue;
+          }
+          const int xyz[3] = {x, y, z};
+          if (oax >= 0 && xyz[oax] == opos) {
+            const size_t P = sim->out_plane;
+            const int t0 = oax == 0 ? 1 : 0, t1 = oax == 2 ? 1 : 2;
+            const size_t p = size_t(xyz[t0]) + size_t(dims[t0]) * size_t(xyz[t1]);
+            if (field == NFLBM_FIELD_F_RAW) {
+              for (int k = 1; k <= Qm; ++k) host_out[size_t(k - 1) * n + q] = outv[size_t(k - 1) * P + p];
+            } else {
+              for (int i = 0; i < NE; ++i)
+                for (int k = 0; k < sim->Q; ++k)
+                  host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] =
+                      outv[(size_t(Qm) + size_t(i) * sim->Q + k) * P + p];
+            }
             continue;
           }
           if (field == NFLBM_FIELD_G_RAW)

@@ -366,6 +366,25 @@ __device__ __forceinline__ int entry_face(const Nbr& b, int k, int open) {
   return wall ? -1 : face;
 }
 
+// Convective outflow plane: the in-plane index p of node (x, y, z) when it
+// lies on the boundary plane of face `face` (inner = 1: on the plane inside
+// it), else -1.  p runs over the two tangential axes, the lower one fastest.
+__device__ __forceinline__ int outflow_plane_index(int face, int inner, int x, int y, int z, const StepArgs& a) {
+  const int ax = face >> 1;
+  const int c[3] = {x, y, z};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  const int pos = (face & 1) ? n[ax] - 1 - inner : inner;
+  if (c[ax] != pos) return -1;
+  const int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+  return c[t0] + n[t0] * c[t1];
+}
+__host__ __device__ __forceinline__ int outflow_plane_size(int face, int nx, int ny, int nz) {
+  const int ax = face >> 1;
+  const int n[3] = {nx, ny, nz};
+  const int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+  return n[t0] * n[t1];
+}
+
 // A solid node holds no fluid: the reconstruction writes C = 0 there and the
 // fields read back as 0; what the update stores there is read by no fluid
 // node (every pull from it is bounced back).

@@ -101,6 +101,13 @@ struct StepArgs {
   // beyond a wall face, bit 0 set at solid nodes themselves.
   const NFLBM_GLOBAL uint32_t* bb;
   const NFLBM_GLOBAL void* faces;     // FaceBC<T> when some face is open, else null
+  // Convective outflow face (-1 none): post-streaming populations of its
+  // boundary plane, f [k-1][p] and g [i][k][p] (all k), and the ghost values
+  // beyond it, C [i][p] and E_B [NE][p], compute precision, p the in-plane index
+  int out_face;
+  NFLBM_GLOBAL void* out_f;
+  NFLBM_GLOBAL void* out_g;
+  NFLBM_GLOBAL void* out_ghost;
   long long n;
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
@@ -161,6 +168,18 @@ struct MobArgs {
   void* phi;
 };
 
+// The convective outflow's per-step work (after the update, on the new
+// state): U from the plane inside the face (partial sums, then U = max(mean,
+// 0) in u[0]), then the convected boundary plane and ghosts.  start: capture
+// the boundary plane and ghosts of the initial state instead.
+struct OutflowArgs {
+  StepArgs sa;
+  double* partial;                    // [blocks]
+  double* u;                          // [1]
+  int blocks;
+  int start;
+};
+
 // Launchers: lat 0 = D2Q9, 1 = D3Q19; nc = N; store = StoreKind.
 hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s);
@@ -183,6 +202,7 @@ size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
 // and the wall faces of a.
 hipError_t launch_build_bb(int lat, const unsigned char* solid, uint32_t* bb, const StepArgs& a,
                            hipStream_t s);
+hipError_t launch_outflow(int lat, int nc, int store, const OutflowArgs& o, hipStream_t s);
 hipError_t launch_mob_potentials(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
 hipError_t launch_mob_source(int lat, int nc, int store, const MobArgs& a, hipStream_t s);
 

@@ -86,31 +86,44 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   T s[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) s[e] = T(0);
-  // open faces: a population entering across one is minus this node's own
-  // opposite one plus g^eq_k + g^eq_kbar of the face (anti-bounce-back)
-  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
-  const int open = (WALLS && FB) ? FB->open : 0;
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    FS v[NE];
-    if (pulled_from_wall<L, WALLS>(nb, k))
-      vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
-    else
-      vld_nt<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
-    const int fc = entry_face<L, WALLS>(nb, k, open);
-    if (fc >= 0) {
-#pragma unroll
-      for (int e = 0; e < NE; ++e) s[e] += FB->gsum[fc][e][k] - S::unpack(v[e]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+  // convective outflow: the boundary plane's post-streaming populations (all
+  // k) are held in the plane buffer, not pulled
+  const int op = (WALLS && a.out_face >= 0) ? outflow_plane_index(a.out_face, 0, x, y, z, a) : -1;
+  if (WALLS && op >= 0) {
+    const uint32_t PL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
+    const T* og = gptr<const T>(a.out_g);
+    for (int e = 0; e < NE; ++e) {
+      T m = T(0);
+      for (int k = 1; k < Q; ++k) m += og[(uint32_t(e) * Q + k) * PL + op];
+      s[e] = og[uint32_t(e) * Q * PL + op] + m;
     }
-  }
-  {
-    G0S r[NE];
-    vld_nt<G0S, NE>(at(g0, node * NE), r);
+  } else {
+    // open faces: a population entering across one is minus this node's own
+    // opposite one plus g^eq_k + g^eq_kbar of the face (anti-bounce-back)
+    const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+    const int open = (WALLS && FB) ? FB->open : 0;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]) + s[e];
+    for (int k = 1; k < Q; ++k) {
+      FS v[NE];
+      if (pulled_from_wall<L, WALLS>(nb, k))
+        vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
+      else
+        vld_nt<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
+      const int fc = entry_face<L, WALLS>(nb, k, open);
+      if (fc >= 0) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) s[e] += FB->gsum[fc][e][k] - S::unpack(v[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) s[e] += S::unpack(v[e]);
+      }
+    }
+    {
+      G0S r[NE];
+      vld_nt<G0S, NE>(at(g0, node * NE), r);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) s[e] = static_cast<T>(r[e]) + s[e];
+    }
   }
   vst<T, NE>(at(gptr<T>(a.conc), node * NE), s);
   T c[NC];
@@ -558,6 +571,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         }
       }
       fill_off[r] = uint32_t(gx) + nx * uint32_t(gy);
+      // beyond an outflow face on x or y: the position's in-plane offset
+      // along the other in-plane axis (z is added per plane)
+      if (WALLS && fill_ok[r] && fill_face[r] >= 0 && fill_face[r] == a.out_face)
+        fill_off[r] = (fill_face[r] >> 1) == 0 ? uint32_t(gy) : uint32_t(gx);
     }
   }
 
@@ -582,6 +599,17 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       const int idx = tid + 256 * r;
       const int face = fill_face[r] >= 0 ? fill_face[r] : plane_face;
       if (WALLS && face >= 0) {
+        if (face == a.out_face) {
+          // the convected ghost values of C and E_B at this position
+          const uint32_t PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
+          const uint32_t p = (face >> 1) == 2 ? fill_off[r]
+                                              : fill_off[r] + uint32_t((face >> 1) == 0 ? a.ny : a.nx) * uint32_t(gz);
+          const T* gh = gptr<const T>(a.out_ghost);
+#pragma unroll
+          for (int e = 0; e < NE; ++e) base[e * PXY + idx] = gh[uint32_t(e) * PL + p];
+          base[NE * PXY + idx] = gh[uint32_t(NE) * PL + p];
+          continue;
+        }
 #pragma unroll
         for (int e = 0; e < NE; ++e) base[e * PXY + idx] = FB->cb[face][e];
         base[NE * PXY + idx] = FB->eb[face];
@@ -599,6 +627,17 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   // post-streaming f of this node, gathered from the upstream neighbours
   T f[Q];
   auto load_f = [&](int z) {
+    if constexpr (WALLS) {
+      // convective outflow: plane N's post-streaming f is in the plane buffer
+      const int op = a.out_face >= 0 ? outflow_plane_index(a.out_face, 0, x, y, z, a) : -1;
+      if (op >= 0) {
+        const uint32_t PL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
+        const T* of = gptr<const T>(a.out_f);
+#pragma unroll
+        for (int k = 1; k < Q; ++k) f[k] = of[uint32_t(k - 1) * PL + op];
+        return;
+      }
+    }
     {
       const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
       const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
@@ -896,6 +935,13 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     Nbr nb;
     if (!GM && (a.flags & kFlagNeedG)) nb = neighbours<L, WALLS>(x, y, z, a);
     const size_t nn = fresh(n);
+    // convective outflow: plane N's post-streaming g is in the plane buffer
+    int gop = -1;
+    uint32_t gPL = 0;
+    if (WALLS && !GM && (a.flags & kFlagNeedG) && a.out_face >= 0) {
+      gop = outflow_plane_index(a.out_face, 0, x, y, z, a);
+      gPL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
+    }
 
     // ---- per direction pair: TRT collision of f with forcing and BGK
     // collision of every evolved g; stores go to this node (pull layout)
@@ -949,6 +995,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           T o1 = S::unpack(ok[i]), o2 = S::unpack(ob[i]);
           if (fk >= 0) o1 = FB->gsum[fk][i][k] - o1;
           if (fb >= 0) o2 = FB->gsum[fb][i][kb] - o2;
+          if (WALLS && gop >= 0) {
+            const T* og = gptr<const T>(a.out_g);
+            o1 = og[(uint32_t(i) * Q + k) * gPL + gop];
+            o2 = og[(uint32_t(i) * Q + kb) * gPL + gop];
+          }
           gk = o1 - (o1 - gk) * P.inv_tau_g[i];
           gb = o2 - (o2 - gb) * P.inv_tau_g[i];
         }

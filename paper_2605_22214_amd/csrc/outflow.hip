@@ -1,0 +1,254 @@
+// Convective outflow (Sec. III C, Eq. convect) for gfx950.
+//
+// On an outflow face every population of the boundary plane (plane N) is
+// replaced after streaming by
+//   q(N, t+1) = (q(N, t) + U q(N-1, t+1)) / (1 + U),
+// q(N, t) the plane's post-streaming values of the previous step and U the
+// mean over plane N-1 of the normal momentum sum_k (e_k . n) f_k after
+// streaming (n the outward normal; U = 0 where that mean points inwards).
+// Stencil neighbours beyond the face read ghost values of C_i and E_B that are
+// convected the same way, psi(N+1, t+1) = (psi(N+1, t) + U psi(N, t+1)) /
+// (1 + U), from psi(N, 0).
+//
+// The state holds post-collision populations (pull streaming), so the
+// post-streaming values of plane N have no place in it: they live in a plane
+// buffer of their own (out_f, out_g, every direction including the rest one),
+// which the reconstruction and the update read at plane-N nodes in place of
+// their pulls, and the update's LDS fill reads the ghost buffer beyond the
+// face.  Per step, after the update (on the state it wrote):
+//   k_outflow_mom    one thread per node of plane N-1: its normal momentum
+//                    after streaming, gathered with the pull rules of the
+//                    update; one FP64 sum per workgroup;
+//   k_outflow_apply  every workgroup sums those partial sums in one fixed
+//                    order (so all of them hold the same U), then one thread
+//                    per plane node blends the pulled plane N-1 populations
+//                    into the plane buffer and convects the ghosts.
+// With start = 1 the apply kernel instead captures plane N of the current
+// state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.h"
+
+namespace nflbm {
+
+namespace {
+
+// Coordinates of in-plane index p on plane `pos` of axis `ax` (the inverse of
+// outflow_plane_index).
+__device__ __forceinline__ void plane_node(int ax, int pos, int p, const StepArgs& a, int& x, int& y, int& z) {
+  const int n[3] = {a.nx, a.ny, a.nz};
+  const int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+  int c[3];
+  c[ax] = pos;
+  c[t0] = p % n[t0];
+  c[t1] = p / n[t0];
+  x = c[0];
+  y = c[1];
+  z = c[2];
+}
+
+__device__ __forceinline__ int plane_pos(int face, int inner, const StepArgs& a) {
+  const int ax = face >> 1;
+  const int n = ax == 0 ? a.nx : (ax == 1 ? a.ny : a.nz);
+  return (face & 1) ? n - 1 - inner : inner;
+}
+
+// Post-streaming f_k (k >= 1) of a node, pulled as the update pulls it:
+// halfway bounce-back at a wall face, plus the velocity correction where the
+// link enters across an open face.
+template <class L, int ST>
+__device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, const Nbr& nb, uint32_t node, int k,
+                                                         const FaceBC<typename StoreT<ST>::T>* FB, int open) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
+  using FS = typename S::FS;
+  const FS* fs = gptr<const FS>(a.f_src);
+  const size_t n = static_cast<size_t>(a.n);
+  if (pulled_from_wall<L, true>(nb, k)) {
+    T v = S::ld(fs + size_t(opposite(k) - 1) * n, node);
+    const int fc = entry_face<L, true>(nb, k, open);
+    if (fc >= 0) v += FB->fcorr[fc][k];
+    return v;
+  }
+  return S::ld(fs + size_t(k - 1) * n, upstream<L>(nb, k));
+}
+
+// Post-streaming g_{e,k} (any k) of an evolved component e, pulled as the
+// reconstruction pulls it (anti-bounce-back across an open face).
+template <class L, int NE, int ST>
+__device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, const Nbr& nb, uint32_t node, int e,
+                                                         int k, const FaceBC<typename StoreT<ST>::T>* FB,
+                                                         int open) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
+  using FS = typename S::FS;
+  using G0S = typename S::G0S;
+  if (k == 0) return static_cast<T>(gptr<const G0S>(a.g0_src)[size_t(node) * NE + e]);
+  const FS* gk = gptr<const FS>(a.gk_src);
+  const size_t n = static_cast<size_t>(a.n);
+  if (pulled_from_wall<L, true>(nb, k)) {
+    const T v = S::unpack(gk[(size_t(opposite(k) - 1) * n + node) * NE + e]);
+    const int fc = entry_face<L, true>(nb, k, open);
+    return fc >= 0 ? FB->gsum[fc][e][k] - v : v;
+  }
+  return S::unpack(gk[(size_t(k - 1) * n + upstream<L>(nb, k)) * NE + e]);
+}
+
+}  // namespace
+
+template <class L, int NC, int ST>
+__global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
+  using T = typename StoreT<ST>::T;
+  const StepArgs& a = o.sa;
+  __shared__ double red[256];
+  const int face = a.out_face, ax = face >> 1;
+  const double sgn = (face & 1) ? 1.0 : -1.0;      // outward normal along ax
+  const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
+  const int p = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  double mom = 0.0;
+  if (p < PL) {
+    int x, y, z;
+    plane_node(ax, plane_pos(face, 1, a), p, a, x, y, z);
+    const Nbr nb = neighbours<L, true>(x, y, z, a);
+    const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
+    const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+    const int open = FB ? FB->open : 0;
+#pragma unroll
+    for (int k = 1; k < L::Q; ++k) {
+      if (L::e[k][ax] == 0) continue;
+      const double v = static_cast<double>(pull_f<L, ST>(a, nb, node, k, FB, open));
+      mom += (L::e[k][ax] > 0) ? v : -v;
+    }
+    mom *= sgn;
+  }
+  red[threadIdx.x] = mom;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) o.partial[blockIdx.x] = red[0];
+}
+
+template <class L, int NC, int ST>
+__global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
+  using T = typename StoreT<ST>::T;
+  constexpr int NE = NC - 1;
+  constexpr int Q = L::Q;
+  const StepArgs& a = o.sa;
+  __shared__ double red[256];
+  const int face = a.out_face, ax = face >> 1;
+  const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
+  const int tid = static_cast<int>(threadIdx.x);
+  // U from the partial sums, in the same order in every workgroup
+  double U = 0.0;
+  if (!o.start) {
+    double s = 0.0;
+    for (int i = tid; i < o.blocks; i += 256) s += o.partial[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    U = red[0] / static_cast<double>(PL);
+    if (!(U > 0.0)) U = 0.0;
+    if (blockIdx.x == 0 && tid == 0) o.u[0] = U;
+  }
+  const int p = static_cast<int>(blockIdx.x) * 256 + tid;
+  if (p >= PL) return;
+  int x, y, z;
+  plane_node(ax, plane_pos(face, o.start ? 0 : 1, a), p, a, x, y, z);
+  const Nbr nb = neighbours<L, true>(x, y, z, a);
+  const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
+  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+  const int open = FB ? FB->open : 0;
+  const T u = static_cast<T>(U);
+  const T den = T(1) + u;
+  T* of = gptr<T>(a.out_f);
+  T* og = gptr<T>(a.out_g);
+  T* gh = gptr<T>(a.out_ghost);
+  const size_t P = static_cast<size_t>(PL);
+  for (int k = 1; k < Q; ++k) {
+    const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
+    T* slot = of + size_t(k - 1) * P + p;
+    *slot = o.start ? q : (*slot + u * q) / den;
+  }
+  // the new plane-N populations of g, and C as the reconstruction sums them
+  // (moving populations first, the rest population last)
+  T c[NC];
+  T rest = T(0);
+  for (int e = 0; e < NE; ++e) {
+    T m = T(0);
+    T r = T(0);
+    for (int k = 0; k < Q; ++k) {
+      const T q = pull_g<L, NE, ST>(a, nb, node, e, k, FB, open);
+      T* slot = og + (size_t(e) * Q + k) * P + p;
+      const T v = o.start ? q : (*slot + u * q) / den;
+      *slot = v;
+      if (k == 0) r = v;
+      else m += v;
+    }
+    c[e] = r + m;
+    rest += c[e];
+  }
+  c[NE] = T(1) - rest;
+  const DevParams<T>& Pp = *gptr<const DevParams<T>>(a.params);
+  const T E = bulk_energy<NC, T>(c, Pp);
+  for (int e = 0; e < NE; ++e) {
+    T* slot = gh + size_t(e) * P + p;
+    *slot = o.start ? c[e] : (*slot + u * c[e]) / den;
+  }
+  T* slot = gh + size_t(NE) * P + p;
+  *slot = o.start ? E : (*slot + u * E) / den;
+}
+
+namespace {
+
+#define NFLBM_OUT_NC_SWITCH(NCV, CALL)    \
+  switch (NCV) {                          \
+    case 2: return CALL(2);               \
+    case 3: return CALL(3);               \
+    case 4: return CALL(4);               \
+    case 5: return CALL(5);               \
+    case 6: return CALL(6);               \
+    case 7: return CALL(7);               \
+    case 8: return CALL(8);               \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <class L, int NC, int ST>
+hipError_t outflow_t(const OutflowArgs& o, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(o.blocks));
+  if (!o.start) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(256), 0, s, o);
+  hipLaunchKernelGGL((k_outflow_apply<L, NC, ST>), grid, dim3(256), 0, s, o);
+  return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t outflow_nc(int nc, const OutflowArgs& o, hipStream_t s) {
+#define CALL_O(K) outflow_t<L, K, ST>(o, s)
+  NFLBM_OUT_NC_SWITCH(nc, CALL_O)
+#undef CALL_O
+}
+
+template <int ST>
+hipError_t outflow_st(int lat, int nc, const OutflowArgs& o, hipStream_t s) {
+  return lat == 0 ? outflow_nc<D2Q9, ST>(nc, o, s) : outflow_nc<D3Q19, ST>(nc, o, s);
+}
+
+}  // namespace
+
+hipError_t launch_outflow(int lat, int nc, int store, const OutflowArgs& o, hipStream_t s) {
+  if (o.sa.out_face < 0 || o.blocks < 1) return hipErrorInvalidValue;
+  switch (store) {
+    case kStoreF64: return outflow_st<kStoreF64>(lat, nc, o, s);
+    case kStoreF32: return outflow_st<kStoreF32>(lat, nc, o, s);
+    case kStoreF16S: return outflow_st<kStoreF16S>(lat, nc, o, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nflbm
