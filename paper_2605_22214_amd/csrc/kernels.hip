@@ -860,16 +860,26 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     // diffusive-only runs (Sec. IV B) do not evolve f: v = 0 and P = 0
     const bool hydro = !(a.flags & kFlagNoHydro);
+    // Over the opposite pairs {k, k+1}: sp = f_k + f_k+1 and dp = f_k - f_k+1
+    // give the moments (sum_k f_k and sum_k e_k f_k) and, below, the even and
+    // odd parts the TRT collision relaxes; f itself is not needed after this.
+    constexpr int NP = Q / 2;
+    T sp[NP], dp[NP];
     T v[3] = {T(0), T(0), T(0)};
     T fsum = T(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) sp[p] = dp[p] = T(0);
     if (hydro) {
       load_f(z);
 #pragma unroll
-      for (int k = 1; k < Q; ++k) {
-        fsum += f[k];
+      for (int p = 0; p < NP; ++p) {
+        const int k = 2 * p + 1;
+        sp[p] = f[k] + f[k + 1];
+        dp[p] = f[k] - f[k + 1];
+        fsum += sp[p];
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? f[k] : -f[k];
+          if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? dp[p] : -dp[p];
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
@@ -926,9 +936,22 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
     const T vF = fma(v[2], F[2], fma(v[1], F[1], v[0] * F[0]));
     const T cP = T(3) * Pn;
-    const T hp = T(0.5) * fma(-T(0.5), wp, T(1));
-    const T hm = T(0.5) * fma(-T(0.5), wm, T(1));
     const T base_s = -T(1.5) * vv;
+    // Per-node factors of the pair collision.  With s = f_k + f_k+1,
+    // d = f_k - f_k+1, e_k.v and e_k.F of the odd member k, the TRT step with
+    // Guo forcing (Eqs. TRT, FTRT, hydroforce) is, in exact arithmetic,
+    //   f*_k = S + D,  f*_k+1 = S - D,
+    //   S = (1 - w+)/2 s + w_k [w+ (3P + 4.5 (e.v)^2 - 1.5 v.v) + (1 - w+/2)(9 (e.v)(e.F) - 3 v.F)]
+    //   D = (1 - w-)/2 d + w_k [3 w- e.v + 3 (1 - w-/2) e.F]
+    // i.e. the even and odd parts relax towards those of f^eq and take those
+    // of F_k, with the equilibrium and force pair terms written out.
+    const T A3 = cP + base_s;
+    const T B3 = -T(3) * vF;
+    const T hp2 = fma(-T(0.5), wp, T(1));
+    const T hm6 = T(3) * fma(-T(0.5), wm, T(1));
+    const T wm3 = T(3) * wm;
+    const T cs = T(0.5) * (T(1) - wp);
+    const T cd = T(0.5) * (T(1) - wm);
     T moved[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) moved[i] = T(0);
@@ -948,25 +971,23 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
       const int kb = k + 1;
+      const int p = k >> 1;
       const T wk = static_cast<T>(L::w[k]);
       const T ev = proj<L>(k, v), eF = proj<L>(k, F);
+      if (hydro) {
+        const T q = fma(T(4.5) * ev, ev, A3);
+        const T fo = fma(T(9) * ev, eF, B3);
+        const T Is = fma(hp2, fo, wp * q);
+        const T Ia = fma(hm6, eF, wm3 * ev);
+        const T Sx = fma(cs, sp[p], wk * Is);
+        const T Dx = fma(cd, dp[p], wk * Ia);
+        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(Sx + Dx));
+        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(Sx - Dx));
+      }
+      if constexpr (GM) continue;
       const T quad = quad_term<L>(ev, base_s);
       const T sk_k = s_pair_member<L>(k, ev, quad);
       const T sk_b = s_pair_member<L>(kb, ev, quad);
-      const T feq_k = fma(wk, cP, sk_k);
-      const T feq_b = fma(wk, cP, sk_b);
-      const T fodd = wk * fma(T(9) * ev, eF, -T(3) * vF);
-      const T Fk = fma(wk * T(3), eF, fodd);
-      const T Fb = fma(-wk * T(3), eF, fodd);
-      const T fp = T(0.5) * (f[k] + f[kb]), fm = T(0.5) * (f[k] - f[kb]);
-      const T ep = T(0.5) * (feq_k + feq_b), em = T(0.5) * (feq_k - feq_b);
-      const T sym = fma(-wp, fp - ep, hp * (Fk + Fb));
-      const T asym = fma(-wm, fm - em, hm * (Fk - Fb));
-      if (hydro) {
-        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(f[k] + sym + asym));
-        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(f[kb] + sym - asym));
-      }
-      if constexpr (GM) continue;
       const T mw = wk * P.m;
       FS qk[NE], qb[NE];
       FS ok[NE], ob[NE];
