@@ -291,7 +291,7 @@ int nflbm_get_coeffs(const nflbm_sim *sim, double *alpha, double *gamma);
 
 /* Raw state checkpoint: nflbm_state_bytes gives the size, get_state copies
  * the device state (storage precision: f_1..f_{Q-1}, then the populations of
- * g or, in the moment form, the node records C, mu~, (v, v.v)) to host_raw,
+ * g or, in the moment form, the node records C, mu~, (v, -3/2 v.v)) to host_raw,
  * set_state restores it bit for bit.  Synchronise. */
 int nflbm_state_bytes(nflbm_sim *sim, size_t *bytes);
 int nflbm_get_state(nflbm_sim *sim, void *host_raw);

@@ -57,7 +57,7 @@ struct nflbm_sim {
   // moment form (the collision's C of the current state, and the next C)
   void* conc[2] = {nullptr, nullptr};
   void* mu = nullptr;    // moment form: mu~ [node][i]
-  void* vel = nullptr;   // moment form: (v, v.v) [node][4]
+  void* vel = nullptr;   // moment form: (v, -3/2 v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
   // open faces: FaceBC<T> on the device, and the host's copy of each face
   void* faces = nullptr;
@@ -524,7 +524,7 @@ int compute_fields(nflbm_sim* s) {
 
 // Device arrays that make up the current state, in checkpoint order:
 // f_1..f_{Q-1}, then the populations g_{i,0}, g_{i,k} (population form) or
-// the node records C, mu~, (v, v.v) (moment form).
+// the node records C, mu~, (v, -3/2 v.v) (moment form).
 std::vector<std::pair<void*, size_t>> state_segments(nflbm_sim* s) {
   const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
   std::vector<std::pair<void*, size_t>> v;
@@ -1569,8 +1569,8 @@ int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   const double Qm = sim->Q - 1, NE = sim->NE;
   double b;
   if (sim->gform) {
-    // f read and written; reconstruction reads C, mu~, (v, v.v) and writes
-    // C, E_B; the update reads C, E_B and writes mu~, (v, v.v)
+    // f read and written; reconstruction reads C, mu~, (v, -3/2 v.v) and
+    // writes C, E_B; the update reads C, E_B and writes mu~, (v, -3/2 v.v)
     b = 2.0 * Qm * sim->fs + (NE + NE + 4 + NE + 1 + NE + 1 + NE + 4) * double(sim->ts);
   } else {
     b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;

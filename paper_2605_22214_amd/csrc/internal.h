@@ -63,7 +63,7 @@ enum StepFlags {
   kFlagNeedG = 1,         // some tau_g != 1: the update reads g
   kFlagPotential = 2,     // potential-form surface tension
   kFlagOmega = 4,         // Omega != 0
-  kFlagMoments = 8,       // moment form of g (tau_g = 1): C, mu~, v, v.v per node
+  kFlagMoments = 8,       // moment form of g (tau_g = 1): C, mu~, v, -3/2 v.v per node
   kFlagNoHydro = 16       // diffusive-only: f not evolved, v = 0
 };
 
@@ -89,7 +89,7 @@ struct StepArgs {
   NFLBM_GLOBAL void* gk_dst;
   NFLBM_GLOBAL void* conc;            // reconstructed C (compute precision)
   // moment form: the node records of the previous step (C the collision
-  // used, mu~ [node][i], and (v, v.v) [node][4]); the populations are unused
+  // used, mu~ [node][i], and (v, -3/2 v.v) [node][4]); the populations are unused
   const NFLBM_GLOBAL void* cprev;
   NFLBM_GLOBAL void* mu;
   NFLBM_GLOBAL void* vel;

@@ -287,7 +287,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       }
     }
   };
-  // C, mu~ and (v, v.v) of the position at rec (a record start, or in the
+  // C, mu~ and (v, -3/2 v.v) of the position at rec (a record start, or in the
   // field-major layout the position's slot in the first field)
   auto read_pos = [&](const T* rec, T (&cs)[NEP], T (&ms)[NEP], T (&v4)[4]) {
     if constexpr (AOS) {
@@ -335,15 +335,17 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       v[0] = v4[0];
       v[1] = v4[1];
       v[2] = v4[2];
-      base_s = -T(1.5) * v4[3];
+      base_s = v4[3];
     }
     // moving populations streamed in along e_k from x - e_k (or this node's
     // own opposite one where x - e_k lies in a wall): sum_k C s_k and
     // sum_k w_k mu~ over the sources, kept apart, so that the incoming
-    // populations sum to sc - m sm
-    T sc[NE], smu[NE];
+    // populations sum to sc - m sm.  s_k / w_k = (e.v)(4.5 e.v +- 3) - 1.5 v.v
+    // (Eqs. feq, geq); with float records it is summed per weight class (axis
+    // and diagonal directions) and weighted once at the end.
+    T sc[NE], sd[NE], smu[NE];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) sc[e] = smu[e] = T(0);
+    for (int e = 0; e < NE; ++e) sc[e] = sd[e] = smu[e] = T(0);
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
@@ -362,14 +364,28 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       read_pos(src, cs, ms, v4);
       const T vs[3] = {v4[0], v4[1], v4[2]};
       const T ev = proj<L>(kp, vs);
-      const T quad = quad_term<L>(ev, -T(1.5) * v4[3]);
-      const T sk = s_pair_member<L>(kd, ev, quad);
+      const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
       const T wk = static_cast<T>(L::w[kp]);
+      if constexpr (!AOS) {
+        // FP64: weighted per direction (the class sums' extra accumulators
+        // cost the double-width kernel more than the multiplies they save)
+        const T sk = wk * u;
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        sc[e] = fma(cs[e], sk, sc[e]);
-        smu[e] = fma(wk, ms[e], smu[e]);
+        for (int e = 0; e < NE; ++e) sc[e] = fma(cs[e], sk, sc[e]);
+      } else if (L::w[kp] == L::w[1]) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) sc[e] = fma(cs[e], u, sc[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) sd[e] = fma(cs[e], u, sd[e]);
       }
+#pragma unroll
+      for (int e = 0; e < NE; ++e) smu[e] = fma(wk, ms[e], smu[e]);
+    }
+    if constexpr (AOS) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+        sc[e] = fma(static_cast<T>(L::w[1]), sc[e], static_cast<T>(L::w[Q - 1]) * sd[e]);
     }
     // rest population of this node (Eq. geq) plus the streamed-in ones, as
     // C plus the net change: the small terms are summed first and meet C in
@@ -450,7 +466,7 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
   vld<T, NE>(gptr<const T>(a.mu) + node * NE, mu);
   vld<T, 4>(gptr<const T>(a.vel) + node * 4, vel);
   const T v[3] = {vel[0], vel[1], vel[2]};
-  const T base_s = -T(1.5) * vel[3];
+  const T base_s = vel[3];
   FS* gk = gptr<FS>(a.gk_dst);
 #pragma unroll
   for (int k = 1; k < Q; k += 2) {
@@ -928,15 +944,15 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     FS* gkdst = gptr<FS>(a.gk_dst);
     G0S* g0dst = gptr<G0S>(a.g0_dst);
     const FS* gksrc = gptr<const FS>(a.gk_src);
+    const T base_s = -T(1.5) * vv;
     if constexpr (GM) {
-      // moment form: the reconstruction re-forms g* from mu~, v and v.v
+      // moment form: the reconstruction re-forms g* from mu~, v and -3/2 v.v
       vst_nt<T, NE>(at(gptr<T>(a.mu), node * NE), mu);
-      const T vel[4] = {v[0], v[1], v[2], vv};
+      const T vel[4] = {v[0], v[1], v[2], base_s};
       vst_nt<T, 4>(at(gptr<T>(a.vel), node * 4), vel);
     }
     const T vF = fma(v[2], F[2], fma(v[1], F[1], v[0] * F[0]));
     const T cP = T(3) * Pn;
-    const T base_s = -T(1.5) * vv;
     // Per-node factors of the pair collision.  With s = f_k + f_k+1,
     // d = f_k - f_k+1, e_k.v and e_k.F of the odd member k, the TRT step with
     // Guo forcing (Eqs. TRT, FTRT, hydroforce) is, in exact arithmetic,
