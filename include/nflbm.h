@@ -331,9 +331,10 @@ int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, doub
 int nflbm_set_launch(nflbm_sim *sim, int tx_log2, int zchunk);
 int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
 /* The same for the reconstruction kernel (zeroth moment of g, Sec. III B),
- * which has a launch shape of its own: in D3Q19 with float records it
- * defaults to 16 x 16 tiles, whose smaller LDS window lets three workgroups
- * share a CU, while the update keeps 64 x 4.  Results do not depend on it. */
+ * which has a launch shape of its own: in D3Q19 with g in the moment form it
+ * marches along z with one plane of node records in LDS and defaults to
+ * z runs that leave about 1024 workgroups, while the update keeps its own.
+ * Results do not depend on it. */
 int nflbm_set_conc_launch(nflbm_sim *sim, int tx_log2, int zchunk);
 int nflbm_get_conc_launch(nflbm_sim *sim, int *tx_log2, int *zchunk);
 

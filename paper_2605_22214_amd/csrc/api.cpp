@@ -279,10 +279,11 @@ int zchunk_for(const nflbm_sim* s, int l, long long target) {
 // Default shapes.  Update: tiles 64 x 4 (16 x 16 when nx <= 16 or when the
 // wider LDS window does not fit), in 3-D a z run per workgroup that leaves
 // about 8192 workgroups (1024 in FP64, where longer runs measured faster).
-// Moment-form reconstruction in 3-D with float records: 16 x 16 tiles and
-// about 4096 workgroups (its LDS window then allows three workgroups per CU);
-// otherwise the update's shape (the population form's pointwise gather reads
-// rows of 64 nodes better than rows of 16).
+// Reconstruction: the update's tile width; in the moment form's 3-D z march a
+// run that leaves about 1024 workgroups (each run re-loads two planes beyond
+// its ends, so long runs pay off as long as the CUs stay busy: 0.255 ms at
+// 256^3 in FP32 against 0.262 ms for 8192 workgroups); otherwise about 4096
+// (1024 in FP64).
 int choose_launch(nflbm_sim* s) {
   s->lds_max = device_lds_max();
   auto fits = [&](int t) {
@@ -294,8 +295,7 @@ int choose_launch(nflbm_sim* s) {
   if (!fits(l)) return -1;
   const bool f64 = s->store == NFLBM_FP64;
   if (!apply_launch(s, l, zchunk_for(s, l, f64 ? 1024 : 8192))) return -1;
-  if (s->lat == NFLBM_D3Q19 && !f64 && s->gform && apply_conc_launch(s, 4, zchunk_for(s, 4, 4096))) return 0;
-  return apply_conc_launch(s, l, zchunk_for(s, l, f64 ? 1024 : 4096)) ? 0 : -1;
+  return apply_conc_launch(s, l, zchunk_for(s, l, (f64 || s->gform) ? 1024 : 4096)) ? 0 : -1;
 }
 
 // The step arguments with the reconstruction's launch shape.

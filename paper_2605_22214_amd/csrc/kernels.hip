@@ -167,9 +167,12 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
 // directly rather than as C minus the node's own outgoing populations: the
 // two forms of g then agree to rounding instead of bit for bit, for a third
 // of this kernel's arithmetic.  Mass is kept to the rounding of C at each
-// node (no systematic drift; see the comment at the final sum).  The per-node records of
-// the tile and a one-node halo sit in LDS (three planes in D3Q19, marched
-// along z like the update).
+// node (no systematic drift; see the comment at the final sum).  The per-node
+// records of the tile and a one-node halo sit in LDS one plane at a time: in
+// D3Q19 a workgroup marches along z and each plane's records are added to
+// the three nodes of every column that they reach (the planes below, at and
+// above it), so that only one plane of records occupies LDS and more
+// workgroups share a CU.
 // LDS record of one position: C in [0, NEP), mu~ in [NEP, 2 NEP), then v and
 // v.v, with NEP = NE rounded up to 4 so every group starts 16-byte aligned and
 // moves with vector reads.  The record is padded to an odd multiple of 16
@@ -207,7 +210,6 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   constexpr int TY = 256 >> TXL;
   constexpr int PX = TX + 2;
   constexpr int PXY = PX * (TY + 2);
-  constexpr int plane_stride = REC * PXY;
   T* sm = reinterpret_cast<T*>(smem_raw);
   const DevParams<T>* P0 = gptr<const DevParams<T>>(Pp);
   const int tid = threadIdx.x;
@@ -250,13 +252,14 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     }
   }
 
-  // Records of plane gz into an LDS slot, one record per position.
-  // Positions inside a wall stay unfilled: a population pulled from a wall is
-  // this node's own, so they are never read.
-  auto load_plane = [&](int slot, int gz) {
-    T* base = sm + slot * plane_stride;
+  // Records of plane gz into the LDS plane, one record per position; false
+  // for a plane beyond a wall face (nothing is loaded).  Positions inside a
+  // wall stay unfilled: a population pulled from a wall is this node's own,
+  // so they are never read.
+  auto load_plane = [&](int gz) -> bool {
+    T* base = sm;
     if (gz < 0 || gz >= a.nz) {
-      if (WALLS && a.wall_z) return;
+      if (WALLS && a.wall_z) return false;
       gz = (gz < 0) ? gz + a.nz : gz - a.nz;
     }
     const uint32_t zoff = uint32_t(gz) * nxy;
@@ -286,6 +289,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
         for (int d = 0; d < 4; ++d) base[(2 * NE + d) * PXY + idx] = vv[d];
       }
     }
+    return true;
   };
   // C, mu~ and (v, -3/2 v.v) of the position at rec (a record start, or in the
   // field-major layout the position's slot in the first field)
@@ -306,101 +310,117 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   };
   constexpr int PSTEP = AOS ? REC : 1;   // distance between positions
 
-  auto process = [&](int z, int s_dn, int s_c, int s_up) {
-    const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
-    const T m = P.m;
-    const int li = (ty + 1) * PX + (tx + 1);
-    const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
-    const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
-    if (solid_node<WALLS>(nb)) {
-      T zero[NE];
+  // Per-target sums of the z march: sc (and, with float records, sd) hold
+  // sum C s_k / w_k of the incoming populations per weight class (axis and
+  // diagonal directions), smu sum w_k mu~ of their sources, c and d0 the
+  // node's own C and its rest-population term C s_0 + (1 - w_0) m mu~.
+  struct Acc {
+    T sc[NE], sd[NE], smu[NE], c[NE], d0[NE];
+    bool solid;
+  };
+  auto zero_acc = [&](Acc& A) {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) zero[e] = T(0);
-      vst<T, NE>(at(gptr<T>(a.conc), node * NE), zero);
+    for (int e = 0; e < NE; ++e) A.sc[e] = A.sd[e] = A.smu[e] = A.c[e] = A.d0[e] = T(0);
+    A.solid = false;
+  };
+  // One incoming population of direction kd whose source record is at src:
+  // s_k / w_k = (e.v)(4.5 e.v +- 3) - 3/2 v.v (Eqs. feq, geq) from the
+  // source's v, formed through the odd member of the pair.
+  auto add_source = [&](Acc& A, const T* src, int kd) {
+    const int kp = (kd & 1) ? kd : kd - 1;
+    T cs[NEP], ms[NEP], v4[4];
+    read_pos(src, cs, ms, v4);
+    const T vs[3] = {v4[0], v4[1], v4[2]};
+    const T ev = proj<L>(kp, vs);
+    const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
+    const T wk = static_cast<T>(L::w[kp]);
+    if constexpr (!AOS) {
+      // FP64: weighted per direction (the class sums' extra accumulators
+      // cost the double-width kernel more than the multiplies they save)
+      const T sk = wk * u;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) A.sc[e] = fma(cs[e], sk, A.sc[e]);
+    } else if (L::w[kp] == L::w[1]) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) A.sc[e] = fma(cs[e], u, A.sc[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) A.sd[e] = fma(cs[e], u, A.sd[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) A.smu[e] = fma(wk, ms[e], A.smu[e]);
+  };
+  const int li = (ty + 1) * PX + (tx + 1);
+  // record of the position x - e (in-plane part of e) in the LDS plane
+  const T* corner = sm + (li - PX - 1) * PSTEP;
+  auto src_at = [&](int ex, int ey) { return corner + ((1 - ey) * PX + (1 - ex)) * PSTEP; };
+
+  // The populations held in plane p reach three targets of this column: the
+  // node of plane p + 1 (directions with e_z = +1), the node of plane p
+  // itself (in-plane directions, its rest population, and every population
+  // bounced back at a wall, which is its own), and the node of plane p - 1
+  // (e_z = -1).  A target is complete once plane t + 1 has been seen.
+  auto plane_step = [&](int p, bool have, Acc& lo, Acc& mid, Acc& hi) {
+    if (D3 && have && p + 1 >= z0 && p + 1 < z1) {
+      const Nbr nb = neighbours<L, WALLS>(x, y, p + 1, a);
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        if (L::e[k][2] == 1 && !pulled_from_wall<L, WALLS>(nb, k)) add_source(hi, src_at(L::e[k][0], L::e[k][1]), k);
+    }
+    if (p >= z0 && p < z1) {
+      const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
+      const Nbr nb = neighbours<L, WALLS>(x, y, p, a);
+      mid.solid = solid_node<WALLS>(nb);
+      const T* own = src_at(0, 0);
+      {
+        T cs[NEP], ms[NEP], v4[4];
+        read_pos(own, cs, ms, v4);
+        const T s0 = static_cast<T>(L::w[0]) * v4[3];
+        const T m0 = moving_weight_sum<L, T>() * P.m;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          mid.c[e] = cs[e];
+          mid.d0[e] = fma(cs[e], s0, m0 * ms[e]);
+        }
+      }
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        if (pulled_from_wall<L, WALLS>(nb, k)) add_source(mid, own, opposite(k));
+        else if (L::e[k][2] == 0) add_source(mid, src_at(L::e[k][0], L::e[k][1]), k);
+      }
+    }
+    if (D3 && have && p - 1 >= z0 && p - 1 < z1) {
+      const Nbr nb = neighbours<L, WALLS>(x, y, p - 1, a);
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        if (L::e[k][2] == -1 && !pulled_from_wall<L, WALLS>(nb, k)) add_source(lo, src_at(L::e[k][0], L::e[k][1]), k);
+    }
+  };
+
+  // C of a complete target: its own C plus the net change (rest population
+  // less C, plus the streamed-in ones), the small terms summed first so that
+  // they meet C in one rounding.  Added to C on its own, C s_0 (never
+  // positive) would be lost below half an ulp at every node and step alike: a
+  // steady mass gain in float storage (1e-5 per step on the 64^2 lens).
+  auto finish = [&](const Acc& A, int z) {
+    const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
+    T sum[NE];
+    if (A.solid) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) sum[e] = T(0);
+      vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
       *at(gptr<T>(a.eb), node) = T(0);
       return;
     }
-    // records of the 3 x 3 neighbourhood are reached from its lowest corner
-    // with non-negative immediate offsets
-    const T* corner_dn = sm + s_dn * plane_stride + (li - PX - 1) * PSTEP;
-    const T* corner_c = sm + s_c * plane_stride + (li - PX - 1) * PSTEP;
-    const T* corner_up = sm + s_up * plane_stride + (li - PX - 1) * PSTEP;
-    auto rec_at = [&](const T* corner, int ex, int ey) { return corner + ((1 + ey) * PX + (1 + ex)) * PSTEP; };
-    const T* own = rec_at(corner_c, 0, 0);
-    T c[NEP], mu[NEP], v[3];
-    T base_s;
-    {
-      T v4[4];
-      read_pos(own, c, mu, v4);
-      v[0] = v4[0];
-      v[1] = v4[1];
-      v[2] = v4[2];
-      base_s = v4[3];
-    }
-    // moving populations streamed in along e_k from x - e_k (or this node's
-    // own opposite one where x - e_k lies in a wall): sum_k C s_k and
-    // sum_k w_k mu~ over the sources, kept apart, so that the incoming
-    // populations sum to sc - m sm.  s_k / w_k = (e.v)(4.5 e.v +- 3) - 1.5 v.v
-    // (Eqs. feq, geq); with float records it is summed per weight class (axis
-    // and diagonal directions) and weighted once at the end.
-    T sc[NE], sd[NE], smu[NE];
-#pragma unroll
-    for (int e = 0; e < NE; ++e) sc[e] = sd[e] = smu[e] = T(0);
-#pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
-      const bool wall = pulled_from_wall<L, WALLS>(nb, k);
-      const T* src;
-      int kd = k;
-      if (wall) {
-        src = own;
-        kd = opposite(k);
-      } else {
-        const T* corner = (ez == 0) ? corner_c : (ez > 0 ? corner_dn : corner_up);
-        src = rec_at(corner, -ex, -ey);
-      }
-      const int kp = (kd & 1) ? kd : kd - 1;
-      T cs[NEP], ms[NEP], v4[4];
-      read_pos(src, cs, ms, v4);
-      const T vs[3] = {v4[0], v4[1], v4[2]};
-      const T ev = proj<L>(kp, vs);
-      const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
-      const T wk = static_cast<T>(L::w[kp]);
-      if constexpr (!AOS) {
-        // FP64: weighted per direction (the class sums' extra accumulators
-        // cost the double-width kernel more than the multiplies they save)
-        const T sk = wk * u;
-#pragma unroll
-        for (int e = 0; e < NE; ++e) sc[e] = fma(cs[e], sk, sc[e]);
-      } else if (L::w[kp] == L::w[1]) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) sc[e] = fma(cs[e], u, sc[e]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) sd[e] = fma(cs[e], u, sd[e]);
-      }
-#pragma unroll
-      for (int e = 0; e < NE; ++e) smu[e] = fma(wk, ms[e], smu[e]);
-    }
-    if constexpr (AOS) {
-#pragma unroll
-      for (int e = 0; e < NE; ++e)
-        sc[e] = fma(static_cast<T>(L::w[1]), sc[e], static_cast<T>(L::w[Q - 1]) * sd[e]);
-    }
-    // rest population of this node (Eq. geq) plus the streamed-in ones, as
-    // C plus the net change: the small terms are summed first and meet C in
-    // one rounding.  Added to C on its own, C s_0 (never positive) would be
-    // lost below half an ulp at every node and step alike: a steady mass gain
-    // in float storage (1e-5 per step on the 64^2 lens).
-    const T s0 = static_cast<T>(L::w[0]) * base_s;
-    const T m0 = moving_weight_sum<L, T>() * m;
-    T sum[NE];
+    const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
     T cn[NC];
     T rest = T(0);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      const T d = fma(c[e], s0, m0 * mu[e]) + fma(-m, smu[e], sc[e]);
-      sum[e] = c[e] + d;
+      T sc = A.sc[e];
+      if constexpr (AOS) sc = fma(static_cast<T>(L::w[1]), A.sc[e], static_cast<T>(L::w[Q - 1]) * A.sd[e]);
+      const T d = A.d0[e] + fma(-P.m, A.smu[e], sc);
+      sum[e] = A.c[e] + d;
       cn[e] = sum[e];
       rest += sum[e];
     }
@@ -409,22 +429,25 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     *at(gptr<T>(a.eb), node) = bulk_energy<NC, T>(cn, P);
   };
 
-  if constexpr (D3) {
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
-    for (int z = z0; z < z1; ++z) {
-      const int r = z - z0;
-      const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
-      asm volatile("" ::: "memory");
-      load_plane(s_up, z + 1);
-      __syncthreads();
-      if (active) process(z, s_dn, s_c, s_up);
-      __syncthreads();
-    }
-  } else {
-    load_plane(0, 0);
+  // One LDS plane: planes z0 - 1 .. z1 pass through it in turn (D2Q9: the
+  // single plane), each read by three targets as above.
+  Acc lo, mid, hi;
+  zero_acc(lo);
+  zero_acc(mid);
+  zero_acc(hi);
+  const int p_first = D3 ? z0 - 1 : 0, p_last = D3 ? z1 : 0;
+  for (int p = p_first; p <= p_last; ++p) {
+    if (p != p_first) __syncthreads();      // every read of the previous plane is done
+    const bool have = load_plane(p);
     __syncthreads();
-    if (active) process(0, 0, 0, 0);
+    if (active) {
+      plane_step(p, have, lo, mid, hi);
+      if (!D3) finish(mid, 0);
+      else if (p - 1 >= z0) finish(lo, p - 1);
+    }
+    lo = mid;
+    mid = hi;
+    zero_acc(hi);
   }
 }
 
@@ -1404,7 +1427,8 @@ template <int ST>
 size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
-  const int npl = lat == 1 ? 3 : 1;
+  const int npl = 1;   // one plane of records (the z march keeps no other)
+  (void)lat;
   size_t rec;
   if (sizeof(TT<ST>) == 4) {
     rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4;
