@@ -15,7 +15,9 @@ anti-bounce-back concentration Dirichlet for g) on the CPU.
   outflow        the convective outflow (Eq. convect) lets a pulse carried by
                  the flow leave with far less reflection than a velocity-
                  Dirichlet outlet, and inlet + outflow keep a uniform plug
-                 flow exactly
+                 flow exactly; mirrored in x (inlet on x+, outflow on x-) a
+                 three-component run gives the mirrored fields, which pins
+                 the outward normal and the planes of the x- face
 """
 import numpy as np
 import pytest
@@ -139,3 +141,29 @@ def test_inlet_outflow_plug_flow_is_a_fixed_point(lat, shape):
     assert np.abs(mac["C"] - C0).max() <= 1e-13
     assert np.abs(mac["v"] - v0).max() <= 1e-14
     assert abs(par.outflow_state["U"] - u[0]) <= 1e-15
+
+
+def test_outflow_mirror_symmetry():
+    """Inlet on x- and outflow on x+, against the same run mirrored in x:
+    C(x) and v_x(x) of the first equal C(nx-1-x) and -v_x(nx-1-x) of the
+    second to rounding (a wrong sign of the outward normal or a wrong plane
+    of the x- face breaks the symmetry at O(1))."""
+    nx, ny, N = 20, 7, 3
+    w = W.noise("D2Q9", (nx, ny, 1), N, amp=0.1, seed=12, sigma=0.006, m=0.05)
+    Cb = np.array([0.6, 0.3, 0.1])
+    u = 3e-3
+    runs = []
+    for inlet, out, sign in ((0, 1, 1.0), (1, 0, -1.0)):
+        C0 = w["C0"] if sign > 0 else w["C0"][..., ::-1].copy()
+        par = S.Params(D2Q9, (nx, ny, 1), w["sigma"], w["tau"], m=w["m"], walls=(True, False, False),
+                       open_faces={inlet: (np.array([sign * u, 0.0, 0.0]), Cb)}, outflow=out)
+        f, g = S.initial_state(par, C0)
+        for _ in range(80):
+            f, g, _ = S.step(f, g, par)
+        mac = S.macroscopic(f, g, par)
+        runs.append((mac["C"], mac["v"], par.outflow_state["U"]))
+    (C1, v1, U1), (C2, v2, U2) = runs
+    assert U1 > 1e-3 and abs(U1 - U2) <= 1e-15
+    assert np.abs(C1 - C2[..., ::-1]).max() <= 1e-13
+    assert np.abs(v1[0] - (-v2[0][..., ::-1])).max() <= 1e-13 * np.abs(v1[0]).max()
+    assert np.abs(v1[1] - v2[1][..., ::-1]).max() <= 1e-13 * np.abs(v1[0]).max()
