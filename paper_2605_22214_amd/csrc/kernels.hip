@@ -520,10 +520,12 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
 // Occupancy target of the update kernel: three waves per SIMD (at most 168
 // VGPRs) where that needs no spilling (float compute, D3Q19 with N <= 5, all
 // D2Q9, except the D3Q19 wall variant that collides stored g populations);
+// two (at most 256) for the periodic FP64 moment form in D3Q19 with N <= 5;
 // otherwise the compiler's own choice.
 template <class L, int NC, int ST, bool WALLS = false, bool GM = true>
 constexpr int update_waves() {
   if (L::DIM == 3 && WALLS && !GM) return 1;
+  if (ST == kStoreF64 && L::DIM == 3 && !WALLS && GM && NC <= 5) return 2;
   return (ST != kStoreF64 && (L::DIM == 2 || NC <= 5)) ? 3 : 1;
 }
 
@@ -861,6 +863,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       }
       mu[i] = val;
     }
+    if constexpr (GM && !FIELDS) {
+      // moment form: mu~ goes to the node record at once instead of being
+      // held through the gather of f
+      const uint32_t nd = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
+      vst_nt<T, NE>(at(gptr<T>(a.mu), nd * NE), mu);
+    }
 
     // ---- surface tension force (Eq. Fsnew, or Eq. ststand) + body force
     T F[3];
@@ -969,8 +977,8 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const FS* gksrc = gptr<const FS>(a.gk_src);
     const T base_s = -T(1.5) * vv;
     if constexpr (GM) {
-      // moment form: the reconstruction re-forms g* from mu~, v and -3/2 v.v
-      vst_nt<T, NE>(at(gptr<T>(a.mu), node * NE), mu);
+      // moment form: the reconstruction re-forms g* from mu~ (stored above),
+      // v and -3/2 v.v
       const T vel[4] = {v[0], v[1], v[2], base_s};
       vst_nt<T, 4>(at(gptr<T>(a.vel), node * 4), vel);
     }
