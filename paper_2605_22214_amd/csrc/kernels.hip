@@ -1086,7 +1086,50 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   };
 
-  if constexpr (D3) {
+  if constexpr (D3 && !WALLS && sizeof(T) == 4) {
+    // Periodic lattices in float: rolling window of three LDS planes, with
+    // the next plane's values fetched into registers while the current plane
+    // is processed and written to LDS at the top of the next iteration, so
+    // that the fill's load latency overlaps the compute.
+    T nxt[2][NE + 1];
+    auto fetch_plane = [&](int gz) {
+      gz = (gz < 0) ? gz + a.nz : (gz >= a.nz ? gz - a.nz : gz);
+      const uint32_t zoff = uint32_t(gz) * nxy;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (!fill_ok[r]) continue;
+        const uint32_t node = fill_off[r] + zoff;
+        T ce[NE];
+        vld<T, NE>(at(conc, node * NE), ce);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) nxt[r][e] = ce[e];
+        nxt[r][NE] = *at(eb, node);
+      }
+    };
+    auto put_plane = [&](int slot) {
+      T* base = sm + slot * plane_stride;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (!fill_ok[r]) continue;
+        const int idx = tid + 256 * r;
+#pragma unroll
+        for (int e = 0; e <= NE; ++e) base[e * PXY + idx] = nxt[r][e];
+      }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    fetch_plane(z0 + 1);
+    for (int z = z0; z < z1; ++z) {
+      const int r = z - z0;
+      const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
+      asm volatile("" ::: "memory");
+      put_plane(s_up);
+      __syncthreads();
+      if (z + 1 < z1) fetch_plane(z + 2);
+      if (active) process(z, s_dn, s_c, s_up);
+      __syncthreads();
+    }
+  } else if constexpr (D3) {
     // rolling window of three LDS planes: z-1, z, z+1
     load_plane(0, z0 - 1);
     load_plane(1, z0);
