@@ -96,8 +96,22 @@ def case_d3_layered_walls():
     return w
 
 
+def case_d3_thin(nz, walls):
+    def mk():
+        w = W.noise("D3Q19", (12, 10, nz), 4, amp=0.15, seed=20 + nz, sigma=0.006, m=0.05)
+        w["walls"] = walls
+        return w
+    return mk
+
+
 @pytest.mark.parametrize("name,mk,steps,implicit,flags", [
     ("lens_ragged", case_lens_ragged, 20, -1, 0),
+    # one and two planes: the z march of the reconstruction wraps onto the
+    # plane it starts from, or meets the walls at both ends at once
+    ("d3_nz1", case_d3_thin(1, (False, False, False)), 8, -1, 0),
+    ("d3_nz2", case_d3_thin(2, (False, False, False)), 8, -1, 0),
+    ("d3_nz2_walls", case_d3_thin(2, (True, False, True)), 8, -1, 0),
+    ("d3_nz3_walls", case_d3_thin(3, (False, True, True)), 8, -1, 0),
     ("walls_trt", case_walls_trt, 30, -1, 0),
     ("omega", case_omega_potential, 25, 0, 0),
     ("potential_force", case_omega_potential, 25, 0, nf.FLAG_POTENTIAL_FORCE),
