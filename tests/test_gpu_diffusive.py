@@ -6,7 +6,7 @@
   numpy-FFT L_i on the same inputs, in 2-D and 3-D.
 * Fig. 3(d): diffusive coarsening of an N = 4, 400^2 mixture with the constant
   alpha and with the concentration-dependent alpha of Appendix C; L(t) of both.
-Measured values go to gpurun_out/coarsening.json.
+Measured values are written to coarsening.json in the results directory.
 """
 import json
 import math

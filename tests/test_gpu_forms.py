@@ -11,8 +11,8 @@ component (exactly 0.0 in both), FP64 agrees to 1e-13 of each field's scale
 for C and g and 1e-10 for the O(1e-6) derived fields (v, P, F, f); FP32 to
 the bounds in test_forms_agree_to_rounding.  With FP16S the population form
 also rounds g to binary16 and the moment form does not, so there the two
-agree to the FP16S tolerance.  Measured differences go to
-gpurun_out/forms.json.
+agree to the FP16S tolerance.  Measured differences are written to
+forms.json in the results directory.
 """
 import json
 import os

@@ -6,7 +6,7 @@
   max |gpu - oracle| / max |oracle|, held to 1e-12 (v, P and F, which are
   O(1e-6) here, to 1e-10 of their scale as in the quaternary run).
 * FP32 and FP16S storage against FP64 on the diffusive-only case; the
-  differences are written to gpurun_out/mobility.json.
+  differences are written to mobility.json in the results directory.
 * Fig. 3(d): diffusive coarsening of the N = 4, 400^2 mixture with the
   constant alpha and with alpha = C_i^2 C_j^2 (m* = 10); L(t) of both.
 """

@@ -16,7 +16,7 @@ closed forms and against FP64.
   ~6e-4 relative to FP64, ten times the FP64 discretisation error.
 * Conservation in float storage: per-component mass and global momentum.
 
-Measured values are written to gpurun_out/physics.json.
+Measured values are written to physics.json in the results directory.
 """
 import json
 import math

@@ -13,7 +13,7 @@
   zero over the lattice only in exact arithmetic (Eq. Fsnew), so the total
   momentum is held to a rounding-sized budget per node and step.
 
-Measured values go to gpurun_out/quaternary.json.
+Measured values are written to quaternary.json in the results directory.
 """
 import json
 import os

@@ -8,7 +8,7 @@ measured as the paper does: circles fitted to the top and bottom of each lens
 fluid's C = 0.5 contour, away from the 3|4 interface.
 They are checked against Eq. neucosine and set beside the paper's measured
 column.  Fluids 5 and 6 must stay exactly 0.0.  A short run at the same size
-is checked against the oracle.  Measured values go to gpurun_out/table1.json.
+is checked against the oracle.  Measured values are written to table1.json in the results directory.
 """
 import json
 import os
