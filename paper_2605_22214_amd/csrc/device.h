@@ -37,25 +37,38 @@ __host__ __device__ constexpr int opposite(int k) { return (k & 1) ? k + 1 : k -
 
 // ----------------------------------------------------------- storage types
 template <int ST> struct StoreT;
+// ld / pack / unpack convert between a stored moving population and its
+// value; ld_raw / pack_raw move the stored number itself, which is the value
+// times `scale` (a power of two, so arithmetic on raw numbers scaled by it
+// rounds exactly as on the values).
 template <> struct StoreT<kStoreF64> {
   using T = double; using FS = double; using G0S = double;
+  static constexpr double scale = 1.0;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ FS pack(T v) { return v; }
   static __device__ __forceinline__ T unpack(FS v) { return v; }
+  static __device__ __forceinline__ T ld_raw(const FS* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ FS pack_raw(T v) { return v; }
 };
 template <> struct StoreT<kStoreF32> {
   using T = float; using FS = float; using G0S = float;
+  static constexpr float scale = 1.0f;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ FS pack(T v) { return v; }
   static __device__ __forceinline__ T unpack(FS v) { return v; }
+  static __device__ __forceinline__ T ld_raw(const FS* p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ FS pack_raw(T v) { return v; }
 };
 template <> struct StoreT<kStoreF16S> {
   using T = float; using FS = _Float16; using G0S = float;
+  static constexpr float scale = kHalfScale;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) {
     return static_cast<float>(p[i]) * (1.0f / kHalfScale);
   }
   static __device__ __forceinline__ FS pack(T v) { return static_cast<_Float16>(v * kHalfScale); }
   static __device__ __forceinline__ T unpack(FS v) { return static_cast<float>(v) * (1.0f / kHalfScale); }
+  static __device__ __forceinline__ T ld_raw(const FS* p, size_t i) { return static_cast<float>(p[i]); }
+  static __device__ __forceinline__ FS pack_raw(T v) { return static_cast<_Float16>(v); }
 };
 
 // ------------------------------------------------- per-node vector access

@@ -665,8 +665,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   };
 
-  // post-streaming f of this node, gathered from the upstream neighbours
+  // post-streaming f of this node, gathered from the upstream neighbours, as
+  // raw stored numbers (the value times S::scale): the moments unscale once,
+  // and the collision forms the raw numbers it stores directly
   T f[Q];
+  constexpr T FSC = static_cast<T>(S::scale);
+  constexpr T FINV = T(1) / FSC;
   auto load_f = [&](int z) {
     if constexpr (WALLS) {
       // convective outflow: plane N's post-streaming f is in the plane buffer
@@ -675,7 +679,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         const uint32_t PL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
         const T* of = gptr<const T>(a.out_f);
 #pragma unroll
-        for (int k = 1; k < Q; ++k) f[k] = of[uint32_t(k - 1) * PL + op];
+        for (int k = 1; k < Q; ++k) f[k] = of[uint32_t(k - 1) * PL + op] * FSC;
         return;
       }
     }
@@ -686,12 +690,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         if (pulled_from_wall<L, WALLS>(nb, k)) {
-          f[k] = S::ld(at(fsrc + size_t(opposite(k) - 1) * nn, node), 0);
+          f[k] = S::ld_raw(at(fsrc + size_t(opposite(k) - 1) * nn, node), 0);
           // open face: velocity Dirichlet, bounce-back plus 2 w_k (e_k . v_b) / c_s^2
           const int fc = entry_face<L, WALLS>(nb, k, open);
-          if (fc >= 0) f[k] += FB->fcorr[fc][k];
+          if (fc >= 0) f[k] += FB->fcorr[fc][k] * FSC;
         } else {
-          f[k] = S::ld(at(fsrc + size_t(k - 1) * nn, upstream<L>(nb, k)), 0);
+          f[k] = S::ld_raw(at(fsrc + size_t(k - 1) * nn, upstream<L>(nb, k)), 0);
         }
       }
     }
@@ -928,8 +932,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         for (int d = 0; d < 3; ++d)
           if (L::e[k][d] != 0) v[d] += (L::e[k][d] > 0) ? dp[p] : -dp[p];
       }
+      fsum *= FINV;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d]);
+      for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], v[d] * FINV);
     }
     const T vv = fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0]));
     const T s0 = static_cast<T>(L::w[0]) * (-T(1.5) * vv);
@@ -1026,10 +1031,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         const T fo = fma(T(9) * ev, eF, B3);
         const T Is = fma(hp2, fo, wp * q);
         const T Ia = fma(hm6, eF, wm3 * ev);
-        const T Sx = fma(cs, sp[p], wk * Is);
-        const T Dx = fma(cd, dp[p], wk * Ia);
-        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack(Sx + Dx));
-        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack(Sx - Dx));
+        // sp, dp are raw: S and D come out raw too, with w_k scaled
+        const T Sx = fma(cs, sp[p], (wk * FSC) * Is);
+        const T Dx = fma(cd, dp[p], (wk * FSC) * Ia);
+        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack_raw(Sx + Dx));
+        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack_raw(Sx - Dx));
       }
       if constexpr (GM) continue;
       const T quad = quad_term<L>(ev, base_s);
