@@ -310,9 +310,10 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   };
   constexpr int PSTEP = AOS ? REC : 1;   // distance between positions
 
-  // Per-target sums of the z march: sc (and, with float records, sd) hold
-  // sum C s_k / w_k of the incoming populations per weight class (axis and
-  // diagonal directions), smu sum w_k mu~ of their sources, c and d0 the
+  // Per-target sums of the z march: with float records sc and sd hold
+  // sum C s_k / w_k of the incoming populations over the axis and the
+  // diagonal directions (weighted once at the end), in FP64 sc holds
+  // sum C s_k itself; smu holds sum w_k mu~ of their sources, c and d0 the
   // node's own C and its rest-population term C s_0 + (1 - w_0) m mu~.
   struct Acc {
     T sc[NE], sd[NE], smu[NE], c[NE], d0[NE];
