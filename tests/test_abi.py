@@ -203,3 +203,15 @@ def test_single_hip_runtime_in_process(L):
                 mapped.add(path)
     assert len([p for p in mapped if "libamdhip64" in p]) == 1, mapped
     assert len([p for p in mapped if "libhsa-runtime64" in p]) == 1, mapped
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    (status 2) before touching a device."""
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([_sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr and res.stdout == ""
