@@ -49,7 +49,7 @@ enum {
   NFLBM_ENOMEM = -4,    /* device or host allocation failed                 */
   NFLBM_EDEVICE = -5,   /* a HIP runtime call failed                        */
   NFLBM_ENUMERIC = -6,  /* a NaN or Inf was found in the state              */
-  NFLBM_ENOTSUP = -7    /* combination not supported by this build          */
+  NFLBM_ENOTSUP = -7    /* combination the library does not support         */
 };
 
 /* Readback fields for nflbm_get_field (sizes in doubles, n = nx ny nz):
