@@ -6,8 +6,8 @@ concentration Dirichlet for g) through the C ABI (nflbm_set_open_face).
   walls, tau_g != 1, and D3Q19 with inlet, outlet and a moving lid (links that
   cross two faces at the edges).  Metric per field as in the parity tests:
   C and g to 1e-12 of their scale, the O(1e-6) v, P, F and f to 1e-10.
-* FP32: the Couette profile u_x = U (y + 1/2) / n_y, exact for the scheme,
-  within float storage error.
+* FP32 and FP16S: the Couette profile u_x = U (y + 1/2) / n_y, exact for the
+  scheme, within storage error.
 * Argument errors: moment form, an unwalled axis, C_b not summing to 1.
 """
 import json
@@ -121,16 +121,22 @@ def test_fp64_matches_oracle_with_open_faces(name):
         assert errs[k] <= 1e-10, (k, errs)
 
 
-def test_fp32_couette_profile():
+@pytest.mark.parametrize("prec,tol", [(nf.FP32, 1e-4), (nf.FP16S, 2e-2)])
+def test_reduced_precision_couette_profile(prec, tol):
+    """The exact Couette profile in FP32 and FP16S (binary16 f: the face's
+    velocity correction must take on the stored numbers' scale).  FP16S
+    measured 6.4e-3 of U (binary16 rounding acting as a spurious force over
+    the viscous time of the cell); without the scale the wall would not drag
+    the fluid at all."""
     w, faces = couette(nx=8, ny=12, U=1e-3)
-    with gpu_sim(w, faces, nf.FP32) as sim:
+    with gpu_sim(w, faces, prec) as sim:
         sim.step(4000)
         u = sim.get_field("V")[0, 0, :, 0]
     y = np.arange(12) + 0.5
     exact = 1e-3 * y / 12
     err = float(np.abs(u - exact).max() / 1e-3)
-    RESULTS["fp32_couette_rel_err"] = err
-    assert err < 1e-4
+    RESULTS[{nf.FP32: "fp32_couette_rel_err", nf.FP16S: "fp16s_couette_rel_err"}[prec]] = err
+    assert err < tol
 
 
 def test_open_face_argument_errors():

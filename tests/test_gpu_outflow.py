@@ -12,7 +12,8 @@
 * The outflow state travels with nflbm_get_state / nflbm_set_state, and
   starting it in nflbm_set_outflow after nflbm_set_fields or in
   nflbm_set_fields gives the same bits.
-* FP32 against the FP64 oracle on the pulse run, within float storage error.
+* FP32 and FP16S against the FP64 oracle on the pulse run, within their
+  storage error.
 * Argument errors: moment form, an unwalled or too short axis, the face
   already open, an open face on another axis, solid nodes.
 """
@@ -163,17 +164,23 @@ def test_outflow_state_round_trip_and_start():
     assert np.array_equal(a, c)
 
 
-def test_fp32_pulse_against_oracle():
+@pytest.mark.parametrize("prec,tv,tc", [(nf.FP32, 1e-4, 1e-5), (nf.FP16S, 1e-2, 2e-4)])
+def test_reduced_precision_pulse_against_oracle(prec, tv, tc):
+    """FP32 and FP16S (binary16 f and g, whose stored numbers carry a
+    power-of-two scale that the plane buffer's values must take on) against
+    the FP64 oracle.  The FP16S bounds are binary16 storage error: measured
+    2.7e-3 of max |v| and 4e-5 on C after 120 steps (a scale slip would be
+    off by orders of magnitude)."""
     w, faces, out, v0, steps = case("pulse")
     f, g, par = oracle_run(w, faces, out, v0, steps)
     mac = S.macroscopic(f, g, par)
-    with gpu_sim(w, faces, out, v0, nf.FP32) as sim:
+    with gpu_sim(w, faces, out, v0, prec) as sim:
         sim.step(steps)
         v = sim.get_field("V")
         C = sim.get_field("C")
     errs = {"V": rel(v, mac["v"]), "C": float(np.abs(C - mac["C"]).max())}
-    RESULTS["fp32_pulse"] = errs
-    assert errs["V"] < 1e-4 and errs["C"] < 1e-5, errs
+    RESULTS[{nf.FP32: "fp32_pulse", nf.FP16S: "fp16s_pulse"}[prec]] = errs
+    assert errs["V"] < tv and errs["C"] < tc, errs
 
 
 def test_outflow_argument_errors():
