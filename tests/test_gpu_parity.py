@@ -112,6 +112,10 @@ def case_d3_thin(nz, walls):
     ("d3_nz2", case_d3_thin(2, (False, False, False)), 8, -1, 0),
     ("d3_nz2_walls", case_d3_thin(2, (True, False, True)), 8, -1, 0),
     ("d3_nz3_walls", case_d3_thin(3, (False, True, True)), 8, -1, 0),
+    # the largest N: seven evolved components in every per-node array
+    ("d3_n8", lambda: W.noise("D3Q19", (13, 9, 11), 8, amp=0.05, seed=31, sigma=0.006, m=0.05), 8, -1, 0),
+    ("d2_n8_walls", lambda: dict(W.noise("D2Q9", (33, 21, 1), 8, amp=0.05, seed=32, sigma=0.006, m=0.05),
+                                 walls=(True, False, False)), 10, 3, 0),
     ("walls_trt", case_walls_trt, 30, -1, 0),
     ("omega", case_omega_potential, 25, 0, 0),
     ("potential_force", case_omega_potential, 25, 0, nf.FLAG_POTENTIAL_FORCE),
