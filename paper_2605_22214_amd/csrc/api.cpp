@@ -272,7 +272,13 @@ int zchunk_for(const nflbm_sim* s, int l, long long target) {
   if (chunks < 1) chunks = 1;
   if (chunks > s->nz) chunks = s->nz;
   int zc = static_cast<int>((s->nz + chunks - 1) / chunks);
-  if (zc < 4) zc = s->nz < 4 ? s->nz : 4;
+  if (zc < 4) {
+    // runs shorter than 4 planes re-load more halo planes; they are taken
+    // only where 4-plane runs would leave too few workgroups to fill the
+    // chip (a 16 x 16 x 192 channel: 48 workgroups of 4 planes, 192 of one)
+    const int zc4 = s->nz < 4 ? s->nz : 4;
+    if (xy * ((s->nz + zc4 - 1) / zc4) >= 1024) zc = zc4;
+  }
   return zc;
 }
 
