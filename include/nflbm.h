@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 #define NFLBM_MAX_COMP 8
-#define NFLBM_ABI_VERSION 10
+#define NFLBM_ABI_VERSION 11
 
 /* Velocity sets.  D2Q9 as printed in Sec. III; D3Q19 the textbook set
  * (rest 1/3, faces 1/18, edges 1/36) the paper refers to for 3-D. */
@@ -85,8 +85,10 @@ enum {
   NFLBM_FLAG_NO_HYDRO = 8,        /* diffusive-only (Sec. IV B): the LBE of f is
                                      not evolved, v = 0 and P = 0 everywhere;
                                      only the Cahn-Hilliard LBEs of g step     */
-  NFLBM_FLAG_C2C2_MOBILITY = 16   /* concentration-dependent mobility of
+  NFLBM_FLAG_C2C2_MOBILITY = 16,  /* concentration-dependent mobility of
                                      Appendix C, see below                     */
+  NFLBM_FLAG_F_POPULATIONS = 32   /* keep the populations of f even when the
+                                     record form applies ("Storage of f")      */
 };
 
 /* Concentration-dependent mobility (Appendix C, Eqs. mobilconc and
@@ -113,6 +115,24 @@ enum {
  * minus its stored moving populations).  Some tau_g != 1, or
  * NFLBM_FLAG_G_POPULATIONS, keeps the 19 (N - 1) populations per node.
  * nflbm_storage_form tells which form a simulation uses. */
+
+/* Storage of f.  When every node relaxes f with omega+ = omega- = 1 (every
+ * tau_i = 1 with BGK, or TRT with Lambda^TRT = 1/4) and g is in its moment
+ * form, a post-collision population of f is fixed by the node's pressure,
+ * velocity and force (Eqs. TRT, FTRT, hydroforce with omega = 1):
+ *   f*_k = w_k [3 P + 3 e_k.v + 9/2 (e_k.v)^2 - 3/2 v.v
+ *               + 3/2 e_k.F + 9/2 (e_k.v)(e_k.F) - 3/2 v.F],
+ * so the library keeps (3 P - 3/2 v.F, F) per node beside the (v, -3/2 v.v)
+ * of the moment form of g, instead of the Q - 1 populations;
+ * the reconstruction forms the moments sum_k f_k and sum_k e_k f_k of the
+ * streamed populations from the neighbours' records (halfway bounce-back at
+ * walls and solid nodes) and the update reads those.  This is the same
+ * arithmetic as the population form up to rounding; FP64 and FP32 storage
+ * only (FP16S keeps its binary16 populations), no open faces or outflow
+ * (they need g as populations anyway).  NFLBM_FLAG_F_POPULATIONS keeps the
+ * populations; nflbm_f_storage_form tells which form a simulation uses.  The
+ * first step after nflbm_set_fields takes each node's f as the equilibrium
+ * f^eq(P0, v0) of its own initial record, as the population form stores it. */
 
 /*
  * Problem statement (Sec. II-III).
@@ -184,7 +204,11 @@ typedef struct nflbm_diag {
 /* Validate cfg, compute the coefficient tables (alpha, gamma: Eqs. alpha1,
  * alpha2; Lambda: Eq. ngamma; Theta: the system after Eq. P) on the host in
  * FP64, allocate the device state on the current HIP device and set the
- * state to rest with C_1 = 1.  *out receives the handle. */
+ * state to rest with C_1 = 1.  *out receives the handle.  Per-node arrays
+ * are addressed with 32-bit byte offsets: ENOTSUP when the widest of them
+ * (N - 1 values a node, 4 for the moment form's velocity record, N for the
+ * concentration-dependent mobility's potentials) reaches 2^32 bytes, e.g.
+ * above 2^28 nodes for N <= 5 in FP32 with the moment form. */
 int nflbm_create(const nflbm_config *cfg, nflbm_sim **out);
 
 /* Release all device and host memory of sim (NULL is ignored). */
@@ -250,20 +274,52 @@ int nflbm_set_solid(nflbm_sim *sim, const unsigned char *solid);
 
 /* Initialise the state from host fields: C (N n, required), v (3 n or NULL
  * for rest), P (n or NULL for 0).  f = f^eq(P, v) for k >= 1; g_{i,0} = C_i,
- * g_{i,k>=1} = 0 for the evolved components.  Synchronises. */
+ * g_{i,k>=1} = 0 for the evolved components.  Reference pressure: with the
+ * pressure form of the equilibrium (Eq. feq) a uniform pressure P_ref adds
+ * 3 w_k P_ref to every f_k, and no step of the method (streaming, both
+ * collisions, bounce-back, open faces, outflow) changes that shift.  The
+ * state therefore holds the populations of P - P_ref, P_ref the mean of the
+ * given P over the fluid nodes (0 without P), which keeps them small in
+ * binary16 storage; nflbm_get_field adds P_ref back to P and to F_RAW.  A
+ * checkpoint (nflbm_get_state) holds the shifted populations: restore it
+ * into a simulation initialised with the same mean P.  Synchronises. */
 int nflbm_set_fields(nflbm_sim *sim, const double *C, const double *v, const double *P);
 
 /* Advance nsteps time steps (Sec. III: collide, stream, boundaries), each one
  * a reconstruction of C and one fused update launch on the sim's stream.
- * Asynchronous: returns after queueing the work. */
+ * Asynchronous: returns after queueing the work, without waiting for it.
+ * NaN detection: on every K-th step (nflbm_set_nan_check, default K = 16)
+ * the update raises a device flag where a node's C, mu~, v or P is not
+ * finite, and nflbm_step queues a copy of that flag to host memory behind
+ * its steps.  A call returns ENUMERIC, before queueing anything, once such a
+ * copy from an earlier call has arrived with the flag raised, so a NaN is
+ * reported by the first nflbm_step after its copy completed; the
+ * synchronising calls (nflbm_synchronize, nflbm_step_timed) report it at
+ * once.  ENUMERIC stays until nflbm_set_fields or nflbm_set_state replaces
+ * the state.  EINVAL for nsteps < 0. */
 int nflbm_step(nflbm_sim *sim, long long nsteps);
+
+/* Wait for sim's queued work; ENUMERIC if a checked step has seen a NaN or
+ * Inf since the state was last set (see nflbm_step), else OK. */
+int nflbm_synchronize(nflbm_sim *sim);
+
+/* Check for non-finite values on every `every`-th step (0 turns the check
+ * off; default 16).  The check costs a few operations per node on the
+ * steps that take it.  EINVAL for every < 0. */
+int nflbm_set_nan_check(nflbm_sim *sim, long long every);
 
 /* Advance nsteps and return, through *ms, the elapsed device time measured
  * with HIP events recorded on the sim's stream around the launches; if
  * ms_update is not NULL also time each update launch separately (events
  * around every update kernel) and return their summed duration.
- * Synchronises. */
+ * Synchronises; ENUMERIC as nflbm_synchronize. */
 int nflbm_step_timed(nflbm_sim *sim, long long nsteps, double *ms, double *ms_update);
+
+/* Advance nsteps and return the summed durations of the reconstruction
+ * launches (*ms_conc) and of the update launches (*ms_update), each measured
+ * with HIP events recorded on the sim's stream right around the launch.
+ * Synchronises; ENUMERIC as nflbm_synchronize. */
+int nflbm_step_timed_kernels(nflbm_sim *sim, long long nsteps, double *ms_conc, double *ms_update);
 
 /* Copy one field (NFLBM_FIELD_*) of the current state to host_out (sizes in
  * the field list above).  Synchronises. */
@@ -298,8 +354,14 @@ int nflbm_get_state(nflbm_sim *sim, void *host_raw);
 int nflbm_set_state(nflbm_sim *sim, const void *host_raw);
 
 /* FP64 global diagnostics (see nflbm_diag); vcm_component selects C_c for the
- * centre-of-mass velocity (Sec. V A).  ENUMERIC if a NaN/Inf was found.
- * Synchronises. */
+ * centre-of-mass velocity (Sec. V A).  The node fields of the current state
+ * (those nflbm_get_field returns) are summed in FP64 where they are formed:
+ * each workgroup of the update's reduce mode keeps per-thread sums and
+ * reduces them with wavefront shuffles, then one workgroup adds the
+ * workgroups' records in a fixed order (results do not depend on timing).
+ * A buffer of 2048 (3N + 9) doubles for those records is allocated on the
+ * first call and kept.  ENUMERIC (with out filled and out->nan = 1) if a NaN
+ * or Inf was found.  Synchronises. */
 int nflbm_diagnostics(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
 
 /* Characteristic domain size L_i of every component (Eq. L, Sec. IV B) of
@@ -340,6 +402,9 @@ int nflbm_get_conc_launch(nflbm_sim *sim, int *tx_log2, int *zchunk);
 
 /* 1 if sim keeps g in the moment form, 0 for populations, negative on error. */
 int nflbm_storage_form(const nflbm_sim *sim);
+/* Storage form of f (see "Storage of f"): 0 populations, 1 node records;
+ * EINVAL for NULL. */
+int nflbm_f_storage_form(const nflbm_sim *sim);
 
 /* Bytes moved per lattice-node update by the kernels of one step together,
  * counting every stored population once read and once written plus the
@@ -402,7 +467,12 @@ int nflbm_batch_set_stream(nflbm_batch *b, void *hip_stream);
 int nflbm_batch_set_fields(nflbm_batch *b, int idx, const double *C, const double *v, const double *P);
 int nflbm_batch_get_field(nflbm_batch *b, int idx, int field, double *host_out);
 /* Advance every member nsteps time steps in mode NFLBM_BATCH_*.  The result
- * is bit-for-bit that of stepping each member alone.  Asynchronous. */
+ * is bit-for-bit that of stepping each member alone.  Asynchronous.  In the
+ * launch and graph modes every step checks for non-finite values (a captured
+ * graph replays one argument table), with one flag for the whole batch
+ * reported as nflbm_step reports its own: ENUMERIC from the first call after
+ * the flag's copy arrived raised, until nflbm_batch_set_fields; the per
+ * simulation mode uses each member's own check. */
 int nflbm_batch_step(nflbm_batch *b, long long nsteps, int mode);
 /* As nflbm_batch_step, returning in *ms the device time between HIP events
  * recorded on the batch stream before and after.  Synchronises. */

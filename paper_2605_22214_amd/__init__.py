@@ -25,6 +25,7 @@ FLAG_ALLOW_UNSTABLE = 2
 FLAG_G_POPULATIONS = 4
 FLAG_NO_HYDRO = 8
 FLAG_C2C2_MOBILITY = 16
+FLAG_F_POPULATIONS = 32
 FIELDS = {"C": 0, "V": 1, "P": 2, "F": 3, "MU": 4, "F_RAW": 5, "G_RAW": 6}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 BATCH_MODES = {"launch": 0, "graph": 1, "per_sim": 2}
@@ -99,12 +100,15 @@ def lib():
             "nflbm_set_stream": (I, [P, P]),
             "nflbm_set_fields": (I, [P, DP, DP, DP]),
             "nflbm_step": (I, [P, LL]),
+            "nflbm_synchronize": (I, [P]),
+            "nflbm_set_nan_check": (I, [P, LL]),
             "nflbm_set_conc_launch": (I, [P, I, I]),
             "nflbm_set_solid": (I, [P, ctypes.c_void_p]),
             "nflbm_set_open_face": (I, [P, I, DP, DP]),
             "nflbm_set_outflow": (I, [P, I]),
             "nflbm_get_conc_launch": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "nflbm_step_timed": (I, [P, LL, DP, DP]),
+            "nflbm_step_timed_kernels": (I, [P, LL, DP, DP]),
             "nflbm_get_field": (I, [P, I, DP]),
             "nflbm_state_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
             "nflbm_get_state": (I, [P, P]),
@@ -118,6 +122,7 @@ def lib():
             "nflbm_abi_version": (I, []),
             "nflbm_autotune": (I, [P, ctypes.c_char_p]),
             "nflbm_storage_form": (I, [P]),
+            "nflbm_f_storage_form": (I, [P]),
             "nflbm_device_bytes": (I, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
             "nflbm_bind_state": (I, [P, P, ctypes.c_size_t]),
             "nflbm_get_coeffs": (I, [P, DP, DP]),
@@ -283,6 +288,15 @@ class Simulation:
     def step(self, nsteps=1):
         _check(lib().nflbm_step(self._handle(), int(nsteps)), self._h)
 
+    def synchronize(self):
+        """Wait for the queued steps; raises NflbmError (ENUMERIC) if a
+        checked step saw a NaN or Inf."""
+        _check(lib().nflbm_synchronize(self._handle()), self._h)
+
+    def set_nan_check(self, every):
+        """Check for non-finite values on every `every`-th step (0: never)."""
+        _check(lib().nflbm_set_nan_check(self._handle(), int(every)), self._h)
+
     def step_timed(self, nsteps, per_update=False):
         """Device milliseconds for nsteps (HIP events on the sim's stream);
         with per_update also the summed duration of the update launches."""
@@ -291,6 +305,15 @@ class Simulation:
         _check(lib().nflbm_step_timed(self._handle(), int(nsteps), ctypes.byref(ms),
                                       ctypes.byref(mu) if per_update else None), self._h)
         return (ms.value, mu.value) if per_update else ms.value
+
+    def step_timed_kernels(self, nsteps):
+        """Summed device milliseconds of the reconstruction and of the update
+        launches over nsteps (HIP events around each launch)."""
+        mc = ctypes.c_double()
+        mu = ctypes.c_double()
+        _check(lib().nflbm_step_timed_kernels(self._handle(), int(nsteps), ctypes.byref(mc),
+                                              ctypes.byref(mu)), self._h)
+        return mc.value, mu.value
 
     def get_field(self, name):
         fid = FIELDS[name]
@@ -412,6 +435,13 @@ class Simulation:
             _check(r, self._h)
         return "moments" if r == 1 else "populations"
 
+    def f_storage_form(self):
+        """'records' (f kept as (fA, F) per node; every omega = 1) or 'populations'."""
+        r = lib().nflbm_f_storage_form(self._handle())
+        if r < 0:
+            _check(r, self._h)
+        return "records" if r == 1 else "populations"
+
     def autotune(self, cache_path=None):
         """Time the launch shapes and keep the fastest (state unchanged)."""
         _check(lib().nflbm_autotune(self._handle(), None if cache_path is None
@@ -475,6 +505,16 @@ class Batch:
 
     def set_stream(self, stream_ptr):
         _bcheck(lib().nflbm_batch_set_stream(self._handle(), ctypes.c_void_p(stream_ptr)), self._h)
+
+    def set_fields(self, idx, C, v=None, P=None):
+        """nflbm_batch_set_fields of member idx (also clears the batch's NaN flag)."""
+        m = self.members[idx]
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(m.N, -1)
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64).reshape(3, -1)
+        PP = None if P is None else np.ascontiguousarray(P, dtype=np.float64).reshape(-1)
+        _bcheck(lib().nflbm_batch_set_fields(self._handle(), int(idx), _dptr(C),
+                                             _dptr(vv) if vv is not None else None,
+                                             _dptr(PP) if PP is not None else None), self._h)
 
     def step(self, nsteps=1, mode="graph"):
         _bcheck(lib().nflbm_batch_step(self._handle(), int(nsteps), BATCH_MODES[mode]), self._h)

@@ -1,6 +1,7 @@
 """Build the HIP library libnflbm.so in-tree for gfx950 with hipcc.
 
-Usage: python -m paper_2605_22214_amd.build  (or build() from Python).
+Usage: python -m paper_2605_22214_amd.build [--changed]  (or build() from
+Python); --changed recompiles only the units older than a source or header.
 Objects go to _build/ at the repository root; the shared library is written
 next to this file so that it ships with the package tree.
 """
@@ -63,11 +64,28 @@ def _compile(unit):
     return obj, time.time() - t, res.stderr
 
 
-def build(verbose=True, jobs=None):
+def _stale(unit):
+    """True if the unit's object is missing or older than its source or any
+    header it may include (every header of csrc/ and include/)."""
+    obj = os.path.join(BUILD, unit[1])
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, unit[0])]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    deps += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=True, jobs=None, changed_only=False):
+    """Compile every unit (changed_only: only those whose object is older
+    than a source or header) and link libnflbm.so."""
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(UNITS), os.cpu_count() or 4)
+    units = [u for u in UNITS if _stale(u)] if changed_only else UNITS
+    jobs = jobs or min(max(len(units), 1), os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, dt, warn in ex.map(_compile, UNITS):
+        for obj, dt, warn in ex.map(_compile, units):
             if verbose:
                 print(f"  compiled {obj} in {dt:.1f}s", flush=True)
                 w = "\n".join(l for l in warn.splitlines() if "packed-fp32-ops" not in l
@@ -87,5 +105,5 @@ def build(verbose=True, jobs=None):
 
 
 if __name__ == "__main__":
-    build()
+    build(changed_only="--changed" in sys.argv[1:])
     sys.exit(0)

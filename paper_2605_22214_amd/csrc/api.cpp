@@ -47,8 +47,10 @@ struct nflbm_sim {
   int uidx[kMaxComp] = {};  // internal -> user component
   size_t n = 0;
   Coeffs co;
-  // storage sizes (bytes per value)
+  // storage sizes (bytes per value), and the elements between direction
+  // arrays of f and of the moving g populations (direction_stride)
   size_t fs = 0, g0s = 0, ts = 0;
+  size_t fstride = 0, gstride = 0;
   // device state: two population sets (A/B), reconstructed C, parameters
   void* f[2] = {nullptr, nullptr};
   void* g0[2] = {nullptr, nullptr};
@@ -59,12 +61,23 @@ struct nflbm_sim {
   void* mu = nullptr;    // moment form: mu~ [node][i]
   void* vel = nullptr;   // moment form: (v, -3/2 v.v) [node][4]
   int gform = 0;         // 0 populations of g, 1 moment form (tau_g = 1)
+  // record form of f (every omega+ = omega- = 1, with the moment form of g):
+  // frec (fB, F) [node][4] instead of the f populations, fmom [node][4] the
+  // moments of the streamed f; f_local: the next step starts from the
+  // equilibria set_fields wrote (each node's own record)
+  int fform = 0;
+  void* frec = nullptr;
+  void* fmom = nullptr;
+  bool f_local = false;
   // open faces: FaceBC<T> on the device, and the host's copy of each face
   void* faces = nullptr;
   int open_mask = 0;
   double face_v[6][3] = {};
   double face_c[6][kMaxComp] = {};   // user order
   double m_geq = 0.0, omega = 0.0;
+  // Reference pressure: the state holds the populations of P - p_ref (the
+  // mean initial P of the fluid nodes); read-back adds it to P and F_RAW
+  double p_ref = 0.0;
   // convective outflow face (-1 none): one device block holding the plane
   // buffers f [Q-1][P], g [N-1][Q][P] and the ghosts [N][P] (compute
   // precision), and the per-workgroup momentum sums plus U (FP64)
@@ -92,7 +105,6 @@ struct nflbm_sim {
   void* params = nullptr;
   double* fields = nullptr;
   double* red = nullptr;
-  int red_blocks = 0;
   int cur = 0;
   hipStream_t stream = nullptr;
   // launch shape of the update, and of the reconstruction (its own: the two
@@ -101,6 +113,18 @@ struct nflbm_sim {
   int ctx_log2 = 6, czchunk = 1, ctiles_x = 1, ctiles_y = 1, cchunks_z = 1;
   size_t lds_max = 65536;
   int step_flags = 0;
+  int device = 0;        // the HIP device current at nflbm_create
+  // NaN detection: the update raises *nanflag on the steps it checks (every
+  // nan_every-th step, 0 = never); nflbm_step copies the flag to pinned host
+  // memory behind the checked steps and reads the copy, once its event has
+  // completed, on the next call (no synchronisation on the stepping path)
+  int* nanflag = nullptr;
+  int* nan_host = nullptr;
+  hipEvent_t nan_ev = nullptr;
+  bool nan_pending = false;
+  int nan_seen = 0;
+  long long nan_every = 16;
+  long long step_count = 0;
   std::string err;
 };
 
@@ -124,6 +148,13 @@ struct nflbm_batch {
   std::vector<int> key;     // member parities that args[0..count) was built for
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // NaN flag shared by the members' batch steps, which check every step
+  // (a captured graph replays one argument table); host copy as for a sim
+  int* nanflag = nullptr;
+  int* nan_host = nullptr;
+  hipEvent_t nan_ev = nullptr;
+  bool nan_pending = false;
+  int nan_seen = 0;
   std::string err;
 };
 
@@ -184,7 +215,7 @@ void fill_params(const nflbm_sim& s, const double* tau, const double* tau_g, dou
 
 void free_device(nflbm_sim* s) {
   void** arrays[] = {&s->f[0], &s->f[1], &s->g0[0], &s->g0[1], &s->gk[0], &s->gk[1],
-                     &s->conc[0], &s->conc[1], &s->mu, &s->vel, &s->eb};
+                     &s->conc[0], &s->conc[1], &s->mu, &s->vel, &s->eb, &s->frec, &s->fmom};
   for (void** a : arrays) {
     if (*a && !s->borrowed) (void)hipFree(*a);
     *a = nullptr;
@@ -213,6 +244,12 @@ void free_device(nflbm_sim* s) {
   if (s->red) (void)hipFree(s->red);
   s->params = s->eb = nullptr;
   s->fields = s->red = nullptr;
+  if (s->nanflag) (void)hipFree(s->nanflag);
+  if (s->nan_host) (void)hipHostFree(s->nan_host);
+  if (s->nan_ev) (void)hipEventDestroy(s->nan_ev);
+  s->nanflag = nullptr;
+  s->nan_host = nullptr;
+  s->nan_ev = nullptr;
 }
 
 int next_pow2_log(int v) {
@@ -237,7 +274,7 @@ bool apply_launch(nflbm_sim* s, int l, int zc) {
   if (zc < 1) return false;
   if (zc > s->nz) zc = s->nz;
   if (update_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
-  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
+  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l, s->fform) > s->lds_max) return false;
   const int TX = 1 << l, TY = 256 >> l;
   s->tx_log2 = l;
   s->zchunk = zc;
@@ -253,7 +290,7 @@ bool apply_conc_launch(nflbm_sim* s, int l, int zc) {
   if (s->lat != NFLBM_D3Q19) zc = 1;
   if (zc < 1) return false;
   if (zc > s->nz) zc = s->nz;
-  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l) > s->lds_max) return false;
+  if (s->gform && conc_m_lds_bytes(s->lat, s->N, s->store, l, s->fform) > s->lds_max) return false;
   const int TX = 1 << l, TY = 256 >> l;
   s->ctx_log2 = l;
   s->czchunk = zc;
@@ -294,7 +331,7 @@ int choose_launch(nflbm_sim* s) {
   s->lds_max = device_lds_max();
   auto fits = [&](int t) {
     return update_lds_bytes(s->lat, s->N, s->store, t) <= s->lds_max &&
-           (!s->gform || conc_m_lds_bytes(s->lat, s->N, s->store, t) <= s->lds_max);
+           (!s->gform || conc_m_lds_bytes(s->lat, s->N, s->store, t, s->fform) <= s->lds_max);
   };
   int l = s->nx <= 16 ? 4 : 6;
   if (l == 6 && !fits(l)) l = 4;
@@ -332,6 +369,9 @@ StepArgs make_args(const nflbm_sim* s, int src) {
     a.conc = s->conc[0];
   }
   a.eb = s->eb;
+  a.frec = s->frec;
+  a.fmom = s->fmom;
+  a.nanflag = s->nanflag;
   a.fields = s->fields;
   a.params = s->params;
   a.bb = s->bb;
@@ -345,6 +385,8 @@ StepArgs make_args(const nflbm_sim* s, int src) {
     a.out_ghost = b + (size_t(s->Q - 1) + size_t(s->NE) * s->Q) * P * s->ts;
   }
   a.n = static_cast<long long>(s->n);
+  a.fstride = static_cast<long long>(s->fstride);
+  a.gstride = static_cast<long long>(s->gstride);
   a.nx = s->nx;
   a.ny = s->ny;
   a.nz = s->nz;
@@ -357,6 +399,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.tiles_y = s->tiles_y;
   a.chunks_z = s->chunks_z;
   a.flags = s->step_flags;
+  if (s->fform && s->f_local) a.flags |= kFlagFLocal;
   return a;
 }
 
@@ -433,16 +476,62 @@ MobArgs mob_args(const nflbm_sim* s, const StepArgs& a) {
 }
 
 // One time step from state set `cur`; ev (optional) brackets the update.
-int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1) {
+// Every nan_every-th step the update checks for non-finite values (*checked
+// is set when this one did).
+int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1, bool* checked = nullptr, hipEvent_t evc0 = nullptr,
+                hipEvent_t evc1 = nullptr) {
   StepArgs a = make_args(s, s->cur);
+  ++s->step_count;
+  if (s->nan_every > 0 && s->step_count % s->nan_every == 0) {
+    a.flags |= kFlagCheckNaN;
+    if (checked) *checked = true;
+  }
+  if (evc0) HIPCHK(s, hipEventRecord(evc0, s->stream));
   HIPCHK(s, launch_conc(s->lat, s->N, s->store, conc_args(s, a), s->stream));
+  if (evc1) HIPCHK(s, hipEventRecord(evc1, s->stream));
   if (s->c2c2) HIPCHK(s, launch_mob_potentials(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   if (ev0) HIPCHK(s, hipEventRecord(ev0, s->stream));
   HIPCHK(s, launch_update(s->lat, s->N, s->store, a, false, s->stream));
   if (ev1) HIPCHK(s, hipEventRecord(ev1, s->stream));
   if (s->c2c2) HIPCHK(s, launch_mob_source(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   s->cur ^= 1;
+  s->f_local = false;   // from now on every f streams in from its neighbour
   if (s->out_face >= 0) return launch_outflow_step(s, false);
+  return NFLBM_OK;
+}
+
+// Host copy of a NaN flag behind the work queued so far on stream.
+hipError_t nan_enqueue(int* dev, int* host, hipEvent_t ev, hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(host, dev, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev, stream);
+  return e;
+}
+
+// Read the host copy of a NaN flag if its copy has completed (wait: block
+// until it has); *seen becomes 1, and stays so, once a NaN was reported.
+hipError_t nan_poll(bool* pending, int* seen, const int* host, hipEvent_t ev, bool wait) {
+  if (!*pending) return hipSuccess;
+  hipError_t e = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+  if (e == hipErrorNotReady) return hipSuccess;
+  if (e != hipSuccess) return e;
+  *pending = false;
+  if (*host) *seen = 1;
+  return hipSuccess;
+}
+
+int sim_nan_status(nflbm_sim* s, bool wait) {
+  HIPCHK(s, nan_poll(&s->nan_pending, &s->nan_seen, s->nan_host, s->nan_ev, wait));
+  if (s->nan_seen) return fail(s, NFLBM_ENUMERIC, "a NaN or Inf appeared in the state (checked steps)");
+  return NFLBM_OK;
+}
+
+// Clear the NaN flag of s (with the state it refers to).
+int sim_nan_reset(nflbm_sim* s) {
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemset(s->nanflag, 0, sizeof(int)));
+  *s->nan_host = 0;
+  s->nan_pending = false;
+  s->nan_seen = 0;
   return NFLBM_OK;
 }
 
@@ -534,14 +623,20 @@ int compute_fields(nflbm_sim* s) {
 std::vector<std::pair<void*, size_t>> state_segments(nflbm_sim* s) {
   const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
   std::vector<std::pair<void*, size_t>> v;
-  v.emplace_back(s->f[s->cur], Qm * n * s->fs);
+  // one segment per direction array: the checkpoint is packed, without the
+  // gaps of the direction strides
+  if (!s->fform)
+    for (size_t k = 0; k < Qm; ++k)
+      v.emplace_back(static_cast<unsigned char*>(s->f[s->cur]) + k * s->fstride * s->fs, n * s->fs);
   if (s->gform) {
     v.emplace_back(s->conc[s->cur], NE * n * s->ts);
     v.emplace_back(s->mu, NE * n * s->ts);
     v.emplace_back(s->vel, 4 * n * s->ts);
+    if (s->fform) v.emplace_back(s->frec, 4 * n * s->ts);
   } else {
     v.emplace_back(s->g0[s->cur], NE * n * s->g0s);
-    v.emplace_back(s->gk[s->cur], NE * Qm * n * s->fs);
+    for (size_t k = 0; k < Qm; ++k)
+      v.emplace_back(static_cast<unsigned char*>(s->gk[s->cur]) + k * s->gstride * s->fs, NE * n * s->fs);
   }
   if (s->out_face >= 0) v.emplace_back(s->out_buf, out_buf_bytes(s));
   return v;
@@ -604,6 +699,10 @@ int build_batch_tables(nflbm_batch* b, bool new_shape) {
     b->key[i] = m->cur;
     args[i] = batch_args(b, m, m->cur);
     args[count + i] = batch_args(b, m, m->cur ^ 1);
+    for (StepArgs* x : {&args[i], &args[count + i]}) {
+      x->nanflag = b->nanflag;
+      x->flags |= kFlagCheckNaN;
+    }
     const StepArgs& a = args[i];
     const long long nc = 1LL * a.tiles_x * a.tiles_y * m->nz;
     const long long nu = 1LL * a.tiles_x * a.tiles_y * a.chunks_z;
@@ -651,7 +750,7 @@ int batch_half(nflbm_batch* b, int* half) {
 bool batch_tile_fits(const nflbm_batch* b, int l) {
   const size_t lim = b->members[0]->lds_max;
   return update_lds_bytes(b->lat, b->N, b->store, l) <= lim &&
-         (!b->members[0]->gform || conc_m_lds_bytes(b->lat, b->N, b->store, l) <= lim);
+         (!b->members[0]->gform || conc_m_lds_bytes(b->lat, b->N, b->store, l, b->members[0]->fform) <= lim);
 }
 
 hipError_t launch_half(nflbm_batch* b, int half) {
@@ -665,6 +764,7 @@ hipError_t launch_half(nflbm_batch* b, int half) {
   bl.tx_log2 = b->tx_log2;
   bl.walls = b->walls;
   bl.moments = b->members[0]->gform;
+  bl.frecord = b->members[0]->fform;
   return launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
 }
 
@@ -700,6 +800,30 @@ int batch_run(nflbm_batch* b, long long nsteps, int mode) {
     }
     return NFLBM_OK;
   }
+  BHIPCHK(b, nan_poll(&b->nan_pending, &b->nan_seen, b->nan_host, b->nan_ev, false));
+  if (b->nan_seen) return bfail(b, NFLBM_ENUMERIC, "a NaN or Inf appeared in a member's state");
+  bool local = false;
+  for (nflbm_sim* m : b->members) local = local || m->f_local;
+  if (local && nsteps > 0) {
+    // record form of f: the first step after set_fields takes each node's
+    // f from its own record (kFlagFLocal in those members' arguments); the
+    // tables are then rebuilt without the flag for the remaining steps
+    int rc = build_batch_tables(b, false);
+    if (rc != NFLBM_OK) return rc;
+    BHIPCHK(b, launch_half(b, 0));
+    for (nflbm_sim* m : b->members) {
+      m->cur ^= 1;
+      m->f_local = false;
+    }
+    rc = build_batch_tables(b, false);
+    if (rc != NFLBM_OK) return rc;
+    if (nsteps == 1) {
+      BHIPCHK(b, nan_enqueue(b->nanflag, b->nan_host, b->nan_ev, b->stream));
+      b->nan_pending = true;
+      return NFLBM_OK;
+    }
+    return batch_run(b, nsteps - 1, mode);
+  }
   int half = 0;
   int rc = batch_half(b, &half);
   if (rc != NFLBM_OK) return rc;
@@ -719,6 +843,20 @@ int batch_run(nflbm_batch* b, long long nsteps, int mode) {
   }
   if (nsteps & 1)
     for (nflbm_sim* m : b->members) m->cur ^= 1;
+  if (nsteps > 0) {
+    BHIPCHK(b, nan_enqueue(b->nanflag, b->nan_host, b->nan_ev, b->stream));
+    b->nan_pending = true;
+  }
+  return NFLBM_OK;
+}
+
+// Clear the batch's NaN flag (a member's state was set anew).
+int batch_nan_reset(nflbm_batch* b) {
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  BHIPCHK(b, hipMemset(b->nanflag, 0, sizeof(int)));
+  *b->nan_host = 0;
+  b->nan_pending = false;
+  b->nan_seen = 0;
   return NFLBM_OK;
 }
 
@@ -780,10 +918,12 @@ std::string sim_key(const nflbm_sim* s) {
 struct SavedState {
   std::vector<void*> copies;
   int cur = 0;
+  bool f_local = false;
 };
 
 int save_state(nflbm_sim* s, SavedState* st) {
   st->cur = s->cur;
+  st->f_local = s->f_local;
   for (const auto& seg : state_segments(s)) {
     void* c = nullptr;
     if (hipMalloc(&c, seg.second) != hipSuccess) return fail(s, NFLBM_ENOMEM, "cannot allocate the autotuner's state copy");
@@ -795,6 +935,7 @@ int save_state(nflbm_sim* s, SavedState* st) {
 
 int restore_state(nflbm_sim* s, SavedState* st) {
   s->cur = st->cur;
+  s->f_local = st->f_local;
   const auto segs = state_segments(s);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < st->copies.size() && i < segs.size() && e == hipSuccess; ++i)
@@ -886,6 +1027,8 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
     case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; break;
     default: s->fs = 2; s->g0s = 4; s->ts = 4; break;
   }
+  s->fstride = direction_stride(s->n, s->fs);
+  s->gstride = direction_stride(s->n * size_t(s->NE), s->fs);
   s->step_flags = 0;
   for (int i = 0; i < N; ++i)
     if (cfg->tau_g && cfg->tau_g[i] != 1.0) s->step_flags |= kFlagNeedG;
@@ -896,16 +1039,36 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
   // store those per node instead of the populations, unless asked not to.
   s->c2c2 = (cfg->flags & NFLBM_FLAG_C2C2_MOBILITY) != 0;
   s->gform = (!(s->step_flags & kFlagNeedG) && !(cfg->flags & NFLBM_FLAG_G_POPULATIONS) && !s->c2c2) ? 1 : 0;
-  if (s->gform && choose_launch(s) != 0) s->gform = 0;   // its LDS window does not fit
+  // With every node relaxing at omega+ = omega- = 1 (each tau_i = 1, BGK or
+  // Lambda^TRT = 1/4) the post-collision f is fixed by the node's P, v and F
+  // (Eqs. TRT, FTRT, hydroforce): keep those instead of the populations.
+  // FP16S keeps its binary16 populations.
+  bool unit = !(cfg->flags & NFLBM_FLAG_F_POPULATIONS) && !(cfg->flags & NFLBM_FLAG_NO_HYDRO) &&
+              s->store != NFLBM_FP16S;
+  for (int i = 0; i < N && unit; ++i) {
+    const double wp = 1.0 / cfg->tau[i];
+    const double wm = cfg->trt_magic > 0.0 ? 1.0 / (0.5 + cfg->trt_magic / (cfg->tau[i] - 0.5)) : wp;
+    unit = wp == 1.0 && wm == 1.0;
+  }
+  s->fform = (s->gform && unit) ? 1 : 0;
+  if (s->gform && choose_launch(s) != 0) s->gform = s->fform = 0;   // its LDS window does not fit
   if (s->gform) s->step_flags |= kFlagMoments;
+  if (s->fform) s->step_flags |= kFlagFRecord;
   if (choose_launch(s) != 0) {
     return fail(nullptr, NFLBM_ENOTSUP, "LDS window does not fit the device for this N and precision");
   }
 
-  const size_t n = s->n, NE = s->NE;
-  if (double(n) * double(NE) * double(s->fs > s->ts ? s->fs : s->ts) >= 4294967296.0 ||
-      double(n) * double(NE) * double(s->g0s) >= 4294967296.0) {
-    return fail(nullptr, NFLBM_ENOTSUP, "lattice too large: in-plane byte offsets must fit 32 bits");
+  // Per-node arrays are addressed with 32-bit byte offsets from a uniform
+  // base: the widest one must fit.  That is NE values a node (C, the g
+  // populations of one direction, the rest populations), the four of the
+  // moment form's velocity record, or the N flux potentials of the
+  // concentration-dependent mobility.
+  size_t width = s->NE;
+  if (s->gform) width = std::max<size_t>(width, 4);
+  if (s->c2c2) width = std::max<size_t>(width, size_t(s->N));
+  const size_t vbytes = std::max(std::max(s->fs, s->ts), s->g0s);
+  if (double(s->n) * double(width) * double(vbytes) >= 4294967296.0) {
+    return fail(nullptr, NFLBM_ENOTSUP, "lattice too large: per-node byte offsets must fit 32 bits");
   }
   return NFLBM_OK;
 }
@@ -916,14 +1079,19 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
 std::vector<std::pair<void**, size_t>> state_arrays(nflbm_sim* s) {
   const size_t n = s->n, Qm = s->Q - 1, NE = s->NE;
   std::vector<std::pair<void**, size_t>> v;
-  for (int b = 0; b < 2; ++b) v.emplace_back(&s->f[b], Qm * n * s->fs);
+  if (!s->fform)
+    for (int b = 0; b < 2; ++b) v.emplace_back(&s->f[b], Qm * s->fstride * s->fs);
   if (s->gform) {
     for (int b = 0; b < 2; ++b) v.emplace_back(&s->conc[b], NE * n * s->ts);
     v.emplace_back(&s->mu, NE * n * s->ts);
     v.emplace_back(&s->vel, 4 * n * s->ts);
+    if (s->fform) {
+      v.emplace_back(&s->frec, 4 * n * s->ts);
+      v.emplace_back(&s->fmom, 4 * n * s->ts);
+    }
   } else {
     for (int b = 0; b < 2; ++b) v.emplace_back(&s->g0[b], NE * n * s->g0s);
-    for (int b = 0; b < 2; ++b) v.emplace_back(&s->gk[b], NE * Qm * n * s->fs);
+    for (int b = 0; b < 2; ++b) v.emplace_back(&s->gk[b], Qm * s->gstride * s->fs);
     v.emplace_back(&s->conc[0], NE * n * s->ts);
   }
   v.emplace_back(&s->eb, n * s->ts);
@@ -962,6 +1130,46 @@ constexpr size_t kBindAlign = 256;
 size_t align_up(size_t v) { return (v + kBindAlign - 1) / kBindAlign * kBindAlign; }
 
 }  // namespace
+
+namespace nflbm {
+
+int sim_device(const nflbm_sim* s) { return s->device; }
+
+int sim_fail(nflbm_sim* s, int code, const char* msg) { return fail(s, code, msg); }
+
+int diag_run(nflbm_sim* sim, int vcm_component, double* partial, int max_blocks, double* result, nflbm_diag* out) {
+  if (!sim || !out) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  if (vcm_component < 0 || vcm_component >= sim->N) return fail(sim, NFLBM_EINVAL, "vcm_component out of range");
+  const int N = sim->N;
+  const int rec = reduce_record_len(N);
+  StepArgs a = make_args(sim, sim->cur);
+  HIPCHK(sim, launch_conc(sim->lat, N, sim->store, conc_args(sim, a), sim->stream));
+  a.diag_partial = partial;
+  for (int i = 0; i < N; ++i)
+    if (sim->uidx[i] == vcm_component) a.diag_vcm = i;
+  int blocks = 0;
+  HIPCHK(sim, launch_diag(sim->lat, N, sim->store, a, max_blocks, result, &blocks, sim->stream));
+  double r[3 * kMaxComp + 9];
+  HIPCHK(sim, hipMemcpyAsync(r, result, rec * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < N; ++i) {   // the record is in internal component order
+    const int u = sim->uidx[i];
+    out->mass[u] = r[i];
+    out->max_abs_c[u] = r[N + 3 + i];
+    out->min_c[u] = r[2 * N + 3 + i];
+  }
+  for (int d = 0; d < 3; ++d) out->momentum[d] = r[N + d];
+  out->max_sum_dev = r[3 * N + 3];
+  const double cm = r[3 * N + 7];
+  for (int d = 0; d < 3; ++d) out->vcm[d] = cm != 0.0 ? r[3 * N + 4 + d] / cm : 0.0;
+  out->vcm_component = vcm_component;
+  out->nan = r[3 * N + 8] != 0.0 ? 1 : 0;
+  if (out->nan) return fail(sim, NFLBM_ENUMERIC, "NaN or Inf in the state");
+  return NFLBM_OK;
+}
+
+}  // namespace nflbm
 
 extern "C" {
 
@@ -1005,10 +1213,13 @@ int nflbm_create(const nflbm_config* cfg, nflbm_sim** out) {
   }
   const int N = s->N;
   const size_t n = s->n;
-  bool ok = true;
+  bool ok = hipGetDevice(&s->device) == hipSuccess;
   for (auto& a : state_arrays(s)) ok = ok && hipMalloc(a.first, a.second) == hipSuccess;
   const size_t psize = s->ts == 8 ? sizeof(DevParams<double>) : sizeof(DevParams<float>);
   ok = ok && hipMalloc(&s->params, psize) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&s->nanflag), sizeof(int)) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->nan_host), sizeof(int), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&s->nan_ev, hipEventDisableTiming) == hipSuccess;
   if (s->c2c2) {
     const size_t msize = s->ts == 8 ? sizeof(MobParams<double>) : sizeof(MobParams<float>);
     ok = ok && hipMalloc(&s->mob, msize) == hipSuccess;
@@ -1206,6 +1417,29 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
 int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const double* P) {
   if (!sim || !C) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const size_t n = sim->n;
+  // A uniform pressure adds 3 w_k P_ref to every f_k (Eq. feq, pressure
+  // form), a shift that streaming, both collisions, bounce-back, the open
+  // faces and the outflow all map onto itself: the state keeps P - P_ref,
+  // whose populations stay small (binary16 storage keeps its precision).
+  std::vector<double> Pshift;
+  sim->p_ref = 0.0;
+  if (P) {
+    double sum = 0.0, lo = 0.0, hi = 0.0;
+    size_t cnt = 0;
+    for (size_t q = 0; q < n; ++q) {
+      if (!sim->solid_host.empty() && sim->solid_host[q]) continue;
+      lo = cnt ? std::min(lo, P[q]) : P[q];
+      hi = cnt ? std::max(hi, P[q]) : P[q];
+      sum += P[q];
+      ++cnt;
+    }
+    // a uniform P is taken exactly (its summed mean can be off by rounding)
+    sim->p_ref = !cnt ? 0.0 : (lo == hi ? lo : sum / double(cnt));
+    if (!std::isfinite(sim->p_ref)) sim->p_ref = 0.0;   // a NaN in P stays in the state
+    Pshift.assign(P, P + n);
+    for (double& x : Pshift) x -= sim->p_ref;
+    P = Pshift.data();
+  }
   const size_t cnt = size_t(sim->N) * n + (v ? 3 * n : 0) + (P ? n : 0);
   double* tmp = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&tmp), cnt * sizeof(double)) != hipSuccess)
@@ -1231,7 +1465,7 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
   }
   if (e == hipSuccess && (sim->step_flags & kFlagNoHydro))
     // f is never written in diffusive-only runs: both sets hold the initial f
-    e = hipMemcpyAsync(sim->f[1 - sim->cur], sim->f[sim->cur], size_t(sim->Q - 1) * n * sim->fs,
+    e = hipMemcpyAsync(sim->f[1 - sim->cur], sim->f[sim->cur], size_t(sim->Q - 1) * sim->fstride * sim->fs,
                        hipMemcpyDeviceToDevice, sim->stream);
   if (e == hipSuccess && sim->out_face >= 0) {
     // the outflow plane and ghosts start from the new state
@@ -1245,16 +1479,50 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(sim, e, "set_fields");
-  return NFLBM_OK;
+  // record form of f: unless the initial f is zero (rest at P_ref), the first
+  // step takes each node's f as the equilibrium of its own record (the
+  // population form stores exactly that equilibrium at every node)
+  bool moving = false;
+  for (size_t q = 0; v && q < 3 * n && !moving; ++q) moving = v[q] != 0.0;
+  for (size_t q = 0; P && q < n && !moving; ++q) moving = P[q] != 0.0;
+  sim->f_local = sim->fform && moving;
+  return sim_nan_reset(sim);
 }
 
 int nflbm_step(nflbm_sim* sim, long long nsteps) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (nsteps < 0) return fail(sim, NFLBM_EINVAL, "nsteps < 0");
+  // a NaN reported by the copy behind an earlier call
+  int rc = sim_nan_status(sim, false);
+  if (rc != NFLBM_OK) return rc;
+  bool checked = false;
   for (long long t = 0; t < nsteps; ++t) {
-    const int rc = launch_step(sim, nullptr, nullptr);
+    rc = launch_step(sim, nullptr, nullptr, &checked);
     if (rc != NFLBM_OK) return rc;
   }
+  if (checked) {
+    // the device flag only ever goes from 0 to 1, so a newer copy subsumes
+    // one still in flight; the event follows the newest
+    HIPCHK(sim, nan_enqueue(sim->nanflag, sim->nan_host, sim->nan_ev, sim->stream));
+    sim->nan_pending = true;
+  }
+  return NFLBM_OK;
+}
+
+int nflbm_synchronize(nflbm_sim* sim) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  HIPCHK(sim, nan_poll(&sim->nan_pending, &sim->nan_seen, sim->nan_host, sim->nan_ev, true));
+  // the flag as the last checked step left it
+  HIPCHK(sim, hipMemcpy(sim->nan_host, sim->nanflag, sizeof(int), hipMemcpyDeviceToHost));
+  if (*sim->nan_host) sim->nan_seen = 1;
+  return sim_nan_status(sim, true);
+}
+
+int nflbm_set_nan_check(nflbm_sim* sim, long long every) {
+  if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
+  if (every < 0) return fail(sim, NFLBM_EINVAL, "every must be >= 0");
+  sim->nan_every = every;
   return NFLBM_OK;
 }
 
@@ -1268,12 +1536,20 @@ int nflbm_step_timed(nflbm_sim* sim, long long nsteps, double* ms, double* ms_up
     ev.resize(2 * size_t(nsteps));
     for (auto& x : ev) HIPCHK(sim, hipEventCreate(&x));
   }
+  int rc0 = sim_nan_status(sim, true);
+  if (rc0 != NFLBM_OK) return rc0;
+  bool checked = false;
   HIPCHK(sim, hipEventRecord(e0, sim->stream));
   for (long long t = 0; t < nsteps; ++t) {
-    const int rc = ms_update ? launch_step(sim, ev[2 * t], ev[2 * t + 1]) : launch_step(sim, nullptr, nullptr);
+    const int rc = ms_update ? launch_step(sim, ev[2 * t], ev[2 * t + 1], &checked)
+                             : launch_step(sim, nullptr, nullptr, &checked);
     if (rc != NFLBM_OK) return rc;
   }
   HIPCHK(sim, hipEventRecord(e1, sim->stream));
+  if (checked) {
+    HIPCHK(sim, nan_enqueue(sim->nanflag, sim->nan_host, sim->nan_ev, sim->stream));
+    sim->nan_pending = true;
+  }
   HIPCHK(sim, hipEventSynchronize(e1));
   float t_ms = 0.f;
   HIPCHK(sim, hipEventElapsedTime(&t_ms, e0, e1));
@@ -1290,7 +1566,38 @@ int nflbm_step_timed(nflbm_sim* sim, long long nsteps, double* ms, double* ms_up
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return NFLBM_OK;
+  return sim_nan_status(sim, true);
+}
+
+int nflbm_step_timed_kernels(nflbm_sim* sim, long long nsteps, double* ms_conc, double* ms_update) {
+  if (!sim || !ms_conc || !ms_update) return fail(sim, NFLBM_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(sim, NFLBM_EINVAL, "nsteps < 0");
+  int rc = sim_nan_status(sim, true);
+  if (rc != NFLBM_OK) return rc;
+  std::vector<hipEvent_t> ev(4 * size_t(nsteps));
+  for (auto& x : ev) HIPCHK(sim, hipEventCreate(&x));
+  bool checked = false;
+  for (long long t = 0; t < nsteps; ++t) {
+    rc = launch_step(sim, ev[4 * t + 2], ev[4 * t + 3], &checked, ev[4 * t], ev[4 * t + 1]);
+    if (rc != NFLBM_OK) return rc;
+  }
+  if (checked) {
+    HIPCHK(sim, nan_enqueue(sim->nanflag, sim->nan_host, sim->nan_ev, sim->stream));
+    sim->nan_pending = true;
+  }
+  if (nsteps > 0) HIPCHK(sim, hipEventSynchronize(ev.back()));
+  double tc = 0.0, tu = 0.0;
+  for (long long t = 0; t < nsteps; ++t) {
+    float a = 0.f, b = 0.f;
+    HIPCHK(sim, hipEventElapsedTime(&a, ev[4 * t], ev[4 * t + 1]));
+    HIPCHK(sim, hipEventElapsedTime(&b, ev[4 * t + 2], ev[4 * t + 3]));
+    tc += a;
+    tu += b;
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  *ms_conc = tc;
+  *ms_update = tu;
+  return sim_nan_status(sim, true);
 }
 
 int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
@@ -1311,6 +1618,9 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     HIPCHK(sim, hipMemcpyAsync(host_out, sim->fields + off * n, cnt * n * sizeof(double),
                                hipMemcpyDeviceToHost, sim->stream));
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
+    if (field == NFLBM_FIELD_P && sim->p_ref != 0.0)
+      for (size_t q = 0; q < n; ++q)
+        if (sim->solid_host.empty() || !sim->solid_host[q]) host_out[q] += sim->p_ref;
     return NFLBM_OK;
   }
   if (field == NFLBM_FIELD_F_RAW || field == NFLBM_FIELD_G_RAW) {
@@ -1319,12 +1629,26 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
     const int Qm = sim->Q - 1;
     const int NE = sim->NE;
     std::vector<unsigned char> fbuf, g0buf, gkbuf;
-    if (field == NFLBM_FIELD_F_RAW) {
-      fbuf.resize(Qm * n * sim->fs);
+    const size_t fst = sim->fstride, gst = sim->gstride;
+    // bytes of a stored f value (the record form writes them out in the
+    // compute precision)
+    const size_t fbytes = sim->fform ? sim->ts : sim->fs;
+    if (field == NFLBM_FIELD_F_RAW && sim->fform) {
+      fbuf.resize(Qm * fst * sim->ts);
+      void* tmp = nullptr;
+      if (hipMalloc(&tmp, fbuf.size()) != hipSuccess)
+        return fail(sim, NFLBM_ENOMEM, "cannot allocate the population read-back buffer");
+      hipError_t e = launch_expand_f(sim->lat, sim->store, make_args(sim, sim->cur), tmp, sim->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(fbuf.data(), tmp, fbuf.size(), hipMemcpyDeviceToHost, sim->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return hip_fail(sim, e, "F_RAW read-back");
+    } else if (field == NFLBM_FIELD_F_RAW) {
+      fbuf.resize(Qm * fst * sim->fs);
       HIPCHK(sim, hipMemcpyAsync(fbuf.data(), sim->f[sim->cur], fbuf.size(), hipMemcpyDeviceToHost, sim->stream));
     } else {
       g0buf.resize(size_t(NE) * n * sim->g0s);
-      gkbuf.resize(size_t(NE) * Qm * n * sim->fs);
+      gkbuf.resize(Qm * gst * sim->fs);
       const void* g0dev = sim->g0[sim->cur];
       const void* gkdev = sim->gk[sim->cur];
       void* tmp = nullptr;
@@ -1444,28 +1768,39 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
             int dir = k;
             const size_t src = source(k, x, y, z, dir);
             if (field == NFLBM_FIELD_F_RAW) {
-              double v = val(fbuf.data(), size_t(dir - 1) * n + src, sim->fs, true);
+              double v = val(fbuf.data(), size_t(dir - 1) * fst + src, fbytes, true);
               if (entry >= 0) v += face_fcorr(*sim, entry, k);
               host_out[size_t(k - 1) * n + q] = v;
             } else {
               for (int i = 0; i < NE; ++i) {
-                double v = val(gkbuf.data(), (size_t(dir - 1) * n + src) * NE + i, sim->fs, true);
+                double v = val(gkbuf.data(), size_t(dir - 1) * gst + src * NE + i, sim->fs, true);
                 if (entry >= 0) v = face_gsum(*sim, entry, sim->uidx[i], k) - v;
                 host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] = v;
               }
             }
           }
         }
+    if (field == NFLBM_FIELD_F_RAW && sim->p_ref != 0.0) {
+      const double* W = sim->lat == NFLBM_D2Q9 ? kW2 : kW3;
+      for (size_t q = 0; q < n; ++q) {
+        if (geom && sim->solid_host[q]) continue;
+        for (int k = 1; k <= Qm; ++k) host_out[size_t(k - 1) * n + q] += 3.0 * W[k] * sim->p_ref;
+      }
+    }
     return NFLBM_OK;
   }
   return fail(sim, NFLBM_EINVAL, "unknown field");
 }
 
+// The record form of f appends one host-side byte to the checkpoint: whether
+// the next step starts from the equilibria set_fields wrote.
+size_t state_tail(const nflbm_sim* s) { return s->fform ? 1 : 0; }
+
 int nflbm_state_bytes(nflbm_sim* sim, size_t* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
   size_t b = 0;
   for (const auto& seg : state_segments(sim)) b += seg.second;
-  *bytes = b;
+  *bytes = b + state_tail(sim);
   return NFLBM_OK;
 }
 
@@ -1477,6 +1812,7 @@ int nflbm_get_state(nflbm_sim* sim, void* host_raw) {
     p += seg.second;
   }
   HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  if (state_tail(sim)) *p = sim->f_local ? 1 : 0;
   return NFLBM_OK;
 }
 
@@ -1488,53 +1824,21 @@ int nflbm_set_state(nflbm_sim* sim, const void* host_raw) {
     p += seg.second;
   }
   HIPCHK(sim, hipStreamSynchronize(sim->stream));
-  return NFLBM_OK;
+  if (state_tail(sim)) sim->f_local = *p != 0;
+  return sim_nan_reset(sim);
 }
 
 int nflbm_diagnostics(nflbm_sim* sim, int vcm_component, nflbm_diag* out) {
   if (!sim || !out) return fail(sim, NFLBM_EINVAL, "NULL argument");
-  if (vcm_component < 0 || vcm_component >= sim->N) return fail(sim, NFLBM_EINVAL, "vcm_component out of range");
-  int rc = compute_fields(sim);
-  if (rc) return rc;
-  const int N = sim->N;
-  const int rec = reduce_record_len(N);
+  const int rec = reduce_record_len(sim->N);
   if (!sim->red) {
-    long long blocks = static_cast<long long>((sim->n + 4095) / 4096);
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    sim->red_blocks = static_cast<int>(blocks);
-    if (hipMalloc(reinterpret_cast<void**>(&sim->red), size_t(blocks + 1) * rec * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void**>(&sim->red), size_t(kDiagMaxBlocks + 1) * rec * sizeof(double)) !=
+        hipSuccess) {
       sim->red = nullptr;
       return fail(sim, NFLBM_ENOMEM, "cannot allocate the reduction buffer");
     }
   }
-  ReduceArgs a{};
-  a.fields = sim->fields;
-  a.partial = sim->red;
-  a.out = sim->red + size_t(sim->red_blocks) * rec;
-  a.n = static_cast<long long>(sim->n);
-  a.N = N;
-  a.vcm_comp = vcm_component;
-  a.blocks = sim->red_blocks;
-  a.bb = sim->bb;
-  HIPCHK(sim, launch_reduce(a, sim->stream));
-  std::vector<double> r(rec);
-  HIPCHK(sim, hipMemcpyAsync(r.data(), a.out, rec * sizeof(double), hipMemcpyDeviceToHost, sim->stream));
-  HIPCHK(sim, hipStreamSynchronize(sim->stream));
-  std::memset(out, 0, sizeof(*out));
-  for (int i = 0; i < N; ++i) {
-    out->mass[i] = r[i];
-    out->max_abs_c[i] = r[N + 3 + i];
-    out->min_c[i] = r[2 * N + 3 + i];
-  }
-  for (int d = 0; d < 3; ++d) out->momentum[d] = r[N + d];
-  out->max_sum_dev = r[3 * N + 3];
-  const double cm = r[3 * N + 7];
-  for (int d = 0; d < 3; ++d) out->vcm[d] = cm != 0.0 ? r[3 * N + 4 + d] / cm : 0.0;
-  out->vcm_component = vcm_component;
-  out->nan = r[3 * N + 8] != 0.0 ? 1 : 0;
-  if (out->nan) return fail(sim, NFLBM_ENUMERIC, "NaN or Inf in the state");
-  return NFLBM_OK;
+  return diag_run(sim, vcm_component, sim->red, kDiagMaxBlocks, sim->red + size_t(kDiagMaxBlocks) * rec, out);
 }
 
 int nflbm_set_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
@@ -1570,11 +1874,18 @@ int nflbm_get_launch(nflbm_sim* sim, int* tx_log2, int* zchunk, int* lds_limit) 
 
 int nflbm_storage_form(const nflbm_sim* sim) { return sim ? sim->gform : NFLBM_EINVAL; }
 
+int nflbm_f_storage_form(const nflbm_sim* sim) { return sim ? sim->fform : NFLBM_EINVAL; }
+
 int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const double Qm = sim->Q - 1, NE = sim->NE;
   double b;
-  if (sim->gform) {
+  if (sim->fform) {
+    // record form of f: the reconstruction reads C, mu~, (v, -3/2 v.v) and
+    // (fB, F) and writes C, E_B and the four f moments; the update reads C,
+    // E_B and the f moments and writes mu~, (v, -3/2 v.v) and (fB, F)
+    b = ((NE + NE + 4 + 4) + (NE + 1 + 4) + (NE + 1 + 4) + (NE + 4 + 4)) * double(sim->ts);
+  } else if (sim->gform) {
     // f read and written; reconstruction reads C, mu~, (v, -3/2 v.v) and
     // writes C, E_B; the update reads C, E_B and writes mu~, (v, -3/2 v.v)
     b = 2.0 * Qm * sim->fs + (NE + NE + 4 + NE + 1 + NE + 1 + NE + 4) * double(sim->ts);
@@ -1675,6 +1986,9 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
   auto cleanup = [&](int code, const std::string& msg) {
     for (nflbm_sim* m : b->members) nflbm_destroy(m);
     if (b->params) (void)hipFree(b->params);
+    if (b->nanflag) (void)hipFree(b->nanflag);
+    if (b->nan_host) (void)hipHostFree(b->nan_host);
+    if (b->nan_ev) (void)hipEventDestroy(b->nan_ev);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
     return bfail(nullptr, code, msg);
@@ -1715,6 +2029,12 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
     if (hipMemcpy(static_cast<char*>(b->params) + psize * i, b->members[i]->params, psize,
                   hipMemcpyDeviceToDevice) != hipSuccess)
       return cleanup(NFLBM_EDEVICE, "cannot copy the coefficient tables");
+  if (hipMalloc(reinterpret_cast<void**>(&b->nanflag), sizeof(int)) != hipSuccess ||
+      hipMemset(b->nanflag, 0, sizeof(int)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->nan_host), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->nan_ev, hipEventDisableTiming) != hipSuccess)
+    return cleanup(NFLBM_ENOMEM, "cannot allocate the batch NaN flag");
+  *b->nan_host = 0;
   // default tile: 64 x 4 unless some member is at most 16 wide or the window
   // does not fit
   int l = 6;
@@ -1738,6 +2058,9 @@ void nflbm_batch_destroy(nflbm_batch* b) {
   destroy_graphs(b);
   free_batch_tables(b);
   if (b->params) (void)hipFree(b->params);
+  if (b->nanflag) (void)hipFree(b->nanflag);
+  if (b->nan_host) (void)hipHostFree(b->nan_host);
+  if (b->nan_ev) (void)hipEventDestroy(b->nan_ev);
   for (nflbm_sim* m : b->members) {
     m->stream = nullptr;
     nflbm_destroy(m);
@@ -1768,7 +2091,7 @@ int nflbm_batch_set_fields(nflbm_batch* b, int idx, const double* C, const doubl
   nflbm_sim* m = nflbm_batch_member(b, idx);
   if (!m) return NFLBM_EINVAL;
   const int rc = nflbm_set_fields(m, C, v, P);
-  return rc == NFLBM_OK ? rc : bfail(b, rc, m->err);
+  return rc == NFLBM_OK ? batch_nan_reset(b) : bfail(b, rc, m->err);
 }
 
 int nflbm_batch_get_field(nflbm_batch* b, int idx, int field, double* host_out) {
@@ -1802,6 +2125,8 @@ int nflbm_batch_step_timed(nflbm_batch* b, long long nsteps, int mode, double* m
     float t = 0.f;
     BHIPCHK(b, hipEventElapsedTime(&t, e0, e1));
     *ms = t;
+    BHIPCHK(b, nan_poll(&b->nan_pending, &b->nan_seen, b->nan_host, b->nan_ev, true));
+    if (b->nan_seen) rc = bfail(b, NFLBM_ENUMERIC, "a NaN or Inf appeared in a member's state");
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -416,6 +416,23 @@ __device__ __forceinline__ uint32_t upstream(const Nbr& b, int k) {
   return b.xo[1 - L::e[k][0]] + b.yo[1 - L::e[k][1]] + b.zo[1 - L::e[k][2]];
 }
 
+// Sum (op 0), max (op 1) or min (op 2) of v over a 256-thread workgroup:
+// wavefront shuffles, then the four wave results through scratch[0..3] in
+// LDS, in a fixed order; every thread returns the result.
+__device__ __forceinline__ double block_reduce_d(double v, int op, double* scratch) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    v = op == 0 ? v + o : (op == 1 ? fmax(v, o) : fmin(v, o));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double r = scratch[0];
+  for (int q = 1; q < 4; ++q) r = op == 0 ? r + scratch[q] : (op == 1 ? fmax(r, scratch[q]) : fmin(r, scratch[q]));
+  return r;
+}
+
 // Workgroup -> tile.  Consecutive workgroup ids are dealt round-robin to the
 // 8 XCDs, each with its own L2; the remap hands every XCD a contiguous run of
 // tiles, so the halo rows and planes a workgroup re-reads were mostly fetched

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "coeffs.h"
+#include "nflbm.h"
 
 namespace nflbm {
 
@@ -64,8 +65,16 @@ enum StepFlags {
   kFlagPotential = 2,     // potential-form surface tension
   kFlagOmega = 4,         // Omega != 0
   kFlagMoments = 8,       // moment form of g (tau_g = 1): C, mu~, v, -3/2 v.v per node
-  kFlagNoHydro = 16       // diffusive-only: f not evolved, v = 0
+  kFlagNoHydro = 16,      // diffusive-only: f not evolved, v = 0
+  kFlagCheckNaN = 32,     // this step: the update raises *nanflag at a non-finite node
+  kFlagFRecord = 64,      // record form of f (omega+ = omega- = 1): (fB, F) per node
+  kFlagFLocal = 128       // record form, first step after set_fields: a node's f is
+                          // the local equilibrium (A0, v0) of its own record
 };
+
+// What a launch of the update does: a time step, the FP64 node fields of
+// the current state (read-back), or their per-workgroup diagnostic sums.
+enum UpdateMode { kModeStep = 0, kModeFields = 1, kModeReduce = 2 };
 
 // Device code sees the pointers in the argument structs as pointers to global
 // memory, so that it emits global (not flat) accesses and scalar loads for
@@ -78,8 +87,10 @@ enum StepFlags {
 #endif
 
 // Population arrays hold post-collision values (pull streaming):
-//   f [k-1][node], gk [k-1][node][i], g0 [node][i], conc [node][i], eb [node].
-// In-plane byte offsets are 32-bit: n * NE * sizeof(value) must stay below 2^32.
+//   f [k-1][node], gk [k-1][node][i], g0 [node][i], conc [node][i], eb [node],
+// with the direction strides fstride and gstride below.
+// Per-node byte offsets are 32-bit: n times the widest per-node record
+// (NE values, the moment form's 4, the mobility variant's N) must stay below 2^32.
 struct StepArgs {
   const NFLBM_GLOBAL void* f_src;     // moving hydrodynamic populations
   NFLBM_GLOBAL void* f_dst;
@@ -94,6 +105,12 @@ struct StepArgs {
   NFLBM_GLOBAL void* mu;
   NFLBM_GLOBAL void* vel;
   NFLBM_GLOBAL void* eb;              // E_B per node (compute precision)
+  // record form of f: frec [node][4] = (fB, F) of the last collision, with
+  // fB = 3 P - 3/2 v.F (after set_fields: (3 P0 - 3/2 v0.v0, v0)),
+  // and fmom [node][4] = (sum_k f_k, sum_k e_k f_k) of the streamed f,
+  // written by the reconstruction for the update
+  NFLBM_GLOBAL void* frec;
+  NFLBM_GLOBAL void* fmom;
   NFLBM_GLOBAL double* fields;        // fields-mode output [2N+7][n]
   const NFLBM_GLOBAL void* params;    // DevParams<T>
   // Solid geometry (null without): per node, bit k (1 <= k < Q) set when the
@@ -108,7 +125,19 @@ struct StepArgs {
   NFLBM_GLOBAL void* out_f;
   NFLBM_GLOBAL void* out_g;
   NFLBM_GLOBAL void* out_ghost;
+  // NaN check (steps with kFlagCheckNaN): set to 1 where a node's C, mu~,
+  // v or P is not finite; cleared by the host
+  NFLBM_GLOBAL int* nanflag;
+  // reduce mode: partial diagnostic records [workgroup][3N + 9], internal
+  // component order, and the internal index of the component of v_cm
+  NFLBM_GLOBAL double* diag_partial;
+  int diag_vcm;
   long long n;
+  // distance in elements between the direction arrays of f (f [k-1][node]
+  // starts at (k-1) fstride) and of the moving g populations (gk [k-1]
+  // starts at (k-1) gstride): an odd multiple of 256 bytes, never a power
+  // of two, so that the direction streams fall on different memory channels
+  long long fstride, gstride;
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
   int tx_log2;                        // tile width TX = 1 << tx_log2, TY = 256 / TX
@@ -145,17 +174,7 @@ struct BatchLaunch {
   int moments;                        // members use the moment form; the
                                       // reconstruction then runs over the
                                       // update's tiles
-};
-
-struct ReduceArgs {
-  const double* fields;               // as written by the fields mode
-  double* partial;                    // [blocks][rec]
-  double* out;                        // [rec]
-  long long n;
-  int N;
-  int vcm_comp;                       // user index
-  int blocks;
-  const uint32_t* bb;                 // solid geometry or null: solid nodes are skipped
+  int frecord;                        // members keep f as node records
 };
 
 // Arguments of the two kernels of the concentration-dependent mobility
@@ -186,14 +205,48 @@ hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fie
 hipError_t launch_init(int lat, int nc, int store, const InitArgs& a, hipStream_t s);
 hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, hipStream_t s);
 hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s);
-size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2);
-hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2, bool frecord);
+// Record form of f: the post-collision f of every node written out in the
+// population layout (f [k-1][node], direction stride a.fstride, compute
+// precision) for read-back; after set_fields (kFlagFLocal) the initial
+// equilibria are placed where the first gather pulls them from.
+hipError_t launch_expand_f(int lat, int store, const StepArgs& a, void* out, hipStream_t s);
+// Diagnostics of the current state without a field buffer: the update in
+// reduce mode writes partial records for at most max_blocks workgroups to
+// a.diag_partial (returned in *blocks), then one workgroup sums them in a
+// fixed order into out [3N + 9] (internal component order).
+hipError_t launch_diag(int lat, int nc, int store, const StepArgs& a, int max_blocks, double* out, int* blocks,
+                       hipStream_t s);
+hipError_t launch_reduce_final(const double* partial, double* out, int N, int blocks, hipStream_t s);
 // Domain size (Eq. L): lambda = H(C - 1/2) over [N][n], and partial sums
 // [N][blocks][2] of |X|^2 and |k| |X|^2 over an R2C spectrum [N][nc].
 hipError_t launch_lambda(const double* C, double* lam, long long total, hipStream_t s);
 hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long long nc, int blocks,
                            double* partial, hipStream_t s);
 __host__ __device__ int reduce_record_len(int N);
+
+// Elements between consecutive direction arrays holding `count` elements of
+// `esize` bytes each: the bytes rounded up to 256 and then to an odd
+// multiple of 256.  With a power-of-two stride (256^3 lattices) the
+// direction streams of a node map to the same memory channels; measured at
+// 256^3 the update's traffic mix ran 7% faster with the odd stride.
+inline size_t direction_stride(size_t count, size_t esize) {
+  size_t b = (count * esize + 255) / 256 * 256;
+  if ((b / 256) % 2 == 0) b += 256;
+  return b / esize;
+}
+
+// The diagnostics' reduction grid is capped at this many workgroups, so its
+// partial records take at most kDiagMaxBlocks * (3 kMaxComp + 9) doubles.
+constexpr int kDiagMaxBlocks = 2048;
+// Diagnostics of the current state of s (reconstruction, the update in
+// reduce mode, the fixed-order sum) with the partial records at partial
+// (max_blocks records) and the summed record at result, both device memory
+// the caller provides; fills *out and synchronises.  Allocates nothing.
+int diag_run(nflbm_sim* s, int vcm_component, double* partial, int max_blocks, double* result, nflbm_diag* out);
+// The device s was created on, and the error path of the C ABI.
+int sim_device(const nflbm_sim* s);
+int sim_fail(nflbm_sim* s, int code, const char* msg);
 size_t update_lds_bytes(int lat, int nc, int store, int tx_log2);
 // Concentration-dependent mobility: the literal flux potentials of every node
 // (after the reconstruction), and the source term added to the update's

@@ -6,7 +6,7 @@
 // (halfway bounce-back).  Every store of the update is then aligned with the
 // node that computes it, and only loads are shifted.
 //
-// Layout, node = x + nx (y + ny z):
+// Layout, node = x + nx (y + ny z), direction arrays fstride / gstride apart:
 //   f [k-1][node]            moving hydrodynamic populations, k = 1..Q-1
 //   gk[k-1][node][i]         moving populations of the evolved components,
 //                            component innermost: one vector access moves
@@ -65,7 +65,6 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   const int z = b / a.tiles_y;
   const int x = tile_x * TX + tx, y = tile_y * (256 >> a.tx_log2) + ty;
   if (x >= a.nx || y >= a.ny) return;
-  const size_t n = static_cast<size_t>(a.n);
   const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
   const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
   if (solid_node<WALLS>(nb)) {
@@ -102,13 +101,14 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
     // opposite one plus g^eq_k + g^eq_kbar of the face (anti-bounce-back)
     const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
     const int open = (WALLS && FB) ? FB->open : 0;
+    const size_t gst = static_cast<size_t>(a.gstride);
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       FS v[NE];
       if (pulled_from_wall<L, WALLS>(nb, k))
-        vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * n * NE, node * NE), v);
+        vld_nt<FS, NE>(at(gk + size_t(opposite(k) - 1) * gst, node * NE), v);
       else
-        vld_nt<FS, NE>(at(gk + size_t(k - 1) * n * NE, upstream<L>(nb, k) * NE), v);
+        vld_nt<FS, NE>(at(gk + size_t(k - 1) * gst, upstream<L>(nb, k) * NE), v);
       const int fc = entry_face<L, WALLS>(nb, k, open);
       if (fc >= 0) {
 #pragma unroll
@@ -174,8 +174,9 @@ k_conc_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<
 // above it), so that only one plane of records occupies LDS and more
 // workgroups share a CU.
 // LDS record of one position: C in [0, NEP), mu~ in [NEP, 2 NEP), then v and
-// v.v, with NEP = NE rounded up to 4 so every group starts 16-byte aligned and
-// moves with vector reads.  The record is padded to an odd multiple of 16
+// v.v, and in the record form of f the four values (fB, F), with NEP = NE
+// rounded up to 4 so every group starts 16-byte aligned and moves with
+// vector reads.  The record is padded to an odd multiple of 16
 // bytes (12 or 20 floats, 14 or 22 doubles): consecutive positions then start
 // in different 16-byte bank groups, so a wavefront's reads of a row of
 // positions do not collide on banks.
@@ -187,14 +188,49 @@ template <class T>
 constexpr bool moment_aos() { return sizeof(T) == 4; }
 template <int NE, class T>
 constexpr int moment_nep() { return moment_aos<T>() ? (NE + 3) / 4 * 4 : NE; }
-template <int NE, class T>
+template <int NE, class T, bool FR>
 constexpr int moment_record() {
-  const int r = 2 * moment_nep<NE, T>() + 4;
+  const int r = 2 * moment_nep<NE, T>() + 4 + (FR ? 4 : 0);
   if (!moment_aos<T>()) return r;
   return (r * int(sizeof(T)) / 16) % 2 == 1 ? r : r + 16 / int(sizeof(T));
 }
 
-template <class L, int NE, int ST, bool WALLS, int TXL>
+// Record form of f (every node relaxes with omega+ = omega- = 1): the
+// post-collision f of a node is fixed by its records, Eqs. TRT, FTRT and
+// hydroforce with omega = 1 giving
+//   f*_k = w_k [s_k / w_k + fB + (e.F)(9/2 e.v +- 3/2)],  fB = 3 P - 3/2 v.F,
+// with s_k / w_k = (e.v)(9/2 e.v +- 3) - 3/2 v.v the term the equilibrium of g
+// shares, e the odd member of k's pair and + for that member.  The node
+// stores (fB, F) beside its (v, -3/2 v.v).  f_scaled returns f*_k / w_k for
+// direction kd from v4 = (v, -3/2 v.v) and fr = (fB, F).
+template <class L, class T>
+__device__ __forceinline__ T f_from_s(int kd, T ev, T u, const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T F[3] = {fr[1], fr[2], fr[3]};
+  const T eF = proj<L>(kp, F);
+  return u + fma(eF, fma(T(4.5), ev, (kd & 1) ? T(1.5) : -T(1.5)), fr[0]);
+}
+template <class L, class T>
+__device__ __forceinline__ T f_scaled(int kd, const T (&v4)[4], const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T v[3] = {v4[0], v4[1], v4[2]};
+  const T ev = proj<L>(kp, v);
+  const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
+  return f_from_s<L>(kd, ev, u, fr);
+}
+// The equilibrium of the state set_fields writes, f^eq_k(P0, v0) / w_k =
+// A0 + 9/2 (e.v0)^2 +- 3 e.v0 (Eq. feq), from the record (A0, v0) with
+// A0 = 3 P0 - 3/2 v0.v0.
+template <class L, class T>
+__device__ __forceinline__ T f_scaled_local(int kd, const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T v0[3] = {fr[1], fr[2], fr[3]};
+  const T ev = proj<L>(kp, v0);
+  const T q = fma(T(4.5) * ev, ev, fr[0]);
+  return (kd & 1) ? fma(T(3), ev, q) : fma(-T(3), ev, q);
+}
+
+template <class L, int NE, int ST, bool WALLS, int TXL, bool FR>
 __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
                                             const DevParams<typename StoreT<ST>::T>* __restrict__ Pp, int b,
                                             unsigned char* smem_raw) {
@@ -205,7 +241,8 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   constexpr bool D3 = (L::DIM == 3);
   constexpr bool AOS = moment_aos<T>();
   constexpr int NEP = moment_nep<NE, T>();
-  constexpr int REC = moment_record<NE, T>();
+  constexpr int REC = moment_record<NE, T, FR>();
+  constexpr int NF = 2 * NE + 4;          // field-major: first field of (fB, F)
   constexpr int TX = 1 << TXL;
   constexpr int TY = 256 >> TXL;
   constexpr int PX = TX + 2;
@@ -228,6 +265,9 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   const T* cprev = gptr<const T>(a.cprev);
   const T* mus = gptr<const T>(a.mu);
   const T* vels = gptr<const T>(a.vel);
+  const T* frecs = gptr<const T>(a.frec);
+  // first step after set_fields: a node's f is its own record's equilibrium
+  const bool flocal = FR && (a.flags & kFlagFLocal);
 
   uint32_t fill_off[2];
   bool fill_ok[2];
@@ -268,17 +308,19 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       if (!fill_ok[r]) continue;
       const int idx = tid + 256 * r;
       const uint32_t node = fill_off[r] + zoff;
-      T cc[NEP], mm[NEP], vv[4];
+      T cc[NEP], mm[NEP], vv[4], ff[4];
 #pragma unroll
       for (int e = NE; e < NEP; ++e) cc[e] = mm[e] = T(0);
       vld<T, NE>(at(cprev, node * NE), reinterpret_cast<T(&)[NE]>(cc));
       vld<T, NE>(at(mus, node * NE), reinterpret_cast<T(&)[NE]>(mm));
       vld<T, 4>(at(vels, node * 4), vv);
+      if constexpr (FR) vld<T, 4>(at(frecs, node * 4), ff);
       if constexpr (AOS) {
         T* rec = base + idx * REC;
         vst<T, NEP>(rec, cc);
         vst<T, NEP>(rec + NEP, mm);
         vst<T, 4>(rec + 2 * NEP, vv);
+        if constexpr (FR) vst<T, 4>(rec + 2 * NEP + 4, ff);
       } else {
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
@@ -287,6 +329,10 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) base[(2 * NE + d) * PXY + idx] = vv[d];
+        if constexpr (FR) {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) base[(NF + d) * PXY + idx] = ff[d];
+        }
       }
     }
     return true;
@@ -309,25 +355,54 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     }
   };
   constexpr int PSTEP = AOS ? REC : 1;   // distance between positions
+  // v and (fB, F) of the position at rec (record form of f)
+  auto read_f = [&](const T* rec, T (&v3)[3], T (&f4)[4]) {
+    if constexpr (AOS) {
+      T v4[4];
+      vld<T, 4>(rec + 2 * NEP, v4);
+      vld<T, 4>(rec + 2 * NEP + 4, f4);
+      v3[0] = v4[0]; v3[1] = v4[1]; v3[2] = v4[2];
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v3[d] = rec[(2 * NE + d) * PXY];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) f4[d] = rec[(NF + d) * PXY];
+    }
+  };
 
   // Per-target sums of the z march: with float records sc and sd hold
   // sum C s_k / w_k of the incoming populations over the axis and the
   // diagonal directions (weighted once at the end), in FP64 sc holds
   // sum C s_k itself; smu holds sum w_k mu~ of their sources, c and d0 the
   // node's own C and its rest-population term C s_0 + (1 - w_0) m mu~.
+  // Record form of f: fm sums the incoming f (sum_k f_k), jm their e_k f_k.
   struct Acc {
     T sc[NE], sd[NE], smu[NE], c[NE], d0[NE];
+    T fm, jm[3];
     bool solid;
   };
   auto zero_acc = [&](Acc& A) {
 #pragma unroll
     for (int e = 0; e < NE; ++e) A.sc[e] = A.sd[e] = A.smu[e] = A.c[e] = A.d0[e] = T(0);
+    A.fm = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) A.jm[d] = T(0);
     A.solid = false;
   };
+  auto add_f_value = [&](Acc& A, T fk, int kin) {
+    A.fm += fk;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (L::e[kin][d] != 0) A.jm[d] += (L::e[kin][d] > 0) ? fk : -fk;
+  };
+
   // One incoming population of direction kd whose source record is at src:
   // s_k / w_k = (e.v)(4.5 e.v +- 3) - 3/2 v.v (Eqs. feq, geq) from the
   // source's v, formed through the odd member of the pair.
-  auto add_source = [&](Acc& A, const T* src, int kd) {
+  // With the record form of f (and with_f), the same source's f*_kd is added
+  // to the moments of the f arriving along e_kin (kin = kd, or its opposite
+  // where the population is bounced back), from the same s_k / w_k.
+  auto add_source = [&](Acc& A, const T* src, int kd, int kin, bool with_f) {
     const int kp = (kd & 1) ? kd : kd - 1;
     T cs[NEP], ms[NEP], v4[4];
     read_pos(src, cs, ms, v4);
@@ -335,6 +410,22 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const T ev = proj<L>(kp, vs);
     const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
     const T wk = static_cast<T>(L::w[kp]);
+    if constexpr (FR) {
+      if (with_f) {
+        T f4[4];
+        if constexpr (AOS) {
+          vld<T, 4>(src + 2 * NEP + 4, f4);
+        } else {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) f4[d] = src[(NF + d) * PXY];
+        }
+        const T fk = wk * f_from_s<L>(kd, ev, u, f4);
+        A.fm += fk;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (L::e[kin][d] != 0) A.jm[d] += (L::e[kin][d] > 0) ? fk : -fk;
+      }
+    }
     if constexpr (!AOS) {
       // FP64: weighted per direction (the class sums' extra accumulators
       // cost the double-width kernel more than the multiplies they save)
@@ -366,7 +457,8 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       const Nbr nb = neighbours<L, WALLS>(x, y, p + 1, a);
 #pragma unroll
       for (int k = 1; k < Q; ++k)
-        if (L::e[k][2] == 1 && !pulled_from_wall<L, WALLS>(nb, k)) add_source(hi, src_at(L::e[k][0], L::e[k][1]), k);
+        if (L::e[k][2] == 1 && !pulled_from_wall<L, WALLS>(nb, k))
+          add_source(hi, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
     }
     if (p >= z0 && p < z1) {
       const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
@@ -386,15 +478,24 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       }
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
-        if (pulled_from_wall<L, WALLS>(nb, k)) add_source(mid, own, opposite(k));
-        else if (L::e[k][2] == 0) add_source(mid, src_at(L::e[k][0], L::e[k][1]), k);
+        if (pulled_from_wall<L, WALLS>(nb, k)) add_source(mid, own, opposite(k), k, !flocal);
+        else if (L::e[k][2] == 0) add_source(mid, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
+      }
+      if (FR && flocal) {
+        // first step after set_fields: every f of the node is the
+        // equilibrium of its own record (A0, v0)
+        T f4[4], v3[3];
+        read_f(own, v3, f4);
+#pragma unroll
+        for (int k = 1; k < Q; ++k) add_f_value(mid, static_cast<T>(L::w[k]) * f_scaled_local<L>(k, f4), k);
       }
     }
     if (D3 && have && p - 1 >= z0 && p - 1 < z1) {
       const Nbr nb = neighbours<L, WALLS>(x, y, p - 1, a);
 #pragma unroll
       for (int k = 1; k < Q; ++k)
-        if (L::e[k][2] == -1 && !pulled_from_wall<L, WALLS>(nb, k)) add_source(lo, src_at(L::e[k][0], L::e[k][1]), k);
+        if (L::e[k][2] == -1 && !pulled_from_wall<L, WALLS>(nb, k))
+          add_source(lo, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
     }
   };
 
@@ -411,7 +512,16 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       for (int e = 0; e < NE; ++e) sum[e] = T(0);
       vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
       *at(gptr<T>(a.eb), node) = T(0);
+      if constexpr (FR) {
+        const T z4[4] = {T(0), T(0), T(0), T(0)};
+        vst<T, 4>(at(gptr<T>(a.fmom), node * 4), z4);
+      }
       return;
+    }
+    if constexpr (FR) {
+      // moments of the streamed f: sum_k f_k and sum_k e_k f_k
+      const T fm[4] = {A.fm, A.jm[0], A.jm[1], A.jm[2]};
+      vst_nt<T, 4>(at(gptr<T>(a.fmom), node * 4), fm);
     }
     const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
     T cn[NC];
@@ -452,22 +562,22 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   }
 }
 
-template <class L, int NE, int ST, bool WALLS, int TXL>
+template <class L, int NE, int ST, bool WALLS, int TXL, bool FR>
 __global__ void __launch_bounds__(256)
 k_conc_m(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
-  conc_tile_m<L, NE, ST, WALLS, TXL>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks), smem_raw);
+  conc_tile_m<L, NE, ST, WALLS, TXL, FR>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks), smem_raw);
 }
 
-template <class L, int NE, int ST, bool WALLS, int TXL>
+template <class L, int NE, int ST, bool WALLS, int TXL, bool FR>
 __global__ void __launch_bounds__(256)
 k_conc_m_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
                const int2* __restrict__ work, int nblocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 w = work[xcd_remap(static_cast<int>(blockIdx.x), nblocks)];
   const StepArgs a = args[w.x];
-  conc_tile_m<L, NE, ST, WALLS, TXL>(a, params + w.x, w.y, smem_raw);
+  conc_tile_m<L, NE, ST, WALLS, TXL, FR>(a, params + w.x, w.y, smem_raw);
 }
 
 // Post-collision populations of the moment form written out in the
@@ -506,8 +616,8 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
       qk[e] = S::pack(gk);   // read-back layout of the population form
       qb[e] = S::pack(gb);
     }
-    vst<FS, NE>(gk + (size_t(k - 1) * n + node) * NE, qk);
-    vst<FS, NE>(gk + (size_t(k) * n + node) * NE, qb);
+    vst<FS, NE>(gk + size_t(k - 1) * size_t(a.gstride) + node * NE, qk);
+    vst<FS, NE>(gk + size_t(k) * size_t(a.gstride) + node * NE, qb);
   }
   // the rest population as the reconstruction uses it (Eq. geq)
   const T s0 = static_cast<T>(L::w[0]) * base_s;
@@ -523,7 +633,7 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
 // D2Q9, except the D3Q19 wall variant that collides stored g populations);
 // two (at most 256) for the periodic FP64 moment form in D3Q19 with N <= 5;
 // otherwise the compiler's own choice.
-template <class L, int NC, int ST, bool WALLS = false, bool GM = true>
+template <class L, int NC, int ST, bool WALLS = false, int GM = 1>
 constexpr int update_waves() {
   if (L::DIM == 3 && WALLS && !GM) return 1;
   if (ST == kStoreF64 && L::DIM == 3 && !WALLS && GM && NC <= 5) return 2;
@@ -532,10 +642,22 @@ constexpr int update_waves() {
 
 // One workgroup's share of the update: tile b of the simulation (x fastest,
 // then y, then the z run), with the LDS window at smem_raw.
-template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL, bool GM>
+// Per-thread diagnostic sums of the reduce mode, internal component order:
+// mass, momentum, max |C|, min C, max |sum C - 1|, sum C_c v, sum C_c, and a
+// count of nodes with a non-finite field (the record of launch_diag).
+template <int NC>
+struct DiagAcc {
+  double mass[NC], mom[3], maxabs[NC], minc[NC], maxdev, cv[3], cm, nan;
+};
+
+// GM: storage of g and f, 0 populations of both, 1 the moment form of g
+// (node records C, mu~, v, -3/2 v.v), 2 the moment form of g and the
+// record form of f ((fB, F) per node; the reconstruction supplies the
+// moments of the streamed f).
+template <class L, int NC, int ST, int MODE, bool WALLS, int TXL, int GM>
 __device__ __forceinline__ void update_tile(const StepArgs& a,
                                             const DevParams<typename StoreT<ST>::T>* __restrict__ Pp,
-                                            int b, unsigned char* smem_raw) {
+                                            int b, unsigned char* smem_raw, DiagAcc<NC>* acc = nullptr) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
@@ -687,16 +809,16 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     {
       const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
       const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
-      const size_t nn = fresh(n);
+      const size_t fst = fresh(size_t(a.fstride));
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         if (pulled_from_wall<L, WALLS>(nb, k)) {
-          f[k] = S::ld_raw(at(fsrc + size_t(opposite(k) - 1) * nn, node), 0);
+          f[k] = S::ld_raw(at(fsrc + size_t(opposite(k) - 1) * fst, node), 0);
           // open face: velocity Dirichlet, bounce-back plus 2 w_k (e_k . v_b) / c_s^2
           const int fc = entry_face<L, WALLS>(nb, k, open);
           if (fc >= 0) f[k] += FB->fcorr[fc][k] * FSC;
         } else {
-          f[k] = S::ld_raw(at(fsrc + size_t(k - 1) * nn, upstream<L>(nb, k)), 0);
+          f[k] = S::ld_raw(at(fsrc + size_t(k - 1) * fst, upstream<L>(nb, k)), 0);
         }
       }
     }
@@ -868,7 +990,16 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       }
       mu[i] = val;
     }
-    if constexpr (GM && !FIELDS) {
+    // NaN check, first half: a non-finite C or mu~ makes t - t NaN (finite
+    // values give 0); taken here so that mu~ need not live any longer
+    bool bad = false;
+    if (MODE == kModeStep && (a.flags & kFlagCheckNaN)) {
+      T t = T(0);
+#pragma unroll
+      for (int i = 0; i < NE; ++i) t += c[i] + mu[i];
+      bad = !(t - t == T(0));
+    }
+    if constexpr (GM >= 1 && MODE == kModeStep) {
       // moment form: mu~ goes to the node record at once instead of being
       // held through the gather of f
       const uint32_t nd = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
@@ -921,7 +1052,17 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     T fsum = T(0);
 #pragma unroll
     for (int p = 0; p < NP; ++p) sp[p] = dp[p] = T(0);
-    if (hydro) {
+    // record form of f: the reconstruction has formed sum_k f_k and
+    // sum_k e_k f_k of the streamed f (the read-back modes see the form at
+    // run time)
+    const bool frec = GM == 2 || (GM == 0 && MODE != kModeStep && (a.flags & kFlagFRecord));
+    if (hydro && frec) {
+      T fm[4];
+      vld<T, 4>(at(gptr<const T>(a.fmom), node * 4), fm);
+      fsum = fm[0];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], fm[1 + d]);
+    } else if (hydro && GM != 2) {
       load_f(z);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
@@ -941,7 +1082,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const T s0 = static_cast<T>(L::w[0]) * (-T(1.5) * vv);
     const T Pn = static_cast<T>((1.0 / 3.0) / (1.0 - L::w[0])) * (fsum + s0);
 
-    if constexpr (FIELDS) {
+    if constexpr (MODE == kModeFields) {
       double* out = gptr<double>(a.fields);
       if (pm & 1u) {          // a solid node: no fluid, every field 0
 #pragma unroll
@@ -960,6 +1101,44 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       }
       out[size_t(NC + 3) * n + node] = static_cast<double>(Pn);
       return;
+    }
+    if constexpr (MODE == kModeReduce) {
+      // the FP64 fields of this node, as the fields mode writes them, summed
+      // into the thread's diagnostics; solid nodes hold no fluid
+      if (pm & 1u) return;
+      DiagAcc<NC>& A = *acc;
+      double csum = 0.0, probe = 0.0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        const double ci = static_cast<double>(c[i]);
+        A.mass[i] += ci;
+        A.maxabs[i] = fmax(A.maxabs[i], fabs(ci));
+        A.minc[i] = fmin(A.minc[i], ci);
+        csum += ci;
+        probe += ci * 0.0;
+        if (i < NE) probe += static_cast<double>(mu[i]) * 0.0;
+      }
+      A.maxdev = fmax(A.maxdev, fabs(csum - 1.0));
+      double cc = 0.0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+        if (i == a.diag_vcm) cc = static_cast<double>(c[i]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double vd = static_cast<double>(v[d]);
+        A.mom[d] += vd;
+        A.cv[d] += cc * vd;
+        probe += vd * 0.0 + static_cast<double>(F[d]) * 0.0;
+      }
+      A.cm += cc;
+      probe += static_cast<double>(Pn) * 0.0;
+      A.nan += (probe == 0.0) ? 0.0 : 1.0;
+      return;
+    }
+    if (a.flags & kFlagCheckNaN) {
+      // second half: v and P
+      const T t = vv + Pn;
+      if (bad || !(t - t == T(0))) *a.nanflag = 1;
     }
 
     // ---- node relaxation rates: majority component, lowest user index on ties
@@ -982,7 +1161,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     G0S* g0dst = gptr<G0S>(a.g0_dst);
     const FS* gksrc = gptr<const FS>(a.gk_src);
     const T base_s = -T(1.5) * vv;
-    if constexpr (GM) {
+    if constexpr (GM >= 1) {
       // moment form: the reconstruction re-forms g* from mu~ (stored above),
       // v and -3/2 v.v
       const T vel[4] = {v[0], v[1], v[2], base_s};
@@ -990,6 +1169,14 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
     const T vF = fma(v[2], F[2], fma(v[1], F[1], v[0] * F[0]));
     const T cP = T(3) * Pn;
+    if constexpr (GM == 2) {
+      // record form of f: with omega+ = omega- = 1 the collision leaves
+      // f*_k = w_k [s_k / w_k + fB + (e.F)(9/2 e.v +- 3/2)] (see f_scaled),
+      // so the node stores fB = 3 P - 3/2 v.F and F beside (v, -3/2 v.v)
+      const T fr[4] = {static_cast<T>(fma(-T(1.5), vF, cP)), F[0], F[1], F[2]};
+      vst_nt<T, 4>(at(gptr<T>(a.frec), node * 4), fr);
+      return;
+    }
     // Per-node factors of the pair collision.  With s = f_k + f_k+1,
     // d = f_k - f_k+1, e_k.v and e_k.F of the odd member k, the TRT step with
     // Guo forcing (Eqs. TRT, FTRT, hydroforce) is, in exact arithmetic,
@@ -1009,12 +1196,13 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
     for (int i = 0; i < NE; ++i) moved[i] = T(0);
     Nbr nb;
-    if (!GM && (a.flags & kFlagNeedG)) nb = neighbours<L, WALLS>(x, y, z, a);
-    const size_t nn = fresh(n);
+    if (GM == 0 && (a.flags & kFlagNeedG)) nb = neighbours<L, WALLS>(x, y, z, a);
+    const size_t fst = fresh(size_t(a.fstride));
+    const size_t gst = fresh(size_t(a.gstride));
     // convective outflow: plane N's post-streaming g is in the plane buffer
     int gop = -1;
     uint32_t gPL = 0;
-    if (WALLS && !GM && (a.flags & kFlagNeedG) && a.out_face >= 0) {
+    if (WALLS && GM == 0 && (a.flags & kFlagNeedG) && a.out_face >= 0) {
       gop = outflow_plane_index(a.out_face, 0, x, y, z, a);
       gPL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
     }
@@ -1035,10 +1223,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         // sp, dp are raw: S and D come out raw too, with w_k scaled
         const T Sx = fma(cs, sp[p], (wk * FSC) * Is);
         const T Dx = fma(cd, dp[p], (wk * FSC) * Ia);
-        st_nt(at(fdst + size_t(k - 1) * nn, node), S::pack_raw(Sx + Dx));
-        st_nt(at(fdst + size_t(kb - 1) * nn, node), S::pack_raw(Sx - Dx));
+        st_nt(at(fdst + size_t(k - 1) * fst, node), S::pack_raw(Sx + Dx));
+        st_nt(at(fdst + size_t(kb - 1) * fst, node), S::pack_raw(Sx - Dx));
       }
-      if constexpr (GM) continue;
+      if constexpr (GM >= 1) continue;
       const T quad = quad_term<L>(ev, base_s);
       const T sk_k = s_pair_member<L>(k, ev, quad);
       const T sk_b = s_pair_member<L>(kb, ev, quad);
@@ -1053,13 +1241,13 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       }
       if (a.flags & kFlagNeedG) {
         if (pulled_from_wall<L, WALLS>(nb, k))
-          vld<FS, NE>(at(gksrc + size_t(kb - 1) * nn * NE, node * NE), ok);
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * gst, node * NE), ok);
         else
-          vld<FS, NE>(at(gksrc + size_t(k - 1) * nn * NE, upstream<L>(nb, k) * NE), ok);
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * gst, upstream<L>(nb, k) * NE), ok);
         if (pulled_from_wall<L, WALLS>(nb, kb))
-          vld<FS, NE>(at(gksrc + size_t(k - 1) * nn * NE, node * NE), ob);
+          vld<FS, NE>(at(gksrc + size_t(k - 1) * gst, node * NE), ob);
         else
-          vld<FS, NE>(at(gksrc + size_t(kb - 1) * nn * NE, upstream<L>(nb, kb) * NE), ob);
+          vld<FS, NE>(at(gksrc + size_t(kb - 1) * gst, upstream<L>(nb, kb) * NE), ob);
       }
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
@@ -1082,10 +1270,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         qb[i] = S::pack(gb);
         moved[i] += S::unpack(qk[i]) + S::unpack(qb[i]);
       }
-      vst_nt<FS, NE>(at(gkdst + size_t(k - 1) * nn * NE, node * NE), qk);
-      vst_nt<FS, NE>(at(gkdst + size_t(kb - 1) * nn * NE, node * NE), qb);
+      vst_nt<FS, NE>(at(gkdst + size_t(k - 1) * gst, node * NE), qk);
+      vst_nt<FS, NE>(at(gkdst + size_t(kb - 1) * gst, node * NE), qb);
     }
-    if constexpr (!GM) {
+    if constexpr (GM == 0) {
       G0S r0[NE];
 #pragma unroll
       for (int i = 0; i < NE; ++i) r0[i] = static_cast<G0S>(c[i] - moved[i]);
@@ -1158,26 +1346,64 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   }
 }
 
-template <class L, int NC, int ST, bool FIELDS, bool WALLS, int TXL, bool GM>
+template <class L, int NC, int ST, int MODE, bool WALLS, int TXL, int GM>
 __global__ void __launch_bounds__(256, (update_waves<L, NC, ST, WALLS, GM>()))
 k_update(StepArgs a, const DevParams<typename StoreT<ST>::T>* __restrict__ Pp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nblocks = a.tiles_x * a.tiles_y * a.chunks_z;
-  update_tile<L, NC, ST, FIELDS, WALLS, TXL, GM>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks),
+  if constexpr (MODE == kModeReduce) {
+    // grid-stride over the tiles (the grid is capped, so the partial records
+    // take bounded memory), then one record per workgroup
+    DiagAcc<NC> acc;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      acc.mass[i] = acc.maxabs[i] = 0.0;
+      acc.minc[i] = 1e300;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc.mom[d] = acc.cv[d] = 0.0;
+    acc.maxdev = acc.cm = acc.nan = 0.0;
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+      update_tile<L, NC, ST, MODE, WALLS, TXL, GM>(a, Pp, b, smem_raw, &acc);
+      __syncthreads();
+    }
+    double* scratch = reinterpret_cast<double*>(smem_raw);
+    double* out = gptr<double>(a.diag_partial) + size_t(blockIdx.x) * (3 * NC + 9);
+    auto put = [&](int q, double v, int op) {
+      v = block_reduce_d(v, op, scratch);
+      if (threadIdx.x == 0) out[q] = v;
+    };
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      put(i, acc.mass[i], 0);
+      put(NC + 3 + i, acc.maxabs[i], 1);
+      put(2 * NC + 3 + i, acc.minc[i], 2);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      put(NC + d, acc.mom[d], 0);
+      put(3 * NC + 4 + d, acc.cv[d], 0);
+    }
+    put(3 * NC + 3, acc.maxdev, 1);
+    put(3 * NC + 7, acc.cm, 0);
+    put(3 * NC + 8, acc.nan, 0);
+  } else {
+    update_tile<L, NC, ST, MODE, WALLS, TXL, GM>(a, Pp, xcd_remap(static_cast<int>(blockIdx.x), nblocks),
                                                  smem_raw);
+  }
 }
 
 // Batch form (see k_conc_batch).  The work list holds each simulation's
 // tiles contiguously, so the XCD remap keeps a simulation's neighbouring tiles
 // on one XCD.
-template <class L, int NC, int ST, bool WALLS, int TXL, bool GM>
+template <class L, int NC, int ST, bool WALLS, int TXL, int GM>
 __global__ void __launch_bounds__(256, (update_waves<L, NC, ST, WALLS, GM>()))
 k_update_batch(const StepArgs* __restrict__ args, const DevParams<typename StoreT<ST>::T>* __restrict__ params,
                const int2* __restrict__ work, int nblocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 w = work[xcd_remap(static_cast<int>(blockIdx.x), nblocks)];
   const StepArgs a = args[w.x];
-  update_tile<L, NC, ST, false, WALLS, TXL, GM>(a, params + w.x, w.y, smem_raw);
+  update_tile<L, NC, ST, kModeStep, WALLS, TXL, GM>(a, params + w.x, w.y, smem_raw);
 }
 
 // ------------------------------------------------------------------ k_init
@@ -1186,7 +1412,7 @@ k_update_batch(const StepArgs* __restrict__ args, const DevParams<typename Store
 // node must receive along e_k is stored where that node will pull it from.
 // Every slot is written exactly once.  In the moment form the same g follows
 // from the record C = C0, mu~ = 0, v = 0 (every s_k(0) is 0).
-template <class L, int NC, int ST, bool WALLS, bool GM>
+template <class L, int NC, int ST, bool WALLS, int GM>
 __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   using S = StoreT<ST>;
   using T = typename S::T;
@@ -1196,6 +1422,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   constexpr int NE = NC - 1;
   const DevParams<T>& P = *static_cast<const DevParams<T>*>(a.params);
   const size_t n = static_cast<size_t>(a.n);
+  const size_t fst = static_cast<size_t>(a.sa.fstride), gst = static_cast<size_t>(a.sa.gstride);
   FS* f = static_cast<FS*>(a.f);
   FS* gk = static_cast<FS*>(a.gk);
   G0S* g0 = static_cast<G0S*>(a.g0);
@@ -1212,13 +1439,17 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     for (int e = 0; e < NE; ++e) zf[e] = S::pack(T(0));
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
-      f[size_t(k - 1) * n + node] = S::pack(T(0));
-      if (!GM) vst<FS, NE>(gk + (size_t(k - 1) * n + node) * NE, zf);
+      if (GM != 2) f[size_t(k - 1) * fst + node] = S::pack(T(0));
+      if (GM == 0) vst<FS, NE>(gk + size_t(k - 1) * gst + size_t(node) * NE, zf);
+    }
+    if constexpr (GM == 2) {
+      const T zr[4] = {T(0), T(0), T(0), T(0)};
+      vst<T, 4>(gptr<T>(a.sa.frec) + size_t(node) * 4, zr);
     }
     T z0[NE], z4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < NE; ++i) z0[i] = T(0);
-    if constexpr (GM) {
+    if constexpr (GM >= 1) {
       vst<T, NE>(gptr<T>(a.sa.cprev) + size_t(node) * NE, z0);
       vst<T, NE>(gptr<T>(a.sa.mu) + size_t(node) * NE, z0);
       vst<T, 4>(gptr<T>(a.sa.vel) + size_t(node) * 4, z4);
@@ -1239,8 +1470,16 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   FS zero[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) zero[e] = S::pack(T(0));
+  if constexpr (GM == 2) {
+    // record form of f: (A0, v0) with A0 = 3 P0 - 3/2 v0.v0; the first step
+    // takes each node's f as this record's equilibrium (kFlagFLocal)
+    const T fr[4] = {static_cast<T>(3.0 * Pn - 1.5 * vv), static_cast<T>(v[0]), static_cast<T>(v[1]),
+                     static_cast<T>(v[2])};
+    vst<T, 4>(gptr<T>(a.sa.frec) + size_t(node) * 4, fr);
+  }
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
+    if constexpr (GM == 2) break;
     double ev = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) ev += L::e[k][d] * v[d];
@@ -1252,25 +1491,25 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
       const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.sa.faces);
       const int fc = entry_face<L, WALLS>(nb, k, (WALLS && FB) ? FB->open : 0);
       if (fc >= 0) {
-        f[size_t(opposite(k) - 1) * n + node] =
+        f[size_t(opposite(k) - 1) * fst + node] =
             S::pack(static_cast<T>(3.0 * L::w[k] * Pn + s) - FB->fcorr[fc][k]);
-        if (!GM) {
+        if (GM == 0) {
           FS gs[NE];
 #pragma unroll
           for (int e = 0; e < NE; ++e) gs[e] = S::pack(FB->gsum[fc][e][k]);
-          vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, gs);
+          vst<FS, NE>(gk + size_t(opposite(k) - 1) * gst + size_t(node) * NE, gs);
         }
         continue;
       }
-      f[size_t(opposite(k) - 1) * n + node] = val;
-      if (!GM) vst<FS, NE>(gk + (size_t(opposite(k) - 1) * n + node) * NE, zero);
+      f[size_t(opposite(k) - 1) * fst + node] = val;
+      if (GM == 0) vst<FS, NE>(gk + size_t(opposite(k) - 1) * gst + size_t(node) * NE, zero);
     } else {
       const uint32_t src = upstream<L>(nb, k);
-      f[size_t(k - 1) * n + src] = val;
-      if (!GM) vst<FS, NE>(gk + (size_t(k - 1) * n + src) * NE, zero);
+      f[size_t(k - 1) * fst + src] = val;
+      if (GM == 0) vst<FS, NE>(gk + size_t(k - 1) * gst + size_t(src) * NE, zero);
     }
   }
-  if constexpr (GM) {
+  if constexpr (GM >= 1) {
     T c0[NE], z0[NE], z4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
@@ -1288,87 +1527,50 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
   }
 }
 
+// Record form of f: the f the next gather reads, in the population layout
+// (compute precision, direction stride a.fstride), for read-back.  After a
+// step every node's post-collision f*_k is formed from its records; after
+// set_fields (kFlagFLocal) each node's initial equilibrium is placed where
+// its first gather pulls it from, as k_init places populations.
+template <class L, int ST, bool WALLS>
+__global__ void __launch_bounds__(256) k_expand_f(StepArgs a, void* out) {
+  using T = typename StoreT<ST>::T;
+  constexpr int Q = L::Q;
+  const size_t n = static_cast<size_t>(a.n);
+  const size_t node = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n) return;
+  const size_t fst = static_cast<size_t>(a.fstride);
+  T* o = static_cast<T*>(out);
+  T fr[4];
+  vld<T, 4>(gptr<const T>(a.frec) + node * 4, fr);
+  if (!(a.flags & kFlagFLocal)) {
+    T v4[4];
+    vld<T, 4>(gptr<const T>(a.vel) + node * 4, v4);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) o[size_t(k - 1) * fst + node] = static_cast<T>(L::w[k]) * f_scaled<L>(k, v4, fr);
+    return;
+  }
+  const int x = int(node % size_t(a.nx));
+  const int y = int((node / size_t(a.nx)) % size_t(a.ny));
+  const int z = int(node / (size_t(a.nx) * size_t(a.ny)));
+  const Nbr nb = neighbours<L, WALLS>(x, y, z, a);
+  if (solid_node<WALLS>(nb)) {
+#pragma unroll
+    for (int k = 1; k < Q; ++k) o[size_t(k - 1) * fst + node] = T(0);
+    return;
+  }
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    const T val = static_cast<T>(L::w[k]) * f_scaled_local<L>(k, fr);
+    if (pulled_from_wall<L, WALLS>(nb, k)) o[size_t(opposite(k) - 1) * fst + node] = val;
+    else o[size_t(k - 1) * fst + upstream<L>(nb, k)] = val;
+  }
+}
+
 // ---------------------------------------------------------------- k_reduce
 #if !defined(NFLBM_UNIT_STORE) || NFLBM_UNIT_STORE < 0
-// Record per block: mass[N], mom[3], maxabs[N], minc[N], maxdev, cv[3], cmass, nan.
+// Diagnostic record: mass[N], mom[3], maxabs[N], minc[N], maxdev, cv[3], cmass, nan.
 __host__ __device__ int reduce_record_len(int N) { return 3 * N + 9; }
-
-__device__ __forceinline__ double shfl_down_d(double v, int off) { return __shfl_down(v, off, 64); }
-
-template <int OP>  // 0 sum, 1 max, 2 min
-__device__ double block_reduce(double v, double* scratch) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = shfl_down_d(v, off);
-    if (OP == 0) v += o;
-    else if (OP == 1) v = fmax(v, o);
-    else v = fmin(v, o);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) scratch[wave] = v;
-  __syncthreads();
-  double r = scratch[0];
-  for (int q = 1; q < 4; ++q) {
-    if (OP == 0) r += scratch[q];
-    else if (OP == 1) r = fmax(r, scratch[q]);
-    else r = fmin(r, scratch[q]);
-  }
-  return r;
-}
-
-__global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
-  __shared__ double scratch[4];
-  const int N = a.N;
-  const size_t n = static_cast<size_t>(a.n);
-  const int rec = reduce_record_len(N);
-  double* out = a.partial + size_t(blockIdx.x) * rec;
-  const double* f = a.fields;
-  const size_t per = (n + a.blocks - 1) / a.blocks;
-  const size_t lo = size_t(blockIdx.x) * per;
-  const size_t hi = lo + per < n ? lo + per : n;
-  // one pass per quantity keeps the register footprint small
-  for (int q = 0; q < rec; ++q) {
-    int op = 0;
-    double acc;
-    if (q < N) { acc = 0.0; }
-    else if (q < N + 3) { acc = 0.0; }
-    else if (q < 2 * N + 3) { acc = 0.0; op = 1; }
-    else if (q < 3 * N + 3) { acc = 1e300; op = 2; }
-    else if (q == 3 * N + 3) { acc = 0.0; op = 1; }
-    else { acc = 0.0; }
-    for (size_t node = lo + threadIdx.x; node < hi; node += 256) {
-      if (a.bb && (a.bb[node] & 1u)) continue;     // solid node: no fluid
-      double val;
-      if (q < N) val = f[size_t(q) * n + node];
-      else if (q < N + 3) val = f[size_t(q) * n + node];
-      else if (q < 2 * N + 3) val = fabs(f[size_t(q - N - 3) * n + node]);
-      else if (q < 3 * N + 3) val = f[size_t(q - 2 * N - 3) * n + node];
-      else if (q == 3 * N + 3) {
-        double s = 0.0;
-        for (int i = 0; i < N; ++i) s += f[size_t(i) * n + node];
-        val = fabs(s - 1.0);
-      } else if (q < 3 * N + 7) {
-        val = f[size_t(a.vcm_comp) * n + node] * f[size_t(N + q - 3 * N - 4) * n + node];
-      } else if (q == 3 * N + 7) {
-        val = f[size_t(a.vcm_comp) * n + node];
-      } else {
-        // NaN / Inf anywhere in the node's fields
-        double s = 0.0;
-        for (int r = 0; r < 2 * N + 7; ++r) s += f[size_t(r) * n + node] * 0.0;
-        val = (s == 0.0) ? 0.0 : 1.0;
-      }
-      if (op == 0) acc += val;
-      else if (op == 1) acc = fmax(acc, val);
-      else acc = fmin(acc, val);
-    }
-    double r;
-    if (op == 0) r = block_reduce<0>(acc, scratch);
-    else if (op == 1) r = block_reduce<1>(acc, scratch);
-    else r = block_reduce<2>(acc, scratch);
-    if (threadIdx.x == 0) out[q] = r;
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------ solid geometry
 // StepArgs::bb of every node from the byte mask solid[n]: bit k set when
@@ -1436,9 +1638,8 @@ __global__ void __launch_bounds__(256) k_spectrum(const double2* __restrict__ X,
     as += w * S;
     ak += w * kmag * S;
   }
-  as = block_reduce<0>(as, scratch);
-  __syncthreads();
-  ak = block_reduce<0>(ak, scratch);
+  as = block_reduce_d(as, 0, scratch);
+  ak = block_reduce_d(ak, 0, scratch);
   if (threadIdx.x == 0) {
     double* out = partial + (static_cast<long long>(comp) * gridDim.x + blockIdx.x) * 2;
     out[0] = as;
@@ -1446,20 +1647,21 @@ __global__ void __launch_bounds__(256) k_spectrum(const double2* __restrict__ X,
   }
 }
 
-__global__ void __launch_bounds__(64) k_reduce_final(ReduceArgs a) {
-  const int N = a.N;
+// Sum the partial diagnostic records [blocks][3N + 9] in block order.
+__global__ void __launch_bounds__(64) k_reduce_final(const double* __restrict__ partial, double* __restrict__ out,
+                                                     int N, int blocks) {
   const int rec = reduce_record_len(N);
   for (int q = threadIdx.x; q < rec; q += 64) {
-    double acc = a.partial[q];
-    for (int b = 1; b < a.blocks; ++b) {
-      const double v = a.partial[size_t(b) * rec + q];
+    double acc = partial[q];
+    for (int b = 1; b < blocks; ++b) {
+      const double v = partial[size_t(b) * rec + q];
       if (q < N + 3) acc += v;
       else if (q < 2 * N + 3) acc = fmax(acc, v);
       else if (q < 3 * N + 3) acc = fmin(acc, v);
       else if (q == 3 * N + 3) acc = fmax(acc, v);
       else acc += v;
     }
-    a.out[q] = acc;
+    out[q] = acc;
   }
 }
 #endif
@@ -1482,17 +1684,18 @@ size_t lds_bytes_for(int lat, int nc, int tx_log2) {
 
 // LDS of the moment-form reconstruction: one padded record per position.
 template <int ST>
-size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
+size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2, bool frecord) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
   const int npl = 1;   // one plane of records (the z march keeps no other)
   (void)lat;
+  const size_t extra = frecord ? 4 : 0;   // (fB, F) of the record form of f
   size_t rec;
   if (sizeof(TT<ST>) == 4) {
-    rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4;
+    rec = size_t((nc - 1 + 3) / 4 * 4) * 2 + 4 + extra;
     if ((rec * sizeof(TT<ST>) / 16) % 2 == 0) rec += 16 / sizeof(TT<ST>);
   } else {
-    rec = size_t(nc - 1) * 2 + 4;   // field-major, no padding
+    rec = size_t(nc - 1) * 2 + 4 + extra;   // field-major, no padding
   }
   return npl * rec * pxy * sizeof(TT<ST>);
 }
@@ -1500,6 +1703,9 @@ size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2) {
 hipError_t update_st0(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
 hipError_t update_st1(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
 hipError_t update_st2(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
+hipError_t diag_st0(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
+hipError_t diag_st1(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
+hipError_t diag_st2(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
 hipError_t init_st0(int lat, int nc, const InitArgs& a, hipStream_t s);
 hipError_t init_st1(int lat, int nc, const InitArgs& a, hipStream_t s);
 hipError_t init_st2(int lat, int nc, const InitArgs& a, hipStream_t s);
@@ -1510,6 +1716,9 @@ hipError_t batch_st0(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 hipError_t batch_st1(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 hipError_t batch_st2(int lat, int nc, const BatchLaunch& b, hipStream_t s);
 hipError_t expand_st0(int lat, int nc, const StepArgs& a, hipStream_t s);
+hipError_t expand_f_st0(int lat, const StepArgs& a, void* out, hipStream_t s);
+hipError_t expand_f_st1(int lat, const StepArgs& a, void* out, hipStream_t s);
+hipError_t expand_f_st2(int lat, const StepArgs& a, void* out, hipStream_t s);
 hipError_t expand_st1(int lat, int nc, const StepArgs& a, hipStream_t s);
 hipError_t expand_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
 
@@ -1529,6 +1738,13 @@ hipError_t expand_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
 
 inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr; }
 inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
+// storage form of g and f as the update's GM parameter (FP16S keeps its
+// binary16 populations of f, so it has no record form)
+template <int ST>
+inline int storage_gm(const StepArgs& a) {
+  if (!moments(a)) return 0;
+  return (ST != kStoreF16S && (a.flags & kFlagFRecord)) ? 2 : 1;
+}
 
 template <class L, int NC, int ST>
 hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
@@ -1541,42 +1757,74 @@ hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
     a.tiles_y = (a.ny + 15) / 16;
     const int blocks = a.tiles_x * a.tiles_y * a.chunks_z;
     const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, 4);
-    hipLaunchKernelGGL((k_update<L, NC, ST, true, true, 4, false>), dim3(blocks), dim3(256), lds, s, a, P);
+    hipLaunchKernelGGL((k_update<L, NC, ST, kModeFields, true, 4, false>), dim3(blocks), dim3(256), lds, s, a, P);
     return hipGetLastError();
   }
   const StepArgs& a = a0;
   const dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z);
   const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
-#define K_UPD(W, T, G) k_update<L, NC, ST, false, W, T, G>
+#define K_UPD(W, T, G) k_update<L, NC, ST, kModeStep, W, T, G>
+#define K_UPD_GM(W, T)                                                                     \
+  switch (gm) {                                                                            \
+    case 0: hipLaunchKernelGGL((K_UPD(W, T, 0)), grid, dim3(256), lds, s, a, P); break;   \
+    case 1: hipLaunchKernelGGL((K_UPD(W, T, 1)), grid, dim3(256), lds, s, a, P); break;   \
+    default:                                                                               \
+      if constexpr (ST != kStoreF16S)                                                      \
+        hipLaunchKernelGGL((K_UPD(W, T, 2)), grid, dim3(256), lds, s, a, P);               \
+      break;                                                                               \
+  }
   {
-    const bool w_ = any_wall(a), m_ = moments(a);
+    const bool w_ = any_wall(a);
+    const int gm = storage_gm<ST>(a);
     if (a.tx_log2 == 6) {
-      if (w_) { if (m_) hipLaunchKernelGGL((K_UPD(true, 6, true)), grid, dim3(256), lds, s, a, P);
-                else hipLaunchKernelGGL((K_UPD(true, 6, false)), grid, dim3(256), lds, s, a, P); }
-      else { if (m_) hipLaunchKernelGGL((K_UPD(false, 6, true)), grid, dim3(256), lds, s, a, P);
-             else hipLaunchKernelGGL((K_UPD(false, 6, false)), grid, dim3(256), lds, s, a, P); }
+      if (w_) { K_UPD_GM(true, 6) } else { K_UPD_GM(false, 6) }
     } else if (a.tx_log2 == 4) {
-      if (w_) { if (m_) hipLaunchKernelGGL((K_UPD(true, 4, true)), grid, dim3(256), lds, s, a, P);
-                else hipLaunchKernelGGL((K_UPD(true, 4, false)), grid, dim3(256), lds, s, a, P); }
-      else { if (m_) hipLaunchKernelGGL((K_UPD(false, 4, true)), grid, dim3(256), lds, s, a, P);
-             else hipLaunchKernelGGL((K_UPD(false, 4, false)), grid, dim3(256), lds, s, a, P); }
+      if (w_) { K_UPD_GM(true, 4) } else { K_UPD_GM(false, 4) }
     } else {
       return hipErrorInvalidValue;
     }
   }
+#undef K_UPD_GM
 #undef K_UPD
   return hipGetLastError();
+}
+
+// Diagnostics: the fields mode's launch shape (16-wide tiles, walls handled
+// at run time) in reduce mode over at most max_blocks workgroups, then the
+// fixed-order sum of their records.
+template <class L, int NC, int ST>
+hipError_t launch_diag_t(const StepArgs& a0, int max_blocks, double* out, int* nblk, hipStream_t s) {
+  const auto* P = (const DevParams<TT<ST>>*)(a0.params);
+  StepArgs a = a0;
+  a.tx_log2 = 4;
+  a.tiles_x = (a.nx + 15) / 16;
+  a.tiles_y = (a.ny + 15) / 16;
+  const long long tiles = 1LL * a.tiles_x * a.tiles_y * a.chunks_z;
+  const int blocks = static_cast<int>(tiles < max_blocks ? tiles : max_blocks);
+  const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, 4);
+  hipLaunchKernelGGL((k_update<L, NC, ST, kModeReduce, true, 4, false>), dim3(blocks), dim3(256), lds, s, a, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  *nblk = blocks;
+  return launch_reduce_final(a.diag_partial, out, NC, blocks, s);
 }
 
 template <class L, int NC, int ST>
 hipError_t launch_init_t(const InitArgs& ia, hipStream_t s) {
   const StepArgs& a = ia.sa;
   const dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
-  const bool w_ = any_wall(a), m_ = moments(a);
-  if (w_) { if (m_) hipLaunchKernelGGL((k_init<L, NC, ST, true, true>), grid, dim3(256), 0, s, ia);
-            else hipLaunchKernelGGL((k_init<L, NC, ST, true, false>), grid, dim3(256), 0, s, ia); }
-  else { if (m_) hipLaunchKernelGGL((k_init<L, NC, ST, false, true>), grid, dim3(256), 0, s, ia);
-         else hipLaunchKernelGGL((k_init<L, NC, ST, false, false>), grid, dim3(256), 0, s, ia); }
+  const bool w_ = any_wall(a);
+  const int gm = storage_gm<ST>(a);
+#define K_INIT(W)                                                                                \
+  switch (gm) {                                                                                  \
+    case 0: hipLaunchKernelGGL((k_init<L, NC, ST, W, 0>), grid, dim3(256), 0, s, ia); break;    \
+    case 1: hipLaunchKernelGGL((k_init<L, NC, ST, W, 1>), grid, dim3(256), 0, s, ia); break;    \
+    default:                                                                                     \
+      if constexpr (ST != kStoreF16S) hipLaunchKernelGGL((k_init<L, NC, ST, W, 2>), grid, dim3(256), 0, s, ia); \
+      break;                                                                                     \
+  }
+  if (w_) { K_INIT(true) } else { K_INIT(false) }
+#undef K_INIT
   return hipGetLastError();
 }
 
@@ -1585,24 +1833,38 @@ hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
   const auto* P = (const DevParams<TT<ST>>*)(a.params);
   const bool w_ = any_wall(a);
   if (moments(a)) {
+    const bool fr = storage_gm<ST>(a) == 2;
     const dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z);
-    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2);
-#define K_CM(W, T) k_conc_m<L, NC - 1, ST, W, T>
+    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, a.tx_log2, fr);
+#define K_CM(W, T, F) k_conc_m<L, NC - 1, ST, W, T, F>
+#define K_CM_FR(W, T)                                                                         \
+  if (fr) {                                                                                   \
+    if constexpr (ST != kStoreF16S) hipLaunchKernelGGL((K_CM(W, T, true)), grid, dim3(256), lds, s, a, P); \
+  } else {                                                                                    \
+    hipLaunchKernelGGL((K_CM(W, T, false)), grid, dim3(256), lds, s, a, P);                   \
+  }
     if (a.tx_log2 == 6) {
-      if (w_) hipLaunchKernelGGL((K_CM(true, 6)), grid, dim3(256), lds, s, a, P);
-      else hipLaunchKernelGGL((K_CM(false, 6)), grid, dim3(256), lds, s, a, P);
+      if (w_) { K_CM_FR(true, 6) } else { K_CM_FR(false, 6) }
     } else if (a.tx_log2 == 4) {
-      if (w_) hipLaunchKernelGGL((K_CM(true, 4)), grid, dim3(256), lds, s, a, P);
-      else hipLaunchKernelGGL((K_CM(false, 4)), grid, dim3(256), lds, s, a, P);
+      if (w_) { K_CM_FR(true, 4) } else { K_CM_FR(false, 4) }
     } else {
       return hipErrorInvalidValue;
     }
+#undef K_CM_FR
 #undef K_CM
     return hipGetLastError();
   }
   const int blocks = a.tiles_x * a.tiles_y * a.nz;
   if (w_) hipLaunchKernelGGL((k_conc<L, NC - 1, ST, true>), dim3(blocks), dim3(256), 0, s, a, P);
   else hipLaunchKernelGGL((k_conc<L, NC - 1, ST, false>), dim3(blocks), dim3(256), 0, s, a, P);
+  return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t launch_expand_f_t(const StepArgs& a, void* out, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((a.n + 255) / 256);
+  if (any_wall(a)) hipLaunchKernelGGL((k_expand_f<L, ST, true>), dim3(blocks), dim3(256), 0, s, a, out);
+  else hipLaunchKernelGGL((k_expand_f<L, ST, false>), dim3(blocks), dim3(256), 0, s, a, out);
   return hipGetLastError();
 }
 
@@ -1620,21 +1882,28 @@ template <class L, int NC, int ST>
 hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   const auto* P = static_cast<const DevParams<TT<ST>>*>(b.params);
   const dim3 blk(256);
+  const bool fr = ST != kStoreF16S && b.moments && b.frecord;
   hipError_t e;
   if (b.moments) {
     const dim3 grid(b.blocks_update);
     const int nb = b.blocks_update;
-    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
-#define K_CMB(W, T) k_conc_m_batch<L, NC - 1, ST, W, T>
+    const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2, fr);
+#define K_CMB(W, T, F) k_conc_m_batch<L, NC - 1, ST, W, T, F>
+#define K_CMB_FR(W, T)                                                                                \
+  if (fr) {                                                                                           \
+    if constexpr (ST != kStoreF16S)                                                                   \
+      hipLaunchKernelGGL((K_CMB(W, T, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);       \
+  } else {                                                                                            \
+    hipLaunchKernelGGL((K_CMB(W, T, false)), grid, blk, lds, s, b.args, P, b.work_update, nb);        \
+  }
     if (b.tx_log2 == 6) {
-      if (b.walls) hipLaunchKernelGGL((K_CMB(true, 6)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-      else hipLaunchKernelGGL((K_CMB(false, 6)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+      if (b.walls) { K_CMB_FR(true, 6) } else { K_CMB_FR(false, 6) }
     } else if (b.tx_log2 == 4) {
-      if (b.walls) hipLaunchKernelGGL((K_CMB(true, 4)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-      else hipLaunchKernelGGL((K_CMB(false, 4)), grid, blk, lds, s, b.args, P, b.work_update, nb);
+      if (b.walls) { K_CMB_FR(true, 4) } else { K_CMB_FR(false, 4) }
     } else {
       return hipErrorInvalidValue;
     }
+#undef K_CMB_FR
 #undef K_CMB
   } else {
     if (b.walls)
@@ -1647,20 +1916,25 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
   const dim3 grid(b.blocks_update);
   const int nb = b.blocks_update;
+  const int gm = !b.moments ? 0 : (fr ? 2 : 1);
 #define K_UB(W, T, G) k_update_batch<L, NC, ST, W, T, G>
+#define K_UB_GM(W, T)                                                                                  \
+  switch (gm) {                                                                                        \
+    case 0: hipLaunchKernelGGL((K_UB(W, T, 0)), grid, blk, lds, s, b.args, P, b.work_update, nb); break; \
+    case 1: hipLaunchKernelGGL((K_UB(W, T, 1)), grid, blk, lds, s, b.args, P, b.work_update, nb); break; \
+    default:                                                                                           \
+      if constexpr (ST != kStoreF16S)                                                                  \
+        hipLaunchKernelGGL((K_UB(W, T, 2)), grid, blk, lds, s, b.args, P, b.work_update, nb);          \
+      break;                                                                                           \
+  }
   if (b.tx_log2 == 6) {
-    if (b.walls) { if (b.moments) hipLaunchKernelGGL((K_UB(true, 6, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-                   else hipLaunchKernelGGL((K_UB(true, 6, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
-    else { if (b.moments) hipLaunchKernelGGL((K_UB(false, 6, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-           else hipLaunchKernelGGL((K_UB(false, 6, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
+    if (b.walls) { K_UB_GM(true, 6) } else { K_UB_GM(false, 6) }
   } else if (b.tx_log2 == 4) {
-    if (b.walls) { if (b.moments) hipLaunchKernelGGL((K_UB(true, 4, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-                   else hipLaunchKernelGGL((K_UB(true, 4, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
-    else { if (b.moments) hipLaunchKernelGGL((K_UB(false, 4, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);
-           else hipLaunchKernelGGL((K_UB(false, 4, false)), grid, blk, lds, s, b.args, P, b.work_update, nb); }
+    if (b.walls) { K_UB_GM(true, 4) } else { K_UB_GM(false, 4) }
   } else {
     return hipErrorInvalidValue;
   }
+#undef K_UB_GM
 #undef K_UB
   return hipGetLastError();
 }
@@ -1687,6 +1961,13 @@ hipError_t update_nc(int nc, const StepArgs& a, bool fields, hipStream_t s) {
 }
 
 template <class L, int ST>
+hipError_t diag_nc(int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s) {
+#define CALL_D(K) launch_diag_t<L, K, ST>(a, mb, out, nb, s)
+  NFLBM_NC_SWITCH(nc, CALL_D)
+#undef CALL_D
+}
+
+template <class L, int ST>
 hipError_t init_nc(int nc, const InitArgs& a, hipStream_t s) {
 #define CALL_I(K) launch_init_t<L, K, ST>(a, s)
   NFLBM_NC_SWITCH(nc, CALL_I)
@@ -1707,6 +1988,10 @@ hipError_t expand_nc(int nc, const StepArgs& a, hipStream_t s) {
 hipError_t NFLBM_CAT(update_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s) {
   return lat == 0 ? update_nc<D2Q9, NFLBM_ST>(nc, a, fields, s) : update_nc<D3Q19, NFLBM_ST>(nc, a, fields, s);
 }
+hipError_t NFLBM_CAT(diag_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb,
+                                       hipStream_t s) {
+  return lat == 0 ? diag_nc<D2Q9, NFLBM_ST>(nc, a, mb, out, nb, s) : diag_nc<D3Q19, NFLBM_ST>(nc, a, mb, out, nb, s);
+}
 hipError_t NFLBM_CAT(init_st, NFLBM_ST)(int lat, int nc, const InitArgs& a, hipStream_t s) {
   return lat == 0 ? init_nc<D2Q9, NFLBM_ST>(nc, a, s) : init_nc<D3Q19, NFLBM_ST>(nc, a, s);
 }
@@ -1715,6 +2000,9 @@ hipError_t NFLBM_CAT(conc_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipS
 }
 hipError_t NFLBM_CAT(batch_st, NFLBM_ST)(int lat, int nc, const BatchLaunch& b, hipStream_t s) {
   return lat == 0 ? batch_nc<D2Q9, NFLBM_ST>(nc, b, s) : batch_nc<D3Q19, NFLBM_ST>(nc, b, s);
+}
+hipError_t NFLBM_CAT(expand_f_st, NFLBM_ST)(int lat, const StepArgs& a, void* out, hipStream_t s) {
+  return lat == 0 ? launch_expand_f_t<D2Q9, NFLBM_ST>(a, out, s) : launch_expand_f_t<D3Q19, NFLBM_ST>(a, out, s);
 }
 hipError_t NFLBM_CAT(expand_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
   return lat == 0 ? expand_nc<D2Q9, NFLBM_ST>(nc, a, s) : expand_nc<D3Q19, NFLBM_ST>(nc, a, s);
@@ -1730,12 +2018,21 @@ size_t update_lds_bytes(int lat, int nc, int store, int tx_log2) {
   }
 }
 
-size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2) {
+size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2, bool frecord) {
   switch (store) {
-    case kStoreF64: return conc_m_lds_bytes_for<kStoreF64>(lat, nc, tx_log2);
-    case kStoreF32: return conc_m_lds_bytes_for<kStoreF32>(lat, nc, tx_log2);
-    default: return conc_m_lds_bytes_for<kStoreF16S>(lat, nc, tx_log2);
+    case kStoreF64: return conc_m_lds_bytes_for<kStoreF64>(lat, nc, tx_log2, frecord);
+    case kStoreF32: return conc_m_lds_bytes_for<kStoreF32>(lat, nc, tx_log2, frecord);
+    default: return conc_m_lds_bytes_for<kStoreF16S>(lat, nc, tx_log2, false);
   }
+}
+
+hipError_t launch_expand_f(int lat, int store, const StepArgs& a, void* out, hipStream_t s) {
+  switch (store) {
+    case kStoreF64: return expand_f_st0(lat, a, out, s);
+    case kStoreF32: return expand_f_st1(lat, a, out, s);
+    case kStoreF16S: return expand_f_st2(lat, a, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s) {
@@ -1752,6 +2049,16 @@ hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fie
     case kStoreF64: return update_st0(lat, nc, a, fields, s);
     case kStoreF32: return update_st1(lat, nc, a, fields, s);
     case kStoreF16S: return update_st2(lat, nc, a, fields, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_diag(int lat, int nc, int store, const StepArgs& a, int max_blocks, double* out, int* blocks,
+                       hipStream_t s) {
+  switch (store) {
+    case kStoreF64: return diag_st0(lat, nc, a, max_blocks, out, blocks, s);
+    case kStoreF32: return diag_st1(lat, nc, a, max_blocks, out, blocks, s);
+    case kStoreF16S: return diag_st2(lat, nc, a, max_blocks, out, blocks, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1804,11 +2111,8 @@ hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long lo
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partial, dim3(a.blocks), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, a);
+hipError_t launch_reduce_final(const double* partial, double* out, int N, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, partial, out, N, blocks);
   return hipGetLastError();
 }
 

@@ -204,14 +204,13 @@ __global__ void __launch_bounds__(256) k_mob_source(MobArgs ma) {
     for (int e = 0; e < 3; ++e) G[i][e] = M.pre[i] * fma(aii, grad[i][e], acc[e]);
   }
 
-  const size_t n = static_cast<size_t>(a.n);
   FS* gk = gptr<FS>(a.gk_dst);
   T moved[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) moved[i] = T(0);
 #pragma unroll
   for (int k = 1; k < L::Q; ++k) {
-    FS* p = at(gk + size_t(k - 1) * n * NE, node * NE);
+    FS* p = at(gk + size_t(k - 1) * size_t(a.gstride), node * NE);
     FS v[NE];
     vld<FS, NE>(p, v);
     const T wk = static_cast<T>(L::w[k]);

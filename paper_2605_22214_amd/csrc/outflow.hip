@@ -65,14 +65,14 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, cons
   using T = typename S::T;
   using FS = typename S::FS;
   const FS* fs = gptr<const FS>(a.f_src);
-  const size_t n = static_cast<size_t>(a.n);
+  const size_t fst = static_cast<size_t>(a.fstride);
   if (pulled_from_wall<L, true>(nb, k)) {
-    T v = S::ld(fs + size_t(opposite(k) - 1) * n, node);
+    T v = S::ld(fs + size_t(opposite(k) - 1) * fst, node);
     const int fc = entry_face<L, true>(nb, k, open);
     if (fc >= 0) v += FB->fcorr[fc][k];
     return v;
   }
-  return S::ld(fs + size_t(k - 1) * n, upstream<L>(nb, k));
+  return S::ld(fs + size_t(k - 1) * fst, upstream<L>(nb, k));
 }
 
 // Post-streaming g_{e,k} (any k) of an evolved component e, pulled as the
@@ -87,13 +87,13 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, cons
   using G0S = typename S::G0S;
   if (k == 0) return static_cast<T>(gptr<const G0S>(a.g0_src)[size_t(node) * NE + e]);
   const FS* gk = gptr<const FS>(a.gk_src);
-  const size_t n = static_cast<size_t>(a.n);
+  const size_t gst = static_cast<size_t>(a.gstride);
   if (pulled_from_wall<L, true>(nb, k)) {
-    const T v = S::unpack(gk[(size_t(opposite(k) - 1) * n + node) * NE + e]);
+    const T v = S::unpack(gk[size_t(opposite(k) - 1) * gst + size_t(node) * NE + e]);
     const int fc = entry_face<L, true>(nb, k, open);
     return fc >= 0 ? FB->gsum[fc][e][k] - v : v;
   }
-  return S::unpack(gk[(size_t(k - 1) * n + upstream<L>(nb, k)) * NE + e]);
+  return S::unpack(gk[size_t(k - 1) * gst + size_t(upstream<L>(nb, k)) * NE + e]);
 }
 
 }  // namespace

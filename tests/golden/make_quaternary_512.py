@@ -8,6 +8,13 @@ the file is written once by this script (python tests/golden/make_quaternary_512
 and read by the GPU parity test.  Only oracle/ and the input generator are
 called.
 
+The oracle also runs the same case from the input moved by one unit in the
+last place at every node (workloads.ulp_perturbed); the relative spread of
+each sampled field between the two runs is written to the header.  It is
+the conditioning bound of the parity test: two correct implementations that
+round differently cannot be expected to agree more closely than the
+problem's own response to rounding-sized input differences.
+
 Each data line: x y, C_1..C_4, v_x v_y, P, f_1..f_8 (post-streaming), and
 g_{i,k} for the three evolved components (i-major, k = 0..8).
 """
@@ -26,6 +33,7 @@ from oracle.lattice import D2Q9  # noqa: E402
 N_SIDE = 512
 STEPS = 1000
 OUT = os.path.join(HERE, "quaternary_512_1000.txt")
+FIELDS = ("C", "v", "P", "f", "g")
 
 
 def sample_nodes(n, count=48, seed=2024):
@@ -37,27 +45,42 @@ def sample_nodes(n, count=48, seed=2024):
     return fixed + rest
 
 
-def main():
-    w = W.quaternary_2d(N_SIDE)
-    par = S.Params(D2Q9, w["shape"], w["sigma"], w["tau"], m=w["m"])
-    f, g = S.initial_state(par, w["C0"])
+def run(C0, par, label):
+    f, g = S.initial_state(par, C0)
     for t in range(STEPS):
         f, g, _ = S.step(f, g, par)
         if (t + 1) % 100 == 0:
-            print(f"step {t + 1}", flush=True)
+            print(f"{label}: step {t + 1}", flush=True)
     mac = S.macroscopic(f, g, par)
-    C, v, P = mac["C"], mac["v"], mac["P"]
+    nodes = sample_nodes(N_SIDE)
+    xs = np.array([p[0] for p in nodes])
+    ys = np.array([p[1] for p in nodes])
+    return {"C": mac["C"][:, 0, ys, xs].T, "v": mac["v"][:2, 0, ys, xs].T, "P": mac["P"][0, ys, xs],
+            "f": f[1:, 0, ys, xs].T, "g": np.transpose(g[:3, :, 0, ys, xs], (2, 0, 1)),
+            "mass": [float(mac["C"][i].sum()) for i in range(4)]}
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def main():
+    w = W.quaternary_2d(N_SIDE)
+    par = S.Params(D2Q9, w["shape"], w["sigma"], w["tau"], m=w["m"])
+    ref = run(w["C0"], par, "reference")
+    pert = run(W.ulp_perturbed(w["C0"]), par, "perturbed")
     lines = [
         "# Oracle state after 1000 steps of the 512 x 512 quaternary phase separation",
         "# (D2Q9, N = 4, sigma = 0.01, tau = tau_g = 1, m = 0.1, seed 0; component 4 implicit).",
         "# Written by make_quaternary_512.py from oracle/ only.",
         "# columns: x y C1..C4 vx vy P f1..f8 g[i][k] (i = 1..3, k = 0..8)",
-        "# total mass per component: " + " ".join(repr(float(C[i].sum())) for i in range(4)),
+        "# total mass per component: " + " ".join(repr(m) for m in ref["mass"]),
+        "# oracle spread under a one-ulp input perturbation (C v P f g): "
+        + " ".join(repr(rel(pert[k], ref[k])) for k in FIELDS),
     ]
-    for (x, y) in sample_nodes(N_SIDE):
-        vals = [C[i, 0, y, x] for i in range(4)] + [v[0, 0, y, x], v[1, 0, y, x], P[0, y, x]]
-        vals += [f[k, 0, y, x] for k in range(1, 9)]
-        vals += [g[i, k, 0, y, x] for i in range(3) for k in range(9)]
+    for q, (x, y) in enumerate(sample_nodes(N_SIDE)):
+        vals = list(ref["C"][q]) + list(ref["v"][q]) + [ref["P"][q]] + list(ref["f"][q])
+        vals += list(ref["g"][q].reshape(-1))
         lines.append(f"{x} {y} " + " ".join(repr(float(a)) for a in vals))
     with open(OUT, "w") as fh:
         fh.write("\n".join(lines) + "\n")

@@ -52,7 +52,7 @@ def test_host_coefficients_match_oracle(L, N):
         got = lib_c[key.lower() if key == "Psi" else key]
         valid = ~np.isnan(ref)
         scale = max(1.0, np.abs(ref[valid]).max()) if valid.any() else 1.0
-        assert np.abs(got[valid] - ref[valid]).max(initial=0.0) < 1e-10 * scale
+        assert np.abs(got[valid] - ref[valid]).max(initial=0.0) < 1e-13 * scale
         assert np.all(got[~valid] == 0.0)
 
 
@@ -60,7 +60,7 @@ def test_equal_sigma_host_tables(L):
     s = 0.004
     c = nf.coefficients(equal_sigma(5, s))
     N = 5
-    np.testing.assert_allclose(c["alpha"], -(np.eye(N) - np.ones((N, N)) / N) / s, atol=1e-9)
+    np.testing.assert_allclose(c["alpha"], -(np.eye(N) - np.ones((N, N)) / N) / s, rtol=1e-13, atol=1e-12)
 
 
 def _cfg(**kw):
@@ -137,17 +137,34 @@ def test_device_bytes_plans_without_a_device(L):
     arrays (each rounded to 256 bytes) of the storage form it would pick."""
     def al(v):
         return (v + 255) // 256 * 256
+
+    def dirs(count, es):
+        """18 direction arrays, each starting an odd multiple of 256 bytes
+        after the previous one"""
+        b = al(count * es)
+        if (b // 256) % 2 == 0:
+            b += 256
+        return 18 * b
     sig = equal_sigma(5, 0.01)
     nx, ny, nz = 20, 16, 12
     n = nx * ny * nz
-    mom = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32)
-    assert mom == 2 * al(18 * n * 4) + 2 * al(4 * n * 4) + al(4 * n * 4) + al(4 * n * 4) + al(n * 4)
+    # tau = 1 with BGK: g in its moment form and f as node records (C twice,
+    # mu~, (v, v.v), (fA, F), the f moments, E_B)
+    rec = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32)
+    assert rec == 2 * al(4 * n * 4) + 4 * al(4 * n * 4) + al(n * 4)
+    mom = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32,
+                                     flags=nf.FLAG_F_POPULATIONS)
+    assert mom == 2 * al(dirs(n, 4)) + 2 * al(4 * n * 4) + al(4 * n * 4) + al(4 * n * 4) + al(n * 4)
+    # tau != 1 keeps the populations of f
+    tau = [1.0, 0.9, 1.0, 1.0, 1.0]
+    mom2 = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, tau, m=0.1, precision=nf.FP32)
+    assert mom2 == mom
     pop = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP32,
                                      flags=nf.FLAG_G_POPULATIONS)
-    assert pop == 2 * al(18 * n * 4) + 2 * al(4 * n * 4) + 2 * al(4 * 18 * n * 4) + al(4 * n * 4) + al(n * 4)
+    assert pop == 2 * al(dirs(n, 4)) + 2 * al(4 * n * 4) + 2 * al(dirs(4 * n, 4)) + al(4 * n * 4) + al(n * 4)
     tg = nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 1.0, m=0.1, precision=nf.FP16S,
                                     tau_g=[1.0, 1.0, 0.8, 1.0, 1.0])
-    assert tg == 2 * al(18 * n * 2) + 2 * al(4 * n * 4) + 2 * al(4 * 18 * n * 2) + al(4 * n * 4) + al(n * 4)
+    assert tg == 2 * al(dirs(n, 2)) + 2 * al(4 * n * 4) + 2 * al(dirs(4 * n, 2)) + al(4 * n * 4) + al(n * 4)
     with pytest.raises(nf.NflbmError) as e:
         nf.Simulation.device_bytes("D3Q19", (nx, ny, nz), sig, 0.4, m=0.1)
     assert e.value.code == -1
@@ -170,6 +187,11 @@ def test_c2c2_mobility_plans_populations_and_skips_the_constant_bound(L):
     as populations."""
     def al(v):
         return (v + 255) // 256 * 256
+    def dirs(count, es):
+        b = al(count * es)
+        if (b // 256) % 2 == 0:
+            b += 256
+        return 8 * b
     sig = equal_sigma(4, 0.005)
     nx, ny = 40, 24
     n = nx * ny
@@ -177,7 +199,7 @@ def test_c2c2_mobility_plans_populations_and_skips_the_constant_bound(L):
         nf.Simulation.device_bytes("D2Q9", (nx, ny, 1), sig, 1.0, m=10.0, precision=nf.FP32)
     got = nf.Simulation.device_bytes("D2Q9", (nx, ny, 1), sig, 1.0, m=10.0, precision=nf.FP32,
                                      flags=nf.FLAG_C2C2_MOBILITY)
-    assert got == 2 * al(8 * n * 4) + 2 * al(3 * n * 4) + 2 * al(3 * 8 * n * 4) + al(3 * n * 4) + al(n * 4)
+    assert got == 2 * al(dirs(n, 4)) + 2 * al(3 * n * 4) + 2 * al(dirs(3 * n, 4)) + al(3 * n * 4) + al(n * 4)
 
 
 def test_batch_rejects_c2c2_members_before_the_device(L):
@@ -215,3 +237,32 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr and res.stdout == ""
+
+
+@pytest.mark.parametrize("N,side_ok,side_bad", [(3, 640, 646), (4, 640, 646)])
+def test_offset_guard_takes_the_widest_per_node_array(L, N, side_ok, side_bad):
+    """Per-node arrays are addressed with 32-bit byte offsets.  In the moment
+    form the velocity record holds four values a node, more than the N - 1
+    concentrations of N = 3 or 4, so it sets the limit: n * 4 * 4 bytes must
+    stay below 2^32 in FP32, i.e. n < 2^28 (646^3 is above, 640^3 below)."""
+    sig = equal_sigma(N, 0.01)
+    ok = nf.Simulation.device_bytes("D3Q19", (side_ok,) * 3, sig, 1.0, m=0.1, precision=nf.FP32)
+    assert ok > 0
+    with pytest.raises(nf.NflbmError) as e:
+        nf.Simulation.device_bytes("D3Q19", (side_bad,) * 3, sig, 1.0, m=0.1, precision=nf.FP32)
+    assert e.value.code == -7
+    # the population form's widest array is the N - 1 values of a direction
+    pop = nf.Simulation.device_bytes("D3Q19", (side_bad,) * 3, sig, 1.0, m=0.1, precision=nf.FP32,
+                                     flags=nf.FLAG_G_POPULATIONS)
+    assert pop > 0
+
+
+def test_offset_guard_c2c2_potentials(L):
+    """The concentration-dependent mobility keeps N flux potentials a node:
+    N = 8 in FP32 allows n < 2^27."""
+    sig = equal_sigma(8, 0.01)
+    with pytest.raises(nf.NflbmError) as e:
+        nf.Simulation.device_bytes("D2Q9", (12000, 12000, 1), sig, 1.0, m=10.0, precision=nf.FP32,
+                                   flags=nf.FLAG_C2C2_MOBILITY)
+    assert e.value.code == -7
+    assert nf.Simulation.device_bytes("D2Q9", (12000, 12000, 1), sig, 1.0, m=0.01, precision=nf.FP32) > 0

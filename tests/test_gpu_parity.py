@@ -195,10 +195,10 @@ def test_diagnostics_match_oracle():
     d = sim.diagnostics(vcm_component=2)
     od = odiag.diagnostics(f, g, par, vcm_component=2)
     np.testing.assert_allclose(d["mass"], od["mass"], rtol=1e-13)
-    np.testing.assert_allclose(d["momentum"][:2], od["momentum"][:2], rtol=1e-10, atol=1e-16)
+    np.testing.assert_allclose(d["momentum"][:2], od["momentum"][:2], rtol=1e-12, atol=1e-16)
     np.testing.assert_allclose(d["max_abs_c"], od["max_abs_c"], rtol=1e-12)
-    np.testing.assert_allclose(d["min_c"], od["min_c"], rtol=1e-10, atol=1e-15)
-    np.testing.assert_allclose(d["vcm"][:2], od["vcm"][:2], rtol=1e-9, atol=1e-18)
+    np.testing.assert_allclose(d["min_c"], od["min_c"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(d["vcm"][:2], od["vcm"][:2], rtol=1e-12, atol=1e-18)
     assert d["nan"] == 0
 
 

@@ -9,7 +9,8 @@ closed forms and against FP64.
   The diffuse-interface excess over sigma / R falls as R grows.
 * Layered Poiseuille (16 x 16 x 192, six layers, TRT Lambda = 3/16, halfway
   bounce-back, 50000 steps from the analytic profile): L2 of the x-y averaged
-  u_x(z) against Eq. velocityprof (physical sign).  In float storage the
+  u_x(z) against Eq. velocityprof (physical sign); and a run from rest that
+  must converge to the profile (4e5 steps, FP64).  In float storage the
   momentum a step adds at a node (F = 1e-7) is about 1e-4 of the populations
   it is added to (|f_k| ~ 6e-4), so the rounding of every stored population
   acts as a spurious force of ~1e-3 F: float storage moves the profile by
@@ -74,8 +75,9 @@ def test_lens_angle_all_precisions():
                            for q in v} for k, v in ang.items()}
     assert abs(ang["fp64"]["lens"] - 120.0) < 3.0
     assert abs(ang["fp64"]["lens"] - ang["oracle"]["lens"]) < 1e-6
-    assert abs(ang["fp32"]["lens"] - ang["fp64"]["lens"]) < 0.05
-    assert abs(ang["fp16s"]["lens"] - ang["fp64"]["lens"]) < 1.5
+    # about ten times the measured storage error (FP32 2.2e-5, FP16S 2.7e-5 degrees)
+    assert abs(ang["fp32"]["lens"] - ang["fp64"]["lens"]) < 3e-4
+    assert abs(ang["fp16s"]["lens"] - ang["fp64"]["lens"]) < 3e-4
 
 
 def test_laplace_pressure_all_precisions():
@@ -103,11 +105,12 @@ def test_laplace_pressure_all_precisions():
     RESULTS["laplace"] = out
     e12 = out["R12"]["fp64"]["rel_err_vs_laplace"]
     e24 = out["R24"]["fp64"]["rel_err_vs_laplace"]
-    assert abs(e24) < 0.05
+    assert abs(e24) < 0.02           # measured +1.27 % (R = 12: +3.86 %)
     assert abs(e24) < abs(e12)
     for r in ("R12", "R24"):
+        # measured FP32 4.5e-4 (R = 12) and 6e-6; FP16S 2.0e-4 and 1.5e-5
         assert abs(out[r]["fp32"]["rel_diff_vs_fp64"]) < 1e-3
-        assert abs(out[r]["fp16s"]["rel_diff_vs_fp64"]) < 5e-2
+        assert abs(out[r]["fp16s"]["rel_diff_vs_fp64"]) < 2e-3
 
 
 def test_layered_poiseuille_all_precisions():
@@ -133,9 +136,38 @@ def test_layered_poiseuille_all_precisions():
                      "max_abs_uz": float(np.abs(V[2]).max())}
         sim.close()
     RESULTS["poiseuille"] = out
-    assert out["fp64"]["L2_vs_analytic"] < 1e-2
+    # the discrete steady state of the scheme: measured FP64 6.9e-5 against
+    # Eq. velocityprof; float storage 2.0e-4 (FP32), 7.3e-4 (FP16S) from FP64
+    assert out["fp64"]["L2_vs_analytic"] < 5e-4
     assert out["fp32"]["L2_vs_fp64"] < 2e-3
     assert out["fp16s"]["L2_vs_fp64"] < 2e-3
+
+
+def test_layered_poiseuille_from_rest_converges():
+    """From rest the layered channel must reach the analytic profile of
+    Eq. velocityprof by itself.  The slowest momentum-diffusion mode of the six
+    layers decays as exp(-3.32e-5 t), so after 4e5 steps the transient is
+    below 2e-6 of the profile and what remains is the scheme's discretisation
+    error (6.9e-5 in the run started at the profile).  The flow is uniform in
+    x and y, so a 4 x 4 cross-section carries the same profile."""
+    nz, F = 192, 1e-7
+    eta = (np.linspace(0.6, 1.5, 6) - 0.5) / 3.0
+    z = np.arange(nz) + 0.5
+    prof = A.layered_profile(z, [32.0 * q for q in range(7)], eta, F)
+    w = W.layered_3d(4, 4, nz)
+    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:
+        sim.set_fields(w["C0"])
+        l2 = []
+        for _ in range(8):
+            sim.step(50000)
+            u = sim.get_field("V")[0].mean(axis=(1, 2))
+            l2.append(float(np.linalg.norm(u - prof) / np.linalg.norm(prof)))
+    RESULTS["poiseuille_from_rest_L2_every_5e4"] = l2
+    # the transient decays: 0.19 after 5e4 steps by the layered diffusion
+    # operator, then a factor ~5 per 5e4 steps down to the discretisation floor
+    assert 0.1 < l2[0] < 0.3
+    assert all(b < a for a, b in zip(l2[:5], l2[1:6]))
+    assert l2[-1] < 2e-4
 
 
 @pytest.mark.parametrize("name,prec", FORMS)
@@ -155,9 +187,20 @@ def test_mass_and_momentum_conservation(name, prec):
         "absent_max_abs": d1["max_abs_c"][4], "max_sum_dev": d1["max_sum_dev"]}
     sim.close()
     assert d1["max_abs_c"][4] == 0.0
+    # Rounding model: each node-step adds an independent error of the order of
+    # the unit roundoff times the populations it touches, so mass and
+    # momentum wander as the square root of the 2.2e8 node-steps.  Bounds are
+    # about ten times the measured values: FP64 mass 3.9e-16, momentum
+    # 3.2e-16; FP32 7.1e-9, 1.8e-8; FP16S 9.2e-9, 6.1e-7.  Momentum in exact
+    # arithmetic is conserved (Eq. Fsnew sums to zero); the potential form of
+    # the force, or a collision whose first moment misses F, drifts by many
+    # orders of magnitude more.
     if prec == nf.FP64:
-        assert max(rel) < 1e-13
-        assert mom < 1e-12
+        assert max(rel) < 4e-15
+        assert mom < 4e-15
+    elif prec == nf.FP32:
+        assert max(rel) < 1e-7
+        assert mom < 2e-7
     else:
-        assert max(rel) < 1e-6
-        assert mom < 1e-4
+        assert max(rel) < 1e-7
+        assert mom < 6e-6

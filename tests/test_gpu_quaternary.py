@@ -2,16 +2,21 @@
 
 * FP64 after 1000 steps, in the default launch shape, against the oracle's
   state at sampled nodes (tests/golden/quaternary_512_1000.txt, written by
-  make_quaternary_512.py from the oracle alone).  C and the g populations,
-  whose scale is set by C ~ 1/4, agree to 1e-12 of that scale.  v, P and the
-  f populations are O(1e-6) quantities formed from O(1) ones: two oracle
-  runs whose inputs differ by 1e-16 relative already differ by ~2e-12 of
-  max |v| after 1000 steps here, so they are held to 1e-10 of their scale.
+  make_quaternary_512.py from the oracle alone).  Every field is held to
+  1e-12 of its scale or to ten times the problem's own response to a
+  one-ulp perturbation of the input, whichever is larger (the conditioning
+  bound): the oracle's spread is stored in the golden file, the GPU's is
+  measured here from a second run of the perturbed input.  C and the g
+  populations, whose scale is set by C ~ 1/4, meet 1e-12 outright; v, P and
+  the f populations are O(1e-6) quantities formed from O(1) ones, and a
+  one-ulp change of C0 already moves them by about 1e-12 of their scale
+  after 1000 steps of this phase separation.
 * 20000 steps (the full run) in FP64 and FP32: per-component mass, total
   momentum and sum_i C_i = 1 hold to rounding; the FP32 / FP64 difference of
   the concentration field is recorded.  The surface-tension force sums to
   zero over the lattice only in exact arithmetic (Eq. Fsnew), so the total
-  momentum is held to a rounding-sized budget per node and step.
+  momentum is held to a rounding budget that grows as the square root of
+  the node-steps (independent rounding errors of either sign).
 
 Measured values are written to quaternary.json in the results directory.
 """
@@ -41,51 +46,64 @@ def record():
         json.dump(RESULTS, fh, indent=1, sort_keys=True)
 
 
+FIELDS = ("C", "v", "P", "f", "g")
+
+
 def load_golden():
     masses = None
+    spread = None
     rows = []
     with open(GOLDEN) as fh:
         for line in fh:
             if line.startswith("# total mass per component:"):
                 masses = np.array([float(v) for v in line.split(":")[1].split()])
+            elif line.startswith("# oracle spread under a one-ulp input perturbation"):
+                spread = dict(zip(FIELDS, (float(v) for v in line.split(":")[1].split())))
             elif not line.startswith("#") and line.strip():
                 rows.append([float(v) for v in line.split()])
-    return masses, np.array(rows)
+    return masses, spread, np.array(rows)
+
+
+def _sampled(sim, xs, ys):
+    C = sim.get_field("C")[:, 0]
+    V = sim.get_field("V")[:, 0]
+    P = sim.get_field("P")[0]
+    F = sim.get_field("F_RAW")[:, 0]
+    G = sim.get_field("G_RAW")[:, :, 0]
+    return {"C": C[:, ys, xs].T, "v": V[:2, ys, xs].T, "P": P[ys, xs], "f": F[:, ys, xs].T,
+            "g": np.transpose(G[:3, :, ys, xs], (2, 0, 1))}
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
 
 
 def test_fp64_sampled_nodes_after_1000_steps():
-    masses, rows = load_golden()
+    masses, ospread, rows = load_golden()
+    assert ospread is not None, "golden file lacks the oracle's perturbation spread"
     xs, ys = rows[:, 0].astype(int), rows[:, 1].astype(int)
-    ref_C, ref_v, ref_P = rows[:, 2:6], rows[:, 6:8], rows[:, 8]
-    ref_f, ref_g = rows[:, 9:17], rows[:, 17:44].reshape(-1, 3, 9)
+    ref = {"C": rows[:, 2:6], "v": rows[:, 6:8], "P": rows[:, 8], "f": rows[:, 9:17],
+           "g": rows[:, 17:44].reshape(-1, 3, 9)}
     w = W.quaternary_2d(512)
-    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:
-        sim.set_fields(w["C0"])
-        sim.step(1000)
-        C = sim.get_field("C")[:, 0]
-        V = sim.get_field("V")[:, 0]
-        P = sim.get_field("P")[0]
-        F = sim.get_field("F_RAW")[:, 0]
-        G = sim.get_field("G_RAW")[:, :, 0]
-        d = sim.diagnostics()
-    got_C = C[:, ys, xs].T
-    got_v = V[:2, ys, xs].T
-    got_P = P[ys, xs]
-    got_f = F[:, ys, xs].T
-    got_g = np.transpose(G[:3, :, ys, xs], (2, 0, 1))
-
-    def rel(a, b):
-        return float(np.abs(a - b).max() / np.abs(b).max())
-
-    errs = {"C": rel(got_C, ref_C), "g": rel(got_g, ref_g), "v": rel(got_v, ref_v),
-            "P": rel(got_P, ref_P), "f": rel(got_f, ref_f),
-            "mass": float(np.max(np.abs(np.array(d["mass"]) - masses) / masses))}
+    got = {}
+    for key, C0 in (("ref", w["C0"]), ("pert", W.ulp_perturbed(w["C0"]))):
+        with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:
+            sim.set_fields(C0)
+            sim.step(1000)
+            got[key] = _sampled(sim, xs, ys)
+            if key == "ref":
+                d = sim.diagnostics()
+    errs = {k: _rel(got["ref"][k], ref[k]) for k in FIELDS}
+    gspread = {k: _rel(got["pert"][k], got["ref"][k]) for k in FIELDS}
+    tol = {k: max(1e-12, 10.0 * max(ospread[k], gspread[k])) for k in FIELDS}
+    errs["mass"] = float(np.max(np.abs(np.array(d["mass"]) - masses) / masses))
     RESULTS["fp64_1000_sampled_rel_err"] = errs
-    assert errs["C"] <= 1e-12
-    assert errs["g"] <= 1e-12
+    RESULTS["fp64_1000_perturbation_spread"] = {"oracle": ospread, "gpu": gspread}
+    RESULTS["fp64_1000_tolerance"] = tol
     assert errs["mass"] <= 1e-13
-    for k in ("v", "P", "f"):
-        assert errs[k] <= 1e-10, k
+    assert errs["C"] <= 1e-12 and errs["g"] <= 1e-12, errs
+    for k in FIELDS:
+        assert errs[k] <= tol[k], (k, errs, tol)
 
 
 @pytest.mark.parametrize("name,prec", [("fp64", nf.FP64), ("fp32", nf.FP32)])
@@ -109,12 +127,18 @@ def test_full_run_conservation(name, prec):
         RESULTS["full_run"]["fp32_vs_fp64_rel_L2_C"] = float(np.linalg.norm(C - ref) / np.linalg.norm(ref))
     drift = max(abs(b - a) / a for a, b in zip(d0["mass"], d1["mass"]))
     mom = max(abs(v) for v in d1["momentum"])
-    node_steps = 512 * 512 * 20000
+    # Rounding model: every node-step adds an independent rounding error of
+    # either sign, so the total momentum wanders as sqrt(node-steps).  The
+    # bounds are ten times the drift measured on the GPU (FP64 2.5e-14, FP32
+    # 5.1e-5 after 5.2e9 node-steps); a force that does not sum to zero over
+    # the lattice (the potential form, Eq. ststand) drifts by orders of
+    # magnitude more.
+    root = np.sqrt(512.0 * 512.0 * 20000.0)
     if prec == nf.FP64:
         assert drift < 1e-12
-        assert mom < 1e-18 * node_steps
+        assert mom < 3.5e-18 * root          # 2.5e-13: ten times the measured 2.5e-14
         assert d1["max_sum_dev"] < 1e-13
     else:
         assert drift < 1e-5
-        assert mom < 1e-11 * node_steps
+        assert mom < 7e-9 * root             # 5.1e-4: ten times the measured 5.1e-5
         assert d1["max_sum_dev"] < 1e-6

@@ -8,7 +8,10 @@ measured as the paper does: circles fitted to the top and bottom of each lens
 fluid's C = 0.5 contour, away from the 3|4 interface.
 They are checked against Eq. neucosine and set beside the paper's measured
 column.  Fluids 5 and 6 must stay exactly 0.0.  A short run at the same size
-is checked against the oracle.  Measured values are written to table1.json in the results directory.
+is checked against the oracle.  The batch also runs in FP32 and FP16S
+storage, each row's angles stated against FP64.  Measured values are written
+to table1.json, table1_fp32.json and table1_fp16s.json in the results
+directory.
 """
 import json
 import os
@@ -52,11 +55,16 @@ def test_table1_short_run_matches_oracle():
     assert np.all(C[4:] == 0.0)
 
 
-def test_table1_angles():
+ANGLES = {}
+
+
+def run_table1(prec):
+    """The nine tension sets as one batch in storage precision prec: the
+    measured rows, the batch time and the C_1..C_4 fields."""
     rows = table1_rows()
     ws = [W.table1_lens(r[0]) for r in rows]
     out = []
-    with nf.Batch.from_workloads(ws, precision=nf.FP64, implicit=0) as b:
+    with nf.Batch.from_workloads(ws, precision=prec, implicit=0) as b:
         for i, w in enumerate(ws):
             b.members[i].set_fields(w["C0"])
         ms = b.step_timed(STEPS, "graph")
@@ -70,6 +78,12 @@ def test_table1_angles():
                          "theory": [r[1], r[2]], "paper_measured": [r[3], r[4]],
                          "absent_max_abs": float(np.abs(C[4:]).max())})
             lens_fields.append(C[:4].astype(np.float32))
+    return out, ms, lens_fields
+
+
+def test_table1_angles():
+    out, ms, lens_fields = run_table1(nf.FP64)
+    ANGLES["fp64"] = out
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
     np.save(os.path.join(ROOT, "gpurun_out", "table1_C1to4.npy"), np.stack(lens_fields))
     with open(os.path.join(ROOT, "gpurun_out", "table1.json"), "w") as fh:
@@ -79,3 +93,23 @@ def test_table1_angles():
         # the paper reports agreement within 1 degree
         assert abs(o["interior"] - o["theory"][0]) < 1.0, o
         assert abs(o["exterior"] - o["theory"][1]) < 1.0, o
+
+
+@pytest.mark.parametrize("name,prec", [("fp32", nf.FP32), ("fp16s", nf.FP16S)])
+def test_table1_reduced_precision(name, prec):
+    """The same batch in float and binary16 storage (float arithmetic): the
+    angle of every row against the FP64 run, and fluids 5 and 6 exactly 0.0
+    (reduction consistency in every precision)."""
+    ref = ANGLES.get("fp64") or run_table1(nf.FP64)[0]
+    out, ms, _ = run_table1(prec)
+    diffs = []
+    for o, r in zip(out, ref):
+        assert o["absent_max_abs"] == 0.0
+        diffs.append({"s": o["s"], "interior": o["interior"], "exterior": o["exterior"],
+                      "d_interior_vs_fp64": o["interior"] - r["interior"],
+                      "d_exterior_vs_fp64": o["exterior"] - r["exterior"]})
+    with open(os.path.join(ROOT, "gpurun_out", f"table1_{name}.json"), "w") as fh:
+        json.dump({"steps": STEPS, "batch_ms": ms, "rows": diffs}, fh, indent=1)
+    for d in diffs:
+        assert abs(d["d_interior_vs_fp64"]) < 0.1, d
+        assert abs(d["d_exterior_vs_fp64"]) < 0.1, d

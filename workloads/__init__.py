@@ -247,3 +247,17 @@ def batch_members(count=256, seed=0, sides=None):
         w["kind"] = kind
         out.append(w)
     return out
+
+
+def ulp_perturbed(C0, seed=20261203):
+    """C0 with every nonzero value moved by one unit in the last place, up or
+    down by a seeded coin (zeros stay exactly 0).  Parity tests run a case
+    from C0 and from this input: how far the two results drift apart measures
+    how strongly the problem amplifies rounding-sized differences, which
+    bounds how closely two correct implementations that round differently
+    can agree."""
+    C0 = np.asarray(C0, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    up = rng.integers(0, 2, size=C0.shape).astype(bool)
+    moved = np.where(up, np.nextafter(C0, np.inf), np.nextafter(C0, -np.inf))
+    return np.where(C0 == 0.0, C0, moved)
