@@ -364,6 +364,20 @@ int nflbm_set_state(nflbm_sim *sim, const void *host_raw);
  * or Inf was found.  Synchronises. */
 int nflbm_diagnostics(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the diagnostics
+ * of nflbm_diagnostics (same kernels, same results) with the reduction's
+ * partial records in a fixed device array of the library, (2048 + 1)
+ * (3 NFLBM_MAX_COMP + 9) doubles (about 0.5 MiB) that each device holds
+ * until the process ends, instead of a buffer allocated on the first call.
+ * Calls no hipMalloc or hipFree.  Every call on a device shares that
+ * device's array and leaves its records there: calls that overlap on one
+ * device (other threads or streams) race.  Every lattice fits, since the
+ * reduction grid is capped at 2048 workgroups; a record that did not fit
+ * would give ENOTSUP.  EINVAL unless the simulation's device is current;
+ * ENUMERIC as nflbm_diagnostics.  Synchronises. */
+int nflbm_diagnostics_noalloc(nflbm_sim *sim, int vcm_component, nflbm_diag *out);
+
 /* Characteristic domain size L_i of every component (Eq. L, Sec. IV B) of
  * the current state: lambda_i = H(C_i - 1/2) (taken as C_i > 1/2),
  * S_i(k) = |FFT(lambda_i)|^2 over the lattice's wave vectors k = 2 pi m / n

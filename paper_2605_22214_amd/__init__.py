@@ -114,6 +114,7 @@ def lib():
             "nflbm_get_state": (I, [P, P]),
             "nflbm_set_state": (I, [P, P]),
             "nflbm_diagnostics": (I, [P, I, ctypes.POINTER(Diag)]),
+            "nflbm_diagnostics_noalloc": (I, [P, I, ctypes.POINTER(Diag)]),
             "nflbm_coefficients": (I, [I, DP, D, DP, DP, DP, DP, DP]),
             "nflbm_bytes_per_node": (I, [P, DP]),
             "nflbm_set_launch": (I, [P, I, I]),
@@ -346,6 +347,16 @@ class Simulation:
     def diagnostics(self, vcm_component=0, check=True):
         d = Diag()
         code = lib().nflbm_diagnostics(self._handle(), int(vcm_component), ctypes.byref(d))
+        return self._diag_dict(d, code, check)
+
+    def diagnostics_noalloc(self, vcm_component=0, check=True):
+        """nflbm_diagnostics_noalloc: the same diagnostics without any device
+        allocation (the library's fixed array holds the partial sums)."""
+        d = Diag()
+        code = lib().nflbm_diagnostics_noalloc(self._handle(), int(vcm_component), ctypes.byref(d))
+        return self._diag_dict(d, code, check)
+
+    def _diag_dict(self, d, code, check):
         if check:
             _check(code, self._h)
         N = self.N

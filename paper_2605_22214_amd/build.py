@@ -38,6 +38,7 @@ UNITS = [
     ("kernels.hip", "kernels_common.o", True, ["-DNFLBM_UNIT_STORE=-1"]),
     ("mobility.hip", "mobility.o", True, []),
     ("outflow.hip", "outflow.o", True, []),
+    ("noalloc.hip", "noalloc.o", True, []),
 ]
 
 
