@@ -229,12 +229,18 @@ int nflbm_set_stream(nflbm_sim *sim, void *hip_stream);
  * flux potential in it is the bulk one of the uniform state C_b); stencil
  * neighbours beyond the face take C_b and E_B(C_b).  Where a link crosses a
  * wall face and an open face the wall wins, between two open faces the first
- * axis's face.  v_b = C_b = NULL makes the face a wall again.  Needs g as
- * populations (create with NFLBM_FLAG_G_POPULATIONS: ENOTSUP otherwise) and
- * takes neither solid nodes, the concentration-dependent mobility, batch
- * members, the outflow face itself nor, with an outflow face, a face on
- * another axis (ENOTSUP).  Call before nflbm_set_fields.  EINVAL for a bad face,
- * an unwalled axis, non-finite values or C_b not summing to 1. */
+ * axis's face.  With solid nodes (nflbm_set_solid), a solid node on the face
+ * continues beyond it: a link across the face whose in-face part (the link
+ * without its component normal to the face) leads to a solid node is a wall
+ * link (bounce-back, centre value), so solid channel walls meet an inlet as
+ * wall faces do.  Every storage form of g and f, batch members included; in
+ * the moment form the first step after nflbm_set_fields takes g entering
+ * across the face as the initial 0.  v_b = C_b = NULL makes the face a wall
+ * again.  With an outflow face, a face on another axis must meet the outflow
+ * plane only at solid nodes (ENOTSUP otherwise: set the solid nodes first).
+ * ENOTSUP with the concentration-dependent mobility.  Call before
+ * nflbm_set_fields.  EINVAL for a bad face, an unwalled axis, the outflow
+ * face, non-finite values or C_b not summing to 1. */
 int nflbm_set_open_face(nflbm_sim *sim, int face, const double *v_b, const double *C_b);
 
 /* Convective outflow (Sec. III C, Eq. convect): turns the wall face `face`
@@ -250,12 +256,18 @@ int nflbm_set_open_face(nflbm_sim *sim, int face, const double *v_b, const doubl
  * psi(N, 0).  The plane N values, the ghosts and the previous U are state:
  * nflbm_set_fields (and a call here after it) starts them from the current
  * populations, and nflbm_get_state / nflbm_set_state include them (after the
- * populations).  At most one outflow face.  Needs g as populations (ENOTSUP
- * otherwise) and takes neither solid nodes, the concentration-dependent
- * mobility, batch members, nor an open face on another axis (ENOTSUP; an
- * inlet on the opposite face is fine).  Device memory: one plane of (Q-1) +
- * (N-1) Q + N values in the compute precision.  EINVAL for a bad face, an
- * unwalled or too short axis, or an open face there.  Synchronises. */
+ * populations).  At most one outflow face.  Every storage form of g and f
+ * (in the moment form the pulled populations are formed from the node
+ * records, as the reconstruction forms them), batch members included.  With
+ * solid nodes: they must continue straight through the outflow plane (the
+ * same on planes N and N-1; ENOTSUP otherwise), U is the mean over the fluid
+ * nodes of plane N-1, and a stencil link across the face whose in-face part
+ * leads to a solid node is a wall link.  An open face on another axis must
+ * meet the outflow plane only at solid nodes (ENOTSUP otherwise).  ENOTSUP
+ * with the concentration-dependent mobility.  Device memory: one plane of
+ * (Q-1) + (N-1) Q + N values in the compute precision.  EINVAL for a bad
+ * face, an unwalled or too short axis, an open face there, or no fluid node
+ * on plane N-1.  Synchronises. */
 int nflbm_set_outflow(nflbm_sim *sim, int face);
 
 /* Solid geometry (Sec. III C): solid[n] (node order x fastest, copied; 1 =
@@ -268,8 +280,10 @@ int nflbm_set_outflow(nflbm_sim *sim, int face);
  * read back as 0, and diagnostics leave them out.  Call before
  * nflbm_set_fields (which fills only the fluid nodes); NULL removes the
  * geometry.  Takes 4 bytes per node of device memory besides the state.
- * EINVAL if every node is solid, ENOTSUP for a batch member, open faces or an
- * outflow face.  Synchronises. */
+ * Goes with open faces and the outflow face as those describe (ENOTSUP for a
+ * mask the outflow face cannot take), and with batch members (the batch
+ * picks the change up at its next step).  EINVAL if every node is solid.
+ * Synchronises. */
 int nflbm_set_solid(nflbm_sim *sim, const unsigned char *solid);
 
 /* Initialise the state from host fields: C (N n, required), v (3 n or NULL
@@ -450,8 +464,10 @@ int nflbm_autotune(nflbm_sim *sim, const char *cache_path);
  * cover the tiles of all members; NFLBM_BATCH_GRAPH replays runs of
  * graph_steps such steps from a captured HIP graph.  Each member is an
  * nflbm_sim owned by the batch: nflbm_batch_member returns it for set_fields,
- * get_field, diagnostics, state I/O or stepping on its own (never
- * nflbm_destroy it).  All members run on the batch's stream.
+ * get_field, diagnostics, state I/O, solid nodes, open faces, the outflow
+ * face or stepping on its own (never nflbm_destroy it).  A member with an
+ * outflow face adds its two outflow launches after each batch step.  All
+ * members run on the batch's stream.
  * ---------------------------------------------------------------------- */
 typedef struct nflbm_batch nflbm_batch; /* opaque */
 

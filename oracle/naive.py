@@ -2,7 +2,8 @@
 
 Test infrastructure only, for tiny lattices (a few hundred nodes).  It is an
 independent transcription of the same definitions: explicit index arithmetic
-for neighbours and walls instead of array rolls and masks, and the flux
+for neighbours, walls, solid nodes and open faces (Sec. III C) instead of
+array rolls and masks, and the flux
 potential in the literal form of Eq. MU (sum_j alpha_ij (mu_j + phi_j + xi_j))
 instead of the factored form.  Agreement with step.py therefore checks the
 vectorisation and the factored algebra together (to rounding, not bitwise).
@@ -27,26 +28,80 @@ def _is_solid(par, x, y, z):
     return par.solid is not None and bool(par.solid[z, y, x])
 
 
-def _node_neighbour(par, x, y, z, e):
-    """Index of x + e, or None if it is inside a wall or a solid node."""
+def _link(par, x, y, z, e):
+    """Where the link from x along e leads: (X, Y, Z) of a fluid node, None
+    for a wall (a wall face or a solid node), or the open face (an int) it
+    leaves across.  A link that crosses a wall face is a wall link even if
+    it also crosses an open face; across two open faces it takes the first
+    axis's; across an open face it is still a wall link if, with its
+    component normal to the face removed, it leads to a solid node."""
     nx, ny, nz = par.shape
-    p = [x + int(e[0]), y + int(e[1]), z + int(e[2])]
     n = (nx, ny, nz)
+    c = (x, y, z)
+    p = [c[a] + int(e[a]) for a in range(3)]
+    open_face = None
     for a in range(3):
         if p[a] < 0 or p[a] >= n[a]:
-            if par.walls[a]:
+            if not par.walls[a]:
+                p[a] %= n[a]
+                continue
+            face = 2 * a + (1 if p[a] >= n[a] else 0)
+            if face in par.open_faces or face == par.outflow:
+                if open_face is None:
+                    open_face = face
+            else:
                 return None
-            p[a] %= n[a]
+    if open_face is not None:
+        t = list(p)
+        t[open_face // 2] = c[open_face // 2]
+        if t != list(c) and _is_solid(par, t[0], t[1], t[2]):
+            return None
+        return open_face
     if _is_solid(par, p[0], p[1], p[2]):
         return None
     return p[0], p[1], p[2]
 
 
+def _face_values(par, face):
+    """C_b, E_B(C_b), mu~(C_b) (literal form, no gradients) and v_b of an
+    open face."""
+    co, N = par.co, par.N
+    vb, Cb = par.open_faces[face]
+    eb = 0.0
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                eb += 0.5 * co.beta[i, j] * (_fp(Cb[i]) + _fp(Cb[j]) - _fp(Cb[i] + Cb[j]))
+    mu = [sum(co.beta[j, k2] * (_dfp(Cb[j]) - _dfp(Cb[j] + Cb[k2])) for k2 in range(N) if k2 != j)
+          for j in range(N)]
+    ph = [0.0] * N
+    for j in range(N):
+        for k2, l, m in itertools.combinations(range(N), 3):
+            if j not in (k2, l, m):
+                ph[j] += 12.0 / co.D * co.Lam[j, k2, l, m] * Cb[k2] * Cb[l] * Cb[m]
+    xs = [0.0] * N
+    if par.omega_stab != 0.0:
+        for j in range(N):
+            for k2, l in itertools.combinations(range(N), 2):
+                if j in (k2, l):
+                    continue
+                inner = 2.0 * Cb[j]
+                for m in range(N):
+                    if m not in (j, k2, l):
+                        inner -= co.Theta[k2, l, j, m] * Cb[m]
+                xs[j] += 12.0 / co.D * par.omega_stab * Cb[k2] ** 2 * Cb[l] ** 2 * inner
+    mut = [sum(co.alpha[i, j] * (mu[j] + ph[j] + xs[j]) for j in range(N)) for i in range(N)]
+    return list(Cb), eb, mut, list(vb)
+
+
 def step(f, g, par):
+    if par.outflow is not None:
+        raise ValueError("the node loop has no convective outflow")
     lat, co, N = par.lat, par.co, par.N
     Q = lat.Q
     nx, ny, nz = par.shape
     D = co.D
+    faces = {face: _face_values(par, face) for face in par.open_faces}
     C = np.zeros((N, nz, ny, nx))
     for z in range(nz):
         for y in range(ny):
@@ -81,7 +136,7 @@ def step(f, g, par):
             for x in range(nx):
                 if _is_solid(par, x, y, z):
                     continue              # no fluid, nothing collides or streams
-                nb = [_node_neighbour(par, x, y, z, lat.e[k]) for k in range(Q)]
+                nb = [_link(par, x, y, z, lat.e[k]) for k in range(Q)]
                 c0 = [C[i, z, y, x] for i in range(N)]
                 grad = [[0.0, 0.0, 0.0] for _ in range(N)]
                 lap = [0.0] * N
@@ -89,13 +144,19 @@ def step(f, g, par):
                 for k in range(1, Q):
                     if nb[k] is None:
                         continue          # neighbour in the wall: psi(x) - psi(x) = 0
-                    X, Y, Z = nb[k]
+                    if isinstance(nb[k], int):
+                        # beyond an open face: the face's boundary values
+                        cn, en = faces[nb[k]][0], faces[nb[k]][1]
+                    else:
+                        X, Y, Z = nb[k]
+                        cn = [C[i, Z, Y, X] for i in range(N)]
+                        en = EB[Z, Y, X]
                     for i in range(N):
-                        d = C[i, Z, Y, X] - c0[i]
+                        d = cn[i] - c0[i]
                         lap[i] += 2.0 / CS2 * lat.w[k] * d
                         for a in range(3):
                             grad[i][a] += lat.w[k] * lat.e[k, a] * d / CS2
-                    dE = EB[Z, Y, X] - EB[z, y, x]
+                    dE = en - EB[z, y, x]
                     for a in range(3):
                         gE[a] += lat.w[k] * lat.e[k, a] * dE / CS2
                 # chemical potentials (Eq. mu), phi (Eq. G), xi (Eq. P)
@@ -175,6 +236,11 @@ def step(f, g, par):
                     dst = nb[k]
                     if dst is None:
                         fnew[kb, z, y, x] = post
+                    elif isinstance(dst, int):
+                        # velocity Dirichlet: back along kb with 2 w_kb (e_kb . v_b) / c_s^2
+                        vb = faces[dst][3]
+                        ekv = sum(lat.e[kb, a] * vb[a] for a in range(3))
+                        fnew[kb, z, y, x] = post + 2.0 * lat.w[kb] * ekv / CS2
                     else:
                         fnew[k, dst[2], dst[1], dst[0]] = post
                 for i in range(N):
@@ -189,6 +255,16 @@ def step(f, g, par):
                         dst = nb[k]
                         if dst is None:
                             gnew[i, lat.opp[k], z, y, x] = post
+                        elif isinstance(dst, int):
+                            # anti-bounce-back: minus it plus g^eq_k + g^eq_kb of the face
+                            Cb, _, mub, vb = faces[dst]
+                            vvb = vb[0] ** 2 + vb[1] ** 2 + vb[2] ** 2
+                            eq = 0.0
+                            for q in (k, lat.opp[k]):
+                                ev = lat.e[q, 0] * vb[0] + lat.e[q, 1] * vb[1] + lat.e[q, 2] * vb[2]
+                                sq = lat.w[q] * (3 * ev + 4.5 * ev * ev - 1.5 * vvb)
+                                eq += Cb[i] * sq - lat.w[q] * par.m * mub[i]
+                            gnew[i, lat.opp[k], z, y, x] = -post + eq
                         else:
                             gnew[i, k, dst[2], dst[1], dst[0]] = post
     return fnew, gnew

@@ -61,6 +61,10 @@ Readings (where the printed text is garbled or silent):
     C_b.  Stencil neighbours beyond the face take the boundary values (C_b,
     E_B(C_b)).  Where a link crosses a wall face and an open face (a corner),
     the wall wins; where it crosses two open faces, the first axis's face.
+    A solid node on an open face continues beyond it (a prism normal to the
+    face): a link across the face whose in-face part leads to a solid node is
+    a wall link (bounce-back, centre value), which makes solid layers along
+    a channel behave at an inlet exactly as wall faces do.
   * Convective outflow (Sec. III C, Eq. convect, ``outflow=face`` of a walled
     axis): after streaming, every population (all k, f and g) of the boundary
     plane N becomes (q(N, t) + U q(N-1, t+1)) / (1 + U), q(N, t) the plane's
@@ -71,7 +75,10 @@ Readings (where the printed text is garbled or silent):
     ghost values of C_i and E_B convected the same way, psi(N+1, t+1) =
     (psi(N+1, t) + U psi(N, t+1)) / (1 + U), starting at psi(N, 0).  The
     previous planes, U and the ghosts are state: they live in
-    ``par.outflow_state`` (set by initial_state, advanced by step).
+    ``par.outflow_state`` (set by initial_state, advanced by step).  Solid
+    nodes must continue straight through the outflow plane (the same on
+    planes N and N-1); U is the mean over the fluid nodes of plane N-1, and
+    solid nodes of plane N stay empty.
 """
 import numpy as np
 
@@ -120,14 +127,19 @@ class Params:
                 raise ValueError("an open face must lie on a walled axis")
             self.open_faces[int(face)] = (np.asarray(vb, dtype=np.float64).reshape(3),
                                           np.asarray(Cb, dtype=np.float64).reshape(self.N))
-        if self.open_faces and (solid is not None or mobility != "constant"):
-            raise ValueError("open faces take neither solid nodes nor the mobility variant")
+        if self.open_faces and mobility != "constant":
+            raise ValueError("open faces take no mobility variant")
         self.outflow = None if outflow is None else int(outflow)
         if self.outflow is not None:
             if not 0 <= self.outflow < 6 or not self.walls[self.outflow // 2]:
                 raise ValueError("the outflow face must lie on a walled axis")
-            if self.outflow in self.open_faces or solid is not None or mobility != "constant":
-                raise ValueError("the outflow face takes no open face, solid nodes or mobility variant")
+            if self.outflow in self.open_faces or mobility != "constant":
+                raise ValueError("the outflow face takes no open face or mobility variant")
+            if self.solid is not None:
+                bn, inner = _plane(self), _plane(self, 1)
+                if not np.array_equal(self.solid[bn[1:]], self.solid[inner[1:]]):
+                    raise ValueError("solid nodes must continue straight through the outflow plane "
+                                     "(the same on its plane and the plane inside it)")
         self.outflow_state = None
         if mobility not in ("constant", "c2c2"):
             raise ValueError(mobility)
@@ -169,7 +181,10 @@ def wall_mask(par, e):
 
 def open_face_masks(par, e):
     """{face: nodes whose link to x + e leaves across that open face}, with a
-    wall face taking precedence and, between open faces, the first axis."""
+    wall face taking precedence and, between open faces, the first axis.
+    With solid nodes, a solid node on the face continues beyond it: a link
+    whose part along the face (e without its normal component) leads from x
+    to a solid node inside the lattice is a wall link, not an open one."""
     out = {}
     faces = set(par.open_faces)
     if par.outflow is not None:
@@ -193,7 +208,21 @@ def open_face_masks(par, e):
             decided |= cross
         else:
             plain |= cross
-    return {f: m & ~plain for f, m in out.items()}
+    out = {f: m & ~plain for f, m in out.items()}
+    if par.solid is not None:
+        for f in out:
+            et = [int(c) for c in e]
+            et[f // 2] = 0
+            if not any(et):
+                continue
+            # x + et inside the lattice (no face crossed) and solid
+            inside = np.ones((nz, ny, nx), dtype=bool)
+            for a in range(3):
+                if et[a] != 0 and par.walls[a]:
+                    inside &= (idx[a] + et[a] >= 0) & (idx[a] + et[a] < n[a])
+            prism = inside & np.roll(par.solid, shift=(-et[2], -et[1], -et[0]), axis=(0, 1, 2))
+            out[f] = out[f] & ~prism
+    return out
 
 
 def neighbour(psi, e, par, bvals=None):
@@ -516,7 +545,9 @@ def _outflow_apply(f, g, par):
     for k in range(1, lat.Q):
         if lat.e[k, a] != 0:
             mom = mom + sgn * lat.e[k, a] * f[k][inner[1:]]
-    U = max(float(mom.mean()), 0.0)
+    # the mean over the fluid nodes of plane N-1 (solid nodes hold no fluid)
+    fluid = np.ones(mom.shape, dtype=bool) if par.solid is None else ~par.solid[inner[1:]]
+    U = max(float(mom[fluid].mean()), 0.0)
     bn = _plane(par)
     f[bn] = (st["f"] + U * f[inner]) / (1.0 + U)
     g[bn] = (st["g"] + U * g[inner]) / (1.0 + U)

@@ -14,7 +14,9 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_PKG)
-LIB_PATH = os.path.join(_PKG, "libnflbm.so")
+# NFLBM_LIBRARY selects another build of the library (e.g. a development
+# build restricted to one component count); by default the in-tree one.
+LIB_PATH = os.environ.get("NFLBM_LIBRARY") or os.path.join(_PKG, "libnflbm.so")
 HEADER = os.path.join(_ROOT, "include", "nflbm.h")
 MAX_COMP = 8
 

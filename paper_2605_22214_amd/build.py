@@ -29,12 +29,35 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"
           "-Wall", "-Wno-unused-function"]
 
 # Translation units: (source, object, is_device_code, extra defines)
+# kernels.hip is compiled once per storage precision, lattice and group of
+# component counts (each unit registers its launchers when the library
+# loads), so that the units build in parallel; NFLBM_COMPONENTS (e.g. "5")
+# restricts a development build to those N.
+_NC_GROUPS = {0: [(2, 4), (5, 8)], 1: [(2, 3), (4, 4), (5, 5), (6, 6), (7, 7), (8, 8)]}
+
+
+def _kernel_units():
+    only = os.environ.get("NFLBM_COMPONENTS")
+    only = {int(v) for v in only.split(",")} if only else None
+    out = []
+    for st, name in ((0, "f64"), (1, "f32"), (2, "f16s")):
+        for lat in (0, 1):
+            for lo, hi in _NC_GROUPS[lat]:
+                if only is not None:
+                    sel = sorted(n for n in only if lo <= n <= hi)
+                    if not sel:
+                        continue
+                    lo, hi = sel[0], sel[-1]
+                out.append(("kernels.hip", f"kernels_{name}_l{lat}_n{lo}{hi}.o", True,
+                            [f"-DNFLBM_UNIT_STORE={st}", f"-DNFLBM_UNIT_LAT={lat}",
+                             f"-DNFLBM_UNIT_NC_LO={lo}", f"-DNFLBM_UNIT_NC_HI={hi}"]))
+    return out
+
+
 UNITS = [
     ("coeffs.cpp", "coeffs.o", False, []),
     ("api.cpp", "api.o", False, []),
-    ("kernels.hip", "kernels_f64.o", True, ["-DNFLBM_UNIT_STORE=0"]),
-    ("kernels.hip", "kernels_f32.o", True, ["-DNFLBM_UNIT_STORE=1"]),
-    ("kernels.hip", "kernels_f16s.o", True, ["-DNFLBM_UNIT_STORE=2"]),
+] + _kernel_units() + [
     ("kernels.hip", "kernels_common.o", True, ["-DNFLBM_UNIT_STORE=-1"]),
     ("mobility.hip", "mobility.o", True, []),
     ("outflow.hip", "outflow.o", True, []),
@@ -84,6 +107,8 @@ def build(verbose=True, jobs=None, changed_only=False):
     than a source or header) and link libnflbm.so."""
     os.makedirs(BUILD, exist_ok=True)
     units = [u for u in UNITS if _stale(u)] if changed_only else UNITS
+    # the D3Q19 kernel units take longest: start them first
+    units = sorted(units, key=lambda u: ("_l1_" not in u[1], u[1]))
     jobs = jobs or min(max(len(units), 1), os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         for obj, dt, warn in ex.map(_compile, units):

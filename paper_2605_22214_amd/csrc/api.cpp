@@ -83,6 +83,7 @@ struct nflbm_sim {
   // precision), and the per-workgroup momentum sums plus U (FP64)
   int out_face = -1;
   size_t out_plane = 0;
+  double out_fluid = 0.0;   // fluid nodes of plane N-1 (U is their mean)
   void* out_buf = nullptr;
   double* out_red = nullptr;
   int out_blocks = 0;
@@ -101,6 +102,10 @@ struct nflbm_sim {
   void* spec = nullptr;
   double* spart = nullptr;
   bool in_batch = false;
+  // incremented by every change of solid nodes, open faces or the outflow
+  // face: a batch rebuilds its step arguments (and drops its graphs) when a
+  // member's count differs from the one its tables were built for
+  unsigned boundary_version = 0;
   void* eb = nullptr;
   void* params = nullptr;
   double* fields = nullptr;
@@ -146,6 +151,7 @@ struct nflbm_batch {
   int2* work_update = nullptr;
   int blocks_conc = 0, blocks_update = 0;
   std::vector<int> key;     // member parities that args[0..count) was built for
+  std::vector<unsigned> versions;   // members' boundary_version at that build
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   // NaN flag shared by the members' batch steps, which check every step
@@ -399,7 +405,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.tiles_y = s->tiles_y;
   a.chunks_z = s->chunks_z;
   a.flags = s->step_flags;
-  if (s->fform && s->f_local) a.flags |= kFlagFLocal;
+  if (s->gform && s->f_local) a.flags |= kFlagFLocal;
   return a;
 }
 
@@ -452,14 +458,22 @@ void fill_mob(const nflbm_sim& s, const double* tau_g, double m_star, MobParams<
 
 // Convective outflow of the state set `cur` (start: capture its boundary
 // plane instead of convecting).
-int launch_outflow_step(nflbm_sim* s, bool start) {
+OutflowArgs outflow_args(const nflbm_sim* s, int cur, bool start) {
   OutflowArgs o{};
-  o.sa = make_args(s, s->cur);
+  o.sa = make_args(s, cur);
+  // after a step the plane N-1 populations are the streamed ones (the
+  // first-step flag of the moment form describes only the state before it)
+  if (!start) o.sa.flags &= ~kFlagFLocal;
   o.partial = s->out_red;
   o.u = s->out_red + s->out_blocks;
+  o.fluid = s->out_fluid;
   o.blocks = s->out_blocks;
   o.start = start ? 1 : 0;
-  HIPCHK(s, launch_outflow(s->lat, s->N, s->store, o, s->stream));
+  return o;
+}
+
+int launch_outflow_step(nflbm_sim* s, bool start) {
+  HIPCHK(s, launch_outflow(s->lat, s->N, s->store, outflow_args(s, s->cur, start), s->stream));
   return NFLBM_OK;
 }
 
@@ -694,9 +708,14 @@ int build_batch_tables(nflbm_batch* b, bool new_shape) {
   std::vector<int2> wc, wu;
   std::vector<StepArgs> args(2 * size_t(count));
   b->key.assign(count, 0);
+  b->versions.assign(count, 0u);
+  b->walls = 0;
   for (int i = 0; i < count; ++i) {
     const nflbm_sim* m = b->members[i];
     b->key[i] = m->cur;
+    b->versions[i] = m->boundary_version;
+    // one kernel variant for all members: the wall variant if any needs it
+    if (m->wall[0] || m->wall[1] || m->wall[2] || m->bb) b->walls = 1;
     args[i] = batch_args(b, m, m->cur);
     args[count + i] = batch_args(b, m, m->cur ^ 1);
     for (StepArgs* x : {&args[i], &args[count + i]}) {
@@ -765,7 +784,15 @@ hipError_t launch_half(nflbm_batch* b, int half) {
   bl.walls = b->walls;
   bl.moments = b->members[0]->gform;
   bl.frecord = b->members[0]->fform;
-  return launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+  hipError_t e = launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+  // members with a convective outflow face: Eq. convect on the state this
+  // half wrote (parity key ^ 1 after half 0, key after half 1)
+  for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
+    const nflbm_sim* m = b->members[i];
+    if (m->out_face < 0) continue;
+    e = launch_outflow(m->lat, m->N, m->store, outflow_args(m, b->key[i] ^ (half == 0 ? 1 : 0), false), b->stream);
+  }
+  return e;
 }
 
 // Capture graph_steps time steps of the whole batch, starting from argument
@@ -802,6 +829,15 @@ int batch_run(nflbm_batch* b, long long nsteps, int mode) {
   }
   BHIPCHK(b, nan_poll(&b->nan_pending, &b->nan_seen, b->nan_host, b->nan_ev, false));
   if (b->nan_seen) return bfail(b, NFLBM_ENUMERIC, "a NaN or Inf appeared in a member's state");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (i < b->versions.size() && b->members[i]->boundary_version == b->versions[i]) continue;
+    // a member's solid nodes, open faces or outflow changed: new arguments,
+    // and graphs that captured the old outflow launches are dropped
+    destroy_graphs(b);
+    const int rc = build_batch_tables(b, false);
+    if (rc != NFLBM_OK) return rc;
+    break;
+  }
   bool local = false;
   for (nflbm_sim* m : b->members) local = local || m->f_local;
   if (local && nsteps > 0) {
@@ -1290,18 +1326,67 @@ int nflbm_set_stream(nflbm_sim* sim, void* stream) {
   return NFLBM_OK;
 }
 
+// Whether the open faces (mask), the outflow face (-1: none) and the solid
+// mask (empty: none) can go together: solid nodes continue straight through
+// the outflow plane (the same on planes N and N-1), and an open face on
+// another axis meets the outflow plane only at solid nodes (so no fluid node
+// mixes the outflow with another open face).  On success *fluid is the
+// number of fluid nodes on plane N-1 (0 without an outflow face).
+static int check_boundaries(nflbm_sim* sim, int open_mask, int out_face, const unsigned char* solid,
+                            double* fluid) {
+  *fluid = 0.0;
+  if (out_face < 0) return NFLBM_OK;
+  const int dims[3] = {sim->nx, sim->ny, sim->nz};
+  const int ax = out_face / 2;
+  const int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+  const int pN = (out_face & 1) ? dims[ax] - 1 : 0;
+  const int pI = (out_face & 1) ? dims[ax] - 2 : 1;
+  auto at = [&](int a, int b, int c) {   // node of (axis ax = a, t0 = b, t1 = c)
+    int xyz[3];
+    xyz[ax] = a;
+    xyz[t0] = b;
+    xyz[t1] = c;
+    return size_t(xyz[0]) + size_t(sim->nx) * (size_t(xyz[1]) + size_t(sim->ny) * size_t(xyz[2]));
+  };
+  size_t cnt = 0;
+  for (int c = 0; c < dims[t1]; ++c)
+    for (int b = 0; b < dims[t0]; ++b) {
+      const bool sN = solid && solid[at(pN, b, c)];
+      const bool sI = solid && solid[at(pI, b, c)];
+      if (sN != sI)
+        return fail(sim, NFLBM_ENOTSUP,
+                    "solid nodes must continue straight through the outflow plane (the same on it and the plane inside it)");
+      if (!sI) ++cnt;
+      // an open face of another axis touching this plane node
+      for (int f = 0; f < 6; ++f) {
+        if (!((open_mask >> f) & 1) || f / 2 == ax) continue;
+        const int fa = f / 2;
+        const int pos = (f & 1) ? dims[fa] - 1 : 0;
+        const int coord = fa == t0 ? b : c;
+        if (coord == pos && !sN)
+          return fail(sim, NFLBM_ENOTSUP,
+                      "an open face on another axis may meet the outflow face only at solid nodes");
+      }
+    }
+  if (cnt == 0) return fail(sim, NFLBM_EINVAL, "no fluid node on the plane inside the outflow face");
+  *fluid = double(cnt);
+  return NFLBM_OK;
+}
+
 int nflbm_set_open_face(nflbm_sim* sim, int face, const double* v_b, const double* C_b) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
   if (face < 0 || face >= 6 || (sim->lat == NFLBM_D2Q9 && face >= 4))
     return fail(sim, NFLBM_EINVAL, "face is 0..5 (x-, x+, y-, y+, z-, z+; 0..3 in D2Q9)");
   if (!sim->wall[face / 2]) return fail(sim, NFLBM_EINVAL, "an open face must lie on a walled axis");
-  if (sim->in_batch || sim->bb || sim->c2c2)
-    return fail(sim, NFLBM_ENOTSUP, "open faces take neither batches, solid nodes nor the mobility variant");
-  if (sim->gform)
-    return fail(sim, NFLBM_ENOTSUP, "open faces need g as populations (NFLBM_FLAG_G_POPULATIONS)");
+  if (sim->c2c2) return fail(sim, NFLBM_ENOTSUP, "open faces take no concentration-dependent mobility");
   if ((v_b == nullptr) != (C_b == nullptr)) return fail(sim, NFLBM_EINVAL, "v_b and C_b go together");
-  if (v_b && sim->out_face >= 0 && (face == sim->out_face || face / 2 != sim->out_face / 2))
-    return fail(sim, NFLBM_ENOTSUP, "with an outflow face, an open face must be the opposite face of its axis");
+  if (v_b && face == sim->out_face) return fail(sim, NFLBM_EINVAL, "the face is the outflow face");
+  if (v_b) {
+    double fluid = 0.0;
+    const int rc = check_boundaries(sim, sim->open_mask | (1 << face), sim->out_face,
+                                    sim->solid_host.empty() ? nullptr : sim->solid_host.data(), &fluid);
+    if (rc) return rc;
+  }
   if (v_b) {
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(v_b[d])) return fail(sim, NFLBM_EINVAL, "v_b must be finite");
@@ -1317,6 +1402,7 @@ int nflbm_set_open_face(nflbm_sim* sim, int face, const double* v_b, const doubl
   } else {
     sim->open_mask &= ~(1 << face);
   }
+  ++sim->boundary_version;
   return upload_faces(sim);
 }
 
@@ -1325,6 +1411,7 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
   if (face == -1) {
     if (sim->out_face < 0) return NFLBM_OK;
     sim->out_face = -1;
+    ++sim->boundary_version;
     if (sim->out_buf) (void)hipFree(sim->out_buf);
     if (sim->out_red) (void)hipFree(sim->out_red);
     sim->out_buf = nullptr;
@@ -1337,13 +1424,13 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
   if (!sim->wall[face / 2]) return fail(sim, NFLBM_EINVAL, "an outflow face must lie on a walled axis");
   if (dims[face / 2] < 3) return fail(sim, NFLBM_EINVAL, "the outflow axis needs at least 3 nodes");
   if ((sim->open_mask >> face) & 1) return fail(sim, NFLBM_EINVAL, "the face is an open face");
-  if (sim->in_batch || sim->bb || sim->c2c2)
-    return fail(sim, NFLBM_ENOTSUP, "an outflow face takes neither batches, solid nodes nor the mobility variant");
-  if (sim->gform)
-    return fail(sim, NFLBM_ENOTSUP, "an outflow face needs g as populations (NFLBM_FLAG_G_POPULATIONS)");
-  for (int f = 0; f < 6; ++f)
-    if (((sim->open_mask >> f) & 1) && f / 2 != face / 2)
-      return fail(sim, NFLBM_ENOTSUP, "an outflow face takes no open face on another axis");
+  if (sim->c2c2) return fail(sim, NFLBM_ENOTSUP, "an outflow face takes no concentration-dependent mobility");
+  double fluid = 0.0;
+  {
+    const int rc = check_boundaries(sim, sim->open_mask, face,
+                                    sim->solid_host.empty() ? nullptr : sim->solid_host.data(), &fluid);
+    if (rc) return rc;
+  }
   if (sim->out_face >= 0 && sim->out_face != face) {
     const int rc = nflbm_set_outflow(sim, -1);
     if (rc) return rc;
@@ -1374,6 +1461,8 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
     }
   }
   sim->out_face = face;
+  sim->out_fluid = fluid;
+  ++sim->boundary_version;
   int rc = upload_faces(sim);
   if (rc) return rc;
   // start from the current state's boundary plane
@@ -1385,13 +1474,17 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
 
 int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
   if (!sim) return fail(nullptr, NFLBM_EINVAL, "NULL sim");
-  if (sim->in_batch) return fail(sim, NFLBM_ENOTSUP, "batch members take no solid geometry");
-  if (solid && sim->open_mask) return fail(sim, NFLBM_ENOTSUP, "open faces take no solid nodes");
-  if (solid && sim->out_face >= 0) return fail(sim, NFLBM_ENOTSUP, "an outflow face takes no solid nodes");
+  double fluid_out = 0.0;
+  {
+    const int rc = check_boundaries(sim, sim->open_mask, sim->out_face, solid, &fluid_out);
+    if (rc) return rc;
+  }
   if (!solid) {
     if (sim->bb) (void)hipFree(sim->bb);
     sim->bb = nullptr;
     sim->solid_host.clear();
+    sim->out_fluid = fluid_out;
+    ++sim->boundary_version;
     return NFLBM_OK;
   }
   const size_t n = sim->n;
@@ -1411,6 +1504,8 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
   (void)hipFree(dmask);
   if (e != hipSuccess) return hip_fail(sim, e, "set_solid");
   sim->solid_host.assign(solid, solid + n);
+  sim->out_fluid = fluid_out;
+  ++sim->boundary_version;
   return NFLBM_OK;
 }
 
@@ -1479,13 +1574,11 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(sim, e, "set_fields");
-  // record form of f: unless the initial f is zero (rest at P_ref), the first
-  // step takes each node's f as the equilibrium of its own record (the
-  // population form stores exactly that equilibrium at every node)
-  bool moving = false;
-  for (size_t q = 0; v && q < 3 * n && !moving; ++q) moving = v[q] != 0.0;
-  for (size_t q = 0; P && q < n && !moving; ++q) moving = P[q] != 0.0;
-  sim->f_local = sim->fform && moving;
+  // moment form: the first step starts from the initial populations (the
+  // record form of f takes each node's f as the equilibrium of its own
+  // record, which the population form stores at every node; g entering
+  // across an open face is the initial 0)
+  sim->f_local = sim->gform != 0;
   return sim_nan_reset(sim);
 }
 
@@ -1709,6 +1802,24 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
       }
       if (crossed) {
         if (wall) entry = -1;
+        if (entry >= 0 && geom) {
+          // a solid node on the open face continues beyond it: the link whose
+          // in-face part comes from a solid node is a wall link
+          int t[3] = {x - E[k][0], y - E[k][1], z - E[k][2]};
+          t[entry / 2] = entry / 2 == 0 ? x : (entry / 2 == 1 ? y : z);
+          bool inside = true;
+          for (int d = 0; d < 3; ++d) {
+            if (t[d] < 0 || t[d] >= dims[d]) {
+              if (sim->wall[d]) inside = false;
+              else t[d] = (t[d] + dims[d]) % dims[d];
+            }
+          }
+          const int xyz0[3] = {x, y, z};
+          const bool moved = t[0] != xyz0[0] || t[1] != xyz0[1] || t[2] != xyz0[2];
+          if (inside && moved &&
+              sim->solid_host[size_t(t[0]) + size_t(sim->nx) * (size_t(t[1]) + size_t(sim->ny) * size_t(t[2]))])
+            entry = -1;
+        }
         dir = (k & 1) ? k + 1 : k - 1;
         return self;
       }
@@ -1775,6 +1886,8 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
               for (int i = 0; i < NE; ++i) {
                 double v = val(gkbuf.data(), size_t(dir - 1) * gst + src * NE + i, sim->fs, true);
                 if (entry >= 0) v = face_gsum(*sim, entry, sim->uidx[i], k) - v;
+                // moment form before its first step: the initial g_k = 0
+                if (entry >= 0 && sim->gform && sim->f_local) v = 0.0;
                 host_out[(size_t(sim->uidx[i]) * sim->Q + k) * n + q] = v;
               }
             }
@@ -1792,9 +1905,9 @@ int nflbm_get_field(nflbm_sim* sim, int field, double* host_out) {
   return fail(sim, NFLBM_EINVAL, "unknown field");
 }
 
-// The record form of f appends one host-side byte to the checkpoint: whether
+// The moment form appends one host-side byte to the checkpoint: whether
 // the next step starts from the equilibria set_fields wrote.
-size_t state_tail(const nflbm_sim* s) { return s->fform ? 1 : 0; }
+size_t state_tail(const nflbm_sim* s) { return s->gform ? 1 : 0; }
 
 int nflbm_state_bytes(nflbm_sim* sim, size_t* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");

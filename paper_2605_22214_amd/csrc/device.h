@@ -34,6 +34,13 @@ struct D3Q19 {
 };
 // In both sets the opposite of direction k (k >= 1) is k + 1 for odd k.
 __host__ __device__ constexpr int opposite(int k) { return (k & 1) ? k + 1 : k - 1; }
+// Index of the direction (ex, ey, ez) in set L, or -1.
+template <class L>
+__host__ __device__ constexpr int direction_of(int ex, int ey, int ez) {
+  for (int k = 0; k < L::Q; ++k)
+    if (L::e[k][0] == ex && L::e[k][1] == ey && L::e[k][2] == ez) return k;
+  return -1;
+}
 
 // ----------------------------------------------------------- storage types
 template <int ST> struct StoreT;
@@ -362,9 +369,25 @@ __device__ __forceinline__ bool pulled_from_wall(const Nbr& b, int k) {
   if (!WALLS) return false;
   return (b.pm >> k) & 1u;
 }
+// True when the population arriving along e_k comes from beyond a face of
+// the lattice (a walled axis), open or not.
+template <class L>
+__device__ __forceinline__ bool crosses_face(const Nbr& b, int k) {
+  bool c = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (L::e[k][d] > 0) c = c || b.wlo[d];
+    if (L::e[k][d] < 0) c = c || b.whi[d];
+  }
+  return c;
+}
 // The open face (0..5 = x-, x+, y-, y+, z-, z+) the population arriving along
 // e_k enters across, or -1: it crosses no face, or a wall face (a wall wins
-// at a corner; between two open faces the first axis's face).
+// at a corner; between two open faces the first axis's face).  With solid
+// geometry a solid node on an open face continues beyond it: if e_k without
+// its component normal to the face comes from a solid node inside the
+// lattice (that direction's pull bit set, no face crossed), the link is a
+// wall link and -1 is returned.
 template <class L, bool WALLS>
 __device__ __forceinline__ int entry_face(const Nbr& b, int k, int open) {
   if (!WALLS || !open) return -1;
@@ -382,7 +405,54 @@ __device__ __forceinline__ int entry_face(const Nbr& b, int k, int open) {
       wall = true;
     }
   }
-  return wall ? -1 : face;
+  if (wall) return -1;
+  if (face >= 0 && b.geom) {
+    bool prism = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d != (face >> 1) || L::e[k][d] == 0) continue;
+      // the in-face part of e_k: e_k with component d removed
+      const int kt = direction_of<L>(d == 0 ? 0 : L::e[k][0], d == 1 ? 0 : L::e[k][1], d == 2 ? 0 : L::e[k][2]);
+      if (kt > 0) prism = ((b.pm >> kt) & 1u) && !crosses_face<L>(b, kt);
+    }
+    if (prism) return -1;
+  }
+  return face;
+}
+
+// Record form of f (every node relaxes with omega+ = omega- = 1): the
+// post-collision f of a node is fixed by its records, Eqs. TRT, FTRT and
+// hydroforce with omega = 1 giving
+//   f*_k = w_k [s_k / w_k + fB + (e.F)(9/2 e.v +- 3/2)],  fB = 3 P - 3/2 v.F,
+// with s_k / w_k = (e.v)(9/2 e.v +- 3) - 3/2 v.v the term the equilibrium of g
+// shares, e the odd member of k's pair and + for that member.  The node
+// stores (fB, F) beside its (v, -3/2 v.v).  f_scaled returns f*_k / w_k for
+// direction kd from v4 = (v, -3/2 v.v) and fr = (fB, F).
+template <class L, class T>
+__device__ __forceinline__ T f_from_s(int kd, T ev, T u, const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T F[3] = {fr[1], fr[2], fr[3]};
+  const T eF = proj<L>(kp, F);
+  return u + fma(eF, fma(T(4.5), ev, (kd & 1) ? T(1.5) : -T(1.5)), fr[0]);
+}
+template <class L, class T>
+__device__ __forceinline__ T f_scaled(int kd, const T (&v4)[4], const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T v[3] = {v4[0], v4[1], v4[2]};
+  const T ev = proj<L>(kp, v);
+  const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
+  return f_from_s<L>(kd, ev, u, fr);
+}
+// The equilibrium of the state set_fields writes, f^eq_k(P0, v0) / w_k =
+// A0 + 9/2 (e.v0)^2 +- 3 e.v0 (Eq. feq), from the record (A0, v0) with
+// A0 = 3 P0 - 3/2 v0.v0.
+template <class L, class T>
+__device__ __forceinline__ T f_scaled_local(int kd, const T (&fr)[4]) {
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T v0[3] = {fr[1], fr[2], fr[3]};
+  const T ev = proj<L>(kp, v0);
+  const T q = fma(T(4.5) * ev, ev, fr[0]);
+  return (kd & 1) ? fma(T(3), ev, q) : fma(-T(3), ev, q);
 }
 
 // Convective outflow plane: the in-plane index p of node (x, y, z) when it

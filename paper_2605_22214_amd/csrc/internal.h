@@ -68,8 +68,10 @@ enum StepFlags {
   kFlagNoHydro = 16,      // diffusive-only: f not evolved, v = 0
   kFlagCheckNaN = 32,     // this step: the update raises *nanflag at a non-finite node
   kFlagFRecord = 64,      // record form of f (omega+ = omega- = 1): (fB, F) per node
-  kFlagFLocal = 128       // record form, first step after set_fields: a node's f is
-                          // the local equilibrium (A0, v0) of its own record
+  kFlagFLocal = 128       // moment form, first step after set_fields: the incoming
+                          // populations are the initial ones (record form of f: a
+                          // node's f is the local equilibrium (A0, v0) of its own
+                          // record; g entering across an open face is 0)
 };
 
 // What a launch of the update does: a time step, the FP64 node fields of
@@ -195,6 +197,7 @@ struct OutflowArgs {
   StepArgs sa;
   double* partial;                    // [blocks]
   double* u;                          // [1]
+  double fluid;                       // fluid nodes of plane N-1 (U is their mean)
   int blocks;
   int start;
 };

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device.h"
 
@@ -195,41 +196,6 @@ constexpr int moment_record() {
   return (r * int(sizeof(T)) / 16) % 2 == 1 ? r : r + 16 / int(sizeof(T));
 }
 
-// Record form of f (every node relaxes with omega+ = omega- = 1): the
-// post-collision f of a node is fixed by its records, Eqs. TRT, FTRT and
-// hydroforce with omega = 1 giving
-//   f*_k = w_k [s_k / w_k + fB + (e.F)(9/2 e.v +- 3/2)],  fB = 3 P - 3/2 v.F,
-// with s_k / w_k = (e.v)(9/2 e.v +- 3) - 3/2 v.v the term the equilibrium of g
-// shares, e the odd member of k's pair and + for that member.  The node
-// stores (fB, F) beside its (v, -3/2 v.v).  f_scaled returns f*_k / w_k for
-// direction kd from v4 = (v, -3/2 v.v) and fr = (fB, F).
-template <class L, class T>
-__device__ __forceinline__ T f_from_s(int kd, T ev, T u, const T (&fr)[4]) {
-  const int kp = (kd & 1) ? kd : kd - 1;
-  const T F[3] = {fr[1], fr[2], fr[3]};
-  const T eF = proj<L>(kp, F);
-  return u + fma(eF, fma(T(4.5), ev, (kd & 1) ? T(1.5) : -T(1.5)), fr[0]);
-}
-template <class L, class T>
-__device__ __forceinline__ T f_scaled(int kd, const T (&v4)[4], const T (&fr)[4]) {
-  const int kp = (kd & 1) ? kd : kd - 1;
-  const T v[3] = {v4[0], v4[1], v4[2]};
-  const T ev = proj<L>(kp, v);
-  const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
-  return f_from_s<L>(kd, ev, u, fr);
-}
-// The equilibrium of the state set_fields writes, f^eq_k(P0, v0) / w_k =
-// A0 + 9/2 (e.v0)^2 +- 3 e.v0 (Eq. feq), from the record (A0, v0) with
-// A0 = 3 P0 - 3/2 v0.v0.
-template <class L, class T>
-__device__ __forceinline__ T f_scaled_local(int kd, const T (&fr)[4]) {
-  const int kp = (kd & 1) ? kd : kd - 1;
-  const T v0[3] = {fr[1], fr[2], fr[3]};
-  const T ev = proj<L>(kp, v0);
-  const T q = fma(T(4.5) * ev, ev, fr[0]);
-  return (kd & 1) ? fma(T(3), ev, q) : fma(-T(3), ev, q);
-}
-
 template <class L, int NE, int ST, bool WALLS, int TXL, bool FR>
 __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
                                             const DevParams<typename StoreT<ST>::T>* __restrict__ Pp, int b,
@@ -370,20 +336,23 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     }
   };
 
-  // Per-target sums of the z march: with float records sc and sd hold
-  // sum C s_k / w_k of the incoming populations over the axis and the
-  // diagonal directions (weighted once at the end), in FP64 sc holds
-  // sum C s_k itself; smu holds sum w_k mu~ of their sources, c and d0 the
-  // node's own C and its rest-population term C s_0 + (1 - w_0) m mu~.
+  // Per-target sums of the z march.  s holds the target's net change of C
+  // from its incoming populations, sum_k (C s_k - w_k m mu~) of their
+  // sources, with the rest-population term C s_0 + (1 - w_0) m mu~ of its own
+  // record folded in; c is the node's own C.  With float records and f as
+  // populations (CLASS), s and sd instead hold sum (C s_k / w_k - m mu~) over
+  // the axis and the diagonal directions, weighted once at the end, and d0
+  // the rest-population term: the per-direction weight is then not applied.
   // Record form of f: fm sums the incoming f (sum_k f_k), jm their e_k f_k.
+  constexpr bool CLASS = AOS && !FR;
   struct Acc {
-    T sc[NE], sd[NE], smu[NE], c[NE], d0[NE];
+    T s[NE], sd[NE], c[NE], d0[NE];
     T fm, jm[3];
     bool solid;
   };
   auto zero_acc = [&](Acc& A) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) A.sc[e] = A.sd[e] = A.smu[e] = A.c[e] = A.d0[e] = T(0);
+    for (int e = 0; e < NE; ++e) A.s[e] = A.sd[e] = A.c[e] = A.d0[e] = T(0);
     A.fm = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) A.jm[d] = T(0);
@@ -396,51 +365,87 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       if (L::e[kin][d] != 0) A.jm[d] += (L::e[kin][d] > 0) ? fk : -fk;
   };
 
-  // One incoming population of direction kd whose source record is at src:
-  // s_k / w_k = (e.v)(4.5 e.v +- 3) - 3/2 v.v (Eqs. feq, geq) from the
-  // source's v, formed through the odd member of the pair.
-  // With the record form of f (and with_f), the same source's f*_kd is added
-  // to the moments of the f arriving along e_kin (kin = kd, or its opposite
-  // where the population is bounced back), from the same s_k / w_k.
-  auto add_source = [&](Acc& A, const T* src, int kd, int kin, bool with_f) {
-    const int kp = (kd & 1) ? kd : kd - 1;
-    T cs[NEP], ms[NEP], v4[4];
-    read_pos(src, cs, ms, v4);
-    const T vs[3] = {v4[0], v4[1], v4[2]};
-    const T ev = proj<L>(kp, vs);
-    const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
-    const T wk = static_cast<T>(L::w[kp]);
-    if constexpr (FR) {
-      if (with_f) {
-        T f4[4];
-        if constexpr (AOS) {
-          vld<T, 4>(src + 2 * NEP + 4, f4);
-        } else {
+  // A source position's record as read from LDS (f4 only with the record
+  // form of f)
+  struct Rec {
+    T cs[NEP], ms[NEP], v4[4], f4[4];
+  };
+  // WF (std::true_type / std::false_type): whether the f* of the sources are
+  // gathered (false only on the first step after set_fields)
+  auto read_rec = [&](const T* src, Rec& R, auto WF) {
+    read_pos(src, R.cs, R.ms, R.v4);
+    if constexpr (FR && decltype(WF)::value) {
+      if constexpr (AOS) {
+        vld<T, 4>(src + 2 * NEP + 4, R.f4);
+      } else {
 #pragma unroll
-          for (int d = 0; d < 4; ++d) f4[d] = src[(NF + d) * PXY];
-        }
-        const T fk = wk * f_from_s<L>(kd, ev, u, f4);
-        A.fm += fk;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (L::e[kin][d] != 0) A.jm[d] += (L::e[kin][d] > 0) ? fk : -fk;
+        for (int d = 0; d < 4; ++d) R.f4[d] = src[(NF + d) * PXY];
       }
     }
-    if constexpr (!AOS) {
-      // FP64: weighted per direction (the class sums' extra accumulators
-      // cost the double-width kernel more than the multiplies they save)
-      const T sk = wk * u;
+  };
+  // One incoming population of direction kd from the source record R:
+  // s_k / w_k = (e.v)(4.5 e.v +- 3) - 3/2 v.v (Eqs. feq, geq) from the
+  // source's v, formed through the odd member of the pair; negm = -m.
+  // With the record form of f (and with_f), the same source's f*_kd is added
+  // to the moments of the f arriving along e_kin (kin = kd, or its opposite
+  // where the population is bounced back), from the same s_k.
+  // NEG (std::true_type): the population of g enters with the opposite sign
+  // (anti-bounce-back at an open face); f keeps its sign.
+  auto acc_rec = [&](Acc& A, const Rec& R, int kd, int kin, auto WF, T negm, auto NEG) {
+    constexpr bool N_ = decltype(NEG)::value;
+    const int kp = (kd & 1) ? kd : kd - 1;
+    const T vs[3] = {R.v4[0], R.v4[1], R.v4[2]};
+    const T ev = proj<L>(kp, vs);
+    const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), R.v4[3]);
+    const T wk = static_cast<T>(L::w[kp]);
+    const T gm = N_ ? -negm : negm;
+    if constexpr (CLASS) {
+      if (L::w[kp] == L::w[1]) {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) A.sc[e] = fma(cs[e], sk, A.sc[e]);
-    } else if (L::w[kp] == L::w[1]) {
+        for (int e = 0; e < NE; ++e) A.s[e] = fma(N_ ? -R.cs[e] : R.cs[e], u, fma(gm, R.ms[e], A.s[e]));
+      } else {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) A.sc[e] = fma(cs[e], u, A.sc[e]);
+        for (int e = 0; e < NE; ++e) A.sd[e] = fma(N_ ? -R.cs[e] : R.cs[e], u, fma(gm, R.ms[e], A.sd[e]));
+      }
     } else {
+      const T wu = wk * u;
+      const T mw = gm * wk;
 #pragma unroll
-      for (int e = 0; e < NE; ++e) A.sd[e] = fma(cs[e], u, A.sd[e]);
+      for (int e = 0; e < NE; ++e) A.s[e] = fma(N_ ? -R.cs[e] : R.cs[e], wu, fma(mw, R.ms[e], A.s[e]));
+      if constexpr (FR && decltype(WF)::value) {
+        // f*_k = w_k s_k / w_k + w_k [fB + (e.F)(9/2 e.v +- 3/2)]
+        const T F[3] = {R.f4[1], R.f4[2], R.f4[3]};
+        const T eF = proj<L>(kp, F);
+        const T t = fma(eF, fma(T(4.5), ev, (kd & 1) ? T(1.5) : -T(1.5)), R.f4[0]);
+        add_f_value(A, fma(wk, t, wu), kin);
+      }
     }
+  };
+  auto add_source = [&](Acc& A, const T* src, int kd, int kin, auto WF, T negm) {
+    Rec R;
+    read_rec(src, R, WF);
+    acc_rec(A, R, kd, kin, WF, negm, std::false_type{});
+  };
+  // open faces (anti-bounce-back for g, velocity Dirichlet for f): the
+  // population entering along e_k across face fc is minus (f: plus) this
+  // node's own opposite one, plus g^eq_k + g^eq_kbar of the face (f: plus
+  // 2 w_k (e_k . v_b) / c_s^2).  On the first step after set_fields the
+  // incoming populations are the initial ones, g_k = 0 (and f from the
+  // node's own record, added separately).
+  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+  const int open = (WALLS && FB) ? FB->open : 0;
+  const bool first = (a.flags & kFlagFLocal) != 0;
+  auto add_open = [&](Acc& A, const T* own, int k, int fc, auto WF, T negm) {
+    if (first) return;
+    Rec R;
+    read_rec(own, R, WF);
+    acc_rec(A, R, opposite(k), k, WF, negm, std::true_type{});
 #pragma unroll
-    for (int e = 0; e < NE; ++e) A.smu[e] = fma(wk, ms[e], A.smu[e]);
+    for (int e = 0; e < NE; ++e) {
+      if constexpr (CLASS) A.d0[e] += FB->gsum[fc][e][k];
+      else A.s[e] += FB->gsum[fc][e][k];
+    }
+    if constexpr (FR && decltype(WF)::value) add_f_value(A, FB->fcorr[fc][k], k);
   };
   const int li = (ty + 1) * PX + (tx + 1);
   // record of the position x - e (in-plane part of e) in the LDS plane
@@ -452,16 +457,34 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   // itself (in-plane directions, its rest population, and every population
   // bounced back at a wall, which is its own), and the node of plane p - 1
   // (e_z = -1).  A target is complete once plane t + 1 has been seen.
-  auto plane_step = [&](int p, bool have, Acc& lo, Acc& mid, Acc& hi) {
-    if (D3 && have && p + 1 >= z0 && p + 1 < z1) {
+  auto plane_step = [&](int p, bool have, Acc& lo, Acc& mid, Acc& hi, auto WF) {
+    const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
+    const T negm = -P.m;
+    const bool need_hi = D3 && have && p + 1 >= z0 && p + 1 < z1;
+    const bool need_lo = D3 && have && p - 1 >= z0 && p - 1 < z1;
+    // Away from walls, the node of plane p + 1 (directions (ex, ey, +1)) and
+    // the node of plane p - 1 (directions (ex, ey, -1)) pull from the same
+    // five positions of plane p: each record is read once for both.
+    const bool merged = D3 && !WALLS && need_hi && need_lo;
+    if (merged) {
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        if (L::e[k][2] == 1) {
+          const int km = direction_of<L>(L::e[k][0], L::e[k][1], -1);
+          Rec R;
+          read_rec(src_at(L::e[k][0], L::e[k][1]), R, WF);
+          acc_rec(hi, R, k, k, WF, negm, std::false_type{});
+          acc_rec(lo, R, km, km, WF, negm, std::false_type{});
+        }
+    }
+    if (!merged && need_hi) {
       const Nbr nb = neighbours<L, WALLS>(x, y, p + 1, a);
 #pragma unroll
       for (int k = 1; k < Q; ++k)
         if (L::e[k][2] == 1 && !pulled_from_wall<L, WALLS>(nb, k))
-          add_source(hi, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
+          add_source(hi, src_at(L::e[k][0], L::e[k][1]), k, k, WF, negm);
     }
     if (p >= z0 && p < z1) {
-      const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
       const Nbr nb = neighbours<L, WALLS>(x, y, p, a);
       mid.solid = solid_node<WALLS>(nb);
       const T* own = src_at(0, 0);
@@ -473,15 +496,22 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
           mid.c[e] = cs[e];
-          mid.d0[e] = fma(cs[e], s0, m0 * ms[e]);
+          const T d0 = fma(cs[e], s0, m0 * ms[e]);
+          if constexpr (CLASS) mid.d0[e] = d0;
+          else mid.s[e] += d0;
         }
       }
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
-        if (pulled_from_wall<L, WALLS>(nb, k)) add_source(mid, own, opposite(k), k, !flocal);
-        else if (L::e[k][2] == 0) add_source(mid, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
+        if (pulled_from_wall<L, WALLS>(nb, k)) {
+          const int fc = entry_face<L, WALLS>(nb, k, open);
+          if (WALLS && fc >= 0) add_open(mid, own, k, fc, WF, negm);
+          else add_source(mid, own, opposite(k), k, WF, negm);
+        } else if (L::e[k][2] == 0) {
+          add_source(mid, src_at(L::e[k][0], L::e[k][1]), k, k, WF, negm);
+        }
       }
-      if (FR && flocal) {
+      if constexpr (FR && !decltype(WF)::value) {
         // first step after set_fields: every f of the node is the
         // equilibrium of its own record (A0, v0)
         T f4[4], v3[3];
@@ -490,12 +520,16 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
         for (int k = 1; k < Q; ++k) add_f_value(mid, static_cast<T>(L::w[k]) * f_scaled_local<L>(k, f4), k);
       }
     }
-    if (D3 && have && p - 1 >= z0 && p - 1 < z1) {
+    if (!merged && need_lo) {
+      // in the merged path's order (by the (ex, ey, +1) directions), so that
+      // a node's sums do not depend on where the z runs start and end
       const Nbr nb = neighbours<L, WALLS>(x, y, p - 1, a);
 #pragma unroll
       for (int k = 1; k < Q; ++k)
-        if (L::e[k][2] == -1 && !pulled_from_wall<L, WALLS>(nb, k))
-          add_source(lo, src_at(L::e[k][0], L::e[k][1]), k, k, !flocal);
+        if (L::e[k][2] == 1) {
+          const int km = direction_of<L>(L::e[k][0], L::e[k][1], -1);
+          if (!pulled_from_wall<L, WALLS>(nb, km)) add_source(lo, src_at(L::e[k][0], L::e[k][1]), km, km, WF, negm);
+        }
     }
   };
 
@@ -507,6 +541,39 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   auto finish = [&](const Acc& A, int z) {
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     T sum[NE];
+    // convective outflow: the boundary plane's post-streaming populations
+    // (every k) are the plane buffers, not the gathered sums
+    const int op = (WALLS && a.out_face >= 0) ? outflow_plane_index(a.out_face, 0, x, y, z, a) : -1;
+    if (WALLS && op >= 0 && !A.solid) {
+      const uint32_t PL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
+      const T* og = gptr<const T>(a.out_g);
+      T cn[NC];
+      T rest = T(0);
+      for (int e = 0; e < NE; ++e) {
+        T m = T(0);
+        for (int k = 1; k < Q; ++k) m += og[(uint32_t(e) * Q + k) * PL + op];
+        sum[e] = og[uint32_t(e) * Q * PL + op] + m;
+        cn[e] = sum[e];
+        rest += sum[e];
+      }
+      cn[NE] = T(1) - rest;
+      if constexpr (FR) {
+        const T* of = gptr<const T>(a.out_f);
+        T fm[4] = {T(0), T(0), T(0), T(0)};
+        for (int k = 1; k < Q; ++k) {
+          const T fk = of[uint32_t(k - 1) * PL + op];
+          fm[0] += fk;
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? fk : -fk;
+        }
+        vst_nt<T, 4>(at(gptr<T>(a.fmom), node * 4), fm);
+      }
+      const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
+      vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
+      *at(gptr<T>(a.eb), node) = bulk_energy<NC, T>(cn, P);
+      return;
+    }
     if (A.solid) {
 #pragma unroll
       for (int e = 0; e < NE; ++e) sum[e] = T(0);
@@ -528,9 +595,8 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     T rest = T(0);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      T sc = A.sc[e];
-      if constexpr (AOS) sc = fma(static_cast<T>(L::w[1]), A.sc[e], static_cast<T>(L::w[Q - 1]) * A.sd[e]);
-      const T d = A.d0[e] + fma(-P.m, A.smu[e], sc);
+      T d = A.s[e];
+      if constexpr (CLASS) d = A.d0[e] + fma(static_cast<T>(L::w[1]), A.s[e], static_cast<T>(L::w[Q - 1]) * A.sd[e]);
       sum[e] = A.c[e] + d;
       cn[e] = sum[e];
       rest += sum[e];
@@ -542,24 +608,28 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
 
   // One LDS plane: planes z0 - 1 .. z1 pass through it in turn (D2Q9: the
   // single plane), each read by three targets as above.
-  Acc lo, mid, hi;
-  zero_acc(lo);
-  zero_acc(mid);
-  zero_acc(hi);
-  const int p_first = D3 ? z0 - 1 : 0, p_last = D3 ? z1 : 0;
-  for (int p = p_first; p <= p_last; ++p) {
-    if (p != p_first) __syncthreads();      // every read of the previous plane is done
-    const bool have = load_plane(p);
-    __syncthreads();
-    if (active) {
-      plane_step(p, have, lo, mid, hi);
-      if (!D3) finish(mid, 0);
-      else if (p - 1 >= z0) finish(lo, p - 1);
-    }
-    lo = mid;
-    mid = hi;
+  auto march = [&](auto WF) {
+    Acc lo, mid, hi;
+    zero_acc(lo);
+    zero_acc(mid);
     zero_acc(hi);
-  }
+    const int p_first = D3 ? z0 - 1 : 0, p_last = D3 ? z1 : 0;
+    for (int p = p_first; p <= p_last; ++p) {
+      if (p != p_first) __syncthreads();      // every read of the previous plane is done
+      const bool have = load_plane(p);
+      __syncthreads();
+      if (active) {
+        plane_step(p, have, lo, mid, hi, WF);
+        if (!D3) finish(mid, 0);
+        else if (p - 1 >= z0) finish(lo, p - 1);
+      }
+      lo = mid;
+      mid = hi;
+      zero_acc(hi);
+    }
+  };
+  if (flocal) march(std::false_type{});
+  else march(std::true_type{});
 }
 
 template <class L, int NE, int ST, bool WALLS, int TXL, bool FR>
@@ -824,7 +894,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   };
 
-  auto process = [&](int z, int s_dn, int s_c, int s_up) {
+  // PL (std::true_type): the run has no stabilising term, the conservative
+  // force and hydrodynamics, so those flags are not tested per node
+  auto process = [&](int z, int s_dn, int s_c, int s_up, auto PL) {
+    constexpr bool PLAIN = decltype(PL)::value;
+    const bool omega = !PLAIN && (a.flags & kFlagOmega);
+    const bool potential = !PLAIN && (a.flags & kFlagPotential);
     // the coefficient tables as seen from this plane: their loads take
     // immediate offsets from one base instead of hoisted per-entry addresses
     const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
@@ -907,6 +982,8 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     } else {
       // next to a wall, direction by direction: a neighbour inside a wall
       // takes the centre value, i.e. contributes nothing
+      Nbr nbw;
+      if (geom && open) nbw = neighbours<L, WALLS>(x, y, z, a);
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
@@ -914,6 +991,9 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         bool wall = false;
         if (geom) {
           wall = (pm >> opposite(k)) & 1u;      // x + e_k is x - e_(opposite k)
+          // beyond an open face (not continuing a solid node): an ordinary
+          // LDS position holding the face's values
+          if (wall && open && entry_face<L, WALLS>(nbw, opposite(k), open) >= 0) wall = false;
         } else {
           // a neighbour beyond an open face is an ordinary LDS position
           if (ex != 0 && a.wall_x) wall |= (x + ex < 0 && plain(0)) || (x + ex >= a.nx && plain(1));
@@ -969,7 +1049,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         br = fma(row, c[l], br);
       }
       T val = fma(P.k34D, lap[i], (P.k12D * c[i]) * br);
-      if (a.flags & kFlagOmega) {
+      if (omega) {
         T sx = T(0);
 #pragma unroll
         for (int k2 = 0; k2 < NC; ++k2)
@@ -1008,7 +1088,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 
     // ---- surface tension force (Eq. Fsnew, or Eq. ststand) + body force
     T F[3];
-    if (a.flags & kFlagPotential) {
+    if (potential) {
       F[0] = F[1] = F[2] = T(0);
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
@@ -1042,7 +1122,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     // live through it and cost occupancy.
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     // diffusive-only runs (Sec. IV B) do not evolve f: v = 0 and P = 0
-    const bool hydro = !(a.flags & kFlagNoHydro);
+    const bool hydro = PLAIN || !(a.flags & kFlagNoHydro);
     // Over the opposite pairs {k, k+1}: sp = f_k + f_k+1 and dp = f_k - f_k+1
     // give the moments (sum_k f_k and sum_k e_k f_k) and, below, the even and
     // odd parts the TRT collision relaxes; f itself is not needed after this.
@@ -1281,68 +1361,76 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   };
 
-  if constexpr (D3 && !WALLS && sizeof(T) == 4) {
-    // Periodic lattices in float: rolling window of three LDS planes, with
-    // the next plane's values fetched into registers while the current plane
-    // is processed and written to LDS at the top of the next iteration, so
-    // that the fill's load latency overlaps the compute.
-    T nxt[2][NE + 1];
-    auto fetch_plane = [&](int gz) {
-      gz = (gz < 0) ? gz + a.nz : (gz >= a.nz ? gz - a.nz : gz);
-      const uint32_t zoff = uint32_t(gz) * nxy;
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        if (!fill_ok[r]) continue;
-        const uint32_t node = fill_off[r] + zoff;
-        T ce[NE];
-        vld<T, NE>(at(conc, node * NE), ce);
-#pragma unroll
-        for (int e = 0; e < NE; ++e) nxt[r][e] = ce[e];
-        nxt[r][NE] = *at(eb, node);
+  auto march = [&](auto PL) {
+    if constexpr (D3 && !WALLS && sizeof(T) == 4) {
+      // Periodic lattices in float: rolling window of three LDS planes, with
+      // the next plane's values fetched into registers while the current plane
+      // is processed and written to LDS at the top of the next iteration, so
+      // that the fill's load latency overlaps the compute.
+      T nxt[2][NE + 1];
+      auto fetch_plane = [&](int gz) {
+        gz = (gz < 0) ? gz + a.nz : (gz >= a.nz ? gz - a.nz : gz);
+        const uint32_t zoff = uint32_t(gz) * nxy;
+  #pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if (!fill_ok[r]) continue;
+          const uint32_t node = fill_off[r] + zoff;
+          T ce[NE];
+          vld<T, NE>(at(conc, node * NE), ce);
+  #pragma unroll
+          for (int e = 0; e < NE; ++e) nxt[r][e] = ce[e];
+          nxt[r][NE] = *at(eb, node);
+        }
+      };
+      auto put_plane = [&](int slot) {
+        T* base = sm + slot * plane_stride;
+  #pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if (!fill_ok[r]) continue;
+          const int idx = tid + 256 * r;
+  #pragma unroll
+          for (int e = 0; e <= NE; ++e) base[e * PXY + idx] = nxt[r][e];
+        }
+      };
+      load_plane(0, z0 - 1);
+      load_plane(1, z0);
+      fetch_plane(z0 + 1);
+      for (int z = z0; z < z1; ++z) {
+        const int r = z - z0;
+        const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
+        asm volatile("" ::: "memory");
+        put_plane(s_up);
+        __syncthreads();
+        if (z + 1 < z1) fetch_plane(z + 2);
+        if (active) process(z, s_dn, s_c, s_up, PL);
+        __syncthreads();
       }
-    };
-    auto put_plane = [&](int slot) {
-      T* base = sm + slot * plane_stride;
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        if (!fill_ok[r]) continue;
-        const int idx = tid + 256 * r;
-#pragma unroll
-        for (int e = 0; e <= NE; ++e) base[e * PXY + idx] = nxt[r][e];
+    } else if constexpr (D3) {
+      // rolling window of three LDS planes: z-1, z, z+1
+      load_plane(0, z0 - 1);
+      load_plane(1, z0);
+      for (int z = z0; z < z1; ++z) {
+        const int r = z - z0;
+        const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
+        // keep the per-plane coefficient loads inside the loop (scalar cache
+        // hits) instead of holding every coefficient live across all planes
+        asm volatile("" ::: "memory");
+        load_plane(s_up, z + 1);
+        __syncthreads();
+        if (active) process(z, s_dn, s_c, s_up, PL);
+        __syncthreads();
       }
-    };
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
-    fetch_plane(z0 + 1);
-    for (int z = z0; z < z1; ++z) {
-      const int r = z - z0;
-      const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
-      asm volatile("" ::: "memory");
-      put_plane(s_up);
+    } else {
+      load_plane(0, 0);
       __syncthreads();
-      if (z + 1 < z1) fetch_plane(z + 2);
-      if (active) process(z, s_dn, s_c, s_up);
-      __syncthreads();
+      if (active) process(0, 0, 0, 0, PL);
     }
-  } else if constexpr (D3) {
-    // rolling window of three LDS planes: z-1, z, z+1
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
-    for (int z = z0; z < z1; ++z) {
-      const int r = z - z0;
-      const int s_dn = r % 3, s_c = (r + 1) % 3, s_up = (r + 2) % 3;
-      // keep the per-plane coefficient loads inside the loop (scalar cache
-      // hits) instead of holding every coefficient live across all planes
-      asm volatile("" ::: "memory");
-      load_plane(s_up, z + 1);
-      __syncthreads();
-      if (active) process(z, s_dn, s_c, s_up);
-      __syncthreads();
-    }
+  };
+  if constexpr (MODE == kModeStep) {
+    if (!(a.flags & (kFlagOmega | kFlagPotential | kFlagNoHydro))) march(std::true_type{});
+    else march(std::false_type{});
   } else {
-    load_plane(0, 0);
-    __syncthreads();
-    if (active) process(0, 0, 0, 0);
+    march(std::false_type{});
   }
 }
 
@@ -1559,11 +1647,19 @@ __global__ void __launch_bounds__(256) k_expand_f(StepArgs a, void* out) {
     for (int k = 1; k < Q; ++k) o[size_t(k - 1) * fst + node] = T(0);
     return;
   }
+  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+  const int open = (WALLS && FB) ? FB->open : 0;
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
-    const T val = static_cast<T>(L::w[k]) * f_scaled_local<L>(k, fr);
-    if (pulled_from_wall<L, WALLS>(nb, k)) o[size_t(opposite(k) - 1) * fst + node] = val;
-    else o[size_t(k - 1) * fst + upstream<L>(nb, k)] = val;
+    T val = static_cast<T>(L::w[k]) * f_scaled_local<L>(k, fr);
+    if (pulled_from_wall<L, WALLS>(nb, k)) {
+      // across an open face the read-back adds the face's correction
+      const int fc = entry_face<L, WALLS>(nb, k, open);
+      if (WALLS && fc >= 0) val -= FB->fcorr[fc][k];
+      o[size_t(opposite(k) - 1) * fst + node] = val;
+    } else {
+      o[size_t(k - 1) * fst + upstream<L>(nb, k)] = val;
+    }
   }
 }
 
@@ -1647,21 +1743,24 @@ __global__ void __launch_bounds__(256) k_spectrum(const double2* __restrict__ X,
   }
 }
 
-// Sum the partial diagnostic records [blocks][3N + 9] in block order.
-__global__ void __launch_bounds__(64) k_reduce_final(const double* __restrict__ partial, double* __restrict__ out,
-                                                     int N, int blocks) {
+// Combine the partial diagnostic records [blocks][3N + 9]: per entry, thread t
+// folds blocks t, t + 256, ... in that order, then the workgroup reduces the
+// 256 results in a fixed shuffle order, so the result is the same on every
+// run.  Entries: N + 3 sums, N maxima, N minima, one maximum, then sums.
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partial, double* __restrict__ out,
+                                                      int N, int blocks) {
+  __shared__ double scratch[4];
   const int rec = reduce_record_len(N);
-  for (int q = threadIdx.x; q < rec; q += 64) {
-    double acc = partial[q];
-    for (int b = 1; b < blocks; ++b) {
+  const int t = static_cast<int>(threadIdx.x);
+  for (int q = 0; q < rec; ++q) {
+    const int op = (q < N + 3) ? 0 : (q < 2 * N + 3) ? 1 : (q < 3 * N + 3) ? 2 : (q == 3 * N + 3) ? 1 : 0;
+    double acc = op == 0 ? 0.0 : (op == 1 ? -HUGE_VAL : HUGE_VAL);
+    for (int b = t; b < blocks; b += 256) {
       const double v = partial[size_t(b) * rec + q];
-      if (q < N + 3) acc += v;
-      else if (q < 2 * N + 3) acc = fmax(acc, v);
-      else if (q < 3 * N + 3) acc = fmin(acc, v);
-      else if (q == 3 * N + 3) acc = fmax(acc, v);
-      else acc += v;
+      acc = op == 0 ? acc + v : (op == 1 ? fmax(acc, v) : fmin(acc, v));
     }
-    out[q] = acc;
+    acc = block_reduce_d(acc, op, scratch);
+    if (t == 0) out[q] = acc;
   }
 }
 #endif
@@ -1700,41 +1799,21 @@ size_t conc_m_lds_bytes_for(int lat, int nc, int tx_log2, bool frecord) {
   return npl * rec * pxy * sizeof(TT<ST>);
 }
 
-hipError_t update_st0(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
-hipError_t update_st1(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
-hipError_t update_st2(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s);
-hipError_t diag_st0(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
-hipError_t diag_st1(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
-hipError_t diag_st2(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s);
-hipError_t init_st0(int lat, int nc, const InitArgs& a, hipStream_t s);
-hipError_t init_st1(int lat, int nc, const InitArgs& a, hipStream_t s);
-hipError_t init_st2(int lat, int nc, const InitArgs& a, hipStream_t s);
-hipError_t conc_st0(int lat, int nc, const StepArgs& a, hipStream_t s);
-hipError_t conc_st1(int lat, int nc, const StepArgs& a, hipStream_t s);
-hipError_t conc_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
-hipError_t batch_st0(int lat, int nc, const BatchLaunch& b, hipStream_t s);
-hipError_t batch_st1(int lat, int nc, const BatchLaunch& b, hipStream_t s);
-hipError_t batch_st2(int lat, int nc, const BatchLaunch& b, hipStream_t s);
-hipError_t expand_st0(int lat, int nc, const StepArgs& a, hipStream_t s);
-hipError_t expand_f_st0(int lat, const StepArgs& a, void* out, hipStream_t s);
-hipError_t expand_f_st1(int lat, const StepArgs& a, void* out, hipStream_t s);
-hipError_t expand_f_st2(int lat, const StepArgs& a, void* out, hipStream_t s);
-hipError_t expand_st1(int lat, int nc, const StepArgs& a, hipStream_t s);
-hipError_t expand_st2(int lat, int nc, const StepArgs& a, hipStream_t s);
+// The launchers of one (precision, lattice, N), registered by the unit that
+// instantiates them (kernels.hip is compiled once per precision, lattice
+// and group of N, in parallel) and looked up by the common unit.
+struct KernelSet {
+  hipError_t (*update)(const StepArgs&, bool, hipStream_t);
+  hipError_t (*diag)(const StepArgs&, int, double*, int*, hipStream_t);
+  hipError_t (*init)(const InitArgs&, hipStream_t);
+  hipError_t (*conc)(const StepArgs&, hipStream_t);
+  hipError_t (*batch)(const BatchLaunch&, hipStream_t);
+  hipError_t (*expand)(const StepArgs&, hipStream_t);
+  hipError_t (*expand_f)(const StepArgs&, void*, hipStream_t);
+};
+KernelSet& kernel_set(int store, int lat, int nc);
 
 #if defined(NFLBM_UNIT_STORE) && NFLBM_UNIT_STORE >= 0
-
-#define NFLBM_NC_SWITCH(NCV, CALL)        \
-  switch (NCV) {                          \
-    case 2: return CALL(2);               \
-    case 3: return CALL(3);               \
-    case 4: return CALL(4);               \
-    case 5: return CALL(5);               \
-    case 6: return CALL(6);               \
-    case 7: return CALL(7);               \
-    case 8: return CALL(8);               \
-    default: return hipErrorInvalidValue; \
-  }
 
 inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr; }
 inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
@@ -1939,74 +2018,49 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class L, int ST>
-hipError_t batch_nc(int nc, const BatchLaunch& b, hipStream_t s) {
-#define CALL_B(K) launch_batch_t<L, K, ST>(b, s)
-  NFLBM_NC_SWITCH(nc, CALL_B)
-#undef CALL_B
+template <class L, int NC, int ST>
+hipError_t diag_launch(const StepArgs& a, int mb, double* out, int* nb, hipStream_t s) {
+  return launch_diag_t<L, NC, ST>(a, mb, out, nb, s);
+}
+template <class L, int NC, int ST>
+hipError_t update_launch(const StepArgs& a, bool fields, hipStream_t s) {
+  return launch_update_t<L, NC, ST>(a, fields, s);
 }
 
-template <class L, int ST>
-hipError_t conc_nc(int nc, const StepArgs& a, hipStream_t s) {
-#define CALL_C(K) launch_conc_t<L, K, ST>(a, s)
-  NFLBM_NC_SWITCH(nc, CALL_C)
-#undef CALL_C
+template <class L, int NC>
+void register_nc() {
+  constexpr int ST = NFLBM_UNIT_STORE;
+  KernelSet& k = kernel_set(ST, L::DIM == 3 ? 1 : 0, NC);
+  k.update = &update_launch<L, NC, ST>;
+  k.diag = &diag_launch<L, NC, ST>;
+  k.init = &launch_init_t<L, NC, ST>;
+  k.conc = &launch_conc_t<L, NC, ST>;
+  k.batch = &launch_batch_t<L, NC, ST>;
+  k.expand = &launch_expand_t<L, NC, ST>;
+  k.expand_f = &launch_expand_f_t<L, ST>;
 }
 
-template <class L, int ST>
-hipError_t update_nc(int nc, const StepArgs& a, bool fields, hipStream_t s) {
-#define CALL_U(K) launch_update_t<L, K, ST>(a, fields, s)
-  NFLBM_NC_SWITCH(nc, CALL_U)
-#undef CALL_U
+template <class L, int K>
+void register_if_in_unit() {
+  if constexpr (NFLBM_UNIT_NC_LO <= K && K <= NFLBM_UNIT_NC_HI) register_nc<L, K>();
 }
 
-template <class L, int ST>
-hipError_t diag_nc(int nc, const StepArgs& a, int mb, double* out, int* nb, hipStream_t s) {
-#define CALL_D(K) launch_diag_t<L, K, ST>(a, mb, out, nb, s)
-  NFLBM_NC_SWITCH(nc, CALL_D)
-#undef CALL_D
-}
-
-template <class L, int ST>
-hipError_t init_nc(int nc, const InitArgs& a, hipStream_t s) {
-#define CALL_I(K) launch_init_t<L, K, ST>(a, s)
-  NFLBM_NC_SWITCH(nc, CALL_I)
-#undef CALL_I
-}
-
-template <class L, int ST>
-hipError_t expand_nc(int nc, const StepArgs& a, hipStream_t s) {
-#define CALL_E(K) launch_expand_t<L, K, ST>(a, s)
-  NFLBM_NC_SWITCH(nc, CALL_E)
-#undef CALL_E
-}
-
-#define NFLBM_CAT2(a, b) a##b
-#define NFLBM_CAT(a, b) NFLBM_CAT2(a, b)
-#define NFLBM_ST NFLBM_UNIT_STORE
-
-hipError_t NFLBM_CAT(update_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, bool fields, hipStream_t s) {
-  return lat == 0 ? update_nc<D2Q9, NFLBM_ST>(nc, a, fields, s) : update_nc<D3Q19, NFLBM_ST>(nc, a, fields, s);
-}
-hipError_t NFLBM_CAT(diag_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, int mb, double* out, int* nb,
-                                       hipStream_t s) {
-  return lat == 0 ? diag_nc<D2Q9, NFLBM_ST>(nc, a, mb, out, nb, s) : diag_nc<D3Q19, NFLBM_ST>(nc, a, mb, out, nb, s);
-}
-hipError_t NFLBM_CAT(init_st, NFLBM_ST)(int lat, int nc, const InitArgs& a, hipStream_t s) {
-  return lat == 0 ? init_nc<D2Q9, NFLBM_ST>(nc, a, s) : init_nc<D3Q19, NFLBM_ST>(nc, a, s);
-}
-hipError_t NFLBM_CAT(conc_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
-  return lat == 0 ? conc_nc<D2Q9, NFLBM_ST>(nc, a, s) : conc_nc<D3Q19, NFLBM_ST>(nc, a, s);
-}
-hipError_t NFLBM_CAT(batch_st, NFLBM_ST)(int lat, int nc, const BatchLaunch& b, hipStream_t s) {
-  return lat == 0 ? batch_nc<D2Q9, NFLBM_ST>(nc, b, s) : batch_nc<D3Q19, NFLBM_ST>(nc, b, s);
-}
-hipError_t NFLBM_CAT(expand_f_st, NFLBM_ST)(int lat, const StepArgs& a, void* out, hipStream_t s) {
-  return lat == 0 ? launch_expand_f_t<D2Q9, NFLBM_ST>(a, out, s) : launch_expand_f_t<D3Q19, NFLBM_ST>(a, out, s);
-}
-hipError_t NFLBM_CAT(expand_st, NFLBM_ST)(int lat, int nc, const StepArgs& a, hipStream_t s) {
-  return lat == 0 ? expand_nc<D2Q9, NFLBM_ST>(nc, a, s) : expand_nc<D3Q19, NFLBM_ST>(nc, a, s);
-}
+// This unit's (precision, lattice, range of N): NFLBM_UNIT_LAT 0 = D2Q9,
+// 1 = D3Q19; N from NFLBM_UNIT_NC_LO to NFLBM_UNIT_NC_HI.  Registered when
+// the library is loaded.
+struct UnitRegistrar {
+  UnitRegistrar() {
+    using L = std::conditional_t<NFLBM_UNIT_LAT == 1, D3Q19, D2Q9>;
+    register_if_in_unit<L, 2>();
+    register_if_in_unit<L, 3>();
+    register_if_in_unit<L, 4>();
+    register_if_in_unit<L, 5>();
+    register_if_in_unit<L, 6>();
+    register_if_in_unit<L, 7>();
+    register_if_in_unit<L, 8>();
+  }
+};
+const UnitRegistrar unit_registrar;
 
 #else  // common unit
 
@@ -2026,68 +2080,58 @@ size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2, bool frecord) {
   }
 }
 
+KernelSet& kernel_set(int store, int lat, int nc) {
+  static KernelSet table[3][2][kMaxComp + 1] = {};
+  return table[store][lat][nc];
+}
+
+namespace {
+// the registered launchers, or none for an out-of-range request
+const KernelSet& kset(int store, int lat, int nc) {
+  static const KernelSet none = {};
+  if (store < 0 || store > 2 || lat < 0 || lat > 1 || nc < 0 || nc > kMaxComp) return none;
+  return kernel_set(store, lat, nc);
+}
+}  // namespace
+
 hipError_t launch_expand_f(int lat, int store, const StepArgs& a, void* out, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return expand_f_st0(lat, a, out, s);
-    case kStoreF32: return expand_f_st1(lat, a, out, s);
-    case kStoreF16S: return expand_f_st2(lat, a, out, s);
+  // the f launcher does not depend on N: any registered N of this lattice
+  for (int nc = 2; nc <= kMaxComp; ++nc) {
+    const KernelSet& k = kset(store, lat, nc);
+    if (k.expand_f) return k.expand_f(a, out, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_expand(int lat, int nc, int store, const StepArgs& a, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return expand_st0(lat, nc, a, s);
-    case kStoreF32: return expand_st1(lat, nc, a, s);
-    case kStoreF16S: return expand_st2(lat, nc, a, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.expand ? k.expand(a, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_update(int lat, int nc, int store, const StepArgs& a, bool fields, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return update_st0(lat, nc, a, fields, s);
-    case kStoreF32: return update_st1(lat, nc, a, fields, s);
-    case kStoreF16S: return update_st2(lat, nc, a, fields, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.update ? k.update(a, fields, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_diag(int lat, int nc, int store, const StepArgs& a, int max_blocks, double* out, int* blocks,
                        hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return diag_st0(lat, nc, a, max_blocks, out, blocks, s);
-    case kStoreF32: return diag_st1(lat, nc, a, max_blocks, out, blocks, s);
-    case kStoreF16S: return diag_st2(lat, nc, a, max_blocks, out, blocks, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.diag ? k.diag(a, max_blocks, out, blocks, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_init(int lat, int nc, int store, const InitArgs& a, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return init_st0(lat, nc, a, s);
-    case kStoreF32: return init_st1(lat, nc, a, s);
-    case kStoreF16S: return init_st2(lat, nc, a, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.init ? k.init(a, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_conc(int lat, int nc, int store, const StepArgs& a, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return conc_st0(lat, nc, a, s);
-    case kStoreF32: return conc_st1(lat, nc, a, s);
-    case kStoreF16S: return conc_st2(lat, nc, a, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.conc ? k.conc(a, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step(int lat, int nc, int store, const BatchLaunch& b, hipStream_t s) {
-  switch (store) {
-    case kStoreF64: return batch_st0(lat, nc, b, s);
-    case kStoreF32: return batch_st1(lat, nc, b, s);
-    case kStoreF16S: return batch_st2(lat, nc, b, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelSet& k = kset(store, lat, nc);
+  return k.batch ? k.batch(b, s) : hipErrorInvalidValue;
 }
 
 hipError_t launch_build_bb(int lat, const unsigned char* solid, uint32_t* bb, const StepArgs& a,
@@ -2112,7 +2156,7 @@ hipError_t launch_spectrum(const void* X, int N, int nx, int ny, int nz, long lo
 }
 
 hipError_t launch_reduce_final(const double* partial, double* out, int N, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, partial, out, N, blocks);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, out, N, blocks);
   return hipGetLastError();
 }
 

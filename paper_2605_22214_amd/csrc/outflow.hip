@@ -24,7 +24,11 @@
 //                    per plane node blends the pulled plane N-1 populations
 //                    into the plane buffer and convects the ghosts.
 // With start = 1 the apply kernel instead captures plane N of the current
-// state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)).
+// state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)).  Solid nodes continue
+// straight through the outflow plane: U is the mean over the fluid nodes of
+// plane N-1, and solid plane nodes keep zeros.  In the moment form of g
+// (and the record form of f) the pulled populations are formed from the
+// source nodes' records, as the reconstruction forms them.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -55,15 +59,56 @@ __device__ __forceinline__ int plane_pos(int face, int inner, const StepArgs& a)
   return (face & 1) ? n - 1 - inner : inner;
 }
 
+// Post-collision f*_kd of the node at index src in the record form of f:
+// w_kd times f_scaled of its records (v, -3/2 v.v) and (fB, F).
+template <class L, class T>
+__device__ __forceinline__ T rec_f(const StepArgs& a, uint32_t src, int kd) {
+  T v4[4], fr[4];
+  vld<T, 4>(gptr<const T>(a.vel) + size_t(src) * 4, v4);
+  vld<T, 4>(gptr<const T>(a.frec) + size_t(src) * 4, fr);
+  return static_cast<T>(L::w[kd]) * f_scaled<L>(kd, v4, fr);
+}
+// Post-collision g*_{e,kd} (kd >= 1) of the node at src in the moment form:
+// C_e s_kd(v) - w_kd m mu~_e from its records (Eq. geq with tau_g = 1).
+template <class L, int NE, class T>
+__device__ __forceinline__ T rec_g(const StepArgs& a, const DevParams<T>& P, uint32_t src, int e, int kd) {
+  const T c = gptr<const T>(a.cprev)[size_t(src) * NE + e];
+  const T mu = gptr<const T>(a.mu)[size_t(src) * NE + e];
+  T v4[4];
+  vld<T, 4>(gptr<const T>(a.vel) + size_t(src) * 4, v4);
+  const int kp = (kd & 1) ? kd : kd - 1;
+  const T v[3] = {v4[0], v4[1], v4[2]};
+  const T ev = proj<L>(kp, v);
+  const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
+  const T wk = static_cast<T>(L::w[kd]);
+  return fma(c, wk * u, -(wk * P.m) * mu);
+}
+
 // Post-streaming f_k (k >= 1) of a node, pulled as the update pulls it:
 // halfway bounce-back at a wall face, plus the velocity correction where the
-// link enters across an open face.
+// link enters across an open face.  In the record form of f the
+// post-collision values are formed from the source's records (on the first
+// step after set_fields: the node's own initial equilibrium).
 template <class L, int ST>
 __device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, const Nbr& nb, uint32_t node, int k,
                                                          const FaceBC<typename StoreT<ST>::T>* FB, int open) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
+  if (a.flags & kFlagFRecord) {
+    if (a.flags & kFlagFLocal) {
+      T fr[4];
+      vld<T, 4>(gptr<const T>(a.frec) + size_t(node) * 4, fr);
+      return static_cast<T>(L::w[k]) * f_scaled_local<L>(k, fr);
+    }
+    if (pulled_from_wall<L, true>(nb, k)) {
+      T v = rec_f<L, T>(a, node, opposite(k));
+      const int fc = entry_face<L, true>(nb, k, open);
+      if (fc >= 0) v += FB->fcorr[fc][k];
+      return v;
+    }
+    return rec_f<L, T>(a, upstream<L>(nb, k), k);
+  }
   const FS* fs = gptr<const FS>(a.f_src);
   const size_t fst = static_cast<size_t>(a.fstride);
   if (pulled_from_wall<L, true>(nb, k)) {
@@ -76,7 +121,11 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, cons
 }
 
 // Post-streaming g_{e,k} (any k) of an evolved component e, pulled as the
-// reconstruction pulls it (anti-bounce-back across an open face).
+// reconstruction pulls it (anti-bounce-back across an open face).  In the
+// moment form the post-collision values are formed from the records; the
+// rest population is C_e (1 + s_0) + (1 - w_0) m mu~_e of the node's own,
+// and on the first step after set_fields g entering across an open face is
+// the initial 0.
 template <class L, int NE, int ST>
 __device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, const Nbr& nb, uint32_t node, int e,
                                                          int k, const FaceBC<typename StoreT<ST>::T>* FB,
@@ -85,6 +134,24 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, cons
   using T = typename S::T;
   using FS = typename S::FS;
   using G0S = typename S::G0S;
+  if (a.flags & kFlagMoments) {
+    const DevParams<T>& P = *gptr<const DevParams<T>>(a.params);
+    if (k == 0) {
+      const T c = gptr<const T>(a.cprev)[size_t(node) * NE + e];
+      const T mu = gptr<const T>(a.mu)[size_t(node) * NE + e];
+      const T s0 = static_cast<T>(L::w[0]) * gptr<const T>(a.vel)[size_t(node) * 4 + 3];
+      return c + fma(c, s0, (static_cast<T>(1.0 - L::w[0]) * P.m) * mu);
+    }
+    if (pulled_from_wall<L, true>(nb, k)) {
+      const int fc = entry_face<L, true>(nb, k, open);
+      if (fc >= 0) {
+        if (a.flags & kFlagFLocal) return T(0);
+        return FB->gsum[fc][e][k] - rec_g<L, NE, T>(a, P, node, e, opposite(k));
+      }
+      return rec_g<L, NE, T>(a, P, node, e, opposite(k));
+    }
+    return rec_g<L, NE, T>(a, P, upstream<L>(nb, k), e, k);
+  }
   if (k == 0) return static_cast<T>(gptr<const G0S>(a.g0_src)[size_t(node) * NE + e]);
   const FS* gk = gptr<const FS>(a.gk_src);
   const size_t gst = static_cast<size_t>(a.gstride);
@@ -115,13 +182,15 @@ __global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
     const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
     const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
     const int open = FB ? FB->open : 0;
+    if (!solid_node<true>(nb)) {       // solid nodes hold no fluid
 #pragma unroll
-    for (int k = 1; k < L::Q; ++k) {
-      if (L::e[k][ax] == 0) continue;
-      const double v = static_cast<double>(pull_f<L, ST>(a, nb, node, k, FB, open));
-      mom += (L::e[k][ax] > 0) ? v : -v;
+      for (int k = 1; k < L::Q; ++k) {
+        if (L::e[k][ax] == 0) continue;
+        const double v = static_cast<double>(pull_f<L, ST>(a, nb, node, k, FB, open));
+        mom += (L::e[k][ax] > 0) ? v : -v;
+      }
+      mom *= sgn;
     }
-    mom *= sgn;
   }
   red[threadIdx.x] = mom;
   __syncthreads();
@@ -153,7 +222,7 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    U = red[0] / static_cast<double>(PL);
+    U = red[0] / o.fluid;          // mean over the fluid nodes of plane N-1
     if (!(U > 0.0)) U = 0.0;
     if (blockIdx.x == 0 && tid == 0) o.u[0] = U;
   }
@@ -171,6 +240,16 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   T* og = gptr<T>(a.out_g);
   T* gh = gptr<T>(a.out_ghost);
   const size_t P = static_cast<size_t>(PL);
+  if (solid_node<true>(nb)) {
+    // a solid node of the plane (solid nodes continue straight through the
+    // outflow plane, so plane N-1 is solid here too): no fluid, and a
+    // stencil never reads its ghost (the solid continues beyond the face)
+    for (int k = 1; k < Q; ++k) of[size_t(k - 1) * P + p] = T(0);
+    for (int e = 0; e < NE; ++e)
+      for (int k = 0; k < Q; ++k) og[(size_t(e) * Q + k) * P + p] = T(0);
+    for (int e = 0; e <= NE; ++e) gh[size_t(e) * P + p] = T(0);
+    return;
+  }
   for (int k = 1; k < Q; ++k) {
     const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
     T* slot = of + size_t(k - 1) * P + p;

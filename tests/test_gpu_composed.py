@@ -1,0 +1,218 @@
+"""Open faces, the convective outflow and solid nodes together (Sec. III C;
+the emulsion device of Sec. V B combines all three), in every storage form
+of the library, through the C ABI.
+
+* FP64 against the oracle (tests/parity_util.py metric: every field to 1e-12
+  of its scale, or ten times its spread under a one-ulp input perturbation
+  where that is larger) on a T-junction: a main channel with an inlet on x-
+  and the outflow on x+, a side branch whose inlet is the y+ face, channel
+  walls of solid nodes that meet both open faces and the outflow plane; in
+  D2Q9 and D3Q19 (extruded along periodic z), from a seeded mixture, with g
+  as populations, in the moment form with f as populations (TRT, tau != 1)
+  and in the moment form with f as node records (tau = 1).
+* The moment and record forms on channels the population form already
+  matches: an inlet + outflow channel between wall faces and the outflow on
+  z of a D3Q19 box.
+* The first step after set_fields in the moment form (g entering across an
+  open face is the initial 0): parity after one step.
+* Argument errors: solid nodes that do not continue through the outflow
+  plane, an open face meeting the outflow plane at a fluid node.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_22214_amd as nf
+import workloads as W
+from oracle import step as S
+from oracle.lattice import D2Q9, D3Q19
+from parity_util import conditioned, rel
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RESULTS = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def record():
+    yield
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "composed.json"), "w") as fh:
+        json.dump(RESULTS, fh, indent=1, sort_keys=True)
+
+
+FORMS = {
+    # name: (flags, tau, trt_magic)
+    "populations": (nf.FLAG_G_POPULATIONS, np.array([0.7, 1.0, 1.3]), 3.0 / 16.0),
+    "moments": (0, np.array([0.7, 1.0, 1.3]), 3.0 / 16.0),
+    "records": (0, np.array([1.0, 1.0, 1.0]), 0.0),
+}
+STORAGE = {"populations": ("populations", "populations"), "moments": ("moments", "populations"),
+           "records": ("moments", "records")}
+
+
+def tjunction(lat, form):
+    if lat == "D2Q9":
+        w = W.tjunction("D2Q9", nx=30, ny=16, channel=8, branch=(10, 15), amp=0.1, seed=11)
+    else:
+        w = W.tjunction("D3Q19", nx=16, ny=11, nz=4, channel=6, branch=(5, 9), amp=0.1, seed=12)
+    flags, tau, magic = FORMS[form]
+    w.update(tau=tau, trt_magic=magic, body_force=(1e-6, -2e-7, 0.0))
+    return w, w["faces"], w["outflow"], w["solid"], flags
+
+
+def wall_channel(name, form):
+    flags, tau, magic = FORMS[form]
+    if name == "channel_x":
+        w = W.noise("D2Q9", (40, 18, 1), 3, amp=0.1, seed=4, sigma=0.006, m=0.05)
+        w.update(walls=(True, True, False))
+        faces, out = {0: ((2e-3, 0.0, 0.0), (0.8, 0.15, 0.05))}, 1
+    else:
+        w = W.noise("D3Q19", (10, 9, 14), 3, amp=0.1, seed=9, sigma=0.006, m=0.05)
+        w.update(walls=(False, False, True))
+        faces, out = {4: ((0.0, 2e-4, 1e-3), (0.2, 0.5, 0.3))}, 5
+    w.update(tau=tau, trt_magic=magic)
+    return w, faces, out, None, flags
+
+
+def oracle_run(w, faces, out, solid, steps):
+    lat = D2Q9 if w["lattice"] == "D2Q9" else D3Q19
+    N = w["sigma"].shape[0]
+    par = S.Params(lat, w["shape"], w["sigma"], w["tau"], D=w["D"], omega_stab=w["omega_stab"],
+                   trt_magic=w["trt_magic"], tau_g=w["tau_g"], m=w["m"], body_force=w["body_force"],
+                   walls=w["walls"], implicit=N - 1, open_faces=faces, outflow=out, solid=solid)
+    f, g = S.initial_state(par, w["C0"])
+    for _ in range(steps):
+        f, g, _ = S.step(f, g, par)
+    return f, g, par
+
+
+def gpu_sim(w, faces, out, solid, flags, precision=nf.FP64):
+    sim = nf.Simulation.from_workload(w, precision=precision, flags=flags)
+    if solid is not None:
+        sim.set_solid(solid)
+    for face, (vb, Cb) in faces.items():
+        sim.set_open_face(face, vb, Cb)
+    if out is not None:
+        sim.set_outflow(out)
+    sim.set_fields(w["C0"])
+    return sim
+
+
+def compare(w, faces, out, solid, flags, steps, form, key):
+    f, g, par = oracle_run(w, faces, out, solid, steps)
+    mac = S.macroscopic(f, g, par)
+    ref = {"C": mac["C"], "G_RAW": g[par.evolved], "V": mac["v"], "P": mac["P"], "F": mac["F"],
+           "F_RAW": f[1:]}
+    got = {}
+    for tag, wk in (("ref", w), ("pert", dict(w, C0=W.ulp_perturbed(w["C0"])))):
+        with gpu_sim(wk, faces, out, solid, flags) as sim:
+            assert (sim.storage_form(), sim.f_storage_form()) == STORAGE[form]
+            sim.step(steps)
+            got[tag] = {"C": sim.get_field("C"), "G_RAW": sim.get_field("G_RAW")[par.evolved],
+                        "V": sim.get_field("V"), "P": sim.get_field("P"), "F": sim.get_field("F"),
+                        "F_RAW": sim.get_field("F_RAW")}
+    errs = {k: rel(got["ref"][k], ref[k]) for k in ref}
+    tol = conditioned({k: rel(got["pert"][k], got["ref"][k]) for k in ref})
+    RESULTS.setdefault("fp64_vs_oracle", {})[key] = errs
+    RESULTS.setdefault("fp64_tolerance", {})[key] = tol
+    if solid is not None:
+        assert np.all(got["ref"]["C"][:, solid] == 0.0)
+    assert errs["C"] <= 1e-12 and errs["G_RAW"] <= 1e-12, errs
+    for k in ref:
+        assert errs[k] <= tol[k], (k, errs, tol)
+    return par
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_tjunction_fp64_matches_oracle(lat, form):
+    w, faces, out, solid, flags = tjunction(lat, form)
+    steps = 150 if lat == "D2Q9" else 60
+    par = compare(w, faces, out, solid, flags, steps, form, f"tjunction_{lat}_{form}")
+    assert par.outflow_state["U"] > 0.0
+
+
+@pytest.mark.parametrize("form", ["moments", "records"])
+@pytest.mark.parametrize("name", ["channel_x", "d3_z"])
+def test_outflow_channels_in_moment_forms(name, form):
+    w, faces, out, solid, flags = wall_channel(name, form)
+    steps = 150 if name == "channel_x" else 50
+    compare(w, faces, out, solid, flags, steps, form, f"{name}_{form}")
+
+
+@pytest.mark.parametrize("form", ["moments", "records"])
+def test_first_step_after_set_fields(form):
+    w, faces, out, solid, flags = tjunction("D2Q9", form)
+    compare(w, faces, out, solid, flags, 1, form, f"tjunction_first_step_{form}")
+
+
+def test_composed_argument_errors():
+    w = W.tjunction("D2Q9", nx=30, ny=16, channel=8, branch=(10, 15))
+    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:
+        bad = w["solid"].copy()
+        bad[0, 3, -1] = True                      # on the outflow plane only
+        sim.set_outflow(1)
+        with pytest.raises(nf.NflbmError):
+            sim.set_solid(bad)
+        sim.set_solid(w["solid"])
+        for face, (vb, Cb) in w["faces"].items():
+            sim.set_open_face(face, vb, Cb)
+        # the y- face meets the outflow plane at a fluid node
+        with pytest.raises(nf.NflbmError):
+            sim.set_open_face(2, (0.0, 1e-3, 0.0), (1.0, 0.0, 0.0))
+        # without the solid block the y+ inlet would meet it at a fluid node
+        with pytest.raises(nf.NflbmError):
+            sim.set_solid(None)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("mode", ["graph", "launch"])
+def test_batch_members_with_boundaries_equal_standalone(form, mode):
+    """Batch members carrying solid nodes, open faces and the outflow (two
+    T-junctions of different sizes) beside a plain periodic member end bit
+    for bit where each ends when stepped alone; a boundary change between
+    batch steps is picked up (tables rebuilt, graphs dropped)."""
+    flags, tau, magic = FORMS[form]
+    ws = [W.tjunction("D2Q9", nx=30, ny=16, channel=8, branch=(10, 15), amp=0.1, seed=21),
+          W.tjunction("D2Q9", nx=22, ny=13, channel=6, branch=(7, 11), amp=0.1, seed=22),
+          W.noise("D2Q9", (20, 18, 1), 3, amp=0.1, seed=23, sigma=0.005, m=0.05)]
+    for w in ws:
+        w.update(tau=tau, trt_magic=magic)
+    steps = 21
+
+    def configure(sim, w, with_side_inlet=True):
+        if "solid" in w:
+            sim.set_solid(w["solid"])
+            for face, (vb, Cb) in w["faces"].items():
+                if face == 3 and not with_side_inlet:
+                    continue
+                sim.set_open_face(face, vb, Cb)
+            sim.set_outflow(w["outflow"])
+
+    ref = []
+    for w in ws:
+        with nf.Simulation.from_workload(w, precision=nf.FP64, flags=flags) as sim:
+            configure(sim, w)
+            sim.set_fields(w["C0"])
+            sim.step(steps)
+            if "solid" in w:
+                sim.set_open_face(3)          # the side inlet closes (a wall)
+            sim.step(steps)
+            ref.append(sim.get_state())
+    with nf.Batch.from_workloads(ws, precision=nf.FP64, flags=flags) as b:
+        b.set_launch(graph_steps=4)
+        for i, w in enumerate(ws):
+            configure(b.members[i], w)
+            b.members[i].set_fields(w["C0"])
+        b.step(steps, mode=mode)
+        for i in range(2):
+            b.members[i].set_open_face(3)
+        b.step(steps, mode=mode)
+        got = [m.get_state() for m in b.members]
+    for i in range(len(ws)):
+        assert np.array_equal(got[i], ref[i]), f"member {i}"

@@ -10,7 +10,7 @@ concentration Dirichlet for g) through the C ABI (nflbm_set_open_face).
   larger (P and F of the pure-phase Couette cell are rounding-sized).
 * FP32 and FP16S: the Couette profile u_x = U (y + 1/2) / n_y, exact for the
   scheme, within storage error.
-* Argument errors: moment form, an unwalled axis, C_b not summing to 1.
+* Argument errors: an unwalled axis, C_b not summing to 1.
 """
 import json
 import os
@@ -145,9 +145,6 @@ def test_reduced_precision_couette_profile(prec, tol):
 
 def test_open_face_argument_errors():
     w, faces = couette()
-    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:        # moment form
-        with pytest.raises(nf.NflbmError):
-            sim.set_open_face(3, (1e-3, 0, 0), (1.0, 0.0))
     with nf.Simulation.from_workload(w, precision=nf.FP64, flags=nf.FLAG_G_POPULATIONS) as sim:
         with pytest.raises(nf.NflbmError):
             sim.set_open_face(0, (1e-3, 0, 0), (1.0, 0.0))                 # x is periodic

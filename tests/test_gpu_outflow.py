@@ -17,8 +17,9 @@
   nflbm_set_fields gives the same bits.
 * FP32 and FP16S against the FP64 oracle on the pulse run, within their
   storage error.
-* Argument errors: moment form, an unwalled or too short axis, the face
-  already open, an open face on another axis, solid nodes.
+* Argument errors: an unwalled or too short axis, the face already open, an
+  open face on another axis meeting the outflow plane at a fluid node, solid
+  nodes that do not continue through the outflow plane.
 """
 import json
 import os
@@ -194,9 +195,6 @@ def test_reduced_precision_pulse_against_oracle(prec, tv, tc):
 
 def test_outflow_argument_errors():
     w, faces, out, v0, _ = case("channel_x")
-    with nf.Simulation.from_workload(w, precision=nf.FP64) as sim:          # moment form
-        with pytest.raises(nf.NflbmError):
-            sim.set_outflow(1)
     with nf.Simulation.from_workload(w, precision=nf.FP64, flags=nf.FLAG_G_POPULATIONS) as sim:
         with pytest.raises(nf.NflbmError):
             sim.set_outflow(4)                                               # no z in D2Q9
@@ -205,9 +203,12 @@ def test_outflow_argument_errors():
             sim.set_outflow(0)                                               # already open
         sim.set_outflow(1)
         with pytest.raises(nf.NflbmError):
-            sim.set_open_face(2, (1e-3, 0, 0), (0.5, 0.3, 0.2))              # another axis
+            # another axis, meeting the outflow plane at a fluid node
+            sim.set_open_face(2, (1e-3, 0, 0), (0.5, 0.3, 0.2))
+        bad = np.zeros((1, 18, 40), dtype=bool)
+        bad[0, 5, 39] = True                                                 # not through plane N-1
         with pytest.raises(nf.NflbmError):
-            sim.set_solid(np.zeros((18, 40), dtype=bool))
+            sim.set_solid(bad)
         sim.set_outflow(None)
         sim.set_open_face(2, (1e-3, 0, 0), (0.5, 0.3, 0.2))
     w2 = W.noise("D2Q9", (16, 12, 1), 3, seed=1)

@@ -20,16 +20,15 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2605_22214_amd", "csrc")
 BUILD = os.path.join(ROOT, "_build")
-DEVICE_OBJECTS = ["kernels_f64.o", "kernels_f32.o", "kernels_f16s.o", "kernels_common.o",
-                  "mobility.o", "outflow.o"]
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
 def _device_objects():
-    if not all(os.path.exists(os.path.join(BUILD, o)) for o in DEVICE_OBJECTS):
-        from paper_2605_22214_amd import build
+    from paper_2605_22214_amd import build
+    objs = [u[1] for u in build.UNITS if u[2]]
+    if not all(os.path.exists(os.path.join(BUILD, o)) for o in objs):
         build.build(verbose=False)
-    return [os.path.join(BUILD, o) for o in DEVICE_OBJECTS]
+    return [os.path.join(BUILD, o) for o in objs]
 
 
 @pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang++ not installed")

@@ -261,3 +261,39 @@ def ulp_perturbed(C0, seed=20261203):
     up = rng.integers(0, 2, size=C0.shape).astype(bool)
     moved = np.where(up, np.nextafter(C0, np.inf), np.nextafter(C0, -np.inf))
     return np.where(C0 == 0.0, C0, moved)
+
+
+def tjunction(lattice="D2Q9", nx=48, ny=24, nz=1, channel=12, branch=(14, 22), u_main=3e-3,
+              u_side=2e-3, ncomp=3, amp=0.0, seed=0, sigma=0.005, m=0.05, omega_stab=0.0):
+    """A T-junction in the style of the emulsion device of Sec. V B: a main
+    channel y < channel along x with an inlet of pure fluid 1 on x- (velocity
+    u_main along +x) and the convective outflow on x+; a side branch of
+    columns branch[0] <= x < branch[1] rising to the y+ face, where pure fluid
+    2 enters at u_side along -y.  Solid nodes fill y >= channel outside the
+    branch (they meet both open faces and the outflow at the domain's
+    corners); y- is a wall face.  The main channel starts filled with fluid 3
+    (amp > 0: a seeded uniform mixture 1/N + U(-amp, amp) renormalised
+    instead).  Returns the workload dict plus "solid" [nz, ny, nx], "faces"
+    {face: (v_b, C_b)} and "outflow" (the face index).  In D3Q19 the layout
+    is extruded along z (periodic)."""
+    N = ncomp
+    shape = (nx, ny, nz)
+    w = _base(lattice, shape, _equal_sigma(N, sigma), 1.0, m, omega_stab=omega_stab)
+    w["walls"] = (True, True, False)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = (y >= channel) & ((x < branch[0]) | (x >= branch[1]))
+    C0 = np.zeros((N, nz, ny, nx))
+    if amp > 0.0:
+        rng = np.random.default_rng(seed)
+        C0 = 1.0 / N + rng.uniform(-amp, amp, size=C0.shape)
+        C0 /= C0.sum(axis=0, keepdims=True)
+    else:
+        C0[min(2, N - 1)] = 1.0
+    C0[:, solid] = 0.0
+    Cin = np.zeros(N)
+    Cin[0] = 1.0
+    Cside = np.zeros(N)
+    Cside[min(1, N - 1)] = 1.0
+    w.update(C0=C0, name=f"tjunction_{lattice}_{nx}x{ny}x{nz}", solid=solid,
+             faces={0: ((u_main, 0.0, 0.0), Cin), 3: ((0.0, -u_side, 0.0), Cside)}, outflow=1)
+    return w
