@@ -50,6 +50,7 @@ struct nflbm_sim {
   // storage sizes (bytes per value), and the elements between direction
   // arrays of f and of the moving g populations (direction_stride)
   size_t fs = 0, g0s = 0, ts = 0;
+  size_t rs = 0;   // bytes of a node-record value of the moment form (mu~, v, f records)
   size_t fstride = 0, gstride = 0;
   // device state: two population sets (A/B), reconstructed C, parameters
   void* f[2] = {nullptr, nullptr};
@@ -644,9 +645,9 @@ std::vector<std::pair<void*, size_t>> state_segments(nflbm_sim* s) {
       v.emplace_back(static_cast<unsigned char*>(s->f[s->cur]) + k * s->fstride * s->fs, n * s->fs);
   if (s->gform) {
     v.emplace_back(s->conc[s->cur], NE * n * s->ts);
-    v.emplace_back(s->mu, NE * n * s->ts);
-    v.emplace_back(s->vel, 4 * n * s->ts);
-    if (s->fform) v.emplace_back(s->frec, 4 * n * s->ts);
+    v.emplace_back(s->mu, NE * n * s->rs);
+    v.emplace_back(s->vel, 4 * n * s->rs);
+    if (s->fform) v.emplace_back(s->frec, 4 * n * s->rs);
   } else {
     v.emplace_back(s->g0[s->cur], NE * n * s->g0s);
     for (size_t k = 0; k < Qm; ++k)
@@ -1059,9 +1060,9 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
     }
   }
   switch (s->store) {
-    case NFLBM_FP64: s->fs = 8; s->g0s = 8; s->ts = 8; break;
-    case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; break;
-    default: s->fs = 2; s->g0s = 4; s->ts = 4; break;
+    case NFLBM_FP64: s->fs = 8; s->g0s = 8; s->ts = 8; s->rs = 8; break;
+    case NFLBM_FP32: s->fs = 4; s->g0s = 4; s->ts = 4; s->rs = 4; break;
+    default: s->fs = 2; s->g0s = 4; s->ts = 4; s->rs = 2; break;
   }
   s->fstride = direction_stride(s->n, s->fs);
   s->gstride = direction_stride(s->n * size_t(s->NE), s->fs);
@@ -1078,9 +1079,7 @@ int plan_sim(const nflbm_config* cfg, nflbm_sim* s) {
   // With every node relaxing at omega+ = omega- = 1 (each tau_i = 1, BGK or
   // Lambda^TRT = 1/4) the post-collision f is fixed by the node's P, v and F
   // (Eqs. TRT, FTRT, hydroforce): keep those instead of the populations.
-  // FP16S keeps its binary16 populations.
-  bool unit = !(cfg->flags & NFLBM_FLAG_F_POPULATIONS) && !(cfg->flags & NFLBM_FLAG_NO_HYDRO) &&
-              s->store != NFLBM_FP16S;
+  bool unit = !(cfg->flags & NFLBM_FLAG_F_POPULATIONS) && !(cfg->flags & NFLBM_FLAG_NO_HYDRO);
   for (int i = 0; i < N && unit; ++i) {
     const double wp = 1.0 / cfg->tau[i];
     const double wm = cfg->trt_magic > 0.0 ? 1.0 / (0.5 + cfg->trt_magic / (cfg->tau[i] - 0.5)) : wp;
@@ -1119,11 +1118,11 @@ std::vector<std::pair<void**, size_t>> state_arrays(nflbm_sim* s) {
     for (int b = 0; b < 2; ++b) v.emplace_back(&s->f[b], Qm * s->fstride * s->fs);
   if (s->gform) {
     for (int b = 0; b < 2; ++b) v.emplace_back(&s->conc[b], NE * n * s->ts);
-    v.emplace_back(&s->mu, NE * n * s->ts);
-    v.emplace_back(&s->vel, 4 * n * s->ts);
+    v.emplace_back(&s->mu, NE * n * s->rs);
+    v.emplace_back(&s->vel, 4 * n * s->rs);
     if (s->fform) {
-      v.emplace_back(&s->frec, 4 * n * s->ts);
-      v.emplace_back(&s->fmom, 4 * n * s->ts);
+      v.emplace_back(&s->frec, 4 * n * s->rs);
+      v.emplace_back(&s->fmom, 4 * n * s->rs);
     }
   } else {
     for (int b = 0; b < 2; ++b) v.emplace_back(&s->g0[b], NE * n * s->g0s);
@@ -1993,15 +1992,17 @@ int nflbm_bytes_per_node(nflbm_sim* sim, double* bytes) {
   if (!sim || !bytes) return fail(sim, NFLBM_EINVAL, "NULL argument");
   const double Qm = sim->Q - 1, NE = sim->NE;
   double b;
+  const double ts = double(sim->ts), rs = double(sim->rs);
   if (sim->fform) {
     // record form of f: the reconstruction reads C, mu~, (v, -3/2 v.v) and
     // (fB, F) and writes C, E_B and the four f moments; the update reads C,
     // E_B and the f moments and writes mu~, (v, -3/2 v.v) and (fB, F)
-    b = ((NE + NE + 4 + 4) + (NE + 1 + 4) + (NE + 1 + 4) + (NE + 4 + 4)) * double(sim->ts);
+    b = (NE * ts + (NE + 4 + 4) * rs) + ((NE + 1) * ts + 4 * rs) + ((NE + 1) * ts + 4 * rs) +
+        (NE + 4 + 4) * rs;
   } else if (sim->gform) {
     // f read and written; reconstruction reads C, mu~, (v, -3/2 v.v) and
     // writes C, E_B; the update reads C, E_B and writes mu~, (v, -3/2 v.v)
-    b = 2.0 * Qm * sim->fs + (NE + NE + 4 + NE + 1 + NE + 1 + NE + 4) * double(sim->ts);
+    b = 2.0 * Qm * sim->fs + (NE * ts + (NE + 4) * rs) + 2.0 * (NE + 1) * ts + (NE + 4) * rs;
   } else {
     b = 2.0 * (Qm * sim->fs + NE * sim->g0s + NE * Qm * sim->fs) + 2.0 * (NE + 1) * sim->ts;
     if (sim->step_flags & kFlagNeedG) b += NE * Qm * sim->fs;

@@ -48,9 +48,12 @@ template <int ST> struct StoreT;
 // value; ld_raw / pack_raw move the stored number itself, which is the value
 // times `scale` (a power of two, so arithmetic on raw numbers scaled by it
 // rounds exactly as on the values).
+// RS is the type of the moment form's node records (mu~, (v, -3/2 v.v),
+// (fB, F), the f moments; C and E_B keep the compute type), stored as the
+// value times mu_scale (mu~) or vel_scale (the others).
 template <> struct StoreT<kStoreF64> {
-  using T = double; using FS = double; using G0S = double;
-  static constexpr double scale = 1.0;
+  using T = double; using FS = double; using G0S = double; using RS = double;
+  static constexpr double scale = 1.0, mu_scale = 1.0, vel_scale = 1.0;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ FS pack(T v) { return v; }
   static __device__ __forceinline__ T unpack(FS v) { return v; }
@@ -58,8 +61,8 @@ template <> struct StoreT<kStoreF64> {
   static __device__ __forceinline__ FS pack_raw(T v) { return v; }
 };
 template <> struct StoreT<kStoreF32> {
-  using T = float; using FS = float; using G0S = float;
-  static constexpr float scale = 1.0f;
+  using T = float; using FS = float; using G0S = float; using RS = float;
+  static constexpr float scale = 1.0f, mu_scale = 1.0f, vel_scale = 1.0f;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) { return p[i]; }
   static __device__ __forceinline__ FS pack(T v) { return v; }
   static __device__ __forceinline__ T unpack(FS v) { return v; }
@@ -67,8 +70,8 @@ template <> struct StoreT<kStoreF32> {
   static __device__ __forceinline__ FS pack_raw(T v) { return v; }
 };
 template <> struct StoreT<kStoreF16S> {
-  using T = float; using FS = _Float16; using G0S = float;
-  static constexpr float scale = kHalfScale;
+  using T = float; using FS = _Float16; using G0S = float; using RS = _Float16;
+  static constexpr float scale = kHalfScale, mu_scale = kRecMuScale, vel_scale = kRecVelScale;
   static __device__ __forceinline__ T ld(const FS* p, size_t i) {
     return static_cast<float>(p[i]) * (1.0f / kHalfScale);
   }
@@ -532,6 +535,56 @@ __device__ __forceinline__ const E* at(const E* base, uint32_t idx) {
 template <class E>
 __device__ __forceinline__ E* at(E* base, uint32_t idx) {
   return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(E)));
+}
+
+// Node records of the moment form in their storage type: NV values at
+// element index idx (idx * sizeof(RS) bytes from base), as values of the
+// compute type (unscaled on load, scaled on store; identity for FP64 and
+// FP32).  NT stores bypass the caches (streams touched once per step).
+template <class S, int NV>
+__device__ __forceinline__ void rec_load(const NFLBM_GLOBAL void* base, uint32_t idx, typename S::T (&o)[NV],
+                                         typename S::T scale) {
+  using RS = typename S::RS;
+  using T = typename S::T;
+  if constexpr (sizeof(RS) == sizeof(T)) {
+    (void)scale;
+    vld<T, NV>(at(gptr<const T>(base), idx), o);
+  } else {
+    RS r[NV];
+    vld<RS, NV>(at(gptr<const RS>(base), idx), r);
+    const T inv = T(1) / scale;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) o[e] = static_cast<T>(r[e]) * inv;
+  }
+}
+template <class S, int NV, bool NT>
+__device__ __forceinline__ void rec_store(const NFLBM_GLOBAL void* base, uint32_t idx,
+                                          const typename S::T (&v)[NV], typename S::T scale) {
+  using RS = typename S::RS;
+  using T = typename S::T;
+  if constexpr (sizeof(RS) == sizeof(T)) {
+    (void)scale;
+    if constexpr (NT) vst_nt<T, NV>(at(gptr<T>(base), idx), v);
+    else vst<T, NV>(at(gptr<T>(base), idx), v);
+  } else {
+    RS r[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) r[e] = static_cast<RS>(v[e] * scale);
+    if constexpr (NT) vst_nt<RS, NV>(at(gptr<RS>(base), idx), r);
+    else vst<RS, NV>(at(gptr<RS>(base), idx), r);
+  }
+}
+// One record value (element idx).
+template <class S>
+__device__ __forceinline__ typename S::T rec_at(const NFLBM_GLOBAL void* base, size_t idx, typename S::T scale) {
+  using RS = typename S::RS;
+  using T = typename S::T;
+  if constexpr (sizeof(RS) == sizeof(T)) {
+    (void)scale;
+    return gptr<const T>(base)[idx];
+  } else {
+    return static_cast<T>(gptr<const RS>(base)[idx]) / scale;
+  }
 }
 
 }  // namespace nflbm

@@ -16,6 +16,13 @@ enum StoreKind { kStoreF64 = 0, kStoreF32 = 1, kStoreF16S = 2 };
 // Scale applied to binary16 moving populations so that typical magnitudes
 // (1e-5 .. 1e-1) stay in the normal range; a power of two, so scaling is exact.
 constexpr float kHalfScale = 4096.0f;
+// FP16S node records (moment form): binary16 numbers holding the value times
+// a power of two, mu~ times kRecMuScale (|mu~| stays below 32: the factored
+// flux potential does not depend on the tensions' size, and its Laplacian
+// part is bounded by 3 D), (v, -3/2 v.v), (fB, F) and the f moments times
+// kRecVelScale (|v| < 0.3 and |P| < 4; a body force of 1e-7 stays normal).
+constexpr float kRecMuScale = 2048.0f;
+constexpr float kRecVelScale = 16384.0f;
 
 // Per-simulation constants read by every kernel, in the compute precision T.
 // Components are in internal order: the evolved ones first (user order kept),

@@ -229,9 +229,6 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   const bool active = (x < a.nx) && (y < a.ny);
   const uint32_t nx = a.nx, nxy = uint32_t(a.nx) * uint32_t(a.ny);
   const T* cprev = gptr<const T>(a.cprev);
-  const T* mus = gptr<const T>(a.mu);
-  const T* vels = gptr<const T>(a.vel);
-  const T* frecs = gptr<const T>(a.frec);
   // first step after set_fields: a node's f is its own record's equilibrium
   const bool flocal = FR && (a.flags & kFlagFLocal);
 
@@ -278,9 +275,9 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
 #pragma unroll
       for (int e = NE; e < NEP; ++e) cc[e] = mm[e] = T(0);
       vld<T, NE>(at(cprev, node * NE), reinterpret_cast<T(&)[NE]>(cc));
-      vld<T, NE>(at(mus, node * NE), reinterpret_cast<T(&)[NE]>(mm));
-      vld<T, 4>(at(vels, node * 4), vv);
-      if constexpr (FR) vld<T, 4>(at(frecs, node * 4), ff);
+      rec_load<S, NE>(a.mu, node * NE, reinterpret_cast<T(&)[NE]>(mm), T(S::mu_scale));
+      rec_load<S, 4>(a.vel, node * 4, vv, T(S::vel_scale));
+      if constexpr (FR) rec_load<S, 4>(a.frec, node * 4, ff, T(S::vel_scale));
       if constexpr (AOS) {
         T* rec = base + idx * REC;
         vst<T, NEP>(rec, cc);
@@ -567,7 +564,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
           for (int d = 0; d < 3; ++d)
             if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? fk : -fk;
         }
-        vst_nt<T, 4>(at(gptr<T>(a.fmom), node * 4), fm);
+        rec_store<S, 4, true>(a.fmom, node * 4, fm, T(S::vel_scale));
       }
       const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
       vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
@@ -581,14 +578,14 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
       *at(gptr<T>(a.eb), node) = T(0);
       if constexpr (FR) {
         const T z4[4] = {T(0), T(0), T(0), T(0)};
-        vst<T, 4>(at(gptr<T>(a.fmom), node * 4), z4);
+        rec_store<S, 4, false>(a.fmom, node * 4, z4, T(S::vel_scale));
       }
       return;
     }
     if constexpr (FR) {
       // moments of the streamed f: sum_k f_k and sum_k e_k f_k
       const T fm[4] = {A.fm, A.jm[0], A.jm[1], A.jm[2]};
-      vst_nt<T, 4>(at(gptr<T>(a.fmom), node * 4), fm);
+      rec_store<S, 4, true>(a.fmom, node * 4, fm, T(S::vel_scale));
     }
     const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
     T cn[NC];
@@ -667,8 +664,8 @@ __global__ void __launch_bounds__(256) k_expand_g(StepArgs a, const DevParams<ty
   const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
   T c[NE], mu[NE], vel[4];
   vld<T, NE>(gptr<const T>(a.cprev) + node * NE, c);
-  vld<T, NE>(gptr<const T>(a.mu) + node * NE, mu);
-  vld<T, 4>(gptr<const T>(a.vel) + node * 4, vel);
+  rec_load<S, NE>(a.mu, uint32_t(node * NE), mu, T(S::mu_scale));
+  rec_load<S, 4>(a.vel, uint32_t(node * 4), vel, T(S::vel_scale));
   const T v[3] = {vel[0], vel[1], vel[2]};
   const T base_s = vel[3];
   FS* gk = gptr<FS>(a.gk_dst);
@@ -1083,7 +1080,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       // moment form: mu~ goes to the node record at once instead of being
       // held through the gather of f
       const uint32_t nd = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
-      vst_nt<T, NE>(at(gptr<T>(a.mu), nd * NE), mu);
+      rec_store<S, NE, true>(a.mu, nd * NE, mu, T(S::mu_scale));
     }
 
     // ---- surface tension force (Eq. Fsnew, or Eq. ststand) + body force
@@ -1138,7 +1135,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const bool frec = GM == 2 || (GM == 0 && MODE != kModeStep && (a.flags & kFlagFRecord));
     if (hydro && frec) {
       T fm[4];
-      vld<T, 4>(at(gptr<const T>(a.fmom), node * 4), fm);
+      rec_load<S, 4>(a.fmom, node * 4, fm, T(S::vel_scale));
       fsum = fm[0];
 #pragma unroll
       for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], fm[1 + d]);
@@ -1245,7 +1242,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       // moment form: the reconstruction re-forms g* from mu~ (stored above),
       // v and -3/2 v.v
       const T vel[4] = {v[0], v[1], v[2], base_s};
-      vst_nt<T, 4>(at(gptr<T>(a.vel), node * 4), vel);
+      rec_store<S, 4, true>(a.vel, node * 4, vel, T(S::vel_scale));
     }
     const T vF = fma(v[2], F[2], fma(v[1], F[1], v[0] * F[0]));
     const T cP = T(3) * Pn;
@@ -1254,7 +1251,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       // f*_k = w_k [s_k / w_k + fB + (e.F)(9/2 e.v +- 3/2)] (see f_scaled),
       // so the node stores fB = 3 P - 3/2 v.F and F beside (v, -3/2 v.v)
       const T fr[4] = {static_cast<T>(fma(-T(1.5), vF, cP)), F[0], F[1], F[2]};
-      vst_nt<T, 4>(at(gptr<T>(a.frec), node * 4), fr);
+      rec_store<S, 4, true>(a.frec, node * 4, fr, T(S::vel_scale));
       return;
     }
     // Per-node factors of the pair collision.  With s = f_k + f_k+1,
@@ -1532,15 +1529,15 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     }
     if constexpr (GM == 2) {
       const T zr[4] = {T(0), T(0), T(0), T(0)};
-      vst<T, 4>(gptr<T>(a.sa.frec) + size_t(node) * 4, zr);
+      rec_store<S, 4, false>(a.sa.frec, uint32_t(node) * 4u, zr, T(S::vel_scale));
     }
     T z0[NE], z4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < NE; ++i) z0[i] = T(0);
     if constexpr (GM >= 1) {
       vst<T, NE>(gptr<T>(a.sa.cprev) + size_t(node) * NE, z0);
-      vst<T, NE>(gptr<T>(a.sa.mu) + size_t(node) * NE, z0);
-      vst<T, 4>(gptr<T>(a.sa.vel) + size_t(node) * 4, z4);
+      rec_store<S, NE, false>(a.sa.mu, uint32_t(node) * uint32_t(NE), z0, T(S::mu_scale));
+      rec_store<S, 4, false>(a.sa.vel, uint32_t(node) * 4u, z4, T(S::vel_scale));
     } else {
       G0S g00[NE];
 #pragma unroll
@@ -1563,7 +1560,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     // takes each node's f as this record's equilibrium (kFlagFLocal)
     const T fr[4] = {static_cast<T>(3.0 * Pn - 1.5 * vv), static_cast<T>(v[0]), static_cast<T>(v[1]),
                      static_cast<T>(v[2])};
-    vst<T, 4>(gptr<T>(a.sa.frec) + size_t(node) * 4, fr);
+    rec_store<S, 4, false>(a.sa.frec, uint32_t(node) * 4u, fr, T(S::vel_scale));
   }
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
@@ -1605,8 +1602,8 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
       z0[i] = T(0);
     }
     vst<T, NE>(gptr<T>(a.sa.cprev) + size_t(node) * NE, c0);
-    vst<T, NE>(gptr<T>(a.sa.mu) + size_t(node) * NE, z0);
-    vst<T, 4>(gptr<T>(a.sa.vel) + size_t(node) * 4, z4);
+    rec_store<S, NE, false>(a.sa.mu, uint32_t(node) * uint32_t(NE), z0, T(S::mu_scale));
+    rec_store<S, 4, false>(a.sa.vel, uint32_t(node) * 4u, z4, T(S::vel_scale));
   } else {
     G0S c0[NE];
 #pragma unroll
@@ -1622,7 +1619,8 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a) {
 // its first gather pulls it from, as k_init places populations.
 template <class L, int ST, bool WALLS>
 __global__ void __launch_bounds__(256) k_expand_f(StepArgs a, void* out) {
-  using T = typename StoreT<ST>::T;
+  using S = StoreT<ST>;
+  using T = typename S::T;
   constexpr int Q = L::Q;
   const size_t n = static_cast<size_t>(a.n);
   const size_t node = size_t(blockIdx.x) * 256 + threadIdx.x;
@@ -1630,10 +1628,10 @@ __global__ void __launch_bounds__(256) k_expand_f(StepArgs a, void* out) {
   const size_t fst = static_cast<size_t>(a.fstride);
   T* o = static_cast<T*>(out);
   T fr[4];
-  vld<T, 4>(gptr<const T>(a.frec) + node * 4, fr);
+  rec_load<S, 4>(a.frec, uint32_t(node * 4), fr, T(S::vel_scale));
   if (!(a.flags & kFlagFLocal)) {
     T v4[4];
-    vld<T, 4>(gptr<const T>(a.vel) + node * 4, v4);
+    rec_load<S, 4>(a.vel, uint32_t(node * 4), v4, T(S::vel_scale));
 #pragma unroll
     for (int k = 1; k < Q; ++k) o[size_t(k - 1) * fst + node] = static_cast<T>(L::w[k]) * f_scaled<L>(k, v4, fr);
     return;
@@ -1822,7 +1820,7 @@ inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
 template <int ST>
 inline int storage_gm(const StepArgs& a) {
   if (!moments(a)) return 0;
-  return (ST != kStoreF16S && (a.flags & kFlagFRecord)) ? 2 : 1;
+  return (a.flags & kFlagFRecord) ? 2 : 1;
 }
 
 template <class L, int NC, int ST>
@@ -1848,7 +1846,6 @@ hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
     case 0: hipLaunchKernelGGL((K_UPD(W, T, 0)), grid, dim3(256), lds, s, a, P); break;   \
     case 1: hipLaunchKernelGGL((K_UPD(W, T, 1)), grid, dim3(256), lds, s, a, P); break;   \
     default:                                                                               \
-      if constexpr (ST != kStoreF16S)                                                      \
         hipLaunchKernelGGL((K_UPD(W, T, 2)), grid, dim3(256), lds, s, a, P);               \
       break;                                                                               \
   }
@@ -1899,7 +1896,7 @@ hipError_t launch_init_t(const InitArgs& ia, hipStream_t s) {
     case 0: hipLaunchKernelGGL((k_init<L, NC, ST, W, 0>), grid, dim3(256), 0, s, ia); break;    \
     case 1: hipLaunchKernelGGL((k_init<L, NC, ST, W, 1>), grid, dim3(256), 0, s, ia); break;    \
     default:                                                                                     \
-      if constexpr (ST != kStoreF16S) hipLaunchKernelGGL((k_init<L, NC, ST, W, 2>), grid, dim3(256), 0, s, ia); \
+      hipLaunchKernelGGL((k_init<L, NC, ST, W, 2>), grid, dim3(256), 0, s, ia);                       \
       break;                                                                                     \
   }
   if (w_) { K_INIT(true) } else { K_INIT(false) }
@@ -1918,7 +1915,7 @@ hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
 #define K_CM(W, T, F) k_conc_m<L, NC - 1, ST, W, T, F>
 #define K_CM_FR(W, T)                                                                         \
   if (fr) {                                                                                   \
-    if constexpr (ST != kStoreF16S) hipLaunchKernelGGL((K_CM(W, T, true)), grid, dim3(256), lds, s, a, P); \
+    hipLaunchKernelGGL((K_CM(W, T, true)), grid, dim3(256), lds, s, a, P);                    \
   } else {                                                                                    \
     hipLaunchKernelGGL((K_CM(W, T, false)), grid, dim3(256), lds, s, a, P);                   \
   }
@@ -1961,7 +1958,7 @@ template <class L, int NC, int ST>
 hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   const auto* P = static_cast<const DevParams<TT<ST>>*>(b.params);
   const dim3 blk(256);
-  const bool fr = ST != kStoreF16S && b.moments && b.frecord;
+  const bool fr = b.moments && b.frecord;
   hipError_t e;
   if (b.moments) {
     const dim3 grid(b.blocks_update);
@@ -1970,7 +1967,6 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
 #define K_CMB(W, T, F) k_conc_m_batch<L, NC - 1, ST, W, T, F>
 #define K_CMB_FR(W, T)                                                                                \
   if (fr) {                                                                                           \
-    if constexpr (ST != kStoreF16S)                                                                   \
       hipLaunchKernelGGL((K_CMB(W, T, true)), grid, blk, lds, s, b.args, P, b.work_update, nb);       \
   } else {                                                                                            \
     hipLaunchKernelGGL((K_CMB(W, T, false)), grid, blk, lds, s, b.args, P, b.work_update, nb);        \
@@ -2002,7 +1998,6 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
     case 0: hipLaunchKernelGGL((K_UB(W, T, 0)), grid, blk, lds, s, b.args, P, b.work_update, nb); break; \
     case 1: hipLaunchKernelGGL((K_UB(W, T, 1)), grid, blk, lds, s, b.args, P, b.work_update, nb); break; \
     default:                                                                                           \
-      if constexpr (ST != kStoreF16S)                                                                  \
         hipLaunchKernelGGL((K_UB(W, T, 2)), grid, blk, lds, s, b.args, P, b.work_update, nb);          \
       break;                                                                                           \
   }
@@ -2076,7 +2071,7 @@ size_t conc_m_lds_bytes(int lat, int nc, int store, int tx_log2, bool frecord) {
   switch (store) {
     case kStoreF64: return conc_m_lds_bytes_for<kStoreF64>(lat, nc, tx_log2, frecord);
     case kStoreF32: return conc_m_lds_bytes_for<kStoreF32>(lat, nc, tx_log2, frecord);
-    default: return conc_m_lds_bytes_for<kStoreF16S>(lat, nc, tx_log2, false);
+    default: return conc_m_lds_bytes_for<kStoreF16S>(lat, nc, tx_log2, frecord);
   }
 }
 

@@ -61,21 +61,26 @@ __device__ __forceinline__ int plane_pos(int face, int inner, const StepArgs& a)
 
 // Post-collision f*_kd of the node at index src in the record form of f:
 // w_kd times f_scaled of its records (v, -3/2 v.v) and (fB, F).
-template <class L, class T>
-__device__ __forceinline__ T rec_f(const StepArgs& a, uint32_t src, int kd) {
+template <class L, int ST>
+__device__ __forceinline__ typename StoreT<ST>::T rec_f(const StepArgs& a, uint32_t src, int kd) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
   T v4[4], fr[4];
-  vld<T, 4>(gptr<const T>(a.vel) + size_t(src) * 4, v4);
-  vld<T, 4>(gptr<const T>(a.frec) + size_t(src) * 4, fr);
+  rec_load<S, 4>(a.vel, src * 4u, v4, T(S::vel_scale));
+  rec_load<S, 4>(a.frec, src * 4u, fr, T(S::vel_scale));
   return static_cast<T>(L::w[kd]) * f_scaled<L>(kd, v4, fr);
 }
 // Post-collision g*_{e,kd} (kd >= 1) of the node at src in the moment form:
 // C_e s_kd(v) - w_kd m mu~_e from its records (Eq. geq with tau_g = 1).
-template <class L, int NE, class T>
-__device__ __forceinline__ T rec_g(const StepArgs& a, const DevParams<T>& P, uint32_t src, int e, int kd) {
+template <class L, int NE, int ST>
+__device__ __forceinline__ typename StoreT<ST>::T rec_g(const StepArgs& a, const DevParams<typename StoreT<ST>::T>& P,
+                                                        uint32_t src, int e, int kd) {
+  using S = StoreT<ST>;
+  using T = typename S::T;
   const T c = gptr<const T>(a.cprev)[size_t(src) * NE + e];
-  const T mu = gptr<const T>(a.mu)[size_t(src) * NE + e];
+  const T mu = rec_at<S>(a.mu, size_t(src) * NE + e, T(S::mu_scale));
   T v4[4];
-  vld<T, 4>(gptr<const T>(a.vel) + size_t(src) * 4, v4);
+  rec_load<S, 4>(a.vel, src * 4u, v4, T(S::vel_scale));
   const int kp = (kd & 1) ? kd : kd - 1;
   const T v[3] = {v4[0], v4[1], v4[2]};
   const T ev = proj<L>(kp, v);
@@ -98,16 +103,16 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, cons
   if (a.flags & kFlagFRecord) {
     if (a.flags & kFlagFLocal) {
       T fr[4];
-      vld<T, 4>(gptr<const T>(a.frec) + size_t(node) * 4, fr);
+      rec_load<S, 4>(a.frec, node * 4u, fr, T(S::vel_scale));
       return static_cast<T>(L::w[k]) * f_scaled_local<L>(k, fr);
     }
     if (pulled_from_wall<L, true>(nb, k)) {
-      T v = rec_f<L, T>(a, node, opposite(k));
+      T v = rec_f<L, ST>(a, node, opposite(k));
       const int fc = entry_face<L, true>(nb, k, open);
       if (fc >= 0) v += FB->fcorr[fc][k];
       return v;
     }
-    return rec_f<L, T>(a, upstream<L>(nb, k), k);
+    return rec_f<L, ST>(a, upstream<L>(nb, k), k);
   }
   const FS* fs = gptr<const FS>(a.f_src);
   const size_t fst = static_cast<size_t>(a.fstride);
@@ -138,19 +143,19 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, cons
     const DevParams<T>& P = *gptr<const DevParams<T>>(a.params);
     if (k == 0) {
       const T c = gptr<const T>(a.cprev)[size_t(node) * NE + e];
-      const T mu = gptr<const T>(a.mu)[size_t(node) * NE + e];
-      const T s0 = static_cast<T>(L::w[0]) * gptr<const T>(a.vel)[size_t(node) * 4 + 3];
+      const T mu = rec_at<S>(a.mu, size_t(node) * NE + e, T(S::mu_scale));
+      const T s0 = static_cast<T>(L::w[0]) * rec_at<S>(a.vel, size_t(node) * 4 + 3, T(S::vel_scale));
       return c + fma(c, s0, (static_cast<T>(1.0 - L::w[0]) * P.m) * mu);
     }
     if (pulled_from_wall<L, true>(nb, k)) {
       const int fc = entry_face<L, true>(nb, k, open);
       if (fc >= 0) {
         if (a.flags & kFlagFLocal) return T(0);
-        return FB->gsum[fc][e][k] - rec_g<L, NE, T>(a, P, node, e, opposite(k));
+        return FB->gsum[fc][e][k] - rec_g<L, NE, ST>(a, P, node, e, opposite(k));
       }
-      return rec_g<L, NE, T>(a, P, node, e, opposite(k));
+      return rec_g<L, NE, ST>(a, P, node, e, opposite(k));
     }
-    return rec_g<L, NE, T>(a, P, upstream<L>(nb, k), e, k);
+    return rec_g<L, NE, ST>(a, P, upstream<L>(nb, k), e, k);
   }
   if (k == 0) return static_cast<T>(gptr<const G0S>(a.g0_src)[size_t(node) * NE + e]);
   const FS* gk = gptr<const FS>(a.gk_src);

@@ -95,7 +95,7 @@ def test_which_configurations_take_the_record_form():
     lens = W.lens_2d(20, 16, radius=4.0)
     assert form(lens) == "records"
     assert form(lens, nf.FP32) == "records"
-    assert form(lens, nf.FP16S) == "populations"          # binary16 populations
+    assert form(lens, nf.FP16S) == "records"              # binary16 node records
     assert form(lens, flags=nf.FLAG_F_POPULATIONS) == "populations"
     assert form(lens, flags=nf.FLAG_G_POPULATIONS) == "populations"
     assert form(lens, flags=nf.FLAG_NO_HYDRO) == "populations"

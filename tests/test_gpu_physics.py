@@ -75,9 +75,11 @@ def test_lens_angle_all_precisions():
                            for q in v} for k, v in ang.items()}
     assert abs(ang["fp64"]["lens"] - 120.0) < 3.0
     assert abs(ang["fp64"]["lens"] - ang["oracle"]["lens"]) < 1e-6
-    # about ten times the measured storage error (FP32 2.2e-5, FP16S 2.7e-5 degrees)
+    # about ten times the measured FP32 storage error (2.2e-5 degrees); FP16S
+    # keeps mu~, v and the f records in binary16 (2^-12 relative each step):
+    # measured 3.5e-3 degrees, bounded at about three times that
     assert abs(ang["fp32"]["lens"] - ang["fp64"]["lens"]) < 3e-4
-    assert abs(ang["fp16s"]["lens"] - ang["fp64"]["lens"]) < 3e-4
+    assert abs(ang["fp16s"]["lens"] - ang["fp64"]["lens"]) < 1e-2
 
 
 def test_laplace_pressure_all_precisions():
@@ -108,9 +110,12 @@ def test_laplace_pressure_all_precisions():
     assert abs(e24) < 0.02           # measured +1.27 % (R = 12: +3.86 %)
     assert abs(e24) < abs(e12)
     for r in ("R12", "R24"):
-        # measured FP32 4.5e-4 (R = 12) and 6e-6; FP16S 2.0e-4 and 1.5e-5
+        # measured FP32 4.5e-4 (R = 12) and 6e-6; FP16S (binary16 node
+        # records, the pressure carried by the f moments) 2.1e-4 and 7.7e-3
+        # of a Delta P of 2e-4 at R = 24, below that case's own
+        # discretisation error (1.27 %)
         assert abs(out[r]["fp32"]["rel_diff_vs_fp64"]) < 1e-3
-        assert abs(out[r]["fp16s"]["rel_diff_vs_fp64"]) < 2e-3
+        assert abs(out[r]["fp16s"]["rel_diff_vs_fp64"]) < 2e-2
 
 
 def test_layered_poiseuille_all_precisions():
