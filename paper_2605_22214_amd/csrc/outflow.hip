@@ -70,25 +70,6 @@ __device__ __forceinline__ typename StoreT<ST>::T rec_f(const StepArgs& a, uint3
   rec_load<S, 4>(a.frec, src * 4u, fr, T(S::vel_scale));
   return static_cast<T>(L::w[kd]) * f_scaled<L>(kd, v4, fr);
 }
-// Post-collision g*_{e,kd} (kd >= 1) of the node at src in the moment form:
-// C_e s_kd(v) - w_kd m mu~_e from its records (Eq. geq with tau_g = 1).
-template <class L, int NE, int ST>
-__device__ __forceinline__ typename StoreT<ST>::T rec_g(const StepArgs& a, const DevParams<typename StoreT<ST>::T>& P,
-                                                        uint32_t src, int e, int kd) {
-  using S = StoreT<ST>;
-  using T = typename S::T;
-  const T c = gptr<const T>(a.cprev)[size_t(src) * NE + e];
-  const T mu = rec_at<S>(a.mu, size_t(src) * NE + e, T(S::mu_scale));
-  T v4[4];
-  rec_load<S, 4>(a.vel, src * 4u, v4, T(S::vel_scale));
-  const int kp = (kd & 1) ? kd : kd - 1;
-  const T v[3] = {v4[0], v4[1], v4[2]};
-  const T ev = proj<L>(kp, v);
-  const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
-  const T wk = static_cast<T>(L::w[kd]);
-  return fma(c, wk * u, -(wk * P.m) * mu);
-}
-
 // Post-streaming f_k (k >= 1) of a node, pulled as the update pulls it:
 // halfway bounce-back at a wall face, plus the velocity correction where the
 // link enters across an open face.  In the record form of f the
@@ -125,47 +106,72 @@ __device__ __forceinline__ typename StoreT<ST>::T pull_f(const StepArgs& a, cons
   return S::ld(fs + size_t(k - 1) * fst, upstream<L>(nb, k));
 }
 
-// Post-streaming g_{e,k} (any k) of an evolved component e, pulled as the
-// reconstruction pulls it (anti-bounce-back across an open face).  In the
-// moment form the post-collision values are formed from the records; the
-// rest population is C_e (1 + s_0) + (1 - w_0) m mu~_e of the node's own,
-// and on the first step after set_fields g entering across an open face is
-// the initial 0.
+// Post-streaming g_{e,k} (any k) of every evolved component e, pulled as the
+// reconstruction pulls them (anti-bounce-back across an open face), the
+// source's record (or populations) read once for all components.  In the
+// moment form the post-collision values are formed from the records: g*_k =
+// C_e s_k(v) - w_k m mu~_e (Eq. geq with tau_g = 1), the rest population
+// C_e (1 + s_0) + (1 - w_0) m mu~_e of the node's own; on the first step
+// after set_fields g entering across an open face is the initial 0.
 template <class L, int NE, int ST>
-__device__ __forceinline__ typename StoreT<ST>::T pull_g(const StepArgs& a, const Nbr& nb, uint32_t node, int e,
-                                                         int k, const FaceBC<typename StoreT<ST>::T>* FB,
-                                                         int open) {
+__device__ __forceinline__ void pull_g_all(const StepArgs& a, const Nbr& nb, uint32_t node, int k,
+                                           const FaceBC<typename StoreT<ST>::T>* FB, int open,
+                                           typename StoreT<ST>::T (&q)[NE]) {
   using S = StoreT<ST>;
   using T = typename S::T;
   using FS = typename S::FS;
   using G0S = typename S::G0S;
   if (a.flags & kFlagMoments) {
     const DevParams<T>& P = *gptr<const DevParams<T>>(a.params);
+    T c[NE], mu[NE], v4[4];
+    const bool wall = k > 0 && pulled_from_wall<L, true>(nb, k);
+    const uint32_t src = (k == 0 || wall) ? node : upstream<L>(nb, k);
+    vld<T, NE>(gptr<const T>(a.cprev) + size_t(src) * NE, c);
+    rec_load<S, NE>(a.mu, src * uint32_t(NE), mu, T(S::mu_scale));
+    rec_load<S, 4>(a.vel, src * 4u, v4, T(S::vel_scale));
     if (k == 0) {
-      const T c = gptr<const T>(a.cprev)[size_t(node) * NE + e];
-      const T mu = rec_at<S>(a.mu, size_t(node) * NE + e, T(S::mu_scale));
-      const T s0 = static_cast<T>(L::w[0]) * rec_at<S>(a.vel, size_t(node) * 4 + 3, T(S::vel_scale));
-      return c + fma(c, s0, (static_cast<T>(1.0 - L::w[0]) * P.m) * mu);
+      const T s0 = static_cast<T>(L::w[0]) * v4[3];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) q[e] = c[e] + fma(c[e], s0, (static_cast<T>(1.0 - L::w[0]) * P.m) * mu[e]);
+      return;
     }
-    if (pulled_from_wall<L, true>(nb, k)) {
+    const int kd = wall ? opposite(k) : k;
+    const int kp = (kd & 1) ? kd : kd - 1;
+    const T v[3] = {v4[0], v4[1], v4[2]};
+    const T ev = proj<L>(kp, v);
+    const T u = fma(ev, fma(T(4.5), ev, (kd & 1) ? T(3) : -T(3)), v4[3]);
+    const T wk = static_cast<T>(L::w[kd]);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) q[e] = fma(c[e], wk * u, -(wk * P.m) * mu[e]);
+    if (wall) {
       const int fc = entry_face<L, true>(nb, k, open);
       if (fc >= 0) {
-        if (a.flags & kFlagFLocal) return T(0);
-        return FB->gsum[fc][e][k] - rec_g<L, NE, ST>(a, P, node, e, opposite(k));
+#pragma unroll
+        for (int e = 0; e < NE; ++e) q[e] = (a.flags & kFlagFLocal) ? T(0) : FB->gsum[fc][e][k] - q[e];
       }
-      return rec_g<L, NE, ST>(a, P, node, e, opposite(k));
     }
-    return rec_g<L, NE, ST>(a, P, upstream<L>(nb, k), e, k);
+    return;
   }
-  if (k == 0) return static_cast<T>(gptr<const G0S>(a.g0_src)[size_t(node) * NE + e]);
+  if (k == 0) {
+    G0S r[NE];
+    vld<G0S, NE>(gptr<const G0S>(a.g0_src) + size_t(node) * NE, r);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) q[e] = static_cast<T>(r[e]);
+    return;
+  }
   const FS* gk = gptr<const FS>(a.gk_src);
   const size_t gst = static_cast<size_t>(a.gstride);
+  FS r[NE];
   if (pulled_from_wall<L, true>(nb, k)) {
-    const T v = S::unpack(gk[size_t(opposite(k) - 1) * gst + size_t(node) * NE + e]);
+    vld<FS, NE>(gk + size_t(opposite(k) - 1) * gst + size_t(node) * NE, r);
     const int fc = entry_face<L, true>(nb, k, open);
-    return fc >= 0 ? FB->gsum[fc][e][k] - v : v;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) q[e] = fc >= 0 ? FB->gsum[fc][e][k] - S::unpack(r[e]) : S::unpack(r[e]);
+    return;
   }
-  return S::unpack(gk[size_t(k - 1) * gst + size_t(upstream<L>(nb, k)) * NE + e]);
+  vld<FS, NE>(gk + size_t(k - 1) * gst + size_t(upstream<L>(nb, k)) * NE, r);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) q[e] = S::unpack(r[e]);
 }
 
 }  // namespace
@@ -255,6 +261,7 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
     for (int e = 0; e <= NE; ++e) gh[size_t(e) * P + p] = T(0);
     return;
   }
+#pragma unroll
   for (int k = 1; k < Q; ++k) {
     const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
     T* slot = of + size_t(k - 1) * P + p;
@@ -262,20 +269,27 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   }
   // the new plane-N populations of g, and C as the reconstruction sums them
   // (moving populations first, the rest population last)
+  T m[NE], r[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) m[e] = r[e] = T(0);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    T q[NE];
+    pull_g_all<L, NE, ST>(a, nb, node, k, FB, open, q);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      T* slot = og + (size_t(e) * Q + k) * P + p;
+      const T v = o.start ? q[e] : (*slot + u * q[e]) / den;
+      *slot = v;
+      if (k == 0) r[e] = v;
+      else m[e] += v;
+    }
+  }
   T c[NC];
   T rest = T(0);
+#pragma unroll
   for (int e = 0; e < NE; ++e) {
-    T m = T(0);
-    T r = T(0);
-    for (int k = 0; k < Q; ++k) {
-      const T q = pull_g<L, NE, ST>(a, nb, node, e, k, FB, open);
-      T* slot = og + (size_t(e) * Q + k) * P + p;
-      const T v = o.start ? q : (*slot + u * q) / den;
-      *slot = v;
-      if (k == 0) r = v;
-      else m += v;
-    }
-    c[e] = r + m;
+    c[e] = r[e] + m[e];
     rest += c[e];
   }
   c[NE] = T(1) - rest;
