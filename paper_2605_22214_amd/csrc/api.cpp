@@ -457,25 +457,35 @@ void fill_mob(const nflbm_sim& s, const double* tau_g, double m_star, MobParams<
   }
 }
 
-// Convective outflow of the state set `cur` (start: capture its boundary
-// plane instead of convecting).
-OutflowArgs outflow_args(const nflbm_sim* s, int cur, bool start) {
+// Convective outflow of the state set `cur`.  mode 0 convects after a step,
+// 1 captures the boundary plane of the current state, 2 only re-derives plane
+// N's C, E_B and f moments from the plane buffers (moment form).
+OutflowArgs outflow_args(const nflbm_sim* s, int cur, int mode) {
   OutflowArgs o{};
   o.sa = make_args(s, cur);
   // after a step the plane N-1 populations are the streamed ones (the
   // first-step flag of the moment form describes only the state before it)
-  if (!start) o.sa.flags &= ~kFlagFLocal;
+  if (mode == 0) o.sa.flags &= ~kFlagFLocal;
   o.partial = s->out_red;
   o.u = s->out_red + s->out_blocks;
   o.fluid = s->out_fluid;
   o.blocks = s->out_blocks;
-  o.start = start ? 1 : 0;
+  o.start = mode;
   return o;
 }
 
-int launch_outflow_step(nflbm_sim* s, bool start) {
-  HIPCHK(s, launch_outflow(s->lat, s->N, s->store, outflow_args(s, s->cur, start), s->stream));
+int launch_outflow_step(nflbm_sim* s, int mode) {
+  HIPCHK(s, launch_outflow(s->lat, s->N, s->store, outflow_args(s, s->cur, mode), s->stream));
   return NFLBM_OK;
+}
+
+// In the moment form the reconstruction leaves C, E_B and the f moments of
+// the outflow plane to the outflow kernel, which writes them into arrays that
+// are not part of the state: after the state is replaced they are re-derived
+// from the restored plane buffers.
+int refresh_outflow_plane(nflbm_sim* s) {
+  if (s->out_face < 0 || !s->gform) return NFLBM_OK;
+  return launch_outflow_step(s, 2);
 }
 
 size_t out_buf_bytes(const nflbm_sim* s) {
@@ -511,7 +521,7 @@ int launch_step(nflbm_sim* s, hipEvent_t ev0, hipEvent_t ev1, bool* checked = nu
   if (s->c2c2) HIPCHK(s, launch_mob_source(s->lat, s->N, s->store, mob_args(s, a), s->stream));
   s->cur ^= 1;
   s->f_local = false;   // from now on every f streams in from its neighbour
-  if (s->out_face >= 0) return launch_outflow_step(s, false);
+  if (s->out_face >= 0) return launch_outflow_step(s, 0);
   return NFLBM_OK;
 }
 
@@ -791,7 +801,7 @@ hipError_t launch_half(nflbm_batch* b, int half) {
   for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
     const nflbm_sim* m = b->members[i];
     if (m->out_face < 0) continue;
-    e = launch_outflow(m->lat, m->N, m->store, outflow_args(m, b->key[i] ^ (half == 0 ? 1 : 0), false), b->stream);
+    e = launch_outflow(m->lat, m->N, m->store, outflow_args(m, b->key[i] ^ (half == 0 ? 1 : 0), 0), b->stream);
   }
   return e;
 }
@@ -977,6 +987,8 @@ int restore_state(nflbm_sim* s, SavedState* st) {
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < st->copies.size() && i < segs.size() && e == hipSuccess; ++i)
     e = hipMemcpyAsync(segs[i].first, st->copies[i], segs[i].second, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && s->out_face >= 0 && s->gform)
+    e = launch_outflow(s->lat, s->N, s->store, outflow_args(s, s->cur, 2), s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   for (void* c : st->copies) (void)hipFree(c);
   st->copies.clear();
@@ -1465,7 +1477,7 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
   int rc = upload_faces(sim);
   if (rc) return rc;
   // start from the current state's boundary plane
-  rc = launch_outflow_step(sim, true);
+  rc = launch_outflow_step(sim, 1);
   if (rc) return rc;
   HIPCHK(sim, hipStreamSynchronize(sim->stream));
   return NFLBM_OK;
@@ -1504,6 +1516,11 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
   if (e != hipSuccess) return hip_fail(sim, e, "set_solid");
   sim->solid_host.assign(solid, solid + n);
   sim->out_fluid = fluid_out;
+  {
+    const int rc = refresh_outflow_plane(sim);
+    if (rc) return rc;
+    HIPCHK(sim, hipStreamSynchronize(sim->stream));
+  }
   ++sim->boundary_version;
   return NFLBM_OK;
 }
@@ -1563,7 +1580,7 @@ int nflbm_set_fields(nflbm_sim* sim, const double* C, const double* v, const dou
                        hipMemcpyDeviceToDevice, sim->stream);
   if (e == hipSuccess && sim->out_face >= 0) {
     // the outflow plane and ghosts start from the new state
-    const int rc = launch_outflow_step(sim, true);
+    const int rc = launch_outflow_step(sim, 1);
     if (rc) {
       (void)hipStreamSynchronize(sim->stream);
       (void)hipFree(tmp);
@@ -1935,8 +1952,10 @@ int nflbm_set_state(nflbm_sim* sim, const void* host_raw) {
     HIPCHK(sim, hipMemcpyAsync(seg.first, p, seg.second, hipMemcpyHostToDevice, sim->stream));
     p += seg.second;
   }
-  HIPCHK(sim, hipStreamSynchronize(sim->stream));
   if (state_tail(sim)) sim->f_local = *p != 0;
+  const int rc = refresh_outflow_plane(sim);
+  if (rc) return rc;
+  HIPCHK(sim, hipStreamSynchronize(sim->stream));
   return sim_nan_reset(sim);
 }
 

@@ -206,7 +206,7 @@ struct OutflowArgs {
   double* u;                          // [1]
   double fluid;                       // fluid nodes of plane N-1 (U is their mean)
   int blocks;
-  int start;
+  int start;                          // 0 convect, 1 capture plane N, 2 refresh plane N's C/E_B/f moments
 };
 
 // Launchers: lat 0 = D2Q9, 1 = D3Q19; nc = N; store = StoreKind.

@@ -539,38 +539,10 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
     const uint32_t node = uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z);
     T sum[NE];
     // convective outflow: the boundary plane's post-streaming populations
-    // (every k) are the plane buffers, not the gathered sums
-    const int op = (WALLS && a.out_face >= 0) ? outflow_plane_index(a.out_face, 0, x, y, z, a) : -1;
-    if (WALLS && op >= 0 && !A.solid) {
-      const uint32_t PL = outflow_plane_size(a.out_face, a.nx, a.ny, a.nz);
-      const T* og = gptr<const T>(a.out_g);
-      T cn[NC];
-      T rest = T(0);
-      for (int e = 0; e < NE; ++e) {
-        T m = T(0);
-        for (int k = 1; k < Q; ++k) m += og[(uint32_t(e) * Q + k) * PL + op];
-        sum[e] = og[uint32_t(e) * Q * PL + op] + m;
-        cn[e] = sum[e];
-        rest += sum[e];
-      }
-      cn[NE] = T(1) - rest;
-      if constexpr (FR) {
-        const T* of = gptr<const T>(a.out_f);
-        T fm[4] = {T(0), T(0), T(0), T(0)};
-        for (int k = 1; k < Q; ++k) {
-          const T fk = of[uint32_t(k - 1) * PL + op];
-          fm[0] += fk;
-#pragma unroll
-          for (int d = 0; d < 3; ++d)
-            if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? fk : -fk;
-        }
-        rec_store<S, 4, true>(a.fmom, node * 4, fm, T(S::vel_scale));
-      }
-      const NFLBM_CONST DevParams<T>& P = *fresh_const(P0);
-      vst<T, NE>(at(gptr<T>(a.conc), node * NE), sum);
-      *at(gptr<T>(a.eb), node) = bulk_energy<NC, T>(cn, P);
-      return;
-    }
+    // (every k) are the plane buffers, from which the outflow kernel that
+    // wrote them (after the previous step, or when the state or the outflow
+    // was set) has already formed this node's C, E_B and f moments
+    if (WALLS && !A.solid && a.out_face >= 0 && outflow_plane_index(a.out_face, 0, x, y, z, a) >= 0) return;
     if (A.solid) {
 #pragma unroll
       for (int e = 0; e < NE; ++e) sum[e] = T(0);

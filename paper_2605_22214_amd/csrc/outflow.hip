@@ -24,7 +24,10 @@
 //                    per plane node blends the pulled plane N-1 populations
 //                    into the plane buffer and convects the ghosts.
 // With start = 1 the apply kernel instead captures plane N of the current
-// state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)).  Solid nodes continue
+// state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)); with start = 2 it only
+// re-derives plane N's C, E_B and f moments from the buffers (after a state
+// is restored).  In the moment form the reconstruction leaves the boundary
+// plane to this kernel, which writes those where the reconstruction writes.  Solid nodes continue
 // straight through the outflow plane: U is the mean over the fluid nodes of
 // plane N-1, and solid plane nodes keep zeros.  In the moment form of g
 // (and the record form of f) the pulled populations are formed from the
@@ -214,7 +217,8 @@ __global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
 
 template <class L, int NC, int ST>
 __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
-  using T = typename StoreT<ST>::T;
+  using S = StoreT<ST>;
+  using T = typename S::T;
   constexpr int NE = NC - 1;
   constexpr int Q = L::Q;
   const StepArgs& a = o.sa;
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   const int tid = static_cast<int>(threadIdx.x);
   // U from the partial sums, in the same order in every workgroup
   double U = 0.0;
-  if (!o.start) {
+  if (o.start == 0) {
     double s = 0.0;
     for (int i = tid; i < o.blocks; i += 256) s += o.partial[i];
     red[tid] = s;
@@ -239,6 +243,40 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   }
   const int p = static_cast<int>(blockIdx.x) * 256 + tid;
   if (p >= PL) return;
+  if (o.start == 2) {
+    // refresh (moment form, after a state was restored): C, E_B and the f
+    // moments of plane N from the plane buffers as they stand
+    if (!(a.flags & kFlagMoments)) return;
+    int xN, yN, zN;
+    plane_node(ax, plane_pos(face, 0, a), p, a, xN, yN, zN);
+    const Nbr nbN = neighbours<L, true>(xN, yN, zN, a);
+    if (solid_node<true>(nbN)) return;
+    const uint32_t nodeN = uint32_t(xN) + uint32_t(a.nx) * (uint32_t(yN) + uint32_t(a.ny) * uint32_t(zN));
+    const size_t P = static_cast<size_t>(PL);
+    const T* of = gptr<const T>(a.out_f);
+    const T* og = gptr<const T>(a.out_g);
+    T fm[4] = {T(0), T(0), T(0), T(0)};
+    for (int k = 1; k < Q; ++k) {
+      const T v = of[size_t(k - 1) * P + p];
+      fm[0] += v;
+      for (int d = 0; d < 3; ++d)
+        if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? v : -v;
+    }
+    T c[NC];
+    T rest = T(0);
+    for (int e = 0; e < NE; ++e) {
+      T m = T(0);
+      for (int k = 1; k < Q; ++k) m += og[(size_t(e) * Q + k) * P + p];
+      c[e] = og[size_t(e) * Q * P + p] + m;
+      rest += c[e];
+    }
+    c[NE] = T(1) - rest;
+    const DevParams<T>& Pp = *gptr<const DevParams<T>>(a.params);
+    vst<T, NE>(gptr<T>(a.conc) + size_t(nodeN) * NE, reinterpret_cast<const T(&)[NE]>(c));
+    gptr<T>(a.eb)[nodeN] = bulk_energy<NC, T>(c, Pp);
+    if (a.flags & kFlagFRecord) rec_store<S, 4, false>(a.fmom, nodeN * 4u, fm, T(S::vel_scale));
+    return;
+  }
   int x, y, z;
   plane_node(ax, plane_pos(face, o.start ? 0 : 1, a), p, a, x, y, z);
   const Nbr nb = neighbours<L, true>(x, y, z, a);
@@ -261,11 +299,18 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
     for (int e = 0; e <= NE; ++e) gh[size_t(e) * P + p] = T(0);
     return;
   }
+  // the f moments of the new plane-N populations (record form of f)
+  T fm[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
     const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
     T* slot = of + size_t(k - 1) * P + p;
-    *slot = o.start ? q : (*slot + u * q) / den;
+    const T v = o.start ? q : (*slot + u * q) / den;
+    *slot = v;
+    fm[0] += v;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? v : -v;
   }
   // the new plane-N populations of g, and C as the reconstruction sums them
   // (moving populations first, the rest population last)
@@ -301,6 +346,17 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   }
   T* slot = gh + size_t(NE) * P + p;
   *slot = o.start ? E : (*slot + u * E) / den;
+  if (a.flags & kFlagMoments) {
+    // In the moment form the next reconstruction leaves the boundary plane
+    // to this kernel: C, E_B and (record form of f) the f moments of the new
+    // plane-N populations, where that reconstruction writes its results
+    int xN, yN, zN;
+    plane_node(ax, plane_pos(face, 0, a), p, a, xN, yN, zN);
+    const uint32_t nodeN = uint32_t(xN) + uint32_t(a.nx) * (uint32_t(yN) + uint32_t(a.ny) * uint32_t(zN));
+    vst<T, NE>(gptr<T>(a.conc) + size_t(nodeN) * NE, reinterpret_cast<const T(&)[NE]>(c));
+    gptr<T>(a.eb)[nodeN] = E;
+    if (a.flags & kFlagFRecord) rec_store<S, 4, false>(a.fmom, nodeN * 4u, fm, T(S::vel_scale));
+  }
 }
 
 namespace {
@@ -320,7 +376,7 @@ namespace {
 template <class L, int NC, int ST>
 hipError_t outflow_t(const OutflowArgs& o, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(o.blocks));
-  if (!o.start) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(256), 0, s, o);
+  if (o.start == 0) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(256), 0, s, o);
   hipLaunchKernelGGL((k_outflow_apply<L, NC, ST>), grid, dim3(256), 0, s, o);
   return hipGetLastError();
 }
