@@ -679,6 +679,17 @@ constexpr int update_waves() {
   return (ST != kStoreF64 && (L::DIM == 2 || NC <= 5)) ? 3 : 1;
 }
 
+// LDS planes of the update.  Float with at most four evolved components:
+// each position's concentrations form one record of 1, 2 or 4 values (three
+// padded to four), read with one vector access at an immediate offset from a
+// single base per plane, followed by E_B of every position; otherwise
+// field-major (component e of position p at e * PXY + p, then E_B).  Slot
+// stride (NEP + 1) PXY.
+template <int NE, class T>
+constexpr bool update_aos() { return sizeof(T) == 4 && NE <= 4; }
+template <int NE, class T>
+constexpr int update_nep() { return update_aos<NE, T>() ? (NE == 3 ? 4 : NE) : NE; }
+
 // One workgroup's share of the update: tile b of the simulation (x fastest,
 // then y, then the z run), with the LDS window at smem_raw.
 // Per-thread diagnostic sums of the reduce mode, internal component order:
@@ -713,10 +724,33 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   constexpr int TY = 256 >> TXL;
   constexpr int PX = TX + 2;
   constexpr int PXY = PX * (TY + 2);
-  constexpr int plane_stride = NC * PXY;   // NE concentrations + E_B per LDS slot
+  constexpr bool UAOS = update_aos<NE, T>();
+  constexpr int NEP = update_nep<NE, T>();
+  constexpr int CW = UAOS ? NEP : 1;        // distance between positions' C
+  constexpr int CE = UAOS ? 1 : PXY;        // distance between components
+  constexpr int EOFF = NEP * PXY;           // E_B of the slot's positions
+  constexpr int plane_stride = (NEP + 1) * PXY;
+  static_assert(!UAOS || plane_stride % NEP == 0, "LDS records must stay aligned to their size");
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> TXL;
+  // C of the evolved components at a position's C entry (AoS: one record)
+  auto read_c = [&](const T* p, T (&o)[NEP]) {
+    if constexpr (UAOS) {
+      vld<T, NEP>(p, o);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) o[e] = p[e * CE];
+    }
+  };
+  auto write_c = [&](T* p, const T (&v)[NEP]) {
+    if constexpr (UAOS) {
+      vst<T, NEP>(p, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) p[e * CE] = v[e];
+    }
+  };
 
   const int tile_x = b % a.tiles_x;
   b /= a.tiles_x;
@@ -808,22 +842,25 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           const uint32_t p = (face >> 1) == 2 ? fill_off[r]
                                               : fill_off[r] + uint32_t((face >> 1) == 0 ? a.ny : a.nx) * uint32_t(gz);
           const T* gh = gptr<const T>(a.out_ghost);
+          T cg[NEP] = {};
 #pragma unroll
-          for (int e = 0; e < NE; ++e) base[e * PXY + idx] = gh[uint32_t(e) * PL + p];
-          base[NE * PXY + idx] = gh[uint32_t(NE) * PL + p];
+          for (int e = 0; e < NE; ++e) cg[e] = gh[uint32_t(e) * PL + p];
+          write_c(base + idx * CW, cg);
+          base[EOFF + idx] = gh[uint32_t(NE) * PL + p];
           continue;
         }
+        T cf[NEP] = {};
 #pragma unroll
-        for (int e = 0; e < NE; ++e) base[e * PXY + idx] = FB->cb[face][e];
-        base[NE * PXY + idx] = FB->eb[face];
+        for (int e = 0; e < NE; ++e) cf[e] = FB->cb[face][e];
+        write_c(base + idx * CW, cf);
+        base[EOFF + idx] = FB->eb[face];
         continue;
       }
       const uint32_t node = fill_off[r] + zoff;
-      T ce[NE];
-      vld<T, NE>(at(conc, node * NE), ce);
-#pragma unroll
-      for (int e = 0; e < NE; ++e) base[e * PXY + idx] = ce[e];
-      base[NE * PXY + idx] = *at(eb, node);
+      T ce[NEP] = {};
+      vld<T, NE>(at(conc, node * NE), reinterpret_cast<T(&)[NE]>(ce));
+      write_c(base + idx * CW, ce);
+      base[EOFF + idx] = *at(eb, node);
     }
   };
 
@@ -883,18 +920,41 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         pm = a.bb[uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)];
       }
     }
-    const T* Cc = sm + s_c * plane_stride;
+    // record form of f in a step: the moments of the streamed f are read
+    // here, so that the load's latency passes under the stencil (four
+    // registers, where the gathered populations would hold eighteen)
+    constexpr bool FM_EARLY = GM == 2 && MODE == kModeStep;
+    T fm_early[4];
+    if constexpr (FM_EARLY)
+      rec_load<S, 4>(a.fmom, (uint32_t(x) + nx * uint32_t(y) + nxy * uint32_t(z)) * 4u, fm_early, T(S::vel_scale));
+    // Per-plane LDS bases of the 3 x 3 neighbourhood's lowest corner (C and
+    // E_B entries of the slots below, at and above), made opaque here so
+    // that every stencil read is one of them plus an immediate offset
+    // rather than a hoisted per-neighbour address plus the slot's base.
+    auto opaque = [](uint32_t v) {
+      asm volatile("" : "+v"(v));
+      return v;
+    };
+    const uint32_t corner_c = uint32_t((li - PX - 1) * CW), corner_e = uint32_t(EOFF + li - PX - 1);
+    const uint32_t bc[3] = {D3 ? opaque(uint32_t(s_dn * plane_stride) + corner_c) : 0u,
+                            opaque(uint32_t(s_c * plane_stride) + corner_c),
+                            D3 ? opaque(uint32_t(s_up * plane_stride) + corner_c) : 0u};
+    const uint32_t be[3] = {D3 ? opaque(uint32_t(s_dn * plane_stride) + corner_e) : 0u,
+                            opaque(uint32_t(s_c * plane_stride) + corner_e),
+                            D3 ? opaque(uint32_t(s_up * plane_stride) + corner_e) : 0u};
     T c[NC];
     {
+      T cr[NEP];
+      read_c(sm + bc[1] + (PX + 1) * CW, cr);
       T rest = T(0);
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        c[e] = Cc[e * PXY + li];
+        c[e] = cr[e];
         rest += c[e];
       }
       c[NE] = T(1) - rest;
     }
-    const T E0 = Cc[NE * PXY + li];
+    const T E0 = sm[be[1] + PX + 1];
     T gC[NC][3];
     T lap[NC];
     T gE[3] = {T(0), T(0), T(0)};
@@ -906,9 +966,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     // ---- isotropic stencils (Eq. gradstencil and the Laplacian after it).
     // From the lowest corner of the 3 x 3 neighbourhood every LDS offset is a
     // non-negative immediate.
-    auto nbr = [&](int ex, int ey, int ez) {
-      const int slot = (ez == 0) ? s_c : (ez > 0 ? s_up : s_dn);
-      return sm + slot * plane_stride + (li - PX - 1) + (1 + ey) * PX + (1 + ex);
+    auto nbr = [&](int ex, int ey, int ez) {      // C entry of x + e
+      return sm + bc[ez + 1] + ((1 + ey) * PX + (1 + ex)) * CW;
+    };
+    auto nbr_e = [&](int ex, int ey, int ez) {    // E_B of x + e
+      return sm + be[ez + 1] + (1 + ey) * PX + (1 + ex);
     };
     // A node next to a wall face goes direction by direction; every other
     // node, in every kernel variant and tile shape alike, goes by pairs, so a
@@ -929,18 +991,19 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       for (int k = 1; k < Q; k += 2) {
         const int ex = L::e[k][0], ey = L::e[k][1], ez = L::e[k][2];
         const T wk = static_cast<T>(L::w[k]);
-        const T* Cp = nbr(ex, ey, ez);
-        const T* Cm = nbr(-ex, -ey, -ez);
+        T rp[NEP], rm[NEP];
+        read_c(nbr(ex, ey, ez), rp);
+        read_c(nbr(-ex, -ey, -ez), rm);
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-          const T vp = Cp[i * PXY], vm = Cm[i * PXY];
+          const T vp = rp[i], vm = rm[i];
           const T dd = vp - vm;
           lap[i] = fma(wk, vp + vm, lap[i]);
           if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, dd, gC[i][0]);
           if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, dd, gC[i][1]);
           if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, dd, gC[i][2]);
         }
-        const T dE = Cp[NE * PXY] - Cm[NE * PXY];
+        const T dE = *nbr_e(ex, ey, ez) - *nbr_e(-ex, -ey, -ez);
         if (ex != 0) gE[0] = fma((ex > 0) ? wk : -wk, dE, gE[0]);
         if (ey != 0) gE[1] = fma((ey > 0) ? wk : -wk, dE, gE[1]);
         if (ez != 0) gE[2] = fma((ez > 0) ? wk : -wk, dE, gE[2]);
@@ -970,16 +1033,17 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           if (ez != 0 && a.wall_z) wall |= (z + ez < 0 && plain(4)) || (z + ez >= a.nz && plain(5));
         }
         if (!wall) {
-          const T* Cn = nbr(ex, ey, ez);
+          T rn[NEP];
+          read_c(nbr(ex, ey, ez), rn);
 #pragma unroll
           for (int i = 0; i < NE; ++i) {
-            const T d = Cn[i * PXY] - c[i];
+            const T d = rn[i] - c[i];
             lap[i] = fma(wk, d, lap[i]);
             if (ex != 0) gC[i][0] = fma((ex > 0) ? wk : -wk, d, gC[i][0]);
             if (ey != 0) gC[i][1] = fma((ey > 0) ? wk : -wk, d, gC[i][1]);
             if (ez != 0) gC[i][2] = fma((ez > 0) ? wk : -wk, d, gC[i][2]);
           }
-          const T dE = Cn[NE * PXY] - E0;
+          const T dE = *nbr_e(ex, ey, ez) - E0;
           if (ex != 0) gE[0] = fma((ex > 0) ? wk : -wk, dE, gE[0]);
           if (ey != 0) gE[1] = fma((ey > 0) ? wk : -wk, dE, gE[1]);
           if (ez != 0) gE[2] = fma((ez > 0) ? wk : -wk, dE, gE[2]);
@@ -1107,7 +1171,12 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const bool frec = GM == 2 || (GM == 0 && MODE != kModeStep && (a.flags & kFlagFRecord));
     if (hydro && frec) {
       T fm[4];
-      rec_load<S, 4>(a.fmom, node * 4, fm, T(S::vel_scale));
+      if constexpr (FM_EARLY) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) fm[d] = fm_early[d];
+      } else {
+        rec_load<S, 4>(a.fmom, node * 4, fm, T(S::vel_scale));
+      }
       fsum = fm[0];
 #pragma unroll
       for (int d = 0; d < 3; ++d) v[d] = fma(T(0.5), F[d], fm[1 + d]);
@@ -1336,7 +1405,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
       // the next plane's values fetched into registers while the current plane
       // is processed and written to LDS at the top of the next iteration, so
       // that the fill's load latency overlaps the compute.
-      T nxt[2][NE + 1];
+      T nxt[2][NEP + 1];
       auto fetch_plane = [&](int gz) {
         gz = (gz < 0) ? gz + a.nz : (gz >= a.nz ? gz - a.nz : gz);
         const uint32_t zoff = uint32_t(gz) * nxy;
@@ -1347,8 +1416,8 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
           T ce[NE];
           vld<T, NE>(at(conc, node * NE), ce);
   #pragma unroll
-          for (int e = 0; e < NE; ++e) nxt[r][e] = ce[e];
-          nxt[r][NE] = *at(eb, node);
+          for (int e = 0; e < NEP; ++e) nxt[r][e] = e < NE ? ce[e] : T(0);
+          nxt[r][NEP] = *at(eb, node);
         }
       };
       auto put_plane = [&](int slot) {
@@ -1357,8 +1426,8 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
         for (int r = 0; r < 2; ++r) {
           if (!fill_ok[r]) continue;
           const int idx = tid + 256 * r;
-  #pragma unroll
-          for (int e = 0; e <= NE; ++e) base[e * PXY + idx] = nxt[r][e];
+          write_c(base + idx * CW, reinterpret_cast<const T(&)[NEP]>(nxt[r]));
+          base[EOFF + idx] = nxt[r][NEP];
         }
       };
       load_plane(0, z0 - 1);
@@ -1742,13 +1811,16 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 template <int ST>
 using TT = typename StoreT<ST>::T;
 
-// LDS of the update: NE concentrations + E_B per position, 1 or 3 planes.
+// LDS of the update: the concentrations (NE of them; three as a padded
+// float record of four) and E_B per position, 1 or 3 planes.
 template <int ST>
 size_t lds_bytes_for(int lat, int nc, int tx_log2) {
   const int TX = 1 << tx_log2, TY = 256 >> tx_log2;
   const size_t pxy = size_t(TX + 2) * (TY + 2);
   const int npl = lat == 1 ? 3 : 1;
-  return npl * size_t(nc) * pxy * sizeof(TT<ST>);
+  const int ne = nc - 1;
+  const int nep = (sizeof(TT<ST>) == 4 && ne == 3) ? 4 : ne;
+  return npl * size_t(nep + 1) * pxy * sizeof(TT<ST>);
 }
 
 // LDS of the moment-form reconstruction: one padded record per position.

@@ -180,14 +180,14 @@ __device__ __forceinline__ void pull_g_all(const StepArgs& a, const Nbr& nb, uin
 }  // namespace
 
 template <class L, int NC, int ST>
-__global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
+__global__ void __launch_bounds__(kOutThreads) k_outflow_mom(OutflowArgs o) {
   using T = typename StoreT<ST>::T;
   const StepArgs& a = o.sa;
-  __shared__ double red[256];
+  __shared__ double red[kOutThreads];
   const int face = a.out_face, ax = face >> 1;
   const double sgn = (face & 1) ? 1.0 : -1.0;      // outward normal along ax
   const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
-  const int p = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  const int p = static_cast<int>(blockIdx.x) * kOutThreads + static_cast<int>(threadIdx.x);
   double mom = 0.0;
   if (p < PL) {
     int x, y, z;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
   }
   red[threadIdx.x] = mom;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kOutThreads / 2; s > 0; s >>= 1) {
     if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
@@ -216,13 +216,13 @@ __global__ void __launch_bounds__(256) k_outflow_mom(OutflowArgs o) {
 }
 
 template <class L, int NC, int ST>
-__global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
+__global__ void __launch_bounds__(kOutThreads) k_outflow_apply(OutflowArgs o) {
   using S = StoreT<ST>;
   using T = typename S::T;
   constexpr int NE = NC - 1;
   constexpr int Q = L::Q;
   const StepArgs& a = o.sa;
-  __shared__ double red[256];
+  __shared__ double red[kOutThreads];
   const int face = a.out_face, ax = face >> 1;
   const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
   const int tid = static_cast<int>(threadIdx.x);
@@ -230,10 +230,10 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
   double U = 0.0;
   if (o.start == 0) {
     double s = 0.0;
-    for (int i = tid; i < o.blocks; i += 256) s += o.partial[i];
+    for (int i = tid; i < o.blocks; i += kOutThreads) s += o.partial[i];
     red[tid] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = kOutThreads / 2; w > 0; w >>= 1) {
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_outflow_apply(OutflowArgs o) {
     if (!(U > 0.0)) U = 0.0;
     if (blockIdx.x == 0 && tid == 0) o.u[0] = U;
   }
-  const int p = static_cast<int>(blockIdx.x) * 256 + tid;
+  const int p = static_cast<int>(blockIdx.x) * kOutThreads + tid;
   if (p >= PL) return;
   if (o.start == 2) {
     // refresh (moment form, after a state was restored): C, E_B and the f
@@ -376,8 +376,8 @@ namespace {
 template <class L, int NC, int ST>
 hipError_t outflow_t(const OutflowArgs& o, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(o.blocks));
-  if (o.start == 0) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(256), 0, s, o);
-  hipLaunchKernelGGL((k_outflow_apply<L, NC, ST>), grid, dim3(256), 0, s, o);
+  if (o.start == 0) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(kOutThreads), 0, s, o);
+  hipLaunchKernelGGL((k_outflow_apply<L, NC, ST>), grid, dim3(kOutThreads), 0, s, o);
   return hipGetLastError();
 }
 
