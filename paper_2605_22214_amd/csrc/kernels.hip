@@ -815,15 +815,20 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   }
 
-  // Fill an LDS slot with C (evolved components) and E_B of plane gz.
-  // Positions inside a wall are left unfilled: the stencil never reads them.
-  auto load_plane = [&](int slot, int gz) {
-    T* base = sm + slot * plane_stride;
+  // C (evolved components) and E_B of plane gz at this thread's fill
+  // positions, into registers (fetch_plane), then into an LDS slot
+  // (put_plane).  Positions inside a wall are left unfilled: the stencil
+  // never reads them.  A position beyond an open face takes the face's
+  // values, beyond the outflow face the convected ghost values.
+  T nxt[2][NEP + 1];
+  bool nok[2];
+  auto fetch_plane = [&](int gz) {
     int plane_face = -1;
+    bool skip = false;
     if (gz < 0 || gz >= a.nz) {
       if (WALLS && a.wall_z) {
         plane_face = gz < 0 ? 4 : 5;
-        if (plain(plane_face)) return;
+        skip = plain(plane_face);
         gz = 0;
       } else {
         gz = (gz < 0) ? gz + a.nz : gz - a.nz;
@@ -832,36 +837,44 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     const uint32_t zoff = uint32_t(gz) * nxy;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      if (!fill_ok[r]) continue;
-      const int idx = tid + 256 * r;
+      nok[r] = fill_ok[r] && !skip;
+      if (!nok[r]) continue;
+#pragma unroll
+      for (int e = NE; e < NEP; ++e) nxt[r][e] = T(0);
       const int face = fill_face[r] >= 0 ? fill_face[r] : plane_face;
       if (WALLS && face >= 0) {
         if (face == a.out_face) {
-          // the convected ghost values of C and E_B at this position
           const uint32_t PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
           const uint32_t p = (face >> 1) == 2 ? fill_off[r]
                                               : fill_off[r] + uint32_t((face >> 1) == 0 ? a.ny : a.nx) * uint32_t(gz);
           const T* gh = gptr<const T>(a.out_ghost);
-          T cg[NEP] = {};
 #pragma unroll
-          for (int e = 0; e < NE; ++e) cg[e] = gh[uint32_t(e) * PL + p];
-          write_c(base + idx * CW, cg);
-          base[EOFF + idx] = gh[uint32_t(NE) * PL + p];
+          for (int e = 0; e <= NE; ++e) nxt[r][e == NE ? NEP : e] = gh[uint32_t(e) * PL + p];
           continue;
         }
-        T cf[NEP] = {};
 #pragma unroll
-        for (int e = 0; e < NE; ++e) cf[e] = FB->cb[face][e];
-        write_c(base + idx * CW, cf);
-        base[EOFF + idx] = FB->eb[face];
+        for (int e = 0; e < NE; ++e) nxt[r][e] = FB->cb[face][e];
+        nxt[r][NEP] = FB->eb[face];
         continue;
       }
       const uint32_t node = fill_off[r] + zoff;
-      T ce[NEP] = {};
-      vld<T, NE>(at(conc, node * NE), reinterpret_cast<T(&)[NE]>(ce));
-      write_c(base + idx * CW, ce);
-      base[EOFF + idx] = *at(eb, node);
+      vld<T, NE>(at(conc, node * NE), reinterpret_cast<T(&)[NE]>(nxt[r]));
+      nxt[r][NEP] = *at(eb, node);
     }
+  };
+  auto put_plane = [&](int slot) {
+    T* base = sm + slot * plane_stride;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!nok[r]) continue;
+      const int idx = tid + 256 * r;
+      write_c(base + idx * CW, reinterpret_cast<const T(&)[NEP]>(nxt[r]));
+      base[EOFF + idx] = nxt[r][NEP];
+    }
+  };
+  auto load_plane = [&](int slot, int gz) {
+    fetch_plane(gz);
+    put_plane(slot);
   };
 
   // post-streaming f of this node, gathered from the upstream neighbours, as
@@ -1400,36 +1413,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
   };
 
   auto march = [&](auto PL) {
-    if constexpr (D3 && !WALLS && sizeof(T) == 4) {
-      // Periodic lattices in float: rolling window of three LDS planes, with
-      // the next plane's values fetched into registers while the current plane
-      // is processed and written to LDS at the top of the next iteration, so
-      // that the fill's load latency overlaps the compute.
-      T nxt[2][NEP + 1];
-      auto fetch_plane = [&](int gz) {
-        gz = (gz < 0) ? gz + a.nz : (gz >= a.nz ? gz - a.nz : gz);
-        const uint32_t zoff = uint32_t(gz) * nxy;
-  #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          if (!fill_ok[r]) continue;
-          const uint32_t node = fill_off[r] + zoff;
-          T ce[NE];
-          vld<T, NE>(at(conc, node * NE), ce);
-  #pragma unroll
-          for (int e = 0; e < NEP; ++e) nxt[r][e] = e < NE ? ce[e] : T(0);
-          nxt[r][NEP] = *at(eb, node);
-        }
-      };
-      auto put_plane = [&](int slot) {
-        T* base = sm + slot * plane_stride;
-  #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          if (!fill_ok[r]) continue;
-          const int idx = tid + 256 * r;
-          write_c(base + idx * CW, reinterpret_cast<const T(&)[NEP]>(nxt[r]));
-          base[EOFF + idx] = nxt[r][NEP];
-        }
-      };
+    if constexpr (D3 && sizeof(T) == 4) {
+      // Float: rolling window of three LDS planes, with the next plane's
+      // values fetched into registers while the current plane is processed
+      // and written to LDS at the top of the next iteration, so that the
+      // fill's load latency overlaps the compute.
       load_plane(0, z0 - 1);
       load_plane(1, z0);
       fetch_plane(z0 + 1);
