@@ -1451,7 +1451,7 @@ int nflbm_set_outflow(nflbm_sim* sim, int face) {
   if (!sim->out_buf) {
     sim->out_plane = P;
     sim->out_face = face;   // sizes the buffer
-    const long long blocks = static_cast<long long>((P + kOutThreads - 1) / kOutThreads);
+    const long long blocks = static_cast<long long>((P + kOutNodes - 1) / kOutNodes);
     if (blocks > (1LL << 30)) {
       sim->out_face = -1;
       return fail(sim, NFLBM_EINVAL, "outflow plane too large");

@@ -199,10 +199,12 @@ struct MobArgs {
 // The convective outflow's per-step work (after the update, on the new
 // state): U from the plane inside the face (partial sums, then U = max(mean,
 // 0) in u[0]), then the convected boundary plane and ghosts.  start: capture
-// the boundary plane and ghosts of the initial state instead.  One thread per
-// plane node, kOutThreads (one wavefront) per workgroup: a plane has few
-// nodes, and small workgroups spread them over more compute units.
-constexpr int kOutThreads = 64;
+// the boundary plane and ghosts of the initial state instead.  A workgroup
+// takes kOutNodes plane nodes, its kOutThreads threads splitting each node's
+// directions: a plane has few nodes, and the gathers across the face need
+// the parallelism.
+constexpr int kOutNodes = 64;
+constexpr int kOutThreads = 256;
 struct OutflowArgs {
   StepArgs sa;
   double* partial;                    // [blocks]

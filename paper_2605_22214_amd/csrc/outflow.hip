@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device.h"
 
@@ -179,6 +180,26 @@ __device__ __forceinline__ void pull_g_all(const StepArgs& a, const Nbr& nb, uin
 
 }  // namespace
 
+// Work split of both kernels: a workgroup takes kOutNodes plane nodes (one
+// per lane) and its kOutWaves wavefronts take the directions of those nodes
+// in turn, wavefront w the directions k = w, w + kOutWaves, ...  Each wave
+// sums its directions in that order; the workgroup then adds the waves'
+// partial sums in wave order, so every result has one fixed order.
+constexpr int kOutWaves = kOutThreads / kOutNodes;
+
+// Runs f(std::integral_constant<int, w>) for the wave index w of this thread,
+// so that a wave's direction loop has compile-time directions.
+template <class F>
+__device__ __forceinline__ void for_wave(int w, F&& f) {
+  static_assert(kOutWaves == 4, "four direction groups per workgroup");
+  switch (w) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 3>{}); break;
+  }
+}
+
 template <class L, int NC, int ST>
 __global__ void __launch_bounds__(kOutThreads) k_outflow_mom(OutflowArgs o) {
   using T = typename StoreT<ST>::T;
@@ -187,7 +208,9 @@ __global__ void __launch_bounds__(kOutThreads) k_outflow_mom(OutflowArgs o) {
   const int face = a.out_face, ax = face >> 1;
   const double sgn = (face & 1) ? 1.0 : -1.0;      // outward normal along ax
   const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
-  const int p = static_cast<int>(blockIdx.x) * kOutThreads + static_cast<int>(threadIdx.x);
+  const int lane = static_cast<int>(threadIdx.x) % kOutNodes;
+  const int wave = static_cast<int>(threadIdx.x) / kOutNodes;
+  const int p = static_cast<int>(blockIdx.x) * kOutNodes + lane;
   double mom = 0.0;
   if (p < PL) {
     int x, y, z;
@@ -197,12 +220,15 @@ __global__ void __launch_bounds__(kOutThreads) k_outflow_mom(OutflowArgs o) {
     const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
     const int open = FB ? FB->open : 0;
     if (!solid_node<true>(nb)) {       // solid nodes hold no fluid
+      for_wave(wave, [&](auto WC) {
+        constexpr int W = decltype(WC)::value;
 #pragma unroll
-      for (int k = 1; k < L::Q; ++k) {
-        if (L::e[k][ax] == 0) continue;
-        const double v = static_cast<double>(pull_f<L, ST>(a, nb, node, k, FB, open));
-        mom += (L::e[k][ax] > 0) ? v : -v;
-      }
+        for (int k = (W == 0 ? kOutWaves : W); k < L::Q; k += kOutWaves) {
+          if (L::e[k][ax] == 0) continue;
+          const double v = static_cast<double>(pull_f<L, ST>(a, nb, node, k, FB, open));
+          mom += (L::e[k][ax] > 0) ? v : -v;
+        }
+      });
       mom *= sgn;
     }
   }
@@ -221,11 +247,15 @@ __global__ void __launch_bounds__(kOutThreads) k_outflow_apply(OutflowArgs o) {
   using T = typename S::T;
   constexpr int NE = NC - 1;
   constexpr int Q = L::Q;
+  constexpr int NPART = NE + 4;        // per wave and node: sum of moving g, f moments
   const StepArgs& a = o.sa;
   __shared__ double red[kOutThreads];
+  __shared__ T part[kOutWaves][NPART][kOutNodes];
   const int face = a.out_face, ax = face >> 1;
   const int PL = outflow_plane_size(face, a.nx, a.ny, a.nz);
   const int tid = static_cast<int>(threadIdx.x);
+  const int lane = tid % kOutNodes;
+  const int wave = tid / kOutNodes;
   // U from the partial sums, in the same order in every workgroup
   double U = 0.0;
   if (o.start == 0) {
@@ -241,121 +271,138 @@ __global__ void __launch_bounds__(kOutThreads) k_outflow_apply(OutflowArgs o) {
     if (!(U > 0.0)) U = 0.0;
     if (blockIdx.x == 0 && tid == 0) o.u[0] = U;
   }
-  const int p = static_cast<int>(blockIdx.x) * kOutThreads + tid;
-  if (p >= PL) return;
-  if (o.start == 2) {
-    // refresh (moment form, after a state was restored): C, E_B and the f
-    // moments of plane N from the plane buffers as they stand
-    if (!(a.flags & kFlagMoments)) return;
-    int xN, yN, zN;
-    plane_node(ax, plane_pos(face, 0, a), p, a, xN, yN, zN);
-    const Nbr nbN = neighbours<L, true>(xN, yN, zN, a);
-    if (solid_node<true>(nbN)) return;
-    const uint32_t nodeN = uint32_t(xN) + uint32_t(a.nx) * (uint32_t(yN) + uint32_t(a.ny) * uint32_t(zN));
-    const size_t P = static_cast<size_t>(PL);
-    const T* of = gptr<const T>(a.out_f);
-    const T* og = gptr<const T>(a.out_g);
-    T fm[4] = {T(0), T(0), T(0), T(0)};
-    for (int k = 1; k < Q; ++k) {
-      const T v = of[size_t(k - 1) * P + p];
-      fm[0] += v;
-      for (int d = 0; d < 3; ++d)
-        if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? v : -v;
-    }
-    T c[NC];
-    T rest = T(0);
-    for (int e = 0; e < NE; ++e) {
-      T m = T(0);
-      for (int k = 1; k < Q; ++k) m += og[(size_t(e) * Q + k) * P + p];
-      c[e] = og[size_t(e) * Q * P + p] + m;
-      rest += c[e];
-    }
-    c[NE] = T(1) - rest;
-    const DevParams<T>& Pp = *gptr<const DevParams<T>>(a.params);
-    vst<T, NE>(gptr<T>(a.conc) + size_t(nodeN) * NE, reinterpret_cast<const T(&)[NE]>(c));
-    gptr<T>(a.eb)[nodeN] = bulk_energy<NC, T>(c, Pp);
-    if (a.flags & kFlagFRecord) rec_store<S, 4, false>(a.fmom, nodeN * 4u, fm, T(S::vel_scale));
-    return;
-  }
-  int x, y, z;
-  plane_node(ax, plane_pos(face, o.start ? 0 : 1, a), p, a, x, y, z);
-  const Nbr nb = neighbours<L, true>(x, y, z, a);
-  const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
-  const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
-  const int open = FB ? FB->open : 0;
-  const T u = static_cast<T>(U);
-  const T den = T(1) + u;
+  const int p = static_cast<int>(blockIdx.x) * kOutNodes + lane;
+  const bool active = p < PL;
+  const size_t P = static_cast<size_t>(PL);
   T* of = gptr<T>(a.out_f);
   T* og = gptr<T>(a.out_g);
   T* gh = gptr<T>(a.out_ghost);
-  const size_t P = static_cast<size_t>(PL);
-  if (solid_node<true>(nb)) {
-    // a solid node of the plane (solid nodes continue straight through the
-    // outflow plane, so plane N-1 is solid here too): no fluid, and a
-    // stencil never reads its ghost (the solid continues beyond the face)
-    for (int k = 1; k < Q; ++k) of[size_t(k - 1) * P + p] = T(0);
-    for (int e = 0; e < NE; ++e)
-      for (int k = 0; k < Q; ++k) og[(size_t(e) * Q + k) * P + p] = T(0);
-    for (int e = 0; e <= NE; ++e) gh[size_t(e) * P + p] = T(0);
-    return;
-  }
-  // the f moments of the new plane-N populations (record form of f)
-  T fm[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
-    T* slot = of + size_t(k - 1) * P + p;
-    const T v = o.start ? q : (*slot + u * q) / den;
-    *slot = v;
-    fm[0] += v;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? v : -v;
-  }
-  // the new plane-N populations of g, and C as the reconstruction sums them
-  // (moving populations first, the rest population last)
-  T m[NE], r[NE];
+  // plane N's node (the boundary plane) and, for convecting, plane N-1's
+  int xN = 0, yN = 0, zN = 0;
+  if (active) plane_node(ax, plane_pos(face, 0, a), p, a, xN, yN, zN);
+  const uint32_t nodeN = uint32_t(xN) + uint32_t(a.nx) * (uint32_t(yN) + uint32_t(a.ny) * uint32_t(zN));
+  bool solid = false;
+  if (active) solid = solid_node<true>(neighbours<L, true>(xN, yN, zN, a));
+  const bool moments = (a.flags & kFlagMoments) != 0;
+  if (o.start == 2 && !moments) return;          // nothing to refresh
+  // this wave's directions: blend (start 0), capture (start 1) or only read
+  // back (start 2) their plane-N values, and sum them per node
+  T m[NE], r[NE], fm[4];
 #pragma unroll
   for (int e = 0; e < NE; ++e) m[e] = r[e] = T(0);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    T q[NE];
-    pull_g_all<L, NE, ST>(a, nb, node, k, FB, open, q);
+  for (int d = 0; d < 4; ++d) fm[d] = T(0);
+  if (active && !solid) {
+    int x, y, z;
+    plane_node(ax, plane_pos(face, o.start == 0 ? 1 : 0, a), p, a, x, y, z);
+    const Nbr nb = neighbours<L, true>(x, y, z, a);
+    const uint32_t node = uint32_t(x) + uint32_t(a.nx) * (uint32_t(y) + uint32_t(a.ny) * uint32_t(z));
+    const FaceBC<T>* FB = gptr<const FaceBC<T>>(a.faces);
+    const int open = FB ? FB->open : 0;
+    const T u = static_cast<T>(U);
+    const T den = T(1) + u;
+    for_wave(wave, [&](auto WC) {
+      constexpr int W = decltype(WC)::value;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      T* slot = og + (size_t(e) * Q + k) * P + p;
-      const T v = o.start ? q[e] : (*slot + u * q[e]) / den;
-      *slot = v;
-      if (k == 0) r[e] = v;
-      else m[e] += v;
-    }
+      for (int k = W; k < Q; k += kOutWaves) {
+        if (k >= 1) {
+          T* slot = of + size_t(k - 1) * P + p;
+          T v;
+          if (o.start == 2) {
+            v = *slot;
+          } else {
+            const T q = pull_f<L, ST>(a, nb, node, k, FB, open);
+            v = o.start ? q : (*slot + u * q) / den;
+            *slot = v;
+          }
+          fm[0] += v;
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (L::e[k][d] != 0) fm[1 + d] += (L::e[k][d] > 0) ? v : -v;
+        }
+        T q[NE];
+        if (o.start != 2) pull_g_all<L, NE, ST>(a, nb, node, k, FB, open, q);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          T* slot = og + (size_t(e) * Q + k) * P + p;
+          T v;
+          if (o.start == 2) {
+            v = *slot;
+          } else {
+            v = o.start ? q[e] : (*slot + u * q[e]) / den;
+            *slot = v;
+          }
+          if (k == 0) r[e] = v;
+          else m[e] += v;
+        }
+      }
+    });
+  } else if (active && o.start != 2) {
+    // a solid node of the plane (solid nodes continue straight through the
+    // outflow plane, so plane N-1 is solid here too): no fluid
+    for_wave(wave, [&](auto WC) {
+      constexpr int W = decltype(WC)::value;
+#pragma unroll
+      for (int k = W; k < Q; k += kOutWaves) {
+        if (k >= 1) of[size_t(k - 1) * P + p] = T(0);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) og[(size_t(e) * Q + k) * P + p] = T(0);
+      }
+    });
   }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) part[wave][e][lane] = m[e];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) part[wave][NE + d][lane] = fm[d];
+  __syncthreads();
+  if (wave != 0 || !active) return;
+  if (solid) {
+    // a stencil never reads a solid node's ghost (the solid continues beyond
+    // the face)
+    if (o.start != 2)
+      for (int e = 0; e <= NE; ++e) gh[size_t(e) * P + p] = T(0);
+    return;
+  }
+  // C as the reconstruction sums it: the moving populations, then the rest
   T c[NC];
   T rest = T(0);
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    c[e] = r[e] + m[e];
+    T mt = part[0][e][lane];
+#pragma unroll
+    for (int w = 1; w < kOutWaves; ++w) mt += part[w][e][lane];
+    c[e] = r[e] + mt;
     rest += c[e];
   }
   c[NE] = T(1) - rest;
   const DevParams<T>& Pp = *gptr<const DevParams<T>>(a.params);
   const T E = bulk_energy<NC, T>(c, Pp);
-  for (int e = 0; e < NE; ++e) {
-    T* slot = gh + size_t(e) * P + p;
-    *slot = o.start ? c[e] : (*slot + u * c[e]) / den;
+  if (o.start != 2) {
+    const T u = static_cast<T>(U);
+    const T den = T(1) + u;
+    for (int e = 0; e < NE; ++e) {
+      T* slot = gh + size_t(e) * P + p;
+      *slot = o.start ? c[e] : (*slot + u * c[e]) / den;
+    }
+    T* slot = gh + size_t(NE) * P + p;
+    *slot = o.start ? E : (*slot + u * E) / den;
   }
-  T* slot = gh + size_t(NE) * P + p;
-  *slot = o.start ? E : (*slot + u * E) / den;
-  if (a.flags & kFlagMoments) {
+  if (moments) {
     // In the moment form the next reconstruction leaves the boundary plane
     // to this kernel: C, E_B and (record form of f) the f moments of the new
     // plane-N populations, where that reconstruction writes its results
-    int xN, yN, zN;
-    plane_node(ax, plane_pos(face, 0, a), p, a, xN, yN, zN);
-    const uint32_t nodeN = uint32_t(xN) + uint32_t(a.nx) * (uint32_t(yN) + uint32_t(a.ny) * uint32_t(zN));
     vst<T, NE>(gptr<T>(a.conc) + size_t(nodeN) * NE, reinterpret_cast<const T(&)[NE]>(c));
     gptr<T>(a.eb)[nodeN] = E;
-    if (a.flags & kFlagFRecord) rec_store<S, 4, false>(a.fmom, nodeN * 4u, fm, T(S::vel_scale));
+    if (a.flags & kFlagFRecord) {
+      T ft[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        ft[d] = part[0][NE + d][lane];
+#pragma unroll
+        for (int w = 1; w < kOutWaves; ++w) ft[d] += part[w][NE + d][lane];
+      }
+      rec_store<S, 4, false>(a.fmom, nodeN * 4u, ft, T(S::vel_scale));
+    }
   }
 }
 
@@ -375,7 +422,7 @@ namespace {
 
 template <class L, int NC, int ST>
 hipError_t outflow_t(const OutflowArgs& o, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(o.blocks));
+  const dim3 grid(static_cast<unsigned>(o.blocks));   // kOutNodes plane nodes each
   if (o.start == 0) hipLaunchKernelGGL((k_outflow_mom<L, NC, ST>), grid, dim3(kOutThreads), 0, s, o);
   hipLaunchKernelGGL((k_outflow_apply<L, NC, ST>), grid, dim3(kOutThreads), 0, s, o);
   return hipGetLastError();
