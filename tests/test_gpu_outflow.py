@@ -14,7 +14,9 @@
   floor; its spread sets its bound).
 * The outflow state travels with nflbm_get_state / nflbm_set_state, and
   starting it in nflbm_set_outflow after nflbm_set_fields or in
-  nflbm_set_fields gives the same bits.
+  nflbm_set_fields gives the same bits; in the moment forms as well, where
+  plane N's reconstructed values are re-derived after a restore (also the
+  autotuner's).
 * FP32 and FP16S against the FP64 oracle on the pulse run, within their
   storage error.
 * Argument errors: an unwalled or too short axis, the face already open, an
@@ -170,6 +172,43 @@ def test_outflow_state_round_trip_and_start():
         sim.set_fields(w["C0"], v0)
         sim.set_outflow(out)
         sim.step(35)
+        c = sim.get_state()
+    assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("name,flags,form", [("channel_x", 0, ("moments", "populations")),
+                                             ("pulse", 0, ("moments", "records")),
+                                             ("d3_x", 0, ("moments", "records"))])
+def test_outflow_state_round_trip_moment_forms(name, flags, form, tmp_path):
+    """In the moment form the outflow kernel writes plane N's C, E_B and f
+    moments into arrays outside the state; restoring a state re-derives them
+    from the restored plane buffers, and so does the autotuner's restore, so
+    both continue bit for bit."""
+    w, faces, out, v0, _ = case(name)
+
+    def make():
+        sim = nf.Simulation.from_workload(w, precision=nf.FP64, flags=flags)
+        for face, (vb, Cb) in faces.items():
+            sim.set_open_face(face, vb, Cb)
+        sim.set_outflow(out)
+        sim.set_fields(w["C0"], v0)
+        return sim
+
+    with make() as sim:
+        assert (sim.storage_form(), sim.f_storage_form()) == form
+        sim.step(15)
+        saved = sim.get_state()
+        sim.step(20)
+        a = sim.get_state()
+        sim.step(7)                          # plane-N values of a later state
+        sim.set_state(saved)
+        sim.step(20)
+        b = sim.get_state()
+    assert np.array_equal(a, b)
+    with make() as sim:
+        sim.step(15)
+        sim.autotune(str(tmp_path / "tune.txt"))   # times steps, then restores
+        sim.step(20)
         c = sim.get_state()
     assert np.array_equal(a, c)
 
