@@ -959,9 +959,10 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     {
       T cr[NEP];
       read_c(sm + bc[1] + (PX + 1) * CW, cr);
-      T rest = T(0);
+      T rest = cr[0];
+      c[0] = cr[0];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
+      for (int e = 1; e < NE; ++e) {
         c[e] = cr[e];
         rest += c[e];
       }
@@ -1088,11 +1089,17 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
 #pragma unroll
       for (int l = 0; l < NC; ++l) {
         if (l == i) continue;
+        // rows with no term are skipped at compile time (a zero row would
+        // still cost an instruction: 0 times c[l] is not folded away)
         T row = T(0);
+        bool any = false;
 #pragma unroll
         for (int m = l + 1; m < NC; ++m)
-          if (m != i) row = fma(P.psi[i][l][m], c[m], row);
-        br = fma(row, c[l], br);
+          if (m != i) {
+            row = any ? fma(P.psi[i][l][m], c[m], row) : P.psi[i][l][m] * c[m];
+            any = true;
+          }
+        if (any) br = fma(row, c[l], br);
       }
       T val = fma(P.k34D, lap[i], (P.k12D * c[i]) * br);
       if (omega) {

@@ -11,8 +11,13 @@ the default launch configuration.
   the full lattice.  The samples sit on tile, z-run and lattice
   boundaries of the launch.  FP64: C, v and P to 1e-12 of their scale
   (measured 2e-13 on v and P, O(1e-7) quantities); FP32 storage: C to
-  1e-6 absolute; FP16S: C to 1e-6 absolute and v to 1e-2 of its scale
-  (measured 3e-4: binary16 f).
+  1e-6 absolute (measured 4.6e-8); FP16S: v to 1e-2 of its scale (measured
+  3.6e-4: binary16 f records) and C to 3e-6 absolute.  The FP16S C error
+  comes from the binary16 mu~ records (11 significant bits): each step's C
+  takes m (1 - w_0) mu~ through them, so a half-ulp of mu~ per step adds up
+  over the three steps; measured 7.3e-7, and 1.06e-6 with a build that
+  only changed the rounding order of the stencil's constant factors, so the
+  bound leaves a factor of three over the larger.
 * Properties that hold at any size, FP32, 300 steps: the absent component
   is exactly 0.0 everywhere, sum_i C_i = 1 and the mass of every component
   hold to float rounding.
@@ -101,8 +106,8 @@ def test_full_size_sampled_nodes(workload, oracle_samples, prec):
     elif prec == nf.FP32:
         assert np.abs(got_C - ref_C).max() <= 1e-6
     else:
-        # binary16 f: v and P carry its rounding, C (float records) does not
-        assert np.abs(got_C - ref_C).max() <= 1e-6
+        # binary16 records: v and P carry the rounding of f's, C that of mu~
+        assert np.abs(got_C - ref_C).max() <= 3e-6
         assert np.abs(got_v - ref_v).max() <= 1e-2 * np.abs(ref_v).max()
     assert np.all(got_C[:, 4] == 0.0)
 
