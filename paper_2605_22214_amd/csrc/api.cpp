@@ -343,8 +343,15 @@ int choose_launch(nflbm_sim* s) {
   int l = s->nx <= 16 ? 4 : 6;
   if (l == 6 && !fits(l)) l = 4;
   if (!fits(l)) return -1;
+  // The update takes 16-wide tiles where x is walled in D3Q19: with 64-wide
+  // tiles half of its wavefronts hold a node next to an x wall and run that
+  // node's direction-by-direction stencil beside the pair stencil, against
+  // an eighth with 16-wide ones (update 0.110 -> 0.100 ms with walls on x at
+  // 256 x 128 x 128; the reconstruction measured slower that way and keeps
+  // 64-wide tiles).
+  const int lu = (l == 6 && s->wall[0] && s->lat == NFLBM_D3Q19) ? 4 : l;
   const bool f64 = s->store == NFLBM_FP64;
-  if (!apply_launch(s, l, zchunk_for(s, l, f64 ? 1024 : 8192))) return -1;
+  if (!apply_launch(s, lu, zchunk_for(s, lu, f64 ? 1024 : 8192))) return -1;
   return apply_conc_launch(s, l, zchunk_for(s, l, (f64 || s->gform) ? 1024 : 4096)) ? 0 : -1;
 }
 
