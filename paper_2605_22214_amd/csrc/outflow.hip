@@ -15,23 +15,25 @@
 // buffer of their own (out_f, out_g, every direction including the rest one),
 // which the reconstruction and the update read at plane-N nodes in place of
 // their pulls, and the update's LDS fill reads the ghost buffer beyond the
-// face.  Per step, after the update (on the state it wrote):
-//   k_outflow_mom    one thread per node of plane N-1: its normal momentum
-//                    after streaming, gathered with the pull rules of the
-//                    update; one FP64 sum per workgroup;
+// face.  Per step, after the update (on the state it wrote), both kernels
+// with 64 plane nodes per workgroup and each node's directions split over
+// the workgroup's four wavefronts:
+//   k_outflow_mom    the normal momentum of plane N-1 after streaming,
+//                    gathered with the pull rules of the update; one FP64
+//                    sum per workgroup;
 //   k_outflow_apply  every workgroup sums those partial sums in one fixed
-//                    order (so all of them hold the same U), then one thread
-//                    per plane node blends the pulled plane N-1 populations
-//                    into the plane buffer and convects the ghosts.
+//                    order (so all of them hold the same U), then blends the
+//                    pulled plane N-1 populations into the plane buffer and
+//                    convects the ghosts.
 // With start = 1 the apply kernel instead captures plane N of the current
 // state (q(N, 0), ghosts C(N, 0) and E_B(N, 0)); with start = 2 it only
 // re-derives plane N's C, E_B and f moments from the buffers (after a state
 // is restored).  In the moment form the reconstruction leaves the boundary
-// plane to this kernel, which writes those where the reconstruction writes.  Solid nodes continue
-// straight through the outflow plane: U is the mean over the fluid nodes of
-// plane N-1, and solid plane nodes keep zeros.  In the moment form of g
-// (and the record form of f) the pulled populations are formed from the
-// source nodes' records, as the reconstruction forms them.
+// plane to this kernel, which writes those where the reconstruction writes.
+// Solid nodes continue straight through the outflow plane: U is the mean
+// over the fluid nodes of plane N-1, and solid plane nodes keep zeros.  In
+// the moment form of g (and the record form of f) the pulled populations are
+// formed from the source nodes' records, as the reconstruction forms them.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
