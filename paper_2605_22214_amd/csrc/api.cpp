@@ -328,7 +328,10 @@ int zchunk_for(const nflbm_sim* s, int l, long long target) {
 
 // Default shapes.  Update: tiles 64 x 4 (16 x 16 when nx <= 16 or when the
 // wider LDS window does not fit), in 3-D a z run per workgroup that leaves
-// about 8192 workgroups (1024 in FP64, where longer runs measured faster).
+// about 8192 workgroups (4096 in the float record form of f, whose update
+// prefetches across the run: runs of 16 against 8 planes measured 0.303
+// against 0.314 ms at 256^3; 1024 in FP64, where longer runs measured
+// faster).
 // Reconstruction: the update's tile width; in the moment form's 3-D z march a
 // run that leaves about 1024 workgroups (each run re-loads two planes beyond
 // its ends, so long runs pay off as long as the CUs stay busy: 0.255 ms at
@@ -351,7 +354,7 @@ int choose_launch(nflbm_sim* s) {
   // 64-wide tiles).
   const int lu = (l == 6 && s->wall[0] && s->lat == NFLBM_D3Q19) ? 4 : l;
   const bool f64 = s->store == NFLBM_FP64;
-  if (!apply_launch(s, lu, zchunk_for(s, lu, f64 ? 1024 : 8192))) return -1;
+  if (!apply_launch(s, lu, zchunk_for(s, lu, f64 ? 1024 : (s->fform ? 4096 : 8192)))) return -1;
   return apply_conc_launch(s, l, zchunk_for(s, l, (f64 || s->gform) ? 1024 : 4096)) ? 0 : -1;
 }
 
