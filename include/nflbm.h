@@ -104,7 +104,9 @@ enum {
  * in magnitude per entry here), and the library allocates a scratch array of
  * N values per node in the compute precision for the potentials.  The MU
  * field still reports the constant-alpha flux potential, which this variant
- * does not use.  Batches do not take members with this flag (NFLBM_ENOTSUP). */
+ * does not use.  In a batch such members add their potential and source
+ * launches between and after the batch's two kernels, and every member of
+ * that batch keeps g as populations. */
 
 /* Storage of g.  With every tau_g = 1 a post-collision population of g is
  * its equilibrium, C_i s_k(v) - w_k m mu~_i (Eqs. glbe, geq), so by default
@@ -466,8 +468,10 @@ int nflbm_autotune(nflbm_sim *sim, const char *cache_path);
  * nflbm_sim owned by the batch: nflbm_batch_member returns it for set_fields,
  * get_field, diagnostics, state I/O, solid nodes, open faces, the outflow
  * face or stepping on its own (never nflbm_destroy it).  A member with an
- * outflow face adds its two outflow launches after each batch step.  All
- * members run on the batch's stream.
+ * outflow face adds its two outflow launches after each batch step; one with
+ * the concentration-dependent mobility its potential launch between the
+ * batch's two kernels and its source launch after them.  All members run on
+ * the batch's stream.
  * ---------------------------------------------------------------------- */
 typedef struct nflbm_batch nflbm_batch; /* opaque */
 

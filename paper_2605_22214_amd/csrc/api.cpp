@@ -805,7 +805,30 @@ hipError_t launch_half(nflbm_batch* b, int half) {
   bl.walls = b->walls;
   bl.moments = b->members[0]->gform;
   bl.frecord = b->members[0]->fform;
-  hipError_t e = launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+  bool mob = false;
+  for (const nflbm_sim* m : b->members) mob = mob || m->c2c2;
+  hipError_t e = hipSuccess;
+  if (!mob) {
+    e = launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+  } else {
+    // members with the concentration-dependent mobility (Appendix C): their
+    // potentials between the batch's reconstruction and update, their source
+    // term after it, each on the member's arguments of this half
+    bl.phase = 1;
+    e = launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+    for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
+      const nflbm_sim* m = b->members[i];
+      if (m->c2c2)
+        e = launch_mob_potentials(m->lat, m->N, m->store, mob_args(m, make_args(m, b->key[i] ^ half)), b->stream);
+    }
+    bl.phase = 2;
+    if (e == hipSuccess) e = launch_batch_step(b->lat, b->N, b->store, bl, b->stream);
+    for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
+      const nflbm_sim* m = b->members[i];
+      if (m->c2c2)
+        e = launch_mob_source(m->lat, m->N, m->store, mob_args(m, make_args(m, b->key[i] ^ half)), b->stream);
+    }
+  }
   // members with a convective outflow face: Eq. convect on the state this
   // half wrote (parity key ^ 1 after half 0, key after half 1)
   for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i) {
@@ -2109,14 +2132,11 @@ int nflbm_batch_create(const nflbm_config* cfgs, int count, nflbm_batch** out) {
         cfgs[i].precision != cfgs[0].precision)
       return bfail(nullptr, NFLBM_EINVAL, "batch members must share lattice, ncomp and precision");
   // one storage form of g for every member: populations if any member needs
-  // them (some tau_g != 1, or asked for)
-  for (int i = 0; i < count; ++i)
-    if (cfgs[i].flags & NFLBM_FLAG_C2C2_MOBILITY)
-      return bfail(nullptr, NFLBM_ENOTSUP, "batch members cannot use the concentration-dependent mobility");
+  // them (some tau_g != 1, the concentration-dependent mobility, or asked for)
   std::vector<nflbm_config> cc(cfgs, cfgs + count);
   bool pop = false;
   for (const auto& c : cc) {
-    if (c.flags & NFLBM_FLAG_G_POPULATIONS) pop = true;
+    if (c.flags & (NFLBM_FLAG_G_POPULATIONS | NFLBM_FLAG_C2C2_MOBILITY)) pop = true;
     for (int i = 0; c.tau_g && i < c.ncomp; ++i)
       if (c.tau_g[i] != 1.0) pop = true;
   }

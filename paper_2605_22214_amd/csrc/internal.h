@@ -184,6 +184,8 @@ struct BatchLaunch {
                                       // reconstruction then runs over the
                                       // update's tiles
   int frecord;                        // members keep f as node records
+  int phase;                          // 0 both kernels, 1 the reconstruction
+                                      // only, 2 the update only
 };
 
 // Arguments of the two kernels of the concentration-dependent mobility

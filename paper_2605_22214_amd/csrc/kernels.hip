@@ -1998,8 +1998,10 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
   const auto* P = static_cast<const DevParams<TT<ST>>*>(b.params);
   const dim3 blk(256);
   const bool fr = b.moments && b.frecord;
-  hipError_t e;
-  if (b.moments) {
+  hipError_t e = hipSuccess;
+  if (b.phase == 2) {
+    // the update only
+  } else if (b.moments) {
     const dim3 grid(b.blocks_update);
     const int nb = b.blocks_update;
     const size_t lds = conc_m_lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2, fr);
@@ -2026,7 +2028,7 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t s) {
       hipLaunchKernelGGL((k_conc_batch<L, NC - 1, ST, false>), dim3(b.blocks_conc), blk, 0, s, b.args, P, b.work_conc);
   }
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || b.phase == 1) return e;
   const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, b.tx_log2);
   const dim3 grid(b.blocks_update);
   const int nb = b.blocks_update;

@@ -9,6 +9,8 @@
   differences are written to mobility.json in the results directory.
 * Fig. 3(d): diffusive coarsening of the N = 4, 400^2 mixture with the
   constant alpha and with alpha = C_i^2 C_j^2 (m* = 10); L(t) of both.
+* Batch members with the flag (beside one without it) equal the members
+  stepped alone, bit for bit, launching and replaying graphs.
 """
 import json
 import os
@@ -131,3 +133,37 @@ def test_storage_precisions_against_fp64():
     assert out["fp16s"]["max_abs_dC"] < 1e-2
     assert out["fp32"]["mass_rel_drift"] < 1e-6
 
+
+
+@pytest.mark.parametrize("mode", ["launch", "graph"])
+def test_batch_members_with_c2c2_equal_standalone(mode):
+    """Members with the concentration-dependent mobility in a batch, beside
+    one without it (which then keeps g as populations too), end bit for bit
+    where they end stepped alone: the batch runs their potential and source
+    kernels between and after its own two on each member's arguments."""
+    ws, flags = [], []
+    for k, (shape, walls, c2c2) in enumerate((((32, 24, 1), (False, True, False), True),
+                                              ((40, 40, 1), (False, False, False), True),
+                                              ((28, 20, 1), (True, False, False), False))):
+        w = W.noise("D2Q9", shape, 3, amp=0.05, seed=30 + k, sigma=0.005)
+        w["walls"] = walls
+        if c2c2:
+            w["m"] = M_STAR            # under the flag, m is m*
+        ws.append(w)
+        flags.append(nf.FLAG_C2C2_MOBILITY if c2c2 else nf.FLAG_G_POPULATIONS)
+    steps = 21
+    ref = []
+    for w, fl in zip(ws, flags):
+        with nf.Simulation.from_workload(w, precision=nf.FP64, flags=fl) as s:
+            s.set_fields(w["C0"])
+            s.step(steps)
+            ref.append(s.get_state())
+    probs = [nf._Problem.from_workload(w, precision=nf.FP64, flags=fl) for w, fl in zip(ws, flags)]
+    with nf.Batch(probs) as b:
+        b.set_launch(graph_steps=4)
+        for i, w in enumerate(ws):
+            b.members[i].set_fields(w["C0"])
+        b.step(steps, mode=mode)
+        got = [m.get_state() for m in b.members]
+    for i in range(len(ws)):
+        assert np.array_equal(got[i], ref[i]), i
