@@ -419,7 +419,13 @@ int nflbm_coefficients(int N, const double *sigma, double D, double *alpha, doub
  * planes of concentrations in LDS.  A value <= 0 keeps the current setting.
  * EINVAL if the shape is invalid or its LDS window exceeds the device limit.
  * Results do not depend on the shape.  nflbm_get_launch also reports the
- * device's LDS bytes per workgroup (any output pointer may be NULL). */
+ * device's LDS bytes per workgroup (any output pointer may be NULL).  The
+ * default shape (chosen at nflbm_create, and again by nflbm_set_solid until
+ * a shape is set here, by nflbm_set_conc_launch or by nflbm_autotune)
+ * depends on the lattice, the walls, the solid nodes and the precision.
+ * With walls on x alone and no solid nodes, both kernels run the first and
+ * last tile columns in their wall variant and the columns between in the
+ * periodic one, as two launches. */
 int nflbm_set_launch(nflbm_sim *sim, int tx_log2, int zchunk);
 int nflbm_get_launch(nflbm_sim *sim, int *tx_log2, int *zchunk, int *lds_limit);
 /* The same for the reconstruction kernel (zeroth moment of g, Sec. III B),

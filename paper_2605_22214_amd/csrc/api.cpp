@@ -117,6 +117,8 @@ struct nflbm_sim {
   // kernels measured fastest with different tiles)
   int tx_log2 = 6, zchunk = 1, tiles_x = 1, tiles_y = 1, chunks_z = 1;
   int ctx_log2 = 6, czchunk = 1, ctiles_x = 1, ctiles_y = 1, cchunks_z = 1;
+  // a shape set by the caller or the autotuner, kept when solid nodes come or go
+  bool shape_chosen = false;
   size_t lds_max = 65536;
   int step_flags = 0;
   int device = 0;        // the HIP device current at nflbm_create
@@ -337,8 +339,8 @@ int zchunk_for(const nflbm_sim* s, int l, long long target) {
 // its ends, so long runs pay off as long as the CUs stay busy: 0.255 ms at
 // 256^3 in FP32 against 0.262 ms for 8192 workgroups); otherwise about 4096
 // (1024 in FP64).
-int choose_launch(nflbm_sim* s) {
-  s->lds_max = device_lds_max();
+// Uses the LDS limit already in s->lds_max.
+int default_launch(nflbm_sim* s) {
   auto fits = [&](int t) {
     return update_lds_bytes(s->lat, s->N, s->store, t) <= s->lds_max &&
            (!s->gform || conc_m_lds_bytes(s->lat, s->N, s->store, t, s->fform) <= s->lds_max);
@@ -346,16 +348,33 @@ int choose_launch(nflbm_sim* s) {
   int l = s->nx <= 16 ? 4 : 6;
   if (l == 6 && !fits(l)) l = 4;
   if (!fits(l)) return -1;
-  // The update takes 16-wide tiles where x is walled in D3Q19: with 64-wide
-  // tiles half of its wavefronts hold a node next to an x wall and run that
-  // node's direction-by-direction stencil beside the pair stencil, against
-  // an eighth with 16-wide ones (update 0.110 -> 0.100 ms with walls on x at
-  // 256 x 128 x 128; the reconstruction measured slower that way and keeps
-  // 64-wide tiles).
-  const int lu = (l == 6 && s->wall[0] && s->lat == NFLBM_D3Q19) ? 4 : l;
+  // Walls on x alone and no solid nodes, in D3Q19 with at least three
+  // 64-wide tile columns: both kernels run their edge columns in the wall
+  // variant and the columns between in the periodic one (split_x_walls), two
+  // launches that each need workgroups of their own; in float both take
+  // 64-wide tiles and about 2048 workgroups over the two launches (runs of 8
+  // planes at 256 x 128 x 128: reconstruction 0.171 -> 0.125 ms against the
+  // runs of 16 that 1024 workgroups give, update 0.093 -> 0.087 ms against
+  // 16-wide tiles).
+  const bool split = s->lat == NFLBM_D3Q19 && s->wall[0] && !s->wall[1] && !s->wall[2] && !s->bb &&
+                     (s->nx + 63) / 64 >= 3;
+  // Otherwise the update takes 16-wide tiles where x is walled in D3Q19:
+  // with 64-wide tiles half of its wavefronts hold a node next to an x wall
+  // and run that node's direction-by-direction stencil beside the pair
+  // stencil, against an eighth with 16-wide ones (update 0.110 -> 0.100 ms
+  // with walls on x at 256 x 128 x 128; the reconstruction measured slower
+  // that way and keeps 64-wide tiles).
+  const int lu = (l == 6 && s->wall[0] && s->lat == NFLBM_D3Q19 && !split) ? 4 : l;
   const bool f64 = s->store == NFLBM_FP64;
-  if (!apply_launch(s, lu, zchunk_for(s, lu, f64 ? 1024 : (s->fform ? 4096 : 8192)))) return -1;
-  return apply_conc_launch(s, l, zchunk_for(s, l, (f64 || s->gform) ? 1024 : 4096)) ? 0 : -1;
+  const long long tu = f64 ? 1024 : split ? 2048 : (s->fform ? 4096 : 8192);
+  const long long tc = f64 ? 1024 : split ? 2048 : (s->gform ? 1024 : 4096);
+  if (!apply_launch(s, lu, zchunk_for(s, lu, tu))) return -1;
+  return apply_conc_launch(s, l, zchunk_for(s, l, tc)) ? 0 : -1;
+}
+
+int choose_launch(nflbm_sim* s) {
+  s->lds_max = device_lds_max();
+  return default_launch(s);
 }
 
 // The step arguments with the reconstruction's launch shape.
@@ -415,6 +434,7 @@ StepArgs make_args(const nflbm_sim* s, int src) {
   a.tiles_x = s->tiles_x;
   a.tiles_y = s->tiles_y;
   a.chunks_z = s->chunks_z;
+  a.tile_xstep = 1;
   a.flags = s->step_flags;
   if (s->gform && s->f_local) a.flags |= kFlagFLocal;
   return a;
@@ -1528,6 +1548,7 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
     sim->bb = nullptr;
     sim->solid_host.clear();
     sim->out_fluid = fluid_out;
+    if (!sim->shape_chosen) (void)default_launch(sim);
     ++sim->boundary_version;
     return NFLBM_OK;
   }
@@ -1554,6 +1575,8 @@ int nflbm_set_solid(nflbm_sim* sim, const unsigned char* solid) {
     if (rc) return rc;
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
   }
+  // the default launch shape depends on whether solid nodes are present
+  if (!sim->shape_chosen) (void)default_launch(sim);
   ++sim->boundary_version;
   return NFLBM_OK;
 }
@@ -2010,6 +2033,7 @@ int nflbm_set_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
   const int l = tx_log2 > 0 ? tx_log2 : sim->tx_log2;
   const int zc = zchunk > 0 ? zchunk : sim->zchunk;
   if (!apply_launch(sim, l, zc)) return fail(sim, NFLBM_EINVAL, "invalid launch shape or LDS too large");
+  sim->shape_chosen = true;
   return NFLBM_OK;
 }
 
@@ -2018,6 +2042,7 @@ int nflbm_set_conc_launch(nflbm_sim* sim, int tx_log2, int zchunk) {
   const int l = tx_log2 > 0 ? tx_log2 : sim->ctx_log2;
   const int zc = zchunk > 0 ? zchunk : sim->czchunk;
   if (!apply_conc_launch(sim, l, zc)) return fail(sim, NFLBM_EINVAL, "invalid launch shape or LDS too large");
+  sim->shape_chosen = true;
   return NFLBM_OK;
 }
 
@@ -2073,7 +2098,10 @@ int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
   const std::string key = sim_key(sim);
   std::vector<int> best = {sim->tx_log2, sim->zchunk, sim->ctx_log2, sim->czchunk};
   if (cache_lookup(cache_path, key, &best)) {
-    if (apply_launch(sim, best[0], best[1]) && apply_conc_launch(sim, best[2], best[3])) return NFLBM_OK;
+    if (apply_launch(sim, best[0], best[1]) && apply_conc_launch(sim, best[2], best[3])) {
+      sim->shape_chosen = true;
+      return NFLBM_OK;
+    }
   }
   std::vector<std::pair<int, int>> cands;
   for (int l : {4, 6}) {
@@ -2120,6 +2148,7 @@ int nflbm_autotune(nflbm_sim* sim, const char* cache_path) {
   if (!apply_conc_launch(sim, best[2], best[3])) (void)apply_conc_launch(sim, keep[2], keep[3]);
   if (rc != NFLBM_OK) return rc;
   if (rc2 != NFLBM_OK) return rc2;
+  sim->shape_chosen = true;
   cache_store(cache_path, key, best);
   return NFLBM_OK;
 }

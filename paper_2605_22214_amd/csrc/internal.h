@@ -152,6 +152,9 @@ struct StepArgs {
   int tx_log2;                        // tile width TX = 1 << tx_log2, TY = 256 / TX
   int zchunk;                         // planes per workgroup (D3Q19)
   int tiles_x, tiles_y, chunks_z;
+  // tile column of launch column c (c < tiles_x): tile_x0 + c * tile_xstep,
+  // so that one launch can cover a subset of the lattice's tile columns
+  int tile_x0, tile_xstep;
   int flags;
 };
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ void conc_tile(const StepArgs& a,
   const DevParams<T>& P = *gptr<const DevParams<T>>(Pp);
   const int TX = 1 << a.tx_log2;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> a.tx_log2;
-  const int tile_x = b % a.tiles_x;
+  const int tile_x = a.tile_x0 + (b % a.tiles_x) * a.tile_xstep;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
   const int z = b / a.tiles_y;
@@ -218,7 +218,7 @@ __device__ __forceinline__ void conc_tile_m(const StepArgs& a,
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> TXL;
-  const int tile_x = b % a.tiles_x;
+  const int tile_x = a.tile_x0 + (b % a.tiles_x) * a.tile_xstep;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
   const int chunk = b / a.tiles_y;
@@ -752,7 +752,7 @@ __device__ __forceinline__ void update_tile(const StepArgs& a,
     }
   };
 
-  const int tile_x = b % a.tiles_x;
+  const int tile_x = a.tile_x0 + (b % a.tiles_x) * a.tile_xstep;
   b /= a.tiles_x;
   const int tile_y = b % a.tiles_y;
   const int chunk = b / a.tiles_y;
@@ -1854,6 +1854,27 @@ KernelSet& kernel_set(int store, int lat, int nc);
 
 inline bool any_wall(const StepArgs& a) { return a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr; }
 inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
+// With walls on x only and no solid nodes, a node meets a wall face (in its
+// pulls, its stencil or the open-face and outflow rules of that face) only
+// at x = 0 and x = nx - 1, in the first and last tile columns; every other
+// tile and its one-node halo lie inside the lattice.  The columns between
+// them run the periodic variant,
+// whose arithmetic at a node away from walls is the wall variant's (pair
+// stencil, pulls in the same order): `inner` covers them and `edges` the two
+// edge columns.  False where that does not apply (other walls, solids, fewer
+// than three columns, or a launch already restricted to some columns).
+inline bool split_x_walls(const StepArgs& a, StepArgs& inner, StepArgs& edges) {
+  if (!a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr) return false;
+  if (a.tiles_x < 3 || a.tile_x0 != 0 || a.tile_xstep != 1) return false;
+  inner = a;
+  inner.wall_x = 0;      // its tiles and their halos lie strictly inside x
+  inner.tile_x0 = 1;
+  inner.tiles_x = a.tiles_x - 2;
+  edges = a;
+  edges.tile_xstep = a.tiles_x - 1;
+  edges.tiles_x = 2;
+  return true;
+}
 // storage form of g and f as the update's GM parameter (FP16S keeps its
 // binary16 populations of f, so it has no record form)
 template <int ST>
@@ -1875,6 +1896,13 @@ hipError_t launch_update_t(const StepArgs& a0, bool fields, hipStream_t s) {
     const size_t lds = lds_bytes_for<ST>(L::DIM == 3 ? 1 : 0, NC, 4);
     hipLaunchKernelGGL((k_update<L, NC, ST, kModeFields, true, 4, false>), dim3(blocks), dim3(256), lds, s, a, P);
     return hipGetLastError();
+  }
+  {
+    StepArgs inner, edges;
+    if (split_x_walls(a0, inner, edges)) {
+      hipError_t e = launch_update_t<L, NC, ST>(edges, false, s);
+      return e != hipSuccess ? e : launch_update_t<L, NC, ST>(inner, false, s);
+    }
   }
   const StepArgs& a = a0;
   const dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z);
@@ -1945,6 +1973,13 @@ hipError_t launch_init_t(const InitArgs& ia, hipStream_t s) {
 
 template <class L, int NC, int ST>
 hipError_t launch_conc_t(const StepArgs& a, hipStream_t s) {
+  {
+    StepArgs inner, edges;
+    if (split_x_walls(a, inner, edges)) {
+      hipError_t e = launch_conc_t<L, NC, ST>(edges, s);
+      return e != hipSuccess ? e : launch_conc_t<L, NC, ST>(inner, s);
+    }
+  }
   const auto* P = (const DevParams<TT<ST>>*)(a.params);
   const bool w_ = any_wall(a);
   if (moments(a)) {
