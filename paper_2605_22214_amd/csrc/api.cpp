@@ -348,27 +348,22 @@ int default_launch(nflbm_sim* s) {
   int l = s->nx <= 16 ? 4 : 6;
   if (l == 6 && !fits(l)) l = 4;
   if (!fits(l)) return -1;
-  // Walls on x alone and no solid nodes, in D3Q19 with at least three
-  // 64-wide tile columns: both kernels run their edge columns in the wall
-  // variant and the columns between in the periodic one (split_x_walls), two
-  // launches that each need workgroups of their own; in float both take
-  // 64-wide tiles and about 2048 workgroups over the two launches (runs of 8
-  // planes at 256 x 128 x 128: reconstruction 0.171 -> 0.125 ms against the
-  // runs of 16 that 1024 workgroups give, update 0.093 -> 0.087 ms against
-  // 16-wide tiles).
-  const bool split = s->lat == NFLBM_D3Q19 && s->wall[0] && !s->wall[1] && !s->wall[2] && !s->bb &&
-                     (s->nx + 63) / 64 >= 3;
-  // Otherwise the update takes 16-wide tiles where x is walled in D3Q19:
-  // with 64-wide tiles half of its wavefronts hold a node next to an x wall
-  // and run that node's direction-by-direction stencil beside the pair
-  // stencil, against an eighth with 16-wide ones (update 0.110 -> 0.100 ms
-  // with walls on x at 256 x 128 x 128; the reconstruction measured slower
-  // that way and keeps 64-wide tiles).
-  const int lu = (l == 6 && s->wall[0] && s->lat == NFLBM_D3Q19 && !split) ? 4 : l;
+  // Walls on x in D3Q19, in float: the update's z runs leave about 2048
+  // workgroups (runs of 8 planes at 256 x 128 x 128, 64-wide tiles: inlet +
+  // outflow 0.093 -> 0.087 ms and solid posts 0.116 -> 0.111 ms against the
+  // 16 x 16 tiles with runs of 4 taken before the wall variants prefetched).
+  // With walls on x alone and no solid nodes, and at least three 64-wide tile
+  // columns, both kernels run their edge columns in the wall variant and the
+  // columns between in the periodic one (split_x_walls), two launches that
+  // each need workgroups of their own: the reconstruction's runs then also
+  // leave about 2048 workgroups over the two (0.171 -> 0.125 ms against the
+  // runs of 16 that 1024 give).
+  const bool xw = s->lat == NFLBM_D3Q19 && s->wall[0];
+  const bool split = xw && !s->wall[1] && !s->wall[2] && !s->bb && (s->nx + 63) / 64 >= 3;
   const bool f64 = s->store == NFLBM_FP64;
-  const long long tu = f64 ? 1024 : split ? 2048 : (s->fform ? 4096 : 8192);
+  const long long tu = f64 ? 1024 : xw ? 2048 : (s->fform ? 4096 : 8192);
   const long long tc = f64 ? 1024 : split ? 2048 : (s->gform ? 1024 : 4096);
-  if (!apply_launch(s, lu, zchunk_for(s, lu, tu))) return -1;
+  if (!apply_launch(s, l, zchunk_for(s, l, tu))) return -1;
   return apply_conc_launch(s, l, zchunk_for(s, l, tc)) ? 0 : -1;
 }
 

@@ -128,19 +128,20 @@ def test_split_equals_unsplit_bitwise(prec, flags):
 
 
 def test_default_shape_follows_the_geometry():
-    """The split takes 64-wide tiles in both kernels; solid nodes end the split
-    and the update returns to 16-wide tiles, until a shape is set by hand."""
-    w = W.noise("D3Q19", (200, 16, 8), 3, seed=15)
+    """While the split applies, the reconstruction's z runs leave about 2048
+    workgroups over its two launches (runs of 4 planes here) and otherwise
+    about 1024 (runs of 8): solid nodes end the split and the default shape
+    is chosen again, until a shape is set by hand."""
+    w = W.noise("D3Q19", (200, 64, 128), 3, seed=15)
     w["walls"] = (True, False, False)
-    post = np.zeros((8, 16, 200), dtype=bool)
+    post = np.zeros((128, 64, 200), dtype=bool)
     post[:, 4:8, 40:48] = True
     with nf.Simulation.from_workload(w, precision=nf.FP32) as sim:
-        assert sim.get_launch()[0] == 6 and sim.get_conc_launch()[0] == 6
+        assert sim.get_launch()[:2] == (6, 4) and sim.get_conc_launch() == (6, 4)
         sim.set_solid(post)
-        assert sim.get_launch()[0] == 4 and sim.get_conc_launch()[0] == 6
+        assert sim.get_launch()[:2] == (6, 4) and sim.get_conc_launch() == (6, 8)
         sim.set_solid(None)
-        assert sim.get_launch()[0] == 6
+        assert sim.get_conc_launch() == (6, 4)
         sim.set_launch(4, 2)
         sim.set_solid(post)
-        sim.set_solid(None)
-        assert sim.get_launch()[:2] == (4, 2)
+        assert sim.get_launch()[:2] == (4, 2) and sim.get_conc_launch() == (6, 4)
