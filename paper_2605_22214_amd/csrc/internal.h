@@ -209,7 +209,7 @@ struct MobArgs {
 // directions: a plane has few nodes, and the gathers across the face need
 // the parallelism.
 constexpr int kOutNodes = 64;
-constexpr int kOutThreads = 256;
+constexpr int kOutThreads = 512;
 struct OutflowArgs {
   StepArgs sa;
   double* partial;                    // [blocks]

@@ -17,7 +17,8 @@
 // their pulls, and the update's LDS fill reads the ghost buffer beyond the
 // face.  Per step, after the update (on the state it wrote), both kernels
 // with 64 plane nodes per workgroup and each node's directions split over
-// the workgroup's four wavefronts:
+// the workgroup's eight wavefronts (two per SIMD, so that the gathers across
+// the face overlap):
 //   k_outflow_mom    the normal momentum of plane N-1 after streaming,
 //                    gathered with the pull rules of the update; one FP64
 //                    sum per workgroup;
@@ -193,12 +194,16 @@ constexpr int kOutWaves = kOutThreads / kOutNodes;
 // so that a wave's direction loop has compile-time directions.
 template <class F>
 __device__ __forceinline__ void for_wave(int w, F&& f) {
-  static_assert(kOutWaves == 4, "four direction groups per workgroup");
+  static_assert(kOutWaves == 8, "eight direction groups per workgroup");
   switch (w) {
     case 0: f(std::integral_constant<int, 0>{}); break;
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
-    default: f(std::integral_constant<int, 3>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
   }
 }
 
