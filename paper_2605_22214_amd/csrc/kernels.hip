@@ -1858,11 +1858,11 @@ inline bool moments(const StepArgs& a) { return (a.flags & kFlagMoments) != 0; }
 // pulls, its stencil or the open-face and outflow rules of that face) only
 // at x = 0 and x = nx - 1, in the first and last tile columns; every other
 // tile and its one-node halo lie inside the lattice.  The columns between
-// them run the periodic variant,
-// whose arithmetic at a node away from walls is the wall variant's (pair
-// stencil, pulls in the same order): `inner` covers them and `edges` the two
-// edge columns.  False where that does not apply (other walls, solids, fewer
-// than three columns, or a launch already restricted to some columns).
+// them run the periodic variant, whose arithmetic at a node away from walls
+// is the wall variant's (pair stencil, pulls in the same order): `inner`
+// covers them and `edges` the two edge columns.  False where that does not
+// apply (other walls, solids, fewer than three columns, or a launch already
+// restricted to some columns).
 inline bool split_x_walls(const StepArgs& a, StepArgs& inner, StepArgs& edges) {
   if (!a.wall_x || a.wall_y || a.wall_z || a.bb != nullptr) return false;
   if (a.tiles_x < 3 || a.tile_x0 != 0 || a.tile_xstep != 1) return false;
